@@ -1,0 +1,166 @@
+"""Smoothers, Krylov root solver and V-cycles (oracle; test infrastructure only).
+
+* WAS  - Alg. 5: r = f - A u; u = u + sum_e R^T W A~^-1 R r, n_i times.
+* SCG  - Alg. 6, the inexact Schwarz-preconditioned CG of Golub and Ye,
+         with the flexible beta = z^T (r - r0) / gamma.  Reading: the first
+         search direction is p = z (the standard PCG start); the literal
+         p = r of the printed algorithm is kept behind `first_dir='r'`.
+* FAS  - Alg. 2 with global p-coarsening (every coarse element is a twig, no
+         frozen elements): the projected coarse solution u_bar = P u_l is
+         stored and reused in the prolongation u_l += I (u_{l-1} - u_bar).
+* CS   - Alg. 1, the linear correction scheme, for the FAS == CS check.
+"""
+import numpy as np
+
+from . import operator as op
+from .mesh import Mesh
+from .schwarz import Schwarz
+from . import transfer as tr
+
+
+class Level:
+    def __init__(self, mesh, m):
+        self.mesh = mesh
+        self.schwarz = Schwarz(mesh, m)
+        self.p = mesh.p
+
+    def A(self, u):
+        return op.apply(self.mesh, u)
+
+    def B(self, r):
+        return self.schwarz.apply(r)
+
+
+def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0):
+    """Level list (root first) for global p-coarsening of a uniform-degree mesh."""
+    chain = tr.degree_chain(p)
+    levels = [None] * len(chain)
+    Xl = np.asarray(X, dtype=np.float64)
+    for li in range(len(chain) - 1, -1, -1):
+        pl = chain[li]
+        if li < len(chain) - 1:
+            Xl = tr.coarse_coords(pl, chain[li + 1], Xl)
+        levels[li] = Level(Mesh(pl, Xl, nbr, bc, nu=nu, kappa=kappa, mu_star=mu_star), m)
+    return levels
+
+
+def norm(v):
+    return float(np.sqrt(np.sum(np.asarray(v) ** 2)))
+
+
+def was(level, u, f, n_i):
+    """Alg. 5 (weighted additive Schwarz)."""
+    for _ in range(n_i):
+        r = f - level.A(u)
+        u = u + level.B(r)
+    return u
+
+
+def scg(level, u, f, n_i, r_max=0.0, first_dir='z', precond=None, stats=None):
+    """Alg. 6 (Schwarz-preconditioned inexact CG); exits when ||r|| <= r_max."""
+    B = level.B if precond is None else precond
+    r = f - level.A(u)
+    p = r.copy() if first_dir == 'r' else None
+    gamma = None
+    r0 = None
+    it = 0
+    for i in range(1, n_i + 1):
+        z = B(r)
+        if i > 1:
+            beta = np.sum(z * (r - r0)) / gamma
+            p = beta * p + z
+        elif first_dir == 'z':
+            p = z.copy()
+        q = level.A(p)
+        gamma = np.sum(z * r)
+        alpha = gamma / np.sum(p * q)
+        r0 = r
+        r = r - alpha * q
+        u = u + alpha * p
+        it = i
+        if norm(r) <= r_max:
+            break
+    if stats is not None:
+        stats['iters'] = it
+    return u
+
+
+class Options:
+    """Cycle parameters: smoother 'was'|'scg', ns1, ns2; root 'scg' (to root_rtol) or 'direct'."""
+
+    def __init__(self, smoother='was', ns1=2, ns2=2, root_rtol=1e-12, root_maxit=500, first_dir='z',
+                 root='scg'):
+        self.smoother, self.ns1, self.ns2 = smoother, ns1, ns2
+        self.root_rtol, self.root_maxit, self.first_dir = root_rtol, root_maxit, first_dir
+        self.root = root
+
+
+def smooth(level, u, g, n, opts):
+    if n == 0:
+        return u
+    if opts.smoother == 'was':
+        return was(level, u, g, n)
+    return scg(level, u, g, n, 0.0, opts.first_dir)
+
+
+def root_solve(level, u, g, opts, stats=None):
+    if opts.root == 'direct':
+        A = op.assemble(level.mesh)
+        return np.linalg.solve(A, g.ravel()).reshape(u.shape)
+    r0 = norm(g - level.A(u))
+    return scg(level, u, g, opts.root_maxit, opts.root_rtol * r0, opts.first_dir, stats=stats)
+
+
+def fas_vcycle(levels, u_top, f_top, opts):
+    """Alg. 2 with global p-coarsening; returns the new top-level solution."""
+    L = len(levels)
+    u = [None] * L
+    g = [None] * L
+    ubar = [None] * L
+    u[L - 1], g[L - 1] = u_top, f_top
+    for l in range(L - 1, 0, -1):
+        lv, lc = levels[l], levels[l - 1]
+        u[l] = smooth(lv, u[l], g[l], opts.ns1, opts)
+        r = g[l] - lv.A(u[l])
+        ubar[l - 1] = tr.project(lc.p, lv.p, u[l])
+        u[l - 1] = ubar[l - 1].copy()
+        g[l - 1] = lc.A(u[l - 1]) + tr.restrict(lc.p, lv.p, r)
+    u[0] = root_solve(levels[0], u[0], g[0], opts)
+    for l in range(1, L):
+        lv, lc = levels[l], levels[l - 1]
+        u[l] = u[l] + tr.prolong(lc.p, lv.p, u[l - 1] - ubar[l - 1])
+        u[l] = smooth(lv, u[l], g[l], opts.ns2, opts)
+    return u[L - 1]
+
+
+def cs_vcycle(levels, u_top, f_top, opts):
+    """Alg. 1 (correction scheme)."""
+    L = len(levels)
+    u = [None] * L
+    f = [None] * L
+    u[L - 1], f[L - 1] = u_top, f_top
+    for l in range(L - 1, 0, -1):
+        lv, lc = levels[l], levels[l - 1]
+        u[l] = smooth(lv, u[l], f[l], opts.ns1, opts)
+        u[l - 1] = np.zeros((lc.mesh.E, lc.mesh.n, lc.mesh.n, lc.mesh.n))
+        f[l - 1] = tr.restrict(lc.p, lv.p, f[l] - lv.A(u[l]))
+    u[0] = root_solve(levels[0], u[0], f[0], opts)
+    for l in range(1, L):
+        lv, lc = levels[l], levels[l - 1]
+        u[l] = u[l] + tr.prolong(lc.p, lv.p, u[l - 1])
+        u[l] = smooth(lv, u[l], f[l], opts.ns2, opts)
+    return u[L - 1]
+
+
+def solve(levels, u0, f, opts, max_cycles=30, rtol=1e-10, cycle=fas_vcycle):
+    """Repeat V-cycles until ||r||/||r0|| <= rtol; returns (u, history of relative residuals)."""
+    top = levels[-1]
+    u = u0.copy()
+    r0 = norm(f - top.A(u))
+    hist = [1.0]
+    for _ in range(max_cycles):
+        u = cycle(levels, u, f, opts)
+        hist.append(norm(f - top.A(u)) / r0)
+        if hist[-1] <= rtol:
+            break
+    return u, hist

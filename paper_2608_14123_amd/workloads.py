@@ -1,0 +1,119 @@
+"""Seeded synthetic workloads: mesh topology, vertex geometry, maps and RHS values.
+
+This module holds no arithmetic of the discretisation or the solver.  It
+produces the inputs of the boundary: neighbour tables of structured hex
+grids, physical coordinates at caller-supplied reference points (each side
+passes its own GLL nodes), analytic maps and seeded nodal data.
+
+Element index: e = ex + nx * (ey + ny * ez).  Faces: 0:-x 1:+x 2:-y 3:+y 4:-z 5:+z.
+Element-local nodes are lexicographic with i (along x) fastest, then j, k.
+"""
+import numpy as np
+
+DIRICHLET, NEUMANN = 1, 2
+
+
+def box_topology(nx, ny, nz, periodic=(False, False, False), bc_code=DIRICHLET):
+    """Face-neighbour table (E, 6) int32 (-1 = boundary) and boundary codes (E, 6) int8."""
+    E = nx * ny * nz
+    ex, ey, ez = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing='ij')
+    ex, ey, ez = ex.transpose(2, 1, 0).ravel(), ey.transpose(2, 1, 0).ravel(), ez.transpose(2, 1, 0).ravel()
+    nbr = np.full((E, 6), -1, dtype=np.int32)
+    dims = (nx, ny, nz)
+    coords = [ex, ey, ez]
+    for d in range(3):
+        for s, step in ((0, -1), (1, 1)):
+            c = [ex.copy(), ey.copy(), ez.copy()]
+            c[d] = coords[d] + step
+            if periodic[d]:
+                c[d] %= dims[d]
+                ok = np.ones(E, dtype=bool)
+            else:
+                ok = (c[d] >= 0) & (c[d] < dims[d])
+            idx = c[0] + nx * (c[1] + ny * c[2])
+            nbr[ok, 2 * d + s] = idx[ok]
+    bc = np.where(nbr < 0, bc_code, 0).astype(np.int8)
+    return nbr, bc
+
+
+def box_vertices(nx, ny, nz, lengths=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
+    """Vertex grid V[kz, ky, kx, 3] of a uniform box partition."""
+    xs = [origin[d] + lengths[d] * np.arange(m + 1) / m for d, m in enumerate((nx, ny, nz))]
+    V = np.empty((nz + 1, ny + 1, nx + 1, 3))
+    V[..., 0] = xs[0][None, None, :]
+    V[..., 1] = xs[1][None, :, None]
+    V[..., 2] = xs[2][:, None, None]
+    return V
+
+
+def perturb_vertices(V, fraction, seed):
+    """Displace every interior vertex by U[-fraction, fraction] * (local edge length) per axis."""
+    rng = np.random.default_rng(seed)
+    V = V.copy()
+    nz, ny, nx = (s - 1 for s in V.shape[:3])
+    h = [np.diff(V[0, 0, :, 0]).min(), np.diff(V[0, :, 0, 1]).min(), np.diff(V[:, 0, 0, 2]).min()]
+    disp = rng.uniform(-fraction, fraction, size=V.shape) * np.array(h)
+    interior = np.zeros(V.shape[:3], dtype=bool)
+    interior[1:-1, 1:-1, 1:-1] = True
+    V[interior] += disp[interior]
+    return V
+
+
+def element_coords(V, xi, map_fn=None):
+    """Coordinates (E, 3, n, n, n) at tensor points xi (1D, ascending) of every element.
+
+    Trilinear interpolation of the vertex grid, then the optional pointwise map.
+    """
+    xi = np.asarray(xi, dtype=np.float64)
+    nz, ny, nx = (s - 1 for s in V.shape[:3])
+    lo, hi = 0.5 * (1.0 - xi), 0.5 * (1.0 + xi)
+    shape_fn = (lo, hi)
+    E, n = nx * ny * nz, len(xi)
+    X = np.zeros((nz, ny, nx, n, n, n, 3))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                wgt = shape_fn[dz][:, None, None] * shape_fn[dy][None, :, None] * shape_fn[dx][None, None, :]
+                corner = V[dz:dz + nz, dy:dy + ny, dx:dx + nx]          # (nz, ny, nx, 3)
+                X += wgt[None, None, None, :, :, :, None] * corner[:, :, :, None, None, None, :]
+    X = X.reshape(E, n, n, n, 3)
+    if map_fn is not None:
+        X = map_fn(X)
+    return np.ascontiguousarray(np.moveaxis(X, -1, 1))
+
+
+def sine_bump_map(X, amplitude=0.1):
+    """x'_a = x_a + amplitude * sin(2 pi x) sin(2 pi y) sin(2 pi z) for every component a."""
+    s = amplitude * np.sin(2 * np.pi * X[..., 0]) * np.sin(2 * np.pi * X[..., 1]) * np.sin(2 * np.pi * X[..., 2])
+    return X + s[..., None]
+
+
+def uniform_nodal(shape, seed):
+    """Nodal values ~ U[-1, 1] from numpy's PCG64 with the given seed."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=shape)
+
+
+def sine_solution(X, k=np.pi):
+    """u = sin(k x) sin(k y) sin(k z) at coordinates X (E, 3, ...)."""
+    return np.sin(k * X[:, 0]) * np.sin(k * X[:, 1]) * np.sin(k * X[:, 2])
+
+
+# --- named workloads -----------------------------------------------------------------
+
+def cartesian_unit_cube(ne):
+    """ne^3 uniform cubes on [0,1]^3 with Dirichlet boundary."""
+    nbr, bc = box_topology(ne, ne, ne)
+    return box_vertices(ne, ne, ne), nbr, bc
+
+
+def curved_cube(ne):
+    """ne^3 elements on [0,1]^3 under the sine-bump map (boundary fixed by the map)."""
+    nbr, bc = box_topology(ne, ne, ne)
+    return box_vertices(ne, ne, ne), nbr, bc, sine_bump_map
+
+
+def stretched_perturbed(ne, aspect=100.0, fraction=0.2, seed=4):
+    """ne^3 elements on [0,1]^2 x [0,aspect] with interior vertices perturbed."""
+    nbr, bc = box_topology(ne, ne, ne)
+    V = box_vertices(ne, ne, ne, lengths=(1.0, 1.0, aspect))
+    return perturb_vertices(V, fraction, seed), nbr, bc
