@@ -1,0 +1,156 @@
+/*
+ * dgfas.h - C ABI of the MI355X (gfx950) FAS multigrid / weighted-Schwarz
+ * library for SIPG discontinuous Galerkin spectral elements.
+ *
+ * Problem (Sec. 2.1, eq. helmholtz): kappa u - div(nu grad u) = f on a mesh of
+ * conforming hexahedra with Dirichlet or Neumann faces; constant kappa >= 0
+ * and nu > 0.  Discretisation (Sec. 2.2, eq. helmholtz:dgm): nodal GLL basis of
+ * degree p per element, isoparametric geometry in the same basis, GLL
+ * quadrature, symmetric interior penalty with mu = mu_star avg(p(p+1)/(2 h_perp)).
+ *
+ * Conventions
+ *  - Vectors are device pointers to FP64 data in element-major layout: element
+ *    e owns [e*(p+1)^3, (e+1)*(p+1)^3); inside an element nodes are
+ *    lexicographic with i (xi_1) fastest, then j (xi_2), then k (xi_3).  The
+ *    caller owns every pointer it passes; the library never frees them.
+ *  - Faces are numbered 0:-xi_1 1:+xi_1 2:-xi_2 3:+xi_2 4:-xi_3 5:+xi_3.
+ *    Neighbours must be aligned (face node (a,b) of one side is face node
+ *    (a,b) of the other).
+ *  - Levels count from 1 (root, p = 1) to L (finest), as in Sec. 3.1; each
+ *    coarser level halves the degree: p_{l-1} = max(1, floor(p_l / 2)).
+ *  - All device work is enqueued on the stream given at creation (NULL = the
+ *    null stream) and is asynchronous unless stated otherwise.
+ *  - Errors: every call returns a dgfas_status; on failure nothing has been
+ *    enqueued and dgfas_last_error() gives a message.  Nothing is thrown.
+ *  - One solver object must not be used by two threads at the same time.
+ */
+#ifndef DGFAS_H
+#define DGFAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DGFAS_OK = 0,
+  DGFAS_ENOTCONV = 1,      /* warning: tolerance not reached; outputs are valid */
+  DGFAS_EINVAL = -1,       /* bad argument (null pointer, bad size, bad level) */
+  DGFAS_ENOMEM = -2,       /* device allocation failed */
+  DGFAS_EHIP = -3,         /* HIP runtime error (message in dgfas_last_error) */
+  DGFAS_EUNSUPPORTED = -4, /* valid input outside what this build implements */
+  DGFAS_EBREAKDOWN = -5    /* non-finite value or p^T A p <= 0 inside SCG */
+} dgfas_status;
+
+enum { DGFAS_INTERIOR = 0, DGFAS_DIRICHLET = 1, DGFAS_NEUMANN = 2 };
+enum { DGFAS_WAS = 0, DGFAS_SCG = 1 };
+enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1 };
+
+typedef struct dgfas_solver_s* dgfas_solver;
+
+/* Mesh (Sec. 2.2): host arrays, read during dgfas_create only. */
+typedef struct {
+  int32_t n_elem;
+  const int32_t* degree;    /* [n_elem] polynomial degree per element, 1..8; all equal in this build */
+  const double* coords;     /* [n_elem][3][(p+1)^3] nodal x, y, z at the element's GLL nodes
+                               (the GLL nodes of dgfas_gll); the map must keep det J > 0 */
+  const int32_t* face_nbr;  /* [n_elem][6] neighbour element, or -1 on the boundary */
+  const int8_t* face_bc;    /* [n_elem][6] DGFAS_DIRICHLET / DGFAS_NEUMANN on boundary faces */
+} dgfas_mesh_desc;
+
+/* Solver options.  Defaults come from dgfas_default_options. */
+typedef struct {
+  double kappa;             /* >= 0 */
+  double nu;                /* > 0 */
+  double mu_star;           /* penalty scale of eq. helmholtz:dgm, > 0 */
+  int32_t overlap;          /* Schwarz overlap m in node layers, 0..p (Sec. 4.3.1 item 3) */
+  int32_t smoother;         /* DGFAS_WAS (Alg. 5) or DGFAS_SCG (Alg. 6) on levels > 1 */
+  int32_t ns1, ns2;         /* pre- and post-smoothing steps (Alg. 2) */
+  int32_t root_max_iter;    /* SCG iteration cap of the root solve */
+  double root_rtol;         /* root SCG stops when ||r|| <= root_rtol * ||r_0|| */
+  int32_t precision;        /* DGFAS_FP64, or DGFAS_FP32: smoothing of the correction system
+                               (eq. smoothers:system:correction) in FP32 on levels > 1 with the
+                               FAS residual, tau-correction and root solve in FP64 */
+  int32_t reserved[7];
+} dgfas_options;
+
+void dgfas_default_options(dgfas_options* opt);
+
+/* GLL nodes and weights of degree p (1..16), host arrays of p+1 doubles
+ * (Remark on basis functions).  Usable without a GPU. */
+dgfas_status dgfas_gll(int32_t p, double* x, double* w);
+
+/* Host-only: 1D subdomain tables of the Schwarz method (Sec. 4.3.1) for degree p,
+ * overlap m and face conditions (left, right) in {DGFAS_INTERIOR, DGFAS_DIRICHLET,
+ * DGFAS_NEUMANN}.  Outputs (host, caller-sized): ns = number of subdomain nodes,
+ * S [ns*ns] row-major with S^T M S = I and S^T L S = diag(lam), lam [ns], weights [ns].
+ * ns <= p + 1 + 2m.  Usable without a GPU. */
+dgfas_status dgfas_schwarz_tables_1d(int32_t p, int32_t m, int32_t left, int32_t right,
+                                     double mu_star, int32_t* ns, double* S, double* lam,
+                                     double* weights);
+
+/* Build the level hierarchy, the geometry on every level and the Schwarz data.
+ * stream: a hipStream_t (NULL = null stream).  Synchronous. */
+dgfas_status dgfas_create(const dgfas_mesh_desc* mesh, const dgfas_options* opt, void* stream,
+                          dgfas_solver* out);
+void dgfas_destroy(dgfas_solver s);
+
+/* Number of levels L, and degree / DOF count of one level. */
+dgfas_status dgfas_levels(dgfas_solver s, int32_t* n_levels);
+dgfas_status dgfas_level_info(dgfas_solver s, int32_t level, int32_t* degree, int64_t* n_dof);
+
+/* Right-hand side of eq. helmholtz:system on the finest level from nodal values
+ * (device): f [n_dof], uD [n_dof] (values at Dirichlet face nodes are used; may be
+ * NULL for u_D = 0), qN [n_dof] (Neumann flux at Neumann face nodes; may be NULL).
+ * b [n_dof] is written. */
+dgfas_status dgfas_rhs(dgfas_solver s, const double* f, const double* uD, const double* qN, double* b);
+
+/* Au = A_l u (eq. helmholtz:system on level l). */
+dgfas_status dgfas_apply(dgfas_solver s, int32_t level, const double* u, double* Au);
+
+/* r = g - A_l u (Alg. 2 residual computation). */
+dgfas_status dgfas_residual(dgfas_solver s, int32_t level, const double* u, const double* g, double* r);
+
+/* z = sum_e R_s^T W^e (A~_s^e)^-1 R_s r: one weighted Schwarz application
+ * (eq. schwarz:correction) with fast-diagonalisation subdomain solves. */
+dgfas_status dgfas_schwarz(dgfas_solver s, int32_t level, const double* r, double* z);
+
+/* n_steps smoothing steps of the configured smoother on A_l u = g, in place
+ * (Alg. 5 WAS, or Alg. 6 SCG with r_max = 0). */
+dgfas_status dgfas_smooth(dgfas_solver s, int32_t level, double* u, const double* g, int32_t n_steps);
+
+/* Transfers between level l (fine) and l-1 (coarse), Sec. 3.2:
+ *   restrict:    r_c = R r_f = I^T r_f
+ *   project:     u_c = P u_f (embedded interpolation at the coarse GLL nodes)
+ *   prolong_add: u_f += I (u_c - ubar_c)   (ubar_c may be NULL for u_f += I u_c) */
+dgfas_status dgfas_restrict(dgfas_solver s, int32_t level, const double* r_fine, double* r_coarse);
+dgfas_status dgfas_project(dgfas_solver s, int32_t level, const double* u_fine, double* u_coarse);
+dgfas_status dgfas_prolong_add(dgfas_solver s, int32_t level, const double* u_coarse,
+                               const double* ubar_coarse, double* u_fine);
+
+/* Root solve on level 1: SCG (Alg. 6) from u until ||r|| <= root_rtol ||r_0|| or
+ * root_max_iter iterations; iters (host, may be NULL) receives the count.  Synchronous. */
+dgfas_status dgfas_root_solve(dgfas_solver s, double* u, const double* g, int32_t* iters);
+
+/* One FAS V-cycle (Alg. 2, global p-coarsening) on the finest-level u for rhs f. */
+dgfas_status dgfas_vcycle(dgfas_solver s, double* u, const double* f);
+
+/* FAS V-cycles until ||f - A u|| <= rtol ||f - A u_0|| or max_cycles.
+ * hist (host, may be NULL) receives max_cycles+1 relative residuals (entry 0 = 1);
+ * n_done (host, may be NULL) the number of cycles run.  Synchronises once per cycle.
+ * Returns DGFAS_ENOTCONV (a warning) if the tolerance was not reached. */
+dgfas_status dgfas_solve(dgfas_solver s, double* u, const double* f, int32_t max_cycles, double rtol,
+                         double* hist, int32_t* n_done);
+
+/* Euclidean norm of a level-l vector, written to a host double.  Synchronous. */
+dgfas_status dgfas_norm(dgfas_solver s, int32_t level, const double* v, double* out);
+
+/* Message of the last failed call on this thread. */
+const char* dgfas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGFAS_H */

@@ -1,0 +1,207 @@
+"""ctypes binding of libdgfas.so (include/dgfas.h).
+
+Argument marshalling only: every computation runs inside the HIP library.
+Device vectors are passed as torch CUDA tensors (float64, contiguous); host
+arrays as numpy arrays.  If the shared library is missing this module raises
+at import time: there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libdgfas.so')
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdgfas.so not built: run __graft_entry__.build() (or "
+                      "python paper_2608_14123_amd/csrc/build.py) first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+DGFAS_OK, DGFAS_ENOTCONV = 0, 1
+DGFAS_EINVAL, DGFAS_ENOMEM, DGFAS_EHIP, DGFAS_EUNSUPPORTED, DGFAS_EBREAKDOWN = -1, -2, -3, -4, -5
+INTERIOR, DIRICHLET, NEUMANN = 0, 1, 2
+WAS, SCG = 0, 1
+FP64, FP32 = 0, 1
+
+c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [('n_elem', ctypes.c_int32), ('degree', ctypes.c_void_p), ('coords', ctypes.c_void_p),
+                ('face_nbr', ctypes.c_void_p), ('face_bc', ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [('kappa', ctypes.c_double), ('nu', ctypes.c_double), ('mu_star', ctypes.c_double),
+                ('overlap', ctypes.c_int32), ('smoother', ctypes.c_int32), ('ns1', ctypes.c_int32),
+                ('ns2', ctypes.c_int32), ('root_max_iter', ctypes.c_int32), ('root_rtol', ctypes.c_double),
+                ('precision', ctypes.c_int32), ('reserved', ctypes.c_int32 * 7)]
+
+
+class DgfasError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__('dgfas error %d: %s' % (code, msg))
+        self.code = code
+
+
+_V = ctypes.c_void_p
+_I = ctypes.c_int32
+_sig = {
+    'dgfas_default_options': (None, [ctypes.POINTER(Options)]),
+    'dgfas_gll': (_I, [_I, c_dp, c_dp]),
+    'dgfas_schwarz_tables_1d': (_I, [_I, _I, _I, _I, ctypes.c_double, ctypes.POINTER(_I), c_dp, c_dp, c_dp]),
+    'dgfas_create': (_I, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Options), _V, ctypes.POINTER(_V)]),
+    'dgfas_destroy': (None, [_V]),
+    'dgfas_levels': (_I, [_V, ctypes.POINTER(_I)]),
+    'dgfas_level_info': (_I, [_V, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64)]),
+    'dgfas_rhs': (_I, [_V, _V, _V, _V, _V]),
+    'dgfas_apply': (_I, [_V, _I, _V, _V]),
+    'dgfas_residual': (_I, [_V, _I, _V, _V, _V]),
+    'dgfas_schwarz': (_I, [_V, _I, _V, _V]),
+    'dgfas_smooth': (_I, [_V, _I, _V, _V, _I]),
+    'dgfas_restrict': (_I, [_V, _I, _V, _V]),
+    'dgfas_project': (_I, [_V, _I, _V, _V]),
+    'dgfas_prolong_add': (_I, [_V, _I, _V, _V, _V]),
+    'dgfas_root_solve': (_I, [_V, _V, _V, ctypes.POINTER(_I)]),
+    'dgfas_vcycle': (_I, [_V, _V, _V]),
+    'dgfas_solve': (_I, [_V, _V, _V, _I, ctypes.c_double, c_dp, ctypes.POINTER(_I)]),
+    'dgfas_norm': (_I, [_V, _I, _V, c_dp]),
+    'dgfas_last_error': (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def _check(code, warn_ok=False):
+    if code == DGFAS_OK or (warn_ok and code > 0):
+        return code
+    raise DgfasError(code, _lib.dgfas_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if hasattr(t, 'data_ptr'):
+        if not t.is_contiguous():
+            raise ValueError('tensor must be contiguous')
+        return t.data_ptr()
+    raise TypeError('expected a torch tensor')
+
+
+def default_options(**kw):
+    o = Options()
+    _lib.dgfas_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def gll(p):
+    x = np.zeros(p + 1)
+    w = np.zeros(p + 1)
+    _check(_lib.dgfas_gll(p, x.ctypes.data_as(c_dp), w.ctypes.data_as(c_dp)))
+    return x, w
+
+
+def schwarz_tables_1d(p, m, left, right, mu_star):
+    nsmax = p + 1 + 2 * m
+    ns = _I()
+    S = np.zeros(nsmax * nsmax)
+    lam = np.zeros(nsmax)
+    W = np.zeros(nsmax)
+    _check(_lib.dgfas_schwarz_tables_1d(p, m, left, right, mu_star, ctypes.byref(ns), S.ctypes.data_as(c_dp),
+                                        lam.ctypes.data_as(c_dp), W.ctypes.data_as(c_dp)))
+    k = ns.value
+    return S[:k * k].reshape(k, k), lam[:k], W[:k]
+
+
+class Solver:
+    """One level hierarchy on the current device (see dgfas_create)."""
+
+    def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None):
+        degree = np.ascontiguousarray(degree, dtype=np.int32)
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        face_nbr = np.ascontiguousarray(face_nbr, dtype=np.int32)
+        face_bc = np.ascontiguousarray(face_bc, dtype=np.int8)
+        E = len(degree)
+        if face_nbr.shape != (E, 6) or face_bc.shape != (E, 6):
+            raise ValueError('face tables must be (n_elem, 6)')
+        n = int(degree[0]) + 1
+        if coords.size != E * 3 * n ** 3:
+            raise ValueError('coords must hold n_elem * 3 * (p+1)^3 values')
+        self._keep = (degree, coords, face_nbr, face_bc)
+        desc = MeshDesc(E, degree.ctypes.data, coords.ctypes.data, face_nbr.ctypes.data, face_bc.ctypes.data)
+        self.options = options if options is not None else default_options()
+        h = _V()
+        st = None if stream is None else _V(stream)
+        _check(_lib.dgfas_create(ctypes.byref(desc), ctypes.byref(self.options), st, ctypes.byref(h)))
+        self._h = h
+        nl = _I()
+        _check(_lib.dgfas_levels(self._h, ctypes.byref(nl)))
+        self.n_levels = nl.value
+
+    def close(self):
+        if getattr(self, '_h', None):
+            _lib.dgfas_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level):
+        d = _I()
+        nd = ctypes.c_int64()
+        _check(_lib.dgfas_level_info(self._h, level, ctypes.byref(d), ctypes.byref(nd)))
+        return d.value, nd.value
+
+    def rhs(self, f, b, uD=None, qN=None):
+        _check(_lib.dgfas_rhs(self._h, _ptr(f), _ptr(uD), _ptr(qN), _ptr(b)))
+
+    def apply(self, level, u, Au):
+        _check(_lib.dgfas_apply(self._h, level, _ptr(u), _ptr(Au)))
+
+    def residual(self, level, u, g, r):
+        _check(_lib.dgfas_residual(self._h, level, _ptr(u), _ptr(g), _ptr(r)))
+
+    def schwarz(self, level, r, z):
+        _check(_lib.dgfas_schwarz(self._h, level, _ptr(r), _ptr(z)))
+
+    def smooth(self, level, u, g, n_steps):
+        _check(_lib.dgfas_smooth(self._h, level, _ptr(u), _ptr(g), n_steps))
+
+    def restrict(self, level, r_fine, r_coarse):
+        _check(_lib.dgfas_restrict(self._h, level, _ptr(r_fine), _ptr(r_coarse)))
+
+    def project(self, level, u_fine, u_coarse):
+        _check(_lib.dgfas_project(self._h, level, _ptr(u_fine), _ptr(u_coarse)))
+
+    def prolong_add(self, level, u_coarse, u_fine, ubar=None):
+        _check(_lib.dgfas_prolong_add(self._h, level, _ptr(u_coarse), _ptr(ubar), _ptr(u_fine)))
+
+    def root_solve(self, u, g):
+        it = _I()
+        _check(_lib.dgfas_root_solve(self._h, _ptr(u), _ptr(g), ctypes.byref(it)))
+        return it.value
+
+    def vcycle(self, u, f):
+        _check(_lib.dgfas_vcycle(self._h, _ptr(u), _ptr(f)))
+
+    def solve(self, u, f, max_cycles=30, rtol=1e-10):
+        hist = np.zeros(max_cycles + 1)
+        nd = _I()
+        code = _check(_lib.dgfas_solve(self._h, _ptr(u), _ptr(f), max_cycles, rtol, hist.ctypes.data_as(c_dp),
+                                       ctypes.byref(nd)), warn_ok=True)
+        return hist[:nd.value + 1], code == DGFAS_OK
+
+    def norm(self, level, v):
+        out = ctypes.c_double()
+        _check(_lib.dgfas_norm(self._h, level, _ptr(v), ctypes.byref(out)))
+        return out.value

@@ -1,0 +1,42 @@
+// Device-side helpers shared by the HIP kernels of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgfas {
+
+// XCD-aware block remap: the hardware deals consecutive workgroup ids round-robin
+// over the 8 XCDs; remapping gives every XCD a contiguous range of logical blocks
+// so that neighbouring elements share an L2.  Returns -1 for padding blocks.
+__device__ __forceinline__ int xcd_block(int n_logical) {
+  const int per = (n_logical + 7) / 8;
+  const int b = blockIdx.x;
+  const int lb = (b & 7) * per + (b >> 3);
+  return lb < n_logical ? lb : -1;
+}
+
+inline int xcd_grid(int n_logical) { return 8 * ((n_logical + 7) / 8); }
+
+// Volume index of face node f = (a, b) of face phi (layout: phi 0/1 -> (k, j),
+// 2/3 -> (k, i), 4/5 -> (j, i)) with the normal index set to `t`.
+template <int N>
+__device__ __forceinline__ int face_node(int phi, int f, int t) {
+  const int a = f / N, b = f % N;
+  const int ax = phi >> 1;
+  if (ax == 0) return (a * N + b) * N + t;
+  if (ax == 1) return (a * N + t) * N + b;
+  return (t * N + a) * N + b;
+}
+
+// stride of the normal line of axis ax
+template <int N>
+__device__ __forceinline__ constexpr int axis_stride(int ax) {
+  return ax == 0 ? 1 : (ax == 1 ? N : N * N);
+}
+
+// index of symmetric metric component (b, c) in G[6] = {00, 01, 02, 11, 12, 22}
+__device__ __forceinline__ constexpr int sym_index(int b, int c) {
+  return (b > c) ? sym_index(c, b) : (b == 0 ? c : (b == 1 ? 2 + c : 5));
+}
+
+}  // namespace dgfas

@@ -1,0 +1,250 @@
+// K3: per-element tensor-product transfers between p-levels (Sec. 3.2):
+//   out (=|+=) (T x T x T)(in - in2),  T: n_out x n_in,
+// used for P (projection), R = I^T (restriction) and I (prolongation).
+// K4: BLAS-1 pieces of SCG (Alg. 6) with fixed-shape two-stage reductions, so
+// every dot product is bitwise reproducible.
+#include "device.hpp"
+#include "kernels.hpp"
+#include "blas.hpp"
+
+namespace dgfas {
+
+template <int NI, int NO>
+struct TrShape {
+  static constexpr int NM = NI > NO ? NI : NO;
+  static constexpr int M3 = NM * NM * NM;
+  static constexpr int EPB = (M3 >= 256) ? 1 : (256 / M3);
+  static constexpr int THREADS = ((EPB * M3 + 63) / 64) * 64;
+};
+
+template <int NI, int NO, typename T>
+__global__ void __launch_bounds__((TrShape<NI, NO>::THREADS))
+tensor3_kernel(int E, const T* __restrict__ Tm, const T* __restrict__ in, const T* __restrict__ in2,
+               T* __restrict__ out, int accumulate) {
+  using S = TrShape<NI, NO>;
+  constexpr int M3 = S::M3, EPB = S::EPB, I3 = NI * NI * NI, O3 = NO * NO * NO;
+  const int lb = xcd_block((E + EPB - 1) / EPB);
+  if (lb < 0) return;
+  const int tid = threadIdx.x;
+  const int le = tid / M3, q = tid - le * M3;
+  const int e = lb * EPB + le;
+  const bool act = le < EPB && e < E;
+  __shared__ T sT[NO * NI];
+  __shared__ T s0[EPB][NI * NI * NI];
+  __shared__ T s1[EPB][NI * NI * NO];
+  __shared__ T s2[EPB][NI * NO * NO];
+  for (int t = tid; t < NO * NI; t += S::THREADS) sT[t] = Tm[t];
+  if (act && q < I3) {
+    T v = in[(int64_t)e * I3 + q];
+    if (in2) v -= in2[(int64_t)e * I3 + q];
+    s0[le][q] = v;
+  }
+  __syncthreads();
+  if (act && q < NI * NI * NO) {   // [k][j][a]
+    const int a = q % NO, j = (q / NO) % NI, k = q / (NO * NI);
+    T s = 0;
+    for (int i = 0; i < NI; ++i) s += sT[a * NI + i] * s0[le][(k * NI + j) * NI + i];
+    s1[le][q] = s;
+  }
+  __syncthreads();
+  if (act && q < NI * NO * NO) {   // [k][b][a]
+    const int a = q % NO, b = (q / NO) % NO, k = q / (NO * NO);
+    T s = 0;
+    for (int j = 0; j < NI; ++j) s += sT[b * NI + j] * s1[le][(k * NI + j) * NO + a];
+    s2[le][q] = s;
+  }
+  __syncthreads();
+  if (act && q < O3) {             // [c][b][a]
+    const int a = q % NO, b = (q / NO) % NO, c = q / (NO * NO);
+    T s = 0;
+    for (int k = 0; k < NI; ++k) s += sT[c * NI + k] * s2[le][(k * NO + b) * NO + a];
+    const int64_t o = (int64_t)e * O3 + q;
+    out[o] = accumulate ? out[o] + s : s;
+  }
+}
+
+template <int NI, int NO, typename T>
+void launch_t3(int E, const T* Tm, const T* in, const T* in2, T* out, int acc, hipStream_t st) {
+  using S = TrShape<NI, NO>;
+  const int nb = (E + S::EPB - 1) / S::EPB;
+  hipLaunchKernelGGL((tensor3_kernel<NI, NO, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, E, Tm, in, in2, out,
+                     acc);
+}
+
+template <typename T>
+bool tensor3(int n_in, int n_out, int E, const T* Tm, const T* in, const T* in2, T* out, int acc, hipStream_t st) {
+#define T3C(a, b) \
+  if (n_in == a && n_out == b) { launch_t3<a, b, T>(E, Tm, in, in2, out, acc, st); return true; }
+  // p-coarsening pairs (p_c = max(1, p_f / 2)) and identity-degree copies
+  T3C(3, 2) T3C(2, 3) T3C(4, 2) T3C(2, 4) T3C(5, 3) T3C(3, 5) T3C(6, 3) T3C(3, 6)
+  T3C(7, 4) T3C(4, 7) T3C(8, 4) T3C(4, 8) T3C(9, 5) T3C(5, 9) T3C(2, 2)
+  T3C(3, 3) T3C(4, 4) T3C(5, 5) T3C(6, 6) T3C(7, 7) T3C(8, 8) T3C(9, 9)
+#undef T3C
+  return false;
+}
+
+template bool tensor3<double>(int, int, int, const double*, const double*, const double*, double*, int, hipStream_t);
+template bool tensor3<float>(int, int, int, const float*, const float*, const float*, float*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+
+int reduction_blocks(int64_t n) {
+  int64_t b = (n + kRedThreads * 8 - 1) / (kRedThreads * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// partial[blk] = sum_i a_i (b_i - c_i)   (b, c may be null: b := a, c := 0)
+__global__ void __launch_bounds__(kRedThreads)
+dot_partial_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+                   double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads];
+  double s = 0;
+  const int64_t stride = (int64_t)gridDim.x * kRedThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    const double bv = b ? b[i] : a[i];
+    s += a[i] * (c ? bv - c[i] : bv);
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void dot_partials(int64_t n, const double* a, const double* b, const double* c, double* partial, int nblocks,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, n, a, b, c, partial);
+}
+
+// Second stage: one block sums the partials of `nvals` reductions (stride 1024),
+// then applies the SCG scalar update selected by `op`.
+//   scal: [0] gamma (z^T r)  [1] beta  [2] alpha  [3] r^T r  [4] breakdown flag  [5] p^T q
+__global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double* __restrict__ partial, int op,
+                                                      double* __restrict__ scal, double* __restrict__ out) {
+  __shared__ double sh[1024];
+  const int tid = threadIdx.x;
+  double v0 = 0, v1 = 0;
+  for (int b = tid; b < nblocks; b += 1024) {
+    v0 += partial[b];
+    v1 += partial[1024 + b];
+  }
+  const double s0 = block_sum(v0, sh);
+  __syncthreads();
+  const double s1 = (op == kOpBeta) ? block_sum(v1, sh) : 0.0;
+  if (tid != 0) return;
+  switch (op) {
+    case kOpGamma:          // first iteration: gamma = z^T r
+      scal[0] = s0;
+      scal[1] = 0.0;
+      break;
+    case kOpBeta: {         // beta = z^T (r - r0) / gamma_old ; gamma = z^T r
+      const double beta = s1 / scal[0];
+      scal[1] = beta;
+      scal[0] = s0;
+      if (!isfinite(beta)) scal[4] = 1.0;
+      break;
+    }
+    case kOpAlpha: {        // alpha = gamma / p^T q
+      scal[5] = s0;
+      const double alpha = scal[0] / s0;
+      scal[2] = alpha;
+      if (!(s0 > 0.0) || !isfinite(alpha)) { scal[4] = 1.0; scal[2] = 0.0; }
+      break;
+    }
+    case kOpNorm2:          // r^T r
+      scal[3] = s0;
+      if (!isfinite(s0)) scal[4] = 1.0;
+      break;
+    case kOpStore:
+      out[0] = s0;
+      break;
+  }
+}
+
+void finish(int nblocks, const double* partial, int op, double* scal, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, st, nblocks, partial, op, scal, out);
+}
+
+// p = beta p + z   (first: p = z)
+__global__ void pupdate_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ p,
+                               const double* __restrict__ scal, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = first ? z[i] : scal[1] * p[i] + z[i];
+}
+
+// r0 = r; r -= alpha q; u += alpha p; partial[blk] = sum r^2
+__global__ void __launch_bounds__(kRedThreads)
+cg_update_kernel(int64_t n, double* __restrict__ r, double* __restrict__ r0, const double* __restrict__ q,
+                 double* __restrict__ u, const double* __restrict__ p, const double* __restrict__ scal,
+                 double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads];
+  const double alpha = scal[2];
+  double s = 0;
+  const int64_t stride = (int64_t)gridDim.x * kRedThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
+    const double rv = r[i];
+    if (r0) r0[i] = rv;
+    const double rn = rv - alpha * q[i];
+    r[i] = rn;
+    u[i] += alpha * p[i];
+    s += rn * rn;
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void pupdate(int64_t n, const double* z, double* p, const double* scal, int first, hipStream_t st) {
+  hipLaunchKernelGGL(pupdate_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, z, p, scal, first);
+}
+
+void cg_update(int64_t n, double* r, double* r0, const double* q, double* u, const double* p, const double* scal,
+               double* partial, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(cg_update_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, n, r, r0, q, u, p, scal, partial);
+}
+
+// y = x (with optional conversion) / y += x
+template <typename TI, typename TO>
+__global__ void convert_kernel(int64_t n, const TI* __restrict__ x, TO* __restrict__ y, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = accumulate ? (TO)(y[i] + (TO)x[i]) : (TO)x[i];
+}
+
+template <typename TI, typename TO>
+void convert(int64_t n, const TI* x, TO* y, int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL((convert_kernel<TI, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, y,
+                     accumulate);
+}
+template void convert<double, double>(int64_t, const double*, double*, int, hipStream_t);
+template void convert<double, float>(int64_t, const double*, float*, int, hipStream_t);
+template void convert<float, double>(int64_t, const float*, double*, int, hipStream_t);
+template void convert<float, float>(int64_t, const float*, float*, int, hipStream_t);
+
+__global__ void fill_kernel(int64_t n, double* __restrict__ y, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+void fill(int64_t n, double* y, double v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, y, v);
+}
+__global__ void fillf_kernel(int64_t n, float* __restrict__ y, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+void fill(int64_t n, float* y, float v, hipStream_t st) {
+  hipLaunchKernelGGL(fillf_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, y, v);
+}
+
+}  // namespace dgfas

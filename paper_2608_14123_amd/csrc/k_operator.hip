@@ -1,0 +1,469 @@
+// K1: sum-factorised SIPG operator apply / residual on curvilinear hexahedra
+// (eq. helmholtz:dgm) and the one-time geometry kernels (Sec. 2.2).
+//
+// One workgroup takes EPB elements, one thread per node.  The element's u and
+// the contravariant fluxes F_b = sum_c G_bc d_c u (G_bc = w J nu grad xi_b .
+// grad xi_c) live in LDS.  Face terms use the identity
+//   nu * omega * s * (n_out . grad xi_c) = +-G_bc / w_end     (normal axis b)
+// so the own normal flux is F_b / w_end at the face node and the lifting term
+// adds sigma * G_bc / w_end to F_c there; the neighbour's flux is rebuilt from
+// its normal node line (L2-resident) and its metric at the shared face.  The
+// three face axes are processed one after another so that no node is written
+// by two tasks at once: the result is deterministic without atomics.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace dgfas {
+
+template <int N>
+struct OpShape {
+  static constexpr int N2 = N * N, N3 = N * N * N;
+  static constexpr int EPB = (N3 >= 256) ? 1 : (256 / N3);
+  static constexpr int THREADS = ((EPB * N3 + 63) / 64) * 64;
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(OpShape<N>::THREADS)
+sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __restrict__ out, int mode,
+                  const T* __restrict__ G, const T* __restrict__ WJ, const T* __restrict__ pen,
+                  const int* __restrict__ nbr, const int8_t* __restrict__ bc, const T* __restrict__ Dg,
+                  T kappa, T inv_wend) {
+  using S = OpShape<N>;
+  constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
+  const int lb = xcd_block((E + EPB - 1) / EPB);
+  if (lb < 0) return;
+  const int tid = threadIdx.x;
+  const int le = tid / N3;
+  const int node = tid - le * N3;
+  const int e = lb * EPB + le;
+  const bool active = (le < EPB) && (e < E);
+
+  __shared__ T sD[N2];
+  __shared__ T su[EPB][N3];
+  __shared__ T sF[EPB][3][N3];
+  __shared__ T sRow[EPB][N3];
+  __shared__ T sQ[EPB][6][N2];
+  __shared__ T sTr[EPB][2][N2];
+
+  for (int t = tid; t < N2; t += S::THREADS) sD[t] = Dg[t];
+  const int64_t base = (int64_t)e * N3;
+  T uval = 0;
+  if (active) {
+    uval = u[base + node];
+    su[le][node] = uval;
+    sRow[le][node] = 0;
+  }
+  __syncthreads();
+
+  const int i = node % N, j = (node / N) % N, k = node / N2;
+  if (active) {
+    T d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      d0 += sD[i * N + m] * su[le][(k * N + j) * N + m];
+      d1 += sD[j * N + m] * su[le][(k * N + m) * N + i];
+      d2 += sD[k * N + m] * su[le][(m * N + j) * N + i];
+    }
+    const int64_t ndof = (int64_t)E * N3;
+    const T g00 = G[0 * ndof + base + node], g01 = G[1 * ndof + base + node], g02 = G[2 * ndof + base + node];
+    const T g11 = G[3 * ndof + base + node], g12 = G[4 * ndof + base + node], g22 = G[5 * ndof + base + node];
+    sF[le][0][node] = g00 * d0 + g01 * d1 + g02 * d2;
+    sF[le][1][node] = g01 * d0 + g11 * d1 + g12 * d2;
+    sF[le][2][node] = g02 * d0 + g12 * d1 + g22 * d2;
+  }
+  __syncthreads();
+
+  // pass A: own normal fluxes q = nu omega s n_out.grad u = +-F_b / w_end at every face node
+  if (le < EPB && e < E) {
+    for (int t = node; t < 6 * N2; t += N3) {
+      const int phi = t / N2, f = t - phi * N2;
+      const int ax = phi >> 1;
+      const int vi = face_node<N>(phi, f, (phi & 1) ? N - 1 : 0);
+      const T sgn = (phi & 1) ? T(1) : T(-1);
+      sQ[le][phi][f] = sgn * inv_wend * sF[le][ax][vi];
+    }
+  }
+  __syncthreads();
+
+  const int64_t ndof = (int64_t)E * N3;
+  for (int ax = 0; ax < 3; ++ax) {
+    // stage 1: neighbour trace and normal derivative from its node line
+    T dn_nb[(2 * N2 + N3 - 1) / N3];
+    int cnt = 0;
+    if (le < EPB && e < E) {
+      for (int t = node; t < 2 * N2; t += N3, ++cnt) {
+        const int s = t / N2, f = t - s * N2;
+        const int phi = 2 * ax + s;
+        const int en = nbr[(int64_t)e * 6 + phi];
+        T tr = 0, dn = 0;
+        if (en >= 0) {
+          const int phio = phi ^ 1;
+          const int endo = (phio & 1) ? N - 1 : 0;
+          const int l0 = face_node<N>(phio, f, 0);
+          const T* line = u + (int64_t)en * N3 + l0;
+          constexpr int st0 = 1;
+          const int st = axis_stride<N>(ax);
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const T v = line[m * st];
+            dn += sD[endo * N + m] * v;
+            if (m == endo) tr = v;
+          }
+          (void)st0;
+        }
+        sTr[le][s][f] = tr;
+        dn_nb[cnt] = dn;
+      }
+    }
+    __syncthreads();
+    cnt = 0;
+    if (le < EPB && e < E) {
+      for (int t = node; t < 2 * N2; t += N3, ++cnt) {
+        const int s = t / N2, f = t - s * N2;
+        const int phi = 2 * ax + s;
+        const int en = nbr[(int64_t)e * 6 + phi];
+        const int vi = face_node<N>(phi, f, (phi & 1) ? N - 1 : 0);
+        const T sgn = (phi & 1) ? T(1) : T(-1);
+        const T uo = su[le][vi];
+        const T qo = sQ[le][phi][f];
+        const T pf = pen[((int64_t)e * 6 + phi) * N2 + f];
+        T row = 0, sigma = 0;
+        if (en >= 0) {
+          const int phio = phi ^ 1;
+          const int a = f / N, b = f - a * N;
+          // tangential derivatives of the neighbour trace on the face grid
+          T dlast = 0, dfirst = 0;
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            dlast += sD[b * N + m] * sTr[le][s][a * N + m];
+            dfirst += sD[a * N + m] * sTr[le][s][m * N + b];
+          }
+          T du[3];
+          du[ax] = dn_nb[cnt];
+          if (ax == 0) { du[1] = dlast; du[2] = dfirst; }
+          else if (ax == 1) { du[0] = dlast; du[2] = dfirst; }
+          else { du[0] = dlast; du[1] = dfirst; }
+          const int vio = face_node<N>(phio, f, (phio & 1) ? N - 1 : 0);
+          const int64_t gi = (int64_t)en * N3 + vio;
+          T fl = 0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) fl += G[sym_index(ax, c) * ndof + gi] * du[c];
+          const T qn = -sgn * inv_wend * fl;        // neighbour's outward flux
+          const T jmp = uo - sTr[le][s][f];
+          row = pf * jmp - T(0.5) * (qo - qn);
+          sigma = T(-0.5) * jmp;
+        } else {
+          const int8_t code = bc[(int64_t)e * 6 + phi];
+          if (code == 1) {           // Dirichlet: 2 mu nu w s u - q, lifting -u
+            row = pf * uo - qo;
+            sigma = -uo;
+          }
+        }
+        sRow[le][vi] += row;
+        if (sigma != T(0)) {
+          const int64_t gi = base + vi;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) sF[le][c][vi] += sigma * sgn * inv_wend * G[sym_index(ax, c) * ndof + gi];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (active) {
+    T acc = sRow[le][node];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      acc += sD[m * N + i] * sF[le][0][(k * N + j) * N + m];
+      acc += sD[m * N + j] * sF[le][1][(k * N + m) * N + i];
+      acc += sD[m * N + k] * sF[le][2][(m * N + j) * N + i];
+    }
+    if (WJ) acc += kappa * WJ[base + node] * uval;
+    out[base + node] = mode == 0 ? g[base + node] - acc : acc;
+  }
+}
+
+template <int N, typename T>
+void launch_sipg(const OpArgs<T>& a, hipStream_t st) {
+  using S = OpShape<N>;
+  const int nb = (a.E + S::EPB - 1) / S::EPB;
+  hipLaunchKernelGGL((sipg_apply_kernel<N, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a.E, a.u, a.g,
+                     a.out, a.mode, a.G, a.WJ, a.pen, a.nbr, a.bc, a.D, a.kappa, a.inv_wend);
+}
+
+template <typename T>
+void sipg_apply(int p, const OpArgs<T>& a, hipStream_t st) {
+  switch (p) {
+    case 1: launch_sipg<2, T>(a, st); break;
+    case 2: launch_sipg<3, T>(a, st); break;
+    case 3: launch_sipg<4, T>(a, st); break;
+    case 4: launch_sipg<5, T>(a, st); break;
+    case 5: launch_sipg<6, T>(a, st); break;
+    case 6: launch_sipg<7, T>(a, st); break;
+    case 7: launch_sipg<8, T>(a, st); break;
+    case 8: launch_sipg<9, T>(a, st); break;
+    default: break;
+  }
+}
+
+template void sipg_apply<double>(int, const OpArgs<double>&, hipStream_t);
+template void sipg_apply<float>(int, const OpArgs<float>&, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Geometry (one-time): G_bc = w J nu grad xi_b . grad xi_c, w J, omega*s at face
+// nodes (from the cross product of the two tangential columns of the Jacobian,
+// i.e. tangential derivatives only), element volume and face areas, and the
+// linear Legendre coefficients of the map (surrogate cuboid, Sec. 4.3.1).
+template <int N>
+__global__ void __launch_bounds__(OpShape<N>::THREADS)
+geometry_kernel(int E, const double* __restrict__ X, const double* __restrict__ Dg, const double* __restrict__ w1,
+                const double* __restrict__ x1, double nu, double* __restrict__ G, double* __restrict__ WJ,
+                double* __restrict__ ws, double* __restrict__ vol, double* __restrict__ area,
+                double* __restrict__ lin, int* __restrict__ bad) {
+  using S = OpShape<N>;
+  constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
+  const int lb = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int le = tid / N3;
+  const int node = tid - le * N3;
+  const int e = lb * EPB + le;
+  const bool active = (le < EPB) && (e < E);
+  __shared__ double sX[EPB][3][N3];
+  __shared__ double sWJ[EPB][N3];
+  __shared__ double sws[EPB][6][N2];
+  if (active)
+    for (int a = 0; a < 3; ++a) sX[le][a][node] = X[((int64_t)e * 3 + a) * N3 + node];
+  __syncthreads();
+  const int i = node % N, j = (node / N) % N, k = node / N2;
+  if (active) {
+    double J[3][3];
+    for (int a = 0; a < 3; ++a) {
+      double d0 = 0, d1 = 0, d2 = 0;
+      for (int m = 0; m < N; ++m) {
+        d0 += Dg[i * N + m] * sX[le][a][(k * N + j) * N + m];
+        d1 += Dg[j * N + m] * sX[le][a][(k * N + m) * N + i];
+        d2 += Dg[k * N + m] * sX[le][a][(m * N + j) * N + i];
+      }
+      J[a][0] = d0; J[a][1] = d1; J[a][2] = d2;
+    }
+    // cofactor matrix C[a][b] = d det / d J[a][b]; column b of C = J grad(xi_b) (times det)
+    double C[3][3];
+    C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    if (!(det > 0)) atomicOr(bad, 1);
+    const double wq = w1[i] * w1[j] * w1[k];
+    // grad xi_b = C[:, b] / det  ->  G_bc = w nu (C[:,b] . C[:,c]) / det
+    const int64_t ndof = (int64_t)E * N3, gi = (int64_t)e * N3 + node;
+    const double sc = wq * nu / det;
+    double Gb[6];
+    Gb[0] = sc * (C[0][0] * C[0][0] + C[1][0] * C[1][0] + C[2][0] * C[2][0]);
+    Gb[1] = sc * (C[0][0] * C[0][1] + C[1][0] * C[1][1] + C[2][0] * C[2][1]);
+    Gb[2] = sc * (C[0][0] * C[0][2] + C[1][0] * C[1][2] + C[2][0] * C[2][2]);
+    Gb[3] = sc * (C[0][1] * C[0][1] + C[1][1] * C[1][1] + C[2][1] * C[2][1]);
+    Gb[4] = sc * (C[0][1] * C[0][2] + C[1][1] * C[1][2] + C[2][1] * C[2][2]);
+    Gb[5] = sc * (C[0][2] * C[0][2] + C[1][2] * C[1][2] + C[2][2] * C[2][2]);
+    for (int c = 0; c < 6; ++c) G[c * ndof + gi] = Gb[c];
+    WJ[gi] = wq * det;
+    sWJ[le][node] = wq * det;
+    // face nodes: omega * s with N = dx/dxi_t1 x dx/dxi_t2 (tangential columns of J)
+    const int idx[3] = {i, j, k};
+    for (int ax = 0; ax < 3; ++ax) {
+      const int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+      if (idx[ax] != 0 && idx[ax] != N - 1) continue;
+      const double nx = J[1][t1] * J[2][t2] - J[2][t1] * J[1][t2];
+      const double ny = J[2][t1] * J[0][t2] - J[0][t1] * J[2][t2];
+      const double nz = J[0][t1] * J[1][t2] - J[1][t1] * J[0][t2];
+      const double s = sqrt(nx * nx + ny * ny + nz * nz) * w1[idx[t1]] * w1[idx[t2]];
+      int f;
+      if (ax == 0) f = k * N + j;
+      else if (ax == 1) f = k * N + i;
+      else f = j * N + i;
+      if (idx[ax] == 0) sws[le][2 * ax][f] = s;
+      if (idx[ax] == N - 1) sws[le][2 * ax + 1][f] = s;
+    }
+  }
+  __syncthreads();
+  // per-element sums: tasks 0..5 face areas, 6 volume, 7..15 linear Legendre coefficients
+  for (int task = node; active && task < 16; task += N3) {
+    if (task < 6) {
+      double a = 0;
+      for (int f = 0; f < N2; ++f) a += sws[le][task][f];
+      area[(int64_t)e * 6 + task] = a;
+      for (int f = 0; f < N2; ++f) ws[((int64_t)e * 6 + task) * N2 + f] = sws[le][task][f];
+    } else if (task == 6) {
+      double v = 0;
+      for (int t = 0; t < N3; ++t) v += sWJ[le][t];
+      vol[e] = v;
+    } else {
+      // coefficient of L_1(xi_b) L_0 L_0 in the Legendre expansion of coordinate a
+      const int q = task - 7, a = q / 3, b = q % 3;
+      double s = 0;
+      if (N > 2) {   // GLL quadrature is exact for x * xi_b when p >= 2
+        for (int t = 0; t < N3; ++t) {
+          const int ti = t % N, tj = (t / N) % N, tk = t / N2;
+          const int idx[3] = {ti, tj, tk};
+          s += w1[ti] * w1[tj] * w1[tk] * sX[le][a][t] * x1[idx[b]];
+        }
+        s *= 0.375;
+      } else {       // p = 1: mean half-difference along b of the trilinear map
+        for (int t = 0; t < N3; ++t) {
+          const int ti = t % N, tj = (t / N) % N, tk = t / N2;
+          const int idx[3] = {ti, tj, tk};
+          s += (idx[b] == 1 ? 0.125 : -0.125) * sX[le][a][t];
+        }
+      }
+      lin[(int64_t)e * 9 + q] = s;
+    }
+  }
+}
+
+template <int N>
+void launch_geometry(int E, const double* X, const double* D, const double* w, const double* x, double nu, double* G,
+                     double* WJ, double* ws, double* vol, double* area, double* lin, int* bad, hipStream_t st) {
+  using S = OpShape<N>;
+  const int nb = (E + S::EPB - 1) / S::EPB;
+  hipLaunchKernelGGL((geometry_kernel<N>), dim3(nb), dim3(S::THREADS), 0, st, E, X, D, w, x, nu, G, WJ, ws, vol,
+                     area, lin, bad);
+}
+
+void geometry(int p, int E, const double* X, const double* D, const double* w, const double* x, double nu,
+              double* G, double* WJ, double* ws, double* vol, double* area, double* lin, int* bad, hipStream_t st) {
+  switch (p) {
+    case 1: launch_geometry<2>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 2: launch_geometry<3>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 3: launch_geometry<4>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 4: launch_geometry<5>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 5: launch_geometry<6>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 6: launch_geometry<7>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 7: launch_geometry<8>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 8: launch_geometry<9>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    default: break;
+  }
+}
+
+// Penalty factor per element-face node: interior mu_F nu omega s with
+// mu_F = mu_star avg(p(p+1)/(2 h_perp)), Dirichlet 2 mu nu omega s, Neumann 0;
+// h_perp = vol / area (eq. helmholtz:dgm).
+__global__ void penalty_kernel(int E, int N2, int p, double mu_star, double nu, const int* __restrict__ nbr,
+                               const int8_t* __restrict__ bc, const double* __restrict__ vol,
+                               const double* __restrict__ area, const double* __restrict__ ws,
+                               double* __restrict__ pen) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)E * 6) return;
+  const int e = (int)(t / 6), phi = (int)(t % 6);
+  const double own = p * (p + 1) / (2.0 * (vol[e] / area[t]));
+  const int en = nbr[t];
+  double fac = 0.0;
+  if (en >= 0) {
+    const double oth = p * (p + 1) / (2.0 * (vol[en] / area[(int64_t)en * 6 + (phi ^ 1)]));
+    fac = mu_star * 0.5 * (own + oth) * nu;
+  } else if (bc[t] == 1) {
+    fac = 2.0 * mu_star * own * nu;
+  }
+  for (int f = 0; f < N2; ++f) pen[t * N2 + f] = fac * ws[t * N2 + f];
+}
+
+void penalty(int E, int p, double mu_star, double nu, const int* nbr, const int8_t* bc, const double* vol,
+             const double* area, const double* ws, double* pen, hipStream_t st) {
+  const int64_t n = (int64_t)E * 6;
+  hipLaunchKernelGGL(penalty_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, E, (p + 1) * (p + 1), p,
+                     mu_star, nu, nbr, bc, vol, area, ws, pen);
+}
+
+}  // namespace dgfas
+
+namespace dgfas {
+
+// Right-hand side of eq. helmholtz:system:
+//   b = w J f + Dirichlet faces (2 mu nu omega s u_D at the face node, lifting
+//   -nu omega s u_D (n . grad phi_q)) + Neumann faces (omega s q_N).
+template <int N>
+__global__ void __launch_bounds__(OpShape<N>::THREADS)
+rhs_kernel(int E, const double* __restrict__ f, const double* __restrict__ uD, const double* __restrict__ qN,
+           double* __restrict__ b, const double* __restrict__ G, const double* __restrict__ WJ,
+           const double* __restrict__ pen, const double* __restrict__ ws, const int* __restrict__ nbr,
+           const int8_t* __restrict__ bc, const double* __restrict__ Dg, double inv_wend) {
+  using S = OpShape<N>;
+  constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
+  const int lb = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int le = tid / N3, node = tid - le * N3;
+  const int e = lb * EPB + le;
+  const bool active = (le < EPB) && (e < E);
+  __shared__ double sD[N2];
+  __shared__ double sL[EPB][3][N3];
+  __shared__ double sRow[EPB][N3];
+  for (int t = tid; t < N2; t += S::THREADS) sD[t] = Dg[t];
+  const int64_t base = (int64_t)e * N3, ndof = (int64_t)E * N3;
+  if (active) {
+    sL[le][0][node] = sL[le][1][node] = sL[le][2][node] = 0.0;
+    sRow[le][node] = 0.0;
+  }
+  __syncthreads();
+  for (int ax = 0; ax < 3; ++ax) {
+    if (active) {
+      for (int t = node; t < 2 * N2; t += N3) {
+        const int s = t / N2, fn = t - s * N2;
+        const int phi = 2 * ax + s;
+        if (nbr[(int64_t)e * 6 + phi] >= 0) continue;
+        const int vi = face_node<N>(phi, fn, (phi & 1) ? N - 1 : 0);
+        const int8_t code = bc[(int64_t)e * 6 + phi];
+        if (code == 1 && uD) {
+          const double ud = uD[base + vi];
+          const double sgn = (phi & 1) ? 1.0 : -1.0;
+          sRow[le][vi] += pen[((int64_t)e * 6 + phi) * N2 + fn] * ud;
+          for (int c = 0; c < 3; ++c) sL[le][c][vi] += -ud * sgn * inv_wend * G[sym_index(ax, c) * ndof + base + vi];
+        } else if (code == 2 && qN) {
+          sRow[le][vi] += ws[((int64_t)e * 6 + phi) * N2 + fn] * qN[base + vi];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+    const int i = node % N, j = (node / N) % N, k = node / N2;
+    double acc = WJ[base + node] * f[base + node] + sRow[le][node];
+    for (int m = 0; m < N; ++m) {
+      acc += sD[m * N + i] * sL[le][0][(k * N + j) * N + m];
+      acc += sD[m * N + j] * sL[le][1][(k * N + m) * N + i];
+      acc += sD[m * N + k] * sL[le][2][(m * N + j) * N + i];
+    }
+    b[base + node] = acc;
+  }
+}
+
+template <int N>
+void launch_rhs(int E, const double* f, const double* uD, const double* qN, double* b, const double* G,
+                const double* WJ, const double* pen, const double* ws, const int* nbr, const int8_t* bc,
+                const double* D, double inv_wend, hipStream_t st) {
+  using S = OpShape<N>;
+  const int nb = (E + S::EPB - 1) / S::EPB;
+  hipLaunchKernelGGL((rhs_kernel<N>), dim3(nb), dim3(S::THREADS), 0, st, E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D,
+                     inv_wend);
+}
+
+void rhs(int p, int E, const double* f, const double* uD, const double* qN, double* b, const double* G,
+         const double* WJ, const double* pen, const double* ws, const int* nbr, const int8_t* bc, const double* D,
+         double inv_wend, hipStream_t st) {
+  switch (p) {
+    case 1: launch_rhs<2>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 2: launch_rhs<3>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 3: launch_rhs<4>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 4: launch_rhs<5>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 5: launch_rhs<6>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 6: launch_rhs<7>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 7: launch_rhs<8>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 8: launch_rhs<9>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    default: break;
+  }
+}
+
+}  // namespace dgfas

@@ -1,0 +1,296 @@
+// K2: weighted overlapping Schwarz application z = sum_e R_s^T W^e (A~_s^e)^-1 R_s r
+// (Sec. 4.3.1, eq. schwarz:correction) with fast-diagonalisation subdomain solves
+//   (A~_s)^-1 = (S3 x S2 x S1) D^-1 (S3^T x S2^T x S1^T),
+//   D = g0 + g1 lam1_i + g2 lam2_j + g3 lam3_k.
+//
+// schwarz_solve: one workgroup per subdomain.  The NS^3 tile (NS = N + 2M, smaller
+// variants zero-padded) is gathered from the element and its 26 neighbours into
+// LDS; each 1D contraction runs with one thread per tile line, the other two
+// tile indices spread over the threads so that LDS accesses are unit-stride
+// across the wavefront (the xi_1 lines use an odd row pitch).  The weighted own
+// part goes straight to z (or is added to u), the weighted overlap parts go to a
+// per-element overlap buffer.
+// schwarz_overlap_add: gather form of the scatter, z[node] += contributions of
+// the neighbours' subdomains in a fixed order -- deterministic, no atomics.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace dgfas {
+
+template <int N, int M>
+struct SzShape {
+  static constexpr int NS = N + 2 * M;
+  static constexpr int LS = NS | 1;                 // odd pitch of xi_1 rows
+  static constexpr int TILE = NS * NS * LS;
+  static constexpr int THREADS = ((NS * NS + 63) / 64) * 64 < 64 ? 64 : ((NS * NS + 63) / 64) * 64;
+};
+
+// offsets of the 26 overlap regions (region index (d3+1)*9 + (d2+1)*3 + (d1+1); 13 unused)
+template <int N, int M>
+struct Regions {
+  int off[27];
+  int size;
+  __host__ __device__ constexpr Regions() : off(), size(0) {
+    int o = 0;
+    for (int r = 0; r < 27; ++r) {
+      off[r] = o;
+      if (r == 13) continue;
+      const int d1 = r % 3 - 1, d2 = (r / 3) % 3 - 1, d3 = r / 9 - 1;
+      o += (d1 ? M : N) * (d2 ? M : N) * (d3 ? M : N);
+    }
+    size = o;
+  }
+};
+
+int overlap_size(int p, int m) {
+  const int n = p + 1;
+  return 6 * m * n * n + 12 * m * m * n + 8 * m * m * m;
+}
+
+template <int N, int M, typename T>
+__global__ void __launch_bounds__((SzShape<N, M>::THREADS))
+schwarz_solve_kernel(SchwarzArgs<T> a) {
+  using Sh = SzShape<N, M>;
+  constexpr int NS = Sh::NS, LS = Sh::LS, N3 = N * N * N, THR = Sh::THREADS;
+  constexpr Regions<N, M> R{};
+  const int e = xcd_block(a.E);
+  if (e < 0) return;
+  const int tid = threadIdx.x;
+
+  __shared__ T tA[Sh::TILE];
+  __shared__ T tB[Sh::TILE];
+  __shared__ T sS[3][NS * NS];
+  __shared__ T sLam[3][NS];
+  __shared__ T sW[3][NS];
+  __shared__ int sMap[3][NS];
+  __shared__ int sNb[27];
+
+  const int v0 = a.var[(int64_t)e * 3 + 0], v1 = a.var[(int64_t)e * 3 + 1], v2 = a.var[(int64_t)e * 3 + 2];
+  const int vv[3] = {v0, v1, v2};
+  for (int t = tid; t < 3 * NS * NS; t += THR) {
+    const int d = t / (NS * NS), q = t - d * NS * NS;
+    sS[d][q] = a.S[vv[d] * NS * NS + q];
+  }
+  for (int t = tid; t < 3 * NS; t += THR) {
+    const int d = t / NS, q = t - d * NS;
+    sLam[d][q] = a.lam[vv[d] * NS + q];
+    sW[d][q] = a.W[vv[d] * NS + q];
+    sMap[d][q] = a.map1d[vv[d] * NS + q];
+  }
+  if (tid < 27) sNb[tid] = a.nb27[(int64_t)e * 27 + tid];
+  const T g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
+  const T g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
+  __syncthreads();
+
+  // gather r_s = R_s r
+  for (int q = tid; q < NS * NS * NS; q += THR) {
+    const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
+    const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
+    T v = 0;
+    if (m1 >= 0 && m2 >= 0 && m3 >= 0) {
+      const int r = (m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6);
+      const int src = sNb[r];   // an absent edge/vertex neighbour contributes zeros
+      if (src >= 0) v = a.r[(int64_t)src * N3 + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63)];
+    }
+    tA[(s3 * NS + s2) * LS + s1] = v;
+  }
+  __syncthreads();
+
+  const bool act = tid < NS * NS;
+  const int tlo = tid % NS, thi = tid / NS;
+  T line[NS];
+  T res[NS];
+  // phase 1: xi_1 with S1^T   (thread: s2 = tlo, s3 = thi)
+  if (act) {
+    const int b = (thi * NS + tlo) * LS;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) line[q] = tA[b + q];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += sS[0][q * NS + c] * line[q];
+      tB[b + c] = s;
+    }
+  }
+  __syncthreads();
+  // phase 2: xi_2 with S2^T   (thread: s1 = tlo, s3 = thi)
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) line[q] = tB[(thi * NS + q) * LS + tlo];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += sS[1][q * NS + c] * line[q];
+      tA[(thi * NS + c) * LS + tlo] = s;
+    }
+  }
+  __syncthreads();
+  // phase 3: xi_3 with S3^T, divide by D, xi_3 with S3   (thread: s1 = tlo, s2 = thi)
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) line[q] = tA[(q * NS + thi) * LS + tlo];
+    const T base = g0 + g1 * sLam[0][tlo] + g2 * sLam[1][thi];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += sS[2][q * NS + c] * line[q];
+      res[c] = s / (base + g3 * sLam[2][c]);
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < NS; ++c) s += sS[2][q * NS + c] * res[c];
+      tB[(q * NS + thi) * LS + tlo] = s;
+    }
+  }
+  __syncthreads();
+  // phase 4: xi_2 with S2   (thread: s1 = tlo, s3 = thi)
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) line[q] = tB[(thi * NS + q) * LS + tlo];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += sS[1][c * NS + q] * line[q];
+      tA[(thi * NS + c) * LS + tlo] = s;
+    }
+  }
+  __syncthreads();
+  // phase 5: xi_1 with S1   (thread: s2 = tlo, s3 = thi)
+  if (act) {
+    const int b = (thi * NS + tlo) * LS;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) line[q] = tA[b + q];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += sS[0][c * NS + q] * line[q];
+      tB[b + c] = s;
+    }
+  }
+  __syncthreads();
+  // weighted scatter: own part to z, overlap parts to O
+  T* Oe = a.O + (int64_t)e * R.size;
+  for (int q = tid; q < NS * NS * NS; q += THR) {
+    const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
+    const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
+    if (m1 < 0 || m2 < 0 || m3 < 0) continue;
+    const T v = sW[0][s1] * sW[1][s2] * sW[2][s3] * tB[(s3 * NS + s2) * LS + s1];
+    const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, d3 = (m3 >> 6) - 1;
+    const int l1 = m1 & 63, l2 = m2 & 63, l3 = m3 & 63;
+    if (d1 == 0 && d2 == 0 && d3 == 0) {
+      const int64_t gi = (int64_t)e * N3 + (l3 * N + l2) * N + l1;
+      if (a.mode == 0) a.z[gi] = v;
+      else a.z[gi] += v;
+    } else {
+      const int r = (d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1);
+      const int c1 = d1 < 0 ? l1 - (N - M) : l1, c2 = d2 < 0 ? l2 - (N - M) : l2, c3 = d3 < 0 ? l3 - (N - M) : l3;
+      const int x1 = d1 ? M : N, x2 = d2 ? M : N;
+      Oe[R.off[r] + (c3 * x2 + c2) * x1 + c1] = v;
+    }
+  }
+}
+
+template <int N>
+struct AddShape {
+  static constexpr int N3 = N * N * N;
+  static constexpr int EPB = (N3 >= 256) ? 1 : (256 / N3);
+  static constexpr int THREADS = ((EPB * N3 + 63) / 64) * 64;
+};
+
+template <int N, int M, typename T>
+__global__ void __launch_bounds__(AddShape<N>::THREADS)
+schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
+  using Sh = AddShape<N>;
+  constexpr int N3 = Sh::N3, EPB = Sh::EPB;
+  constexpr Regions<N, M> R{};
+  const int lb = xcd_block((a.E + EPB - 1) / EPB);
+  if (lb < 0) return;
+  const int tid = threadIdx.x;
+  const int le = tid / N3, node = tid - le * N3;
+  const int e = lb * EPB + le;
+  if (le >= EPB || e >= a.E) return;
+  const int l[3] = {node % N, (node / N) % N, node / (N * N)};
+  int lo[3], hi[3];
+  bool any = false;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (l[d] < M) ? -1 : 0;
+    hi[d] = (l[d] >= N - M) ? 1 : 0;
+    any = any || lo[d] < 0 || hi[d] > 0;
+  }
+  if (!any) return;
+  T acc = 0;
+  for (int d3 = lo[2]; d3 <= hi[2]; ++d3)
+    for (int d2 = lo[1]; d2 <= hi[1]; ++d2)
+      for (int d1 = lo[0]; d1 <= hi[0]; ++d1) {
+        if (d1 == 0 && d2 == 0 && d3 == 0) continue;
+        const int en = a.nb27[(int64_t)e * 27 + (d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1)];
+        if (en < 0) continue;
+        // element en sees us at offset -d; our node lies in its region -d
+        const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);
+        const int c1 = d1 > 0 ? l[0] - (N - M) : l[0];
+        const int c2 = d2 > 0 ? l[1] - (N - M) : l[1];
+        const int c3 = d3 > 0 ? l[2] - (N - M) : l[2];
+        const int x1 = d1 ? M : N, x2 = d2 ? M : N;
+        acc += a.O[(int64_t)en * R.size + R.off[r] + (c3 * x2 + c2) * x1 + c1];
+      }
+  a.z[(int64_t)e * N3 + node] += acc;
+}
+
+template <int N, int M, typename T>
+void launch_schwarz(const SchwarzArgs<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL((schwarz_solve_kernel<N, M, T>), dim3(xcd_grid(a.E)), dim3(SzShape<N, M>::THREADS), 0, st, a);
+}
+
+template <int N, int M, typename T>
+void launch_overlap(const SchwarzArgs<T>& a, hipStream_t st) {
+  using Sh = AddShape<N>;
+  const int nb = (a.E + Sh::EPB - 1) / Sh::EPB;
+  hipLaunchKernelGGL((schwarz_overlap_add_kernel<N, M, T>), dim3(xcd_grid(nb)), dim3(Sh::THREADS), 0, st, a);
+}
+
+#define DGFAS_SZ_CASES(F)                                                       \
+  switch (p * 16 + m) {                                                         \
+    case 1 * 16 + 0: F<2, 0, T>(a, st); break;                                  \
+    case 1 * 16 + 1: F<2, 1, T>(a, st); break;                                  \
+    case 2 * 16 + 0: F<3, 0, T>(a, st); break;                                  \
+    case 2 * 16 + 1: F<3, 1, T>(a, st); break;                                  \
+    case 3 * 16 + 0: F<4, 0, T>(a, st); break;                                  \
+    case 3 * 16 + 1: F<4, 1, T>(a, st); break;                                  \
+    case 4 * 16 + 0: F<5, 0, T>(a, st); break;                                  \
+    case 4 * 16 + 1: F<5, 1, T>(a, st); break;                                  \
+    case 4 * 16 + 2: F<5, 2, T>(a, st); break;                                  \
+    case 5 * 16 + 0: F<6, 0, T>(a, st); break;                                  \
+    case 5 * 16 + 1: F<6, 1, T>(a, st); break;                                  \
+    case 6 * 16 + 0: F<7, 0, T>(a, st); break;                                  \
+    case 6 * 16 + 1: F<7, 1, T>(a, st); break;                                  \
+    case 7 * 16 + 0: F<8, 0, T>(a, st); break;                                  \
+    case 7 * 16 + 1: F<8, 1, T>(a, st); break;                                  \
+    case 8 * 16 + 0: F<9, 0, T>(a, st); break;                                  \
+    case 8 * 16 + 1: F<9, 1, T>(a, st); break;                                  \
+    case 8 * 16 + 2: F<9, 2, T>(a, st); break;                                  \
+    default: break;                                                             \
+  }
+
+template <typename T>
+void schwarz_solve(int p, int m, const SchwarzArgs<T>& a, hipStream_t st) {
+  DGFAS_SZ_CASES(launch_schwarz)
+}
+template <typename T>
+void schwarz_overlap_add(int p, int m, const SchwarzArgs<T>& a, hipStream_t st) {
+  if (m == 0) return;
+  DGFAS_SZ_CASES(launch_overlap)
+}
+
+template void schwarz_solve<double>(int, int, const SchwarzArgs<double>&, hipStream_t);
+template void schwarz_solve<float>(int, int, const SchwarzArgs<float>&, hipStream_t);
+template void schwarz_overlap_add<double>(int, int, const SchwarzArgs<double>&, hipStream_t);
+template void schwarz_overlap_add<float>(int, int, const SchwarzArgs<float>&, hipStream_t);
+
+}  // namespace dgfas

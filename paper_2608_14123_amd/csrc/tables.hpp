@@ -1,0 +1,38 @@
+// Host FP64 tables of the nodal GLL spectral element (Sec. 2.2) and of the
+// one-dimensional Schwarz subdomain problems (Sec. 4.3.1).
+#pragma once
+#include <vector>
+
+namespace dgfas {
+
+constexpr int kMaxDegree = 16;
+
+struct Gll {
+  int p = 0;
+  std::vector<double> x, w;   // p+1 nodes (ascending) and weights
+  std::vector<double> D;      // (p+1)^2 row-major: D[i*n+j] = l_j'(x_i)
+};
+
+// Gauss-Lobatto-Legendre nodes/weights/differentiation matrix of degree p.
+const Gll& gll_table(int p);
+
+// T[i*n_from + j] = l_j^{p_from}(x_i^{p_to}): interpolation of a degree-p_from nodal
+// polynomial at the GLL nodes of degree p_to.
+std::vector<double> interp_matrix(int p_from, int p_to);
+
+// Face condition of one side of a 1D subdomain.
+enum Side { kInterior = 0, kDirichlet = 1, kNeumann = 2 };
+
+// 1D subdomain data of a face-condition variant (Sec. 4.3.1): node map, generalized
+// eigen-decomposition L s = lambda M s (S^T M S = I, S^T L S = diag lambda) and weights.
+struct Variant1D {
+  int ns = 0;                   // number of subdomain nodes in this direction
+  std::vector<int> delta, loc;  // per subdomain node: neighbour offset (-1,0,1), local node index
+  std::vector<double> S;        // ns*ns row-major, S[i*ns + a] = component i of eigenvector a
+  std::vector<double> lam;      // ns eigenvalues
+  std::vector<double> W;        // ns weights
+};
+
+Variant1D make_variant_1d(int p, int m, int left, int right, double mu_star);
+
+}  // namespace dgfas

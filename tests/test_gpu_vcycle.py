@@ -1,0 +1,78 @@
+"""GPU V-cycle residual histories against the oracle (history-parity criterion)."""
+import numpy as np
+import pytest
+
+from oracle import operator as oop, solvers as osv
+from paper_2608_14123_amd import workloads as W
+from gpu_cases import Case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip('torch')
+
+
+@pytest.fixture(scope='module')
+def binding():
+    if not torch.cuda.is_available():
+        pytest.fail('GPU tests need a GPU')
+    from paper_2608_14123_amd import binding as b
+    return b
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+
+def histories_agree(hg, ho):
+    """Per cycle |rho_gpu - rho_oracle| <= 1e-6 rho + 1e-14 (the FAS coarse right-hand side
+    g = A u_bar + R r loses digits to cancellation, so agreement is absolute below 1e-8)."""
+    assert len(hg) == len(ho), (hg, ho)
+    for a, b in zip(hg, ho):
+        assert abs(a - b) <= 1e-6 * b + 1e-14, (a, b)
+
+
+@pytest.mark.parametrize('smoother,ns', [('was', (2, 2)), ('scg', (3, 2))])
+def test_c1_unit_cube_p4(binding, smoother, ns):
+    """4^3 Cartesian cubes, p = 4, f = 3 pi^2 sin sin sin, FAS-MG-WAS(2,2) to 1e-10."""
+    case = Case('c1', 4, 4)
+    print('vcycle c1', smoother, flush=True)
+    lv = case.oracle_levels()
+    top = lv[-1].mesh
+    from oracle.gll import gll as ogll
+    Xo = case.coords(ogll(4)[0])
+    bo = oop.rhs(top, 3 * np.pi ** 2 * W.sine_solution(Xo))
+    uo, ho = osv.solve(lv, np.zeros_like(bo), bo, osv.Options(smoother, *ns), max_cycles=20)
+    lib = case.library(binding, smoother=binding.SCG if smoother == 'scg' else binding.WAS, ns1=ns[0], ns2=ns[1])
+    Xg = case.coords(binding.gll(4)[0])
+    f = dev(3 * np.pi ** 2 * W.sine_solution(Xg))
+    b = torch.empty_like(f)
+    lib.rhs(f, b)
+    u = torch.zeros_like(b)
+    hg, ok = lib.solve(u, b, max_cycles=20, rtol=1e-10)
+    assert ok
+    histories_agree(list(hg), ho)
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - uo.ravel()).max() <= 1e-9 * np.abs(uo).max()
+    lib.close()
+
+
+@pytest.mark.parametrize('p,ne,amp,cycles', [(4, 3, 0.03, 25), (7, 2, 0.03, 12), (3, 4, 0.03, 25)])
+def test_curved_history(binding, p, ne, amp, cycles):
+    """Curved meshes; 2^3 elements at p = 7 (7 -> 3 -> 1) converge slowly (rho ~ 0.55 per cycle),
+    so that case compares a fixed number of cycles."""
+    case = Case('curved', p, ne, amp=amp)
+    print('vcycle curved', p, ne, flush=True)
+    lv = case.oracle_levels()
+    top = lv[-1].mesh
+    f = W.uniform_nodal(top.n_dof(), 2)
+    bo = oop.rhs(top, f)
+    uo, ho = osv.solve(lv, np.zeros_like(bo), bo, osv.Options('was', 2, 2), max_cycles=cycles)
+    lib = case.library(binding)
+    b = torch.empty(top.n_dof(), dtype=torch.float64, device='cuda')
+    lib.rhs(dev(f), b)
+    u = torch.zeros_like(b)
+    hg, ok = lib.solve(u, b, max_cycles=cycles, rtol=1e-10)
+    assert ok == (ho[-1] <= 1e-10)
+    histories_agree(list(hg), ho)
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - uo.ravel()).max() <= 1e-9 * np.abs(uo).max()
+    lib.close()

@@ -1,0 +1,66 @@
+"""CPU checks of the HIP library: symbols, host tables against the oracle (values only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, 'paper_2608_14123_amd', 'libdgfas.so')
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, 'include', 'dgfas.h')).read()
+    src = re.sub(r'/\*.*?\*/', '', src, flags=re.S)
+    return sorted(set(re.findall(r'\b(dgfas_[a-z0-9_]+)\s*\(', src)))
+
+
+@pytest.fixture(scope='module')
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail('libdgfas.so is not built (run __graft_entry__.build())')
+    from paper_2608_14123_amd import binding
+    return binding
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    so = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(so, n), n
+    assert set(names) <= set(lib.EXPORTED) | {'dgfas_default_options'}
+
+
+@pytest.mark.parametrize('p', [1, 2, 3, 4, 7, 8, 12, 16])
+def test_gll_matches_oracle(lib, p):
+    from oracle.gll import gll
+    x, w = lib.gll(p)
+    xo, wo = gll(p)
+    assert np.abs(x - xo).max() < 1e-15 and np.abs(w - wo).max() < 1e-15
+
+
+@pytest.mark.parametrize('p,m', [(1, 1), (3, 1), (4, 1), (4, 2), (7, 1), (8, 1), (8, 2)])
+@pytest.mark.parametrize('lr', [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (0, 2), (1, 2)])
+def test_schwarz_tables_match_oracle(lib, p, m, lr):
+    from oracle.schwarz import variant_1d
+    code = 'idn'
+    v = variant_1d(p, m, code[lr[0]], code[lr[1]], 2.0)
+    S, lam, W = lib.schwarz_tables_1d(p, m, lr[0], lr[1], 2.0)
+    assert np.allclose(W, v['W'], atol=1e-15)
+    # eigenpairs up to order and sign: compare the reconstructed operators
+    M = np.diag(v['M'])
+    Linv_lib = S @ np.diag(1 / lam) @ S.T
+    Linv_or = v['S'] @ np.diag(1 / v['lam']) @ v['S'].T
+    assert np.abs(Linv_lib - Linv_or).max() < 1e-11 * np.abs(Linv_or).max()
+    assert np.abs(S.T @ M @ S - np.eye(len(lam))).max() < 1e-13
+    assert np.abs(np.sort(lam) - np.sort(v['lam'])).max() < 1e-11 * np.abs(lam).max()
+
+
+def test_argument_errors_are_reported_without_gpu(lib):
+    with pytest.raises(lib.DgfasError) as ei:
+        lib.gll(0)
+    assert ei.value.code == lib.DGFAS_EINVAL
+    with pytest.raises(lib.DgfasError):
+        lib.schwarz_tables_1d(4, 5, 0, 0, 2.0)
