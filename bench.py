@@ -1,0 +1,216 @@
+"""Benchmark: FAS V-cycles with Schwarz-preconditioned CG smoothing on the curved 32^3, p = 7 workload.
+
+One step = one FAS-MG-SCG(3,2) V-cycle (Alg. 2 with Alg. 6 smoothing, p-levels
+7 -> 3 -> 1, SCG root solve) over the 16.8M-DOF curvilinear mesh (sine-bump
+map, mu_star = 5), FP64, inputs resident in HBM.  Prints one JSON line.
+`value` is the whole-job sweep throughput: fine-level DOF times fine-level
+Schwarz sweeps per cycle (ns1 + ns2), divided by the cycle time.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=10)
+    ap.add_argument('--warmup', type=int, default=2)
+    ap.add_argument('--ne', type=int, default=32)
+    ap.add_argument('--p', type=int, default=7)
+    ap.add_argument('--reps', type=int, default=20, help='repetitions of the isolated kernel timings')
+    ap.add_argument('--no-cpu', action='store_true', help='skip the oracle cpu_baseline leg')
+    ap.add_argument('--no-t10', action='store_true', help='skip the time-to-tolerance solves')
+    ap.add_argument('--calib-copy', action='store_true', help='also run a plain copy kernel (PMC calibration)')
+    return ap.parse_args()
+
+
+def build_workload(ne, p, xi):
+    from paper_2608_14123_amd import workloads as W
+    V, nbr, bc, mp = W.curved_cube(ne)
+    X = W.element_coords(V, xi, mp)
+    return X, nbr, bc
+
+
+def cpu_baseline(ne, p, budget_s=20.0):
+    """Oracle FP64 Schwarz sweep (r = g - A u; u += B r) on an 8^3-element block of the same mesh."""
+    from oracle import solvers as osv
+    from oracle.gll import gll as ogll
+    from oracle.mesh import Mesh
+    from paper_2608_14123_amd import workloads as W
+    sub = 8
+    V, nbr_full, bc_full, mp = W.curved_cube(ne)
+    Vs = V[:sub + 1, :sub + 1, :sub + 1]
+    nbr, bc = W.box_topology(sub, sub, sub)
+    X = W.element_coords(Vs, ogll(p)[0], mp)
+    lv = osv.Level(Mesh(p, X, nbr, bc, mu_star=5.0), 1)
+    nd = lv.mesh.n_dof()
+    g = W.uniform_nodal(lv.mesh.X[:, 0].shape, 2)
+    u = np.zeros_like(g)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        u = osv.was(lv, u, g, 1)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s or reps >= 50:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return {'value': nd / dt / 1e9, 'unit': 'GDOF/s', 'cores': 1, 'kind': 'oracle',
+            'sample': '%d WAS sweeps (residual + Schwarz + update) on the %d^3-element corner block '
+                      '(%d DOF) of the same mesh, numpy FP64 single thread' % (reps, sub, nd)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print('bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "Sharding").',
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2608_14123_amd import binding as B
+    assert torch.cuda.is_available(), 'needs a GPU'
+    ne, p = args.ne, args.p
+    E = ne ** 3
+    n3 = (p + 1) ** 3
+    ndof = E * n3
+    X, nbr, bc = build_workload(ne, p, B.gll(p)[0])
+    from paper_2608_14123_amd import workloads as W
+    f_host = W.uniform_nodal(ndof, 2)
+    stream = torch.cuda.current_stream()
+    cyc = dict(smoother=B.SCG, ns1=3, ns2=2, mu_star=5.0, root_rtol=0.1)
+    opts = B.default_options(**cyc)
+    t_setup = time.perf_counter()
+    lib = B.Solver(np.full(E, p, np.int32), X, nbr, bc, opts, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    L = lib.n_levels
+    levels_str = '->'.join(str(lib.level_info(l)[0]) for l in range(L, 0, -1))
+    f = torch.from_numpy(f_host).cuda()
+    b = torch.empty_like(f)
+    lib.rhs(f, b)
+    u = torch.zeros_like(b)
+    print('setup %.2fs, %d levels, %d DOF' % (t_setup, L, ndof), file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        lib.vcycle(u, b)
+    torch.cuda.synchronize()
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lib.vcycle(u, b)
+    torch.cuda.synchronize()
+    ms_cycle = (time.perf_counter() - t0) * 1e3 / args.steps
+    sweeps = opts.ns1 + opts.ns2
+    value = ndof * sweeps / (ms_cycle * 1e-3) / 1e9
+    print('V-cycle %.3f ms' % ms_cycle, file=sys.stderr, flush=True)
+
+    # isolated kernels on the cycle's stream, timed by events on that stream
+    g = torch.from_numpy(W.uniform_nodal(ndof, 3)).cuda()
+    r = torch.empty_like(g)
+    uu = torch.from_numpy(W.uniform_nodal(ndof, 4)).cuda()
+
+    def timed(fn):
+        fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / args.reps
+
+    ms_res = timed(lambda: lib.residual(L, uu, g, r))
+    ms_sz = timed(lambda: lib.schwarz(L, g, r))
+    ms_sweep = timed(lambda: lib.smooth(L, uu, g, 1))   # residual + one SCG iteration
+    sweep_gdofs = ndof / (ms_sweep * 1e-3) / 1e9
+    print('residual %.3f ms, schwarz %.3f ms, sweep %.3f ms' % (ms_res, ms_sz, ms_sweep), file=sys.stderr,
+          flush=True)
+
+    # algorithmic work ("Roofline accounting")
+    bytes_res = 48.0 * ndof                      # u, g, coordinates (3 x 8 B), r
+    ach_res = bytes_res / (ms_res * 1e-3) / 1e9
+    ns = p + 3
+    n_int = ne - 2
+    # exact FD flops: 4 (n1+n2+n3) n1 n2 n3 + n1 n2 n3 per subdomain, summed over boundary classes
+    sizes = [ns] * n_int + [ns - 1] * 2
+    flops_fd = 0.0
+    for a in sizes:
+        for b_ in sizes:
+            for c in sizes:
+                flops_fd += (4.0 * (a + b_ + c) + 1.0) * a * b_ * c
+    ach_fd = flops_fd / (ms_sz * 1e-3) / 1e12
+    roof_res = {'kernel': 'sipg_apply_kernel<8,double> (residual)', 'bound': 'hbm', 'achieved': round(ach_res, 1),
+                'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': round(ach_res / HBM_PEAK_GBS, 4),
+                'traffic': None}
+    roof_fd = {'kernel': 'schwarz_solve_kernel<8,1,double> + overlap add', 'bound': 'alu',
+               'achieved': round(ach_fd, 2), 'peak': FP64_PEAK_TFLOPS, 'unit': 'TFLOP/s',
+               'frac': round(ach_fd / FP64_PEAK_TFLOPS, 4), 'traffic': None}
+    dominant, other = (roof_res, roof_fd) if 5 * ms_res >= 4 * ms_sz else (roof_fd, roof_res)
+
+    t10 = {}
+    if not args.no_t10:
+        hist, ok = lib.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        hist, ok = lib.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+        torch.cuda.synchronize()
+        t10['fp64'] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1, 'converged': bool(ok),
+                       'final_rho': float(hist[-1])}
+        print('t10 fp64', t10['fp64'], file=sys.stderr, flush=True)
+        lib.close()
+        opts32 = B.default_options(precision=B.FP32, **cyc)
+        lib32 = B.Solver(np.full(E, p, np.int32), X, nbr, bc, opts32, stream=stream.cuda_stream)
+        hist, ok = lib32.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        hist, ok = lib32.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+        torch.cuda.synchronize()
+        t10['fp32_smoother'] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1,
+                                'converged': bool(ok), 'final_rho': float(hist[-1])}
+        print('t10 fp32', t10['fp32_smoother'], file=sys.stderr, flush=True)
+        lib32.close()
+    else:
+        lib.close()
+
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device='cuda')   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    out = {
+        'metric': 'GDOF/s per Schwarz sweep; time-to-1e-10 residual, plain FP64 vs mixed/learned',
+        'value': round(value, 3), 'unit': 'GDOF/s', 'n_gpus': 1, 'steps': args.steps, 'warmup': args.warmup,
+        'ms_per_step': round(ms_cycle, 4), 'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None,
+        'dtype': 'f64', 'data': 'synthetic',
+        'config': {'workload': 'curved_cube_%d^3_p%d_sine_bump_0.1' % (ne, p), 'n_dof': ndof,
+                   'cycle': 'FAS-MG-SCG(3,2), p-levels %s, root SCG to 1e-1' % levels_str, 'overlap': 1,
+                   'mu_star': 5.0,
+                   'rhs': 'U[-1,1] seed 2'},
+        'roofline': dominant,
+        'roofline_other': other,
+        'sweep_gdofs_isolated': round(sweep_gdofs, 3),
+        'kernel_ms': {'residual': round(ms_res, 4), 'schwarz': round(ms_sz, 4),
+                      'residual_plus_scg_iteration': round(ms_sweep, 4)},
+        't10': t10,
+        'setup_s': round(t_setup, 3),
+    }
+    if not args.no_cpu:
+        out['cpu_baseline'] = cpu_baseline(ne, p)
+    print(json.dumps(out))
+
+
+if __name__ == '__main__':
+    main()

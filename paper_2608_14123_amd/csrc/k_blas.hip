@@ -107,25 +107,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return sh[0];
 }
 
-// partial[blk] = sum_i a_i (b_i - c_i)   (b, c may be null: b := a, c := 0)
+// partial[blk] = sum_i a_i (b_i - c_i)   (b, c may be null: b := a, c := 0); FP64 accumulation
+template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
-dot_partial_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+dot_partial_kernel(int64_t n, const T* __restrict__ a, const T* __restrict__ b, const T* __restrict__ c,
                    double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
   double s = 0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
-    const double bv = b ? b[i] : a[i];
-    s += a[i] * (c ? bv - c[i] : bv);
+    const double bv = b ? (double)b[i] : (double)a[i];
+    s += (double)a[i] * (c ? bv - (double)c[i] : bv);
   }
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-void dot_partials(int64_t n, const double* a, const double* b, const double* c, double* partial, int nblocks,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(dot_partial_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, n, a, b, c, partial);
+template <typename T>
+void dot_partials(int64_t n, const T* a, const T* b, const T* c, double* partial, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((dot_partial_kernel<T>), dim3(nblocks), dim3(kRedThreads), 0, st, n, a, b, c, partial);
 }
+template void dot_partials<double>(int64_t, const double*, const double*, const double*, double*, int, hipStream_t);
+template void dot_partials<float>(int64_t, const float*, const float*, const float*, double*, int, hipStream_t);
 
 // Second stage: one block sums the partials of `nvals` reductions (stride 1024),
 // then applies the SCG scalar update selected by `op`.
@@ -177,42 +180,53 @@ void finish(int nblocks, const double* partial, int op, double* scal, double* ou
 }
 
 // p = beta p + z   (first: p = z)
-__global__ void pupdate_kernel(int64_t n, const double* __restrict__ z, double* __restrict__ p,
+template <typename T>
+__global__ void pupdate_kernel(int64_t n, const T* __restrict__ z, T* __restrict__ p,
                                const double* __restrict__ scal, int first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  p[i] = first ? z[i] : scal[1] * p[i] + z[i];
+  p[i] = first ? z[i] : (T)scal[1] * p[i] + z[i];
 }
 
 // r0 = r; r -= alpha q; u += alpha p; partial[blk] = sum r^2
+template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
-cg_update_kernel(int64_t n, double* __restrict__ r, double* __restrict__ r0, const double* __restrict__ q,
-                 double* __restrict__ u, const double* __restrict__ p, const double* __restrict__ scal,
+cg_update_kernel(int64_t n, T* __restrict__ r, T* __restrict__ r0, const T* __restrict__ q,
+                 T* __restrict__ u, const T* __restrict__ p, const double* __restrict__ scal,
                  double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
-  const double alpha = scal[2];
+  const T alpha = (T)scal[2];
   double s = 0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
-    const double rv = r[i];
+    const T rv = r[i];
     if (r0) r0[i] = rv;
-    const double rn = rv - alpha * q[i];
+    const T rn = rv - alpha * q[i];
     r[i] = rn;
     u[i] += alpha * p[i];
-    s += rn * rn;
+    s += (double)rn * (double)rn;
   }
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-void pupdate(int64_t n, const double* z, double* p, const double* scal, int first, hipStream_t st) {
-  hipLaunchKernelGGL(pupdate_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, z, p, scal, first);
+template <typename T>
+void pupdate(int64_t n, const T* z, T* p, const double* scal, int first, hipStream_t st) {
+  hipLaunchKernelGGL((pupdate_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, z, p, scal, first);
 }
 
-void cg_update(int64_t n, double* r, double* r0, const double* q, double* u, const double* p, const double* scal,
-               double* partial, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, n, r, r0, q, u, p, scal, partial);
+template <typename T>
+void cg_update(int64_t n, T* r, T* r0, const T* q, T* u, const T* p, const double* scal, double* partial,
+               int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblocks), dim3(kRedThreads), 0, st, n, r, r0, q, u, p, scal,
+                     partial);
 }
+template void pupdate<double>(int64_t, const double*, double*, const double*, int, hipStream_t);
+template void pupdate<float>(int64_t, const float*, float*, const double*, int, hipStream_t);
+template void cg_update<double>(int64_t, double*, double*, const double*, double*, const double*, const double*,
+                                double*, int, hipStream_t);
+template void cg_update<float>(int64_t, float*, float*, const float*, float*, const float*, const double*, double*,
+                               int, hipStream_t);
 
 // y = x (with optional conversion) / y += x
 template <typename TI, typename TO>

@@ -30,6 +30,7 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
                   T kappa, T inv_wend) {
   using S = OpShape<N>;
   constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
+  constexpr int TPT = (6 * N2 + N3 - 1) / N3;     // face tasks per thread
   const int lb = xcd_block((E + EPB - 1) / EPB);
   if (lb < 0) return;
   const int tid = threadIdx.x;
@@ -37,13 +38,14 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
   const int node = tid - le * N3;
   const int e = lb * EPB + le;
   const bool active = (le < EPB) && (e < E);
+  const int64_t ndof = (int64_t)E * N3;
 
   __shared__ T sD[N2];
   __shared__ T su[EPB][N3];
   __shared__ T sF[EPB][3][N3];
-  __shared__ T sRow[EPB][N3];
-  __shared__ T sQ[EPB][6][N2];
-  __shared__ T sTr[EPB][2][N2];
+  __shared__ T sTr[EPB][6][N2];    // neighbour trace
+  __shared__ T sRow[EPB][6][N2];   // direct face-row term
+  __shared__ T sSig[EPB][6][N2];   // lifting weight sigma
 
   for (int t = tid; t < N2; t += S::THREADS) sD[t] = Dg[t];
   const int64_t base = (int64_t)e * N3;
@@ -51,11 +53,45 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
   if (active) {
     uval = u[base + node];
     su[le][node] = uval;
-    sRow[le][node] = 0;
+  }
+  // phase 0: neighbour data of every face node: trace, normal derivative and metric row
+  T dn_nb[TPT], gn[TPT][3];
+  int en_t[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int t = node + k * N3;
+    en_t[k] = -1;
+    dn_nb[k] = 0;
+    gn[k][0] = gn[k][1] = gn[k][2] = 0;
+    if (!active || t >= 6 * N2) continue;
+    const int phi = t / N2, f = t - phi * N2, ax = phi >> 1;
+    const int en = nbr[(int64_t)e * 6 + phi];
+    en_t[k] = en;
+    T tr = 0;
+    if (en >= 0) {
+      const int phio = phi ^ 1;
+      const int endo = (phio & 1) ? N - 1 : 0;
+      const T* line = u + (int64_t)en * N3 + face_node<N>(phio, f, 0);
+      const int st = axis_stride<N>(ax);
+      T dn = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        const T v = line[m * st];
+        dn += Dg[endo * N + m] * v;
+        if (m == endo) tr = v;
+      }
+      dn_nb[k] = dn;
+      const int64_t gi = (int64_t)en * N3 + face_node<N>(phio, f, endo);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gn[k][c] = G[sym_index(ax, c) * ndof + gi];
+    }
+    sTr[le][phi][f] = tr;
   }
   __syncthreads();
 
+  // phase 1: reference derivatives and contravariant fluxes F_b = sum_c G_bc d_c u
   const int i = node % N, j = (node / N) % N, k = node / N2;
+  T gl[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
     T d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
@@ -64,114 +100,74 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
       d1 += sD[j * N + m] * su[le][(k * N + m) * N + i];
       d2 += sD[k * N + m] * su[le][(m * N + j) * N + i];
     }
-    const int64_t ndof = (int64_t)E * N3;
-    const T g00 = G[0 * ndof + base + node], g01 = G[1 * ndof + base + node], g02 = G[2 * ndof + base + node];
-    const T g11 = G[3 * ndof + base + node], g12 = G[4 * ndof + base + node], g22 = G[5 * ndof + base + node];
-    sF[le][0][node] = g00 * d0 + g01 * d1 + g02 * d2;
-    sF[le][1][node] = g01 * d0 + g11 * d1 + g12 * d2;
-    sF[le][2][node] = g02 * d0 + g12 * d1 + g22 * d2;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gl[c] = G[c * ndof + base + node];
+    sF[le][0][node] = gl[0] * d0 + gl[1] * d1 + gl[2] * d2;
+    sF[le][1][node] = gl[1] * d0 + gl[3] * d1 + gl[4] * d2;
+    sF[le][2][node] = gl[2] * d0 + gl[4] * d1 + gl[5] * d2;
   }
   __syncthreads();
 
-  // pass A: own normal fluxes q = nu omega s n_out.grad u = +-F_b / w_end at every face node
-  if (le < EPB && e < E) {
-    for (int t = node; t < 6 * N2; t += N3) {
-      const int phi = t / N2, f = t - phi * N2;
-      const int ax = phi >> 1;
-      const int vi = face_node<N>(phi, f, (phi & 1) ? N - 1 : 0);
-      const T sgn = (phi & 1) ? T(1) : T(-1);
-      sQ[le][phi][f] = sgn * inv_wend * sF[le][ax][vi];
+  // phase 2: face terms per face node (no two tasks share an output slot)
+#pragma unroll
+  for (int kk = 0; kk < TPT; ++kk) {
+    const int t = node + kk * N3;
+    if (!active || t >= 6 * N2) continue;
+    const int phi = t / N2, f = t - phi * N2, ax = phi >> 1;
+    const int vi = face_node<N>(phi, f, (phi & 1) ? N - 1 : 0);
+    const T sgn = (phi & 1) ? T(1) : T(-1);
+    const T uo = su[le][vi];
+    const T qo = sgn * inv_wend * sF[le][ax][vi];    // nu omega s n_out . grad u
+    const T pf = pen[((int64_t)e * 6 + phi) * N2 + f];
+    T row = 0, sigma = 0;
+    if (en_t[kk] >= 0) {
+      const int a = f / N, b = f - a * N;
+      T dlast = 0, dfirst = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        dlast += sD[b * N + m] * sTr[le][phi][a * N + m];
+        dfirst += sD[a * N + m] * sTr[le][phi][m * N + b];
+      }
+      T du0, du1, du2;
+      if (ax == 0) { du0 = dn_nb[kk]; du1 = dlast; du2 = dfirst; }
+      else if (ax == 1) { du0 = dlast; du1 = dn_nb[kk]; du2 = dfirst; }
+      else { du0 = dlast; du1 = dfirst; du2 = dn_nb[kk]; }
+      const T fl = gn[kk][0] * du0 + gn[kk][1] * du1 + gn[kk][2] * du2;
+      const T qn = -sgn * inv_wend * fl;             // neighbour's outward flux
+      const T jmp = uo - sTr[le][phi][f];
+      row = pf * jmp - T(0.5) * (qo - qn);
+      sigma = T(-0.5) * jmp;
+    } else if (bc[(int64_t)e * 6 + phi] == 1) {      // Dirichlet: 2 mu nu omega s u - q, lifting -u
+      row = pf * uo - qo;
+      sigma = -uo;
     }
+    sRow[le][phi][f] = row;
+    sSig[le][phi][f] = sigma;
   }
   __syncthreads();
 
-  const int64_t ndof = (int64_t)E * N3;
-  for (int ax = 0; ax < 3; ++ax) {
-    // stage 1: neighbour trace and normal derivative from its node line
-    T dn_nb[(2 * N2 + N3 - 1) / N3];
-    int cnt = 0;
-    if (le < EPB && e < E) {
-      for (int t = node; t < 2 * N2; t += N3, ++cnt) {
-        const int s = t / N2, f = t - s * N2;
-        const int phi = 2 * ax + s;
-        const int en = nbr[(int64_t)e * 6 + phi];
-        T tr = 0, dn = 0;
-        if (en >= 0) {
-          const int phio = phi ^ 1;
-          const int endo = (phio & 1) ? N - 1 : 0;
-          const int l0 = face_node<N>(phio, f, 0);
-          const T* line = u + (int64_t)en * N3 + l0;
-          constexpr int st0 = 1;
-          const int st = axis_stride<N>(ax);
+  // phase 3: every node collects the terms of the faces it lies on (its own slots)
+  T rowsum = 0;
+  if (active) {
+    const int fidx[3] = {k * N + j, k * N + i, j * N + i};
+    const int idx[3] = {i, j, k};
 #pragma unroll
-          for (int m = 0; m < N; ++m) {
-            const T v = line[m * st];
-            dn += sD[endo * N + m] * v;
-            if (m == endo) tr = v;
-          }
-          (void)st0;
-        }
-        sTr[le][s][f] = tr;
-        dn_nb[cnt] = dn;
-      }
+    for (int ax = 0; ax < 3; ++ax) {
+      int phi = -1;
+      if (idx[ax] == 0) phi = 2 * ax;
+      else if (idx[ax] == N - 1) phi = 2 * ax + 1;
+      if (phi < 0) continue;
+      rowsum += sRow[le][phi][fidx[ax]];
+      const T sg = sSig[le][phi][fidx[ax]] * ((phi & 1) ? inv_wend : -inv_wend);
+      sF[le][0][node] += sg * gl[sym_index(ax, 0)];
+      sF[le][1][node] += sg * gl[sym_index(ax, 1)];
+      sF[le][2][node] += sg * gl[sym_index(ax, 2)];
     }
-    __syncthreads();
-    cnt = 0;
-    if (le < EPB && e < E) {
-      for (int t = node; t < 2 * N2; t += N3, ++cnt) {
-        const int s = t / N2, f = t - s * N2;
-        const int phi = 2 * ax + s;
-        const int en = nbr[(int64_t)e * 6 + phi];
-        const int vi = face_node<N>(phi, f, (phi & 1) ? N - 1 : 0);
-        const T sgn = (phi & 1) ? T(1) : T(-1);
-        const T uo = su[le][vi];
-        const T qo = sQ[le][phi][f];
-        const T pf = pen[((int64_t)e * 6 + phi) * N2 + f];
-        T row = 0, sigma = 0;
-        if (en >= 0) {
-          const int phio = phi ^ 1;
-          const int a = f / N, b = f - a * N;
-          // tangential derivatives of the neighbour trace on the face grid
-          T dlast = 0, dfirst = 0;
-#pragma unroll
-          for (int m = 0; m < N; ++m) {
-            dlast += sD[b * N + m] * sTr[le][s][a * N + m];
-            dfirst += sD[a * N + m] * sTr[le][s][m * N + b];
-          }
-          T du[3];
-          du[ax] = dn_nb[cnt];
-          if (ax == 0) { du[1] = dlast; du[2] = dfirst; }
-          else if (ax == 1) { du[0] = dlast; du[2] = dfirst; }
-          else { du[0] = dlast; du[1] = dfirst; }
-          const int vio = face_node<N>(phio, f, (phio & 1) ? N - 1 : 0);
-          const int64_t gi = (int64_t)en * N3 + vio;
-          T fl = 0;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) fl += G[sym_index(ax, c) * ndof + gi] * du[c];
-          const T qn = -sgn * inv_wend * fl;        // neighbour's outward flux
-          const T jmp = uo - sTr[le][s][f];
-          row = pf * jmp - T(0.5) * (qo - qn);
-          sigma = T(-0.5) * jmp;
-        } else {
-          const int8_t code = bc[(int64_t)e * 6 + phi];
-          if (code == 1) {           // Dirichlet: 2 mu nu w s u - q, lifting -u
-            row = pf * uo - qo;
-            sigma = -uo;
-          }
-        }
-        sRow[le][vi] += row;
-        if (sigma != T(0)) {
-          const int64_t gi = base + vi;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) sF[le][c][vi] += sigma * sgn * inv_wend * G[sym_index(ax, c) * ndof + gi];
-        }
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
 
   if (active) {
-    T acc = sRow[le][node];
+    T acc = rowsum;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       acc += sD[m * N + i] * sF[le][0][(k * N + j) * N + m];

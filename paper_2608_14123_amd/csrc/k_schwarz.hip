@@ -59,23 +59,24 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
 
   __shared__ T tA[Sh::TILE];
   __shared__ T tB[Sh::TILE];
-  __shared__ T sS[3][NS * NS];
-  __shared__ T sLam[3][NS];
   __shared__ T sW[3][NS];
   __shared__ int sMap[3][NS];
   __shared__ int sNb[27];
 
-  const int v0 = a.var[(int64_t)e * 3 + 0], v1 = a.var[(int64_t)e * 3 + 1], v2 = a.var[(int64_t)e * 3 + 2];
-  const int vv[3] = {v0, v1, v2};
-  for (int t = tid; t < 3 * NS * NS; t += THR) {
-    const int d = t / (NS * NS), q = t - d * NS * NS;
-    sS[d][q] = a.S[vv[d] * NS * NS + q];
-  }
+  // variant per direction: uniform over the workgroup, so the eigenvector tables
+  // are read through the scalar cache straight into SGPR operands
+  const int v0 = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 0]);
+  const int v1 = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 1]);
+  const int v2 = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 2]);
+  const T* __restrict__ S1 = a.S + v0 * NS * NS;
+  const T* __restrict__ S2 = a.S + v1 * NS * NS;
+  const T* __restrict__ S3 = a.S + v2 * NS * NS;
+  const T* __restrict__ L3 = a.lam + v2 * NS;
   for (int t = tid; t < 3 * NS; t += THR) {
     const int d = t / NS, q = t - d * NS;
-    sLam[d][q] = a.lam[vv[d] * NS + q];
-    sW[d][q] = a.W[vv[d] * NS + q];
-    sMap[d][q] = a.map1d[vv[d] * NS + q];
+    const int v = d == 0 ? v0 : (d == 1 ? v1 : v2);
+    sW[d][q] = a.W[v * NS + q];
+    sMap[d][q] = a.map1d[v * NS + q];
   }
   if (tid < 27) sNb[tid] = a.nb27[(int64_t)e * 27 + tid];
   const T g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
@@ -99,7 +100,6 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   const bool act = tid < NS * NS;
   const int tlo = tid % NS, thi = tid / NS;
   T line[NS];
-  T res[NS];
   // phase 1: xi_1 with S1^T   (thread: s2 = tlo, s3 = thi)
   if (act) {
     const int b = (thi * NS + tlo) * LS;
@@ -109,7 +109,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += sS[0][q * NS + c] * line[q];
+      for (int q = 0; q < NS; ++q) s += S1[q * NS + c] * line[q];
       tB[b + c] = s;
     }
   }
@@ -122,28 +122,29 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += sS[1][q * NS + c] * line[q];
+      for (int q = 0; q < NS; ++q) s += S2[q * NS + c] * line[q];
       tA[(thi * NS + c) * LS + tlo] = s;
     }
   }
   __syncthreads();
   // phase 3: xi_3 with S3^T, divide by D, xi_3 with S3   (thread: s1 = tlo, s2 = thi)
   if (act) {
+    T res[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) line[q] = tA[(q * NS + thi) * LS + tlo];
-    const T base = g0 + g1 * sLam[0][tlo] + g2 * sLam[1][thi];
+    const T base = g0 + g1 * a.lam[v0 * NS + tlo] + g2 * a.lam[v1 * NS + thi];
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += sS[2][q * NS + c] * line[q];
-      res[c] = s / (base + g3 * sLam[2][c]);
+      for (int q = 0; q < NS; ++q) s += S3[q * NS + c] * line[q];
+      res[c] = s / (base + g3 * L3[c]);
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < NS; ++c) s += sS[2][q * NS + c] * res[c];
+      for (int c = 0; c < NS; ++c) s += S3[q * NS + c] * res[c];
       tB[(q * NS + thi) * LS + tlo] = s;
     }
   }
@@ -156,7 +157,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += sS[1][c * NS + q] * line[q];
+      for (int q = 0; q < NS; ++q) s += S2[c * NS + q] * line[q];
       tA[(thi * NS + c) * LS + tlo] = s;
     }
   }
@@ -170,13 +171,13 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += sS[0][c * NS + q] * line[q];
+      for (int q = 0; q < NS; ++q) s += S1[c * NS + q] * line[q];
       tB[b + c] = s;
     }
   }
   __syncthreads();
-  // weighted scatter: own part to z, overlap parts to O
-  T* Oe = a.O + (int64_t)e * R.size;
+  // weighted scatter: own part to z, each overlap part into the receiving
+  // element's inbox (region seen from the receiver), read back by overlap_add
   for (int q = tid; q < NS * NS * NS; q += THR) {
     const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
     const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
@@ -189,10 +190,12 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
       if (a.mode == 0) a.z[gi] = v;
       else a.z[gi] += v;
     } else {
-      const int r = (d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1);
+      const int dest = sNb[(d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1)];
+      if (dest < 0) continue;
+      const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
       const int c1 = d1 < 0 ? l1 - (N - M) : l1, c2 = d2 < 0 ? l2 - (N - M) : l2, c3 = d3 < 0 ? l3 - (N - M) : l3;
       const int x1 = d1 ? M : N, x2 = d2 ? M : N;
-      Oe[R.off[r] + (c3 * x2 + c2) * x1 + c1] = v;
+      a.O[(int64_t)dest * R.size + R.off[r] + (c3 * x2 + c2) * x1 + c1] = v;
     }
   }
 }
@@ -204,6 +207,8 @@ struct AddShape {
   static constexpr int THREADS = ((EPB * N3 + 63) / 64) * 64;
 };
 
+// z[node] += sum of the neighbours' overlap contributions in the element's own
+// inbox, in a fixed order.  Inbox regions of absent neighbours stay zero.
 template <int N, int M, typename T>
 __global__ void __launch_bounds__(AddShape<N>::THREADS)
 schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
@@ -225,20 +230,18 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
     any = any || lo[d] < 0 || hi[d] > 0;
   }
   if (!any) return;
+  const T* __restrict__ box = a.O + (int64_t)e * R.size;
   T acc = 0;
   for (int d3 = lo[2]; d3 <= hi[2]; ++d3)
     for (int d2 = lo[1]; d2 <= hi[1]; ++d2)
       for (int d1 = lo[0]; d1 <= hi[0]; ++d1) {
         if (d1 == 0 && d2 == 0 && d3 == 0) continue;
-        const int en = a.nb27[(int64_t)e * 27 + (d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1)];
-        if (en < 0) continue;
-        // element en sees us at offset -d; our node lies in its region -d
-        const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);
+        const int r = (d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1);
         const int c1 = d1 > 0 ? l[0] - (N - M) : l[0];
         const int c2 = d2 > 0 ? l[1] - (N - M) : l[1];
         const int c3 = d3 > 0 ? l[2] - (N - M) : l[2];
         const int x1 = d1 ? M : N, x2 = d2 ? M : N;
-        acc += a.O[(int64_t)en * R.size + R.off[r] + (c3 * x2 + c2) * x1 + c1];
+        acc += box[R.off[r] + (c3 * x2 + c2) * x1 + c1];
       }
   a.z[(int64_t)e * N3 + node] += acc;
 }

@@ -60,9 +60,6 @@ template <typename T>
 bool tensor3(int n_in, int n_out, int E, const T* Tm, const T* in, const T* in2, T* out, int accumulate,
              hipStream_t st);
 
-// BLAS-1 with deterministic two-stage reductions
-void dot_partials(int64_t n, const double* a, const double* b, const double* c, double* partial, int nblocks,
-                  hipStream_t st);   // partial[blk] = sum a*(b - c) (c may be null)
 int reduction_blocks(int64_t n);
 
 }  // namespace dgfas

@@ -84,7 +84,14 @@ struct Level {
   // vectors
   double *u = nullptr, *g = nullptr, *ubar = nullptr, *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr,
          *r0 = nullptr;
-  float *r32 = nullptr, *du32 = nullptr, *rc32 = nullptr;
+  float *r32 = nullptr, *du32 = nullptr, *rc32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr,
+        *r0_32 = nullptr;
+
+  template <typename T>
+  void scg_vectors(T*& r_, T*& z_, T*& p_, T*& q_, T*& r0_) {
+    if constexpr (sizeof(T) == 8) { r_ = r; z_ = z; p_ = pv; q_ = q; r0_ = r0; }
+    else { r_ = rc32; z_ = z32; p_ = p32; q_ = q32; r0_ = r0_32; }
+  }
 };
 
 struct Solver {
@@ -172,7 +179,7 @@ struct Solver {
 
   double dot_sync(Level& L, const double* a, const double* b) {
     const int nb = reduction_blocks(L.ndof);
-    dot_partials(L.ndof, a, b, nullptr, partial, nb, st);
+    dot_partials<double>(L.ndof, a, b, nullptr, partial, nb, st);
     finish(nb, partial, kOpStore, scal, scratch, st);
     double h = 0;
     HIPC(hipMemcpyAsync(&h, scratch, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -180,28 +187,47 @@ struct Solver {
     return h;
   }
 
+  void apply_t(Level& L, const double* u, double* Au) { apply(L, u, Au); }
+  void apply_t(Level& L, const float* u, float* Au) {
+    OpArgs<float> a = op_args<float>(L, 1, u, nullptr, Au);
+    sipg_apply<float>(L.p, a, st);
+  }
+  void residual_t(Level& L, const double* u, const double* g, double* r) { residual(L, u, g, r); }
+  void residual_t(Level& L, const float* u, const float* g, float* r) { residual32(L, u, g, r); }
+  void schwarz_t(Level& L, const double* r, double* z, int mode) { schwarz(L, r, z, mode); }
+  void schwarz_t(Level& L, const float* r, float* z, int mode) { schwarz32(L, r, z, mode); }
+
   // Alg. 6 with p = z in the first iteration.  r_max <= 0: exactly n iterations, no sync.
-  int scg(Level& L, double* u, const double* f, int n, double r_max, bool* breakdown) {
+  // zero_start: x = 0 and r = f without an operator application (correction form).
+  template <typename T>
+  int scg(Level& L, T* x, const T* f, int n, double r_max, bool* breakdown, bool zero_start = false) {
     const int nb = reduction_blocks(L.ndof);
-    residual(L, u, f, L.r);
+    T *r, *z, *pv, *q, *r0;
+    L.scg_vectors<T>(r, z, pv, q, r0);
+    if (zero_start) {
+      fill(L.ndof, x, (T)0, st);
+      convert<T, T>(L.ndof, f, r, 0, st);
+    } else {
+      residual_t(L, x, f, r);
+    }
     HIPC(hipMemsetAsync(scal, 0, 8 * sizeof(double), st));
     int it = 0;
     for (int i = 1; i <= n; ++i) {
-      schwarz(L, L.r, L.z, 0);
+      schwarz_t(L, r, z, 0);
       if (i > 1) {
-        dot_partials(L.ndof, L.z, L.r, nullptr, partial, nb, st);
-        dot_partials(L.ndof, L.z, L.r, L.r0, partial + 1024, nb, st);
+        dot_partials<T>(L.ndof, z, r, nullptr, partial, nb, st);
+        dot_partials<T>(L.ndof, z, r, r0, partial + 1024, nb, st);
         finish(nb, partial, kOpBeta, scal, nullptr, st);
-        pupdate(L.ndof, L.z, L.pv, scal, 0, st);
+        pupdate<T>(L.ndof, z, pv, scal, 0, st);
       } else {
-        dot_partials(L.ndof, L.z, L.r, nullptr, partial, nb, st);
+        dot_partials<T>(L.ndof, z, r, nullptr, partial, nb, st);
         finish(nb, partial, kOpGamma, scal, nullptr, st);
-        pupdate(L.ndof, L.z, L.pv, scal, 1, st);
+        pupdate<T>(L.ndof, z, pv, scal, 1, st);
       }
-      apply(L, L.pv, L.q);
-      dot_partials(L.ndof, L.pv, L.q, nullptr, partial, nb, st);
+      apply_t(L, pv, q);
+      dot_partials<T>(L.ndof, pv, q, nullptr, partial, nb, st);
       finish(nb, partial, kOpAlpha, scal, nullptr, st);
-      cg_update(L.ndof, L.r, L.r0, L.q, u, L.pv, scal, partial, nb, st);
+      cg_update<T>(L.ndof, r, r0, q, x, pv, scal, partial, nb, st);
       finish(nb, partial, kOpNorm2, scal, nullptr, st);
       it = i;
       if (r_max > 0) {
@@ -215,11 +241,26 @@ struct Solver {
     return it;
   }
 
+  // Correction-form SCG smoothing in FP32: r = g - A u (FP64), n SCG iterations
+  // on A du = r in FP32 from du = 0, u += du (FP64).
+  void scg_mixed(Level& L, double* u, const double* g, int n) {
+    residual(L, u, g, L.r);
+    convert<double, float>(L.ndof, L.r, L.r32, 0, st);
+    scg<float>(L, L.du32, L.r32, n, 0.0, nullptr, true);
+    convert<float, double>(L.ndof, L.du32, u, 1, st);
+  }
+
   void smooth(Level& L, double* u, const double* g, int n) {
     if (n <= 0) return;
-    if (opt.smoother == DGFAS_SCG) scg(L, u, g, n, 0.0, nullptr);
-    else if (opt.precision == DGFAS_FP32) was_mixed(L, u, g, n);
-    else was(L, u, g, n);
+    const bool mixed = opt.precision == DGFAS_FP32;
+    if (opt.smoother == DGFAS_SCG) {
+      if (mixed) scg_mixed(L, u, g, n);
+      else scg<double>(L, u, g, n, 0.0, nullptr);
+    } else if (mixed) {
+      was_mixed(L, u, g, n);
+    } else {
+      was(L, u, g, n);
+    }
   }
 
   int root_solve(double* u, const double* g, bool* breakdown) {
@@ -227,7 +268,7 @@ struct Solver {
     residual(L, u, g, L.r);
     const double r0 = std::sqrt(dot_sync(L, L.r, L.r));
     if (r0 == 0.0) return 0;
-    return scg(L, u, g, opt.root_max_iter, opt.root_rtol * r0, breakdown);
+    return scg<double>(L, u, g, opt.root_max_iter, opt.root_rtol * r0, breakdown);
   }
 
   // Alg. 2 with global p-coarsening.
@@ -404,6 +445,11 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
   const int osz = overlap_size(p, L.m);
   L.O = s.own(dalloc<double>((size_t)L.E * osz));
   L.O32 = s.own(dalloc<float>((size_t)L.E * osz));
+  // inbox regions of absent neighbours are never written and must read as zero
+  if (osz) {
+    HIPC(hipMemsetAsync(L.O, 0, (size_t)L.E * osz * sizeof(double), st));
+    HIPC(hipMemsetAsync(L.O32, 0, (size_t)L.E * osz * sizeof(float), st));
+  }
   // work vectors
   L.r = s.own(dalloc<double>(L.ndof));
   L.z = s.own(dalloc<double>(L.ndof));
@@ -414,6 +460,12 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
     L.r32 = s.own(dalloc<float>(L.ndof));
     L.du32 = s.own(dalloc<float>(L.ndof));
     L.rc32 = s.own(dalloc<float>(L.ndof));
+    if (s.opt.smoother == DGFAS_SCG) {
+      L.z32 = s.own(dalloc<float>(L.ndof));
+      L.p32 = s.own(dalloc<float>(L.ndof));
+      L.q32 = s.own(dalloc<float>(L.ndof));
+      L.r0_32 = s.own(dalloc<float>(L.ndof));
+    }
   }
   HIPC(hipStreamSynchronize(st));
 }
@@ -442,8 +494,6 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
   if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32) throw Error(DGFAS_EINVAL, "unknown precision");
-  if (o->precision == DGFAS_FP32 && o->smoother != DGFAS_WAS)
-    throw Error(DGFAS_EUNSUPPORTED, "FP32 smoothing is implemented for WAS");
 }
 
 Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
