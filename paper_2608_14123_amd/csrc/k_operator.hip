@@ -13,6 +13,7 @@
 #include "device.hpp"
 #include "kernels.hpp"
 
+
 namespace dgfas {
 
 template <int N>
@@ -47,32 +48,53 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
   __shared__ T sRow[EPB][6][N2];   // direct face-row term
   __shared__ T sSig[EPB][6][N2];   // lifting weight sigma
 
-  for (int t = tid; t < N2; t += S::THREADS) sD[t] = Dg[t];
   const int64_t base = (int64_t)e * N3;
-  T uval = 0;
-  if (active) {
-    uval = u[base + node];
-    su[le][node] = uval;
-  }
-  // phase 0: neighbour data of every face node: trace, normal derivative and metric row
-  T dn_nb[TPT], gn[TPT][3];
+  // prologue: every independent load first (neighbour ids, penalties, boundary codes, u, metric, g)
   int en_t[TPT];
+  T pen_t[TPT];
+  int8_t bc_t[TPT];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     const int t = node + k * N3;
     en_t[k] = -1;
+    pen_t[k] = 0;
+    bc_t[k] = 0;
+    if (active && t < 6 * N2) {
+      const int phi = t / N2;
+      en_t[k] = nbr[(int64_t)e * 6 + phi];
+      pen_t[k] = pen[(int64_t)e * 6 * N2 + t];
+      bc_t[k] = bc[(int64_t)e * 6 + phi];
+    }
+  }
+  T uval = 0, gval = 0;
+  T gl[6] = {0, 0, 0, 0, 0, 0};
+  if (active) {
+    uval = u[base + node];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gl[c] = G[c * ndof + base + node];
+    if (mode == 0) gval = g[base + node];
+  }
+  for (int t = tid; t < N2; t += S::THREADS) sD[t] = Dg[t];
+  if (active) su[le][node] = uval;
+  // phase 0: neighbour data of every face node: trace, normal derivative and metric row
+  T dn_nb[TPT], gn[TPT][3];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int t = node + k * N3;
     dn_nb[k] = 0;
     gn[k][0] = gn[k][1] = gn[k][2] = 0;
     if (!active || t >= 6 * N2) continue;
     const int phi = t / N2, f = t - phi * N2, ax = phi >> 1;
-    const int en = nbr[(int64_t)e * 6 + phi];
-    en_t[k] = en;
+    const int en = en_t[k];
     T tr = 0;
     if (en >= 0) {
       const int phio = phi ^ 1;
       const int endo = (phio & 1) ? N - 1 : 0;
       const T* line = u + (int64_t)en * N3 + face_node<N>(phio, f, 0);
       const int st = axis_stride<N>(ax);
+      const int64_t gi = (int64_t)en * N3 + face_node<N>(phio, f, endo);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gn[k][c] = G[sym_index(ax, c) * ndof + gi];
       T dn = 0;
 #pragma unroll
       for (int m = 0; m < N; ++m) {
@@ -81,9 +103,6 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
         if (m == endo) tr = v;
       }
       dn_nb[k] = dn;
-      const int64_t gi = (int64_t)en * N3 + face_node<N>(phio, f, endo);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) gn[k][c] = G[sym_index(ax, c) * ndof + gi];
     }
     sTr[le][phi][f] = tr;
   }
@@ -91,7 +110,6 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
 
   // phase 1: reference derivatives and contravariant fluxes F_b = sum_c G_bc d_c u
   const int i = node % N, j = (node / N) % N, k = node / N2;
-  T gl[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
     T d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
@@ -100,8 +118,6 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
       d1 += sD[j * N + m] * su[le][(k * N + m) * N + i];
       d2 += sD[k * N + m] * su[le][(m * N + j) * N + i];
     }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) gl[c] = G[c * ndof + base + node];
     sF[le][0][node] = gl[0] * d0 + gl[1] * d1 + gl[2] * d2;
     sF[le][1][node] = gl[1] * d0 + gl[3] * d1 + gl[4] * d2;
     sF[le][2][node] = gl[2] * d0 + gl[4] * d1 + gl[5] * d2;
@@ -118,7 +134,7 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
     const T sgn = (phi & 1) ? T(1) : T(-1);
     const T uo = su[le][vi];
     const T qo = sgn * inv_wend * sF[le][ax][vi];    // nu omega s n_out . grad u
-    const T pf = pen[((int64_t)e * 6 + phi) * N2 + f];
+    const T pf = pen_t[kk];
     T row = 0, sigma = 0;
     if (en_t[kk] >= 0) {
       const int a = f / N, b = f - a * N;
@@ -137,7 +153,7 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
       const T jmp = uo - sTr[le][phi][f];
       row = pf * jmp - T(0.5) * (qo - qn);
       sigma = T(-0.5) * jmp;
-    } else if (bc[(int64_t)e * 6 + phi] == 1) {      // Dirichlet: 2 mu nu omega s u - q, lifting -u
+    } else if (bc_t[kk] == 1) {                      // Dirichlet: 2 mu nu omega s u - q, lifting -u
       row = pf * uo - qo;
       sigma = -uo;
     }
@@ -175,7 +191,7 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
       acc += sD[m * N + k] * sF[le][2][(m * N + j) * N + i];
     }
     if (WJ) acc += kappa * WJ[base + node] * uval;
-    out[base + node] = mode == 0 ? g[base + node] - acc : acc;
+    out[base + node] = mode == 0 ? gval - acc : acc;
   }
 }
 

@@ -62,6 +62,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   __shared__ T sW[3][NS];
   __shared__ int sMap[3][NS];
   __shared__ int sNb[27];
+  __shared__ int sOff[27];
 
   // variant per direction: uniform over the workgroup, so the eigenvector tables
   // are read through the scalar cache straight into SGPR operands
@@ -78,38 +79,60 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     sW[d][q] = a.W[v * NS + q];
     sMap[d][q] = a.map1d[v * NS + q];
   }
-  if (tid < 27) sNb[tid] = a.nb27[(int64_t)e * 27 + tid];
+  if (tid < 27) {
+    sNb[tid] = a.nb27[(int64_t)e * 27 + tid];
+    sOff[tid] = R.off[tid];
+  }
   const T g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
   const T g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
   __syncthreads();
 
-  // gather r_s = R_s r
-  for (int q = tid; q < NS * NS * NS; q += THR) {
-    const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
-    const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
-    T v = 0;
-    if (m1 >= 0 && m2 >= 0 && m3 >= 0) {
-      const int r = (m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6);
-      const int src = sNb[r];   // an absent edge/vertex neighbour contributes zeros
-      if (src >= 0) v = a.r[(int64_t)src * N3 + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63)];
+  // gather r_s = R_s r: all loads of a thread are issued before the LDS stores
+  constexpr int GIT = (NS * NS * NS + THR - 1) / THR;
+  {
+    T vals[GIT];
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) {
+      const int q = tid + it * THR;
+      vals[it] = 0;
+      if (q < NS * NS * NS) {
+        const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
+        const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
+        if (m1 >= 0 && m2 >= 0 && m3 >= 0) {
+          const int src = sNb[(m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6)];   // absent neighbour: zeros
+          if (src >= 0) vals[it] = a.r[(int64_t)src * N3 + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63)];
+        }
+      }
     }
-    tA[(s3 * NS + s2) * LS + s1] = v;
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) {
+      const int q = tid + it * THR;
+      if (q < NS * NS * NS) {
+        const int s1 = q % NS, s23 = q / NS;
+        tA[s23 * LS + s1] = vals[it];
+      }
+    }
   }
   __syncthreads();
 
+  // Each contraction: one thread per tile line, out_c = sum_q M[c][q] line_q with the
+  // row M[c][:] read through the scalar cache (uniform over the workgroup).
   const bool act = tid < NS * NS;
   const int tlo = tid % NS, thi = tid / NS;
+  const T* __restrict__ S1T = a.ST + v0 * NS * NS;
+  const T* __restrict__ S2T = a.ST + v1 * NS * NS;
+  const T* __restrict__ S3T = a.ST + v2 * NS * NS;
   T line[NS];
   // phase 1: xi_1 with S1^T   (thread: s2 = tlo, s3 = thi)
   if (act) {
     const int b = (thi * NS + tlo) * LS;
 #pragma unroll
     for (int q = 0; q < NS; ++q) line[q] = tA[b + q];
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += S1[q * NS + c] * line[q];
+      for (int q = 0; q < NS; ++q) s += S1T[c * NS + q] * line[q];
       tB[b + c] = s;
     }
   }
@@ -118,34 +141,36 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   if (act) {
 #pragma unroll
     for (int q = 0; q < NS; ++q) line[q] = tB[(thi * NS + q) * LS + tlo];
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += S2[q * NS + c] * line[q];
+      for (int q = 0; q < NS; ++q) s += S2T[c * NS + q] * line[q];
       tA[(thi * NS + c) * LS + tlo] = s;
     }
   }
   __syncthreads();
-  // phase 3: xi_3 with S3^T, divide by D, xi_3 with S3   (thread: s1 = tlo, s2 = thi)
+  // phase 3: xi_3 with S3^T, divide by D, xi_3 with S3   (thread: s1 = tlo, s2 = thi);
+  // the thread's own k-line of tA holds the intermediate
   if (act) {
-    T res[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) line[q] = tA[(q * NS + thi) * LS + tlo];
     const T base = g0 + g1 * a.lam[v0 * NS + tlo] + g2 * a.lam[v1 * NS + thi];
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) s += S3[q * NS + c] * line[q];
-      res[c] = s / (base + g3 * L3[c]);
+      for (int q = 0; q < NS; ++q) s += S3T[c * NS + q] * line[q];
+      tA[(c * NS + thi) * LS + tlo] = s / (base + g3 * L3[c]);
     }
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
+    for (int q = 0; q < NS; ++q) line[q] = tA[(q * NS + thi) * LS + tlo];
+#pragma unroll 1
+    for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
-      for (int c = 0; c < NS; ++c) s += S3[q * NS + c] * res[c];
-      tB[(q * NS + thi) * LS + tlo] = s;
+      for (int q = 0; q < NS; ++q) s += S3[c * NS + q] * line[q];
+      tB[(c * NS + thi) * LS + tlo] = s;
     }
   }
   __syncthreads();
@@ -153,7 +178,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   if (act) {
 #pragma unroll
     for (int q = 0; q < NS; ++q) line[q] = tB[(thi * NS + q) * LS + tlo];
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
@@ -167,7 +192,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     const int b = (thi * NS + tlo) * LS;
 #pragma unroll
     for (int q = 0; q < NS; ++q) line[q] = tA[b + q];
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < NS; ++c) {
       T s = 0;
 #pragma unroll
@@ -178,7 +203,10 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   __syncthreads();
   // weighted scatter: own part to z, each overlap part into the receiving
   // element's inbox (region seen from the receiver), read back by overlap_add
-  for (int q = tid; q < NS * NS * NS; q += THR) {
+#pragma unroll
+  for (int it = 0; it < GIT; ++it) {
+    const int q = tid + it * THR;
+    if (q >= NS * NS * NS) continue;
     const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
     const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
     if (m1 < 0 || m2 < 0 || m3 < 0) continue;
@@ -195,7 +223,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
       const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
       const int c1 = d1 < 0 ? l1 - (N - M) : l1, c2 = d2 < 0 ? l2 - (N - M) : l2, c3 = d3 < 0 ? l3 - (N - M) : l3;
       const int x1 = d1 ? M : N, x2 = d2 ? M : N;
-      a.O[(int64_t)dest * R.size + R.off[r] + (c3 * x2 + c2) * x1 + c1] = v;
+      a.O[(int64_t)dest * R.size + sOff[r] + (c3 * x2 + c2) * x1 + c1] = v;
     }
   }
 }
@@ -218,31 +246,47 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
   const int lb = xcd_block((a.E + EPB - 1) / EPB);
   if (lb < 0) return;
   const int tid = threadIdx.x;
+  __shared__ int sOff[27];
+  if (tid < 27) sOff[tid] = R.off[tid];
+  __syncthreads();
   const int le = tid / N3, node = tid - le * N3;
   const int e = lb * EPB + le;
   if (le >= EPB || e >= a.E) return;
   const int l[3] = {node % N, (node / N) % N, node / (N * N)};
-  int lo[3], hi[3];
+  // per direction the offset towards the one neighbour whose overlap can cover this node
+  int od[3];
   bool any = false;
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    lo[d] = (l[d] < M) ? -1 : 0;
-    hi[d] = (l[d] >= N - M) ? 1 : 0;
-    any = any || lo[d] < 0 || hi[d] > 0;
+    od[d] = (l[d] < M) ? -1 : ((l[d] >= N - M) ? 1 : 0);
+    any = any || od[d] != 0;
   }
   if (!any) return;
   const T* __restrict__ box = a.O + (int64_t)e * R.size;
+  // the up to 7 candidates (subsets of the non-zero directions): every load is issued
+  // unconditionally (invalid ones read entry 0 and are masked) so that none waits on another
+  T vals[7];
+  bool ok[7];
+#pragma unroll
+  for (int bits = 1; bits < 8; ++bits) {
+    const int dd[3] = {(bits & 1) ? od[0] : 0, (bits & 2) ? od[1] : 0, (bits & 4) ? od[2] : 0};
+    const bool valid = ((bits & 1) == 0 || od[0] != 0) && ((bits & 2) == 0 || od[1] != 0) &&
+                       ((bits & 4) == 0 || od[2] != 0);
+    int off = 0;
+    if (valid) {
+      const int r = (dd[2] + 1) * 9 + (dd[1] + 1) * 3 + (dd[0] + 1);
+      const int c1 = dd[0] > 0 ? l[0] - (N - M) : l[0];
+      const int c2 = dd[1] > 0 ? l[1] - (N - M) : l[1];
+      const int c3 = dd[2] > 0 ? l[2] - (N - M) : l[2];
+      const int x1 = dd[0] ? M : N, x2 = dd[1] ? M : N;
+      off = sOff[r] + (c3 * x2 + c2) * x1 + c1;
+    }
+    ok[bits - 1] = valid;
+    vals[bits - 1] = box[off];
+  }
   T acc = 0;
-  for (int d3 = lo[2]; d3 <= hi[2]; ++d3)
-    for (int d2 = lo[1]; d2 <= hi[1]; ++d2)
-      for (int d1 = lo[0]; d1 <= hi[0]; ++d1) {
-        if (d1 == 0 && d2 == 0 && d3 == 0) continue;
-        const int r = (d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1);
-        const int c1 = d1 > 0 ? l[0] - (N - M) : l[0];
-        const int c2 = d2 > 0 ? l[1] - (N - M) : l[1];
-        const int c3 = d3 > 0 ? l[2] - (N - M) : l[2];
-        const int x1 = d1 ? M : N, x2 = d2 ? M : N;
-        acc += box[R.off[r] + (c3 * x2 + c2) * x1 + c1];
-      }
+#pragma unroll
+  for (int t = 0; t < 7; ++t) acc += ok[t] ? vals[t] : T(0);
   a.z[(int64_t)e * N3 + node] += acc;
 }
 

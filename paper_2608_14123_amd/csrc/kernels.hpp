@@ -43,7 +43,8 @@ struct SchwarzArgs {
   const int* nb27 = nullptr;  // [E][27]
   const int8_t* var = nullptr;   // [E][3] variant index (left*3+right)
   const T* gco = nullptr;     // [E][4] g0..g3
-  const T* S = nullptr;       // [9][ns*ns] padded eigenvector tables
+  const T* S = nullptr;       // [9][ns*ns] padded eigenvector tables, S[i*ns + a] = (s_a)_i
+  const T* ST = nullptr;      // [9][ns*ns] transposes
   const T* lam = nullptr;     // [9][ns]
   const T* W = nullptr;       // [9][ns]
   const int* map1d = nullptr; // [9][ns]: (delta+1)*64 + loc, or -1 for padding

@@ -76,8 +76,8 @@ struct Level {
   // Schwarz
   int* nb27 = nullptr;
   int8_t* var = nullptr;
-  double *gco = nullptr, *S = nullptr, *lam = nullptr, *W = nullptr, *O = nullptr;
-  float *gco32 = nullptr, *S32 = nullptr, *lam32 = nullptr, *W32 = nullptr, *O32 = nullptr;
+  double *gco = nullptr, *S = nullptr, *ST = nullptr, *lam = nullptr, *W = nullptr, *O = nullptr;
+  float *gco32 = nullptr, *S32 = nullptr, *ST32 = nullptr, *lam32 = nullptr, *W32 = nullptr, *O32 = nullptr;
   int* map1d = nullptr;
   // transfer matrices to the next coarser level (this = fine)
   double *Pm = nullptr, *Im = nullptr, *Rm = nullptr;
@@ -333,9 +333,9 @@ SchwarzArgs<T> Solver::sz_args(Level& L, const T* r, T* z, int mode) {
   a.var = L.var;
   a.map1d = L.map1d;
   if constexpr (sizeof(T) == 8) {
-    a.O = L.O; a.gco = L.gco; a.S = L.S; a.lam = L.lam; a.W = L.W;
+    a.O = L.O; a.gco = L.gco; a.S = L.S; a.ST = L.ST; a.lam = L.lam; a.W = L.W;
   } else {
-    a.O = L.O32; a.gco = L.gco32; a.S = L.S32; a.lam = L.lam32; a.W = L.W32;
+    a.O = L.O32; a.gco = L.gco32; a.S = L.S32; a.ST = L.ST32; a.lam = L.lam32; a.W = L.W32;
   }
   return a;
 }
@@ -414,7 +414,12 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
         map[v * NS + i] = (t.delta[i] + 1) * 64 + t.loc[i];
       }
     }
+  std::vector<double> ST(S.size());
+  for (int v = 0; v < 9; ++v)
+    for (int i = 0; i < NS; ++i)
+      for (int a = 0; a < NS; ++a) ST[v * NS * NS + a * NS + i] = S[v * NS * NS + i * NS + a];
   L.S = s.own(upload(S, st)); L.S32 = s.own(upload(to_float(S), st));
+  L.ST = s.own(upload(ST, st)); L.ST32 = s.own(upload(to_float(ST), st));
   L.lam = s.own(upload(lam, st)); L.lam32 = s.own(upload(to_float(lam), st));
   L.W = s.own(upload(W, st)); L.W32 = s.own(upload(to_float(W), st));
   L.map1d = s.own(upload(map, st));
