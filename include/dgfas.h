@@ -73,7 +73,10 @@ typedef struct {
   int32_t precision;        /* DGFAS_FP64, or DGFAS_FP32: smoothing of the correction system
                                (eq. smoothers:system:correction) in FP32 on levels > 1 with the
                                FAS residual, tau-correction and root solve in FP64 */
-  int32_t reserved[7];
+  int32_t n_rhs;            /* right-hand sides solved together, 1..64: every vector argument is then
+                               [n_rhs][n_dof] (each right-hand side contiguous) and every SCG scalar is
+                               kept per right-hand side; the geometry is shared */
+  int32_t reserved[6];
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);
@@ -137,14 +140,16 @@ dgfas_status dgfas_root_solve(dgfas_solver s, double* u, const double* g, int32_
 /* One FAS V-cycle (Alg. 2, global p-coarsening) on the finest-level u for rhs f. */
 dgfas_status dgfas_vcycle(dgfas_solver s, double* u, const double* f);
 
-/* FAS V-cycles until ||f - A u|| <= rtol ||f - A u_0|| or max_cycles.
- * hist (host, may be NULL) receives max_cycles+1 relative residuals (entry 0 = 1);
+/* FAS V-cycles until ||f - A u|| <= rtol ||f - A u_0|| for every right-hand side, or max_cycles.
+ * hist (host, may be NULL) receives max_cycles+1 relative residuals, the largest over the
+ * right-hand sides (entry 0 = 1);
  * n_done (host, may be NULL) the number of cycles run.  Synchronises once per cycle.
  * Returns DGFAS_ENOTCONV (a warning) if the tolerance was not reached. */
 dgfas_status dgfas_solve(dgfas_solver s, double* u, const double* f, int32_t max_cycles, double rtol,
                          double* hist, int32_t* n_done);
 
-/* Euclidean norm of a level-l vector, written to a host double.  Synchronous. */
+/* Euclidean norm of a level-l vector per right-hand side, written to out (host, n_rhs doubles).
+ * Synchronous. */
 dgfas_status dgfas_norm(dgfas_solver s, int32_t level, const double* v, double* out);
 
 /* Message of the last failed call on this thread. */

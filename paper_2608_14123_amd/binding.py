@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
     _fields_ = [('kappa', ctypes.c_double), ('nu', ctypes.c_double), ('mu_star', ctypes.c_double),
                 ('overlap', ctypes.c_int32), ('smoother', ctypes.c_int32), ('ns1', ctypes.c_int32),
                 ('ns2', ctypes.c_int32), ('root_max_iter', ctypes.c_int32), ('root_rtol', ctypes.c_double),
-                ('precision', ctypes.c_int32), ('reserved', ctypes.c_int32 * 7)]
+                ('precision', ctypes.c_int32), ('n_rhs', ctypes.c_int32), ('reserved', ctypes.c_int32 * 6)]
 
 
 class DgfasError(RuntimeError):
@@ -202,6 +202,7 @@ class Solver:
         return hist[:nd.value + 1], code == DGFAS_OK
 
     def norm(self, level, v):
-        out = ctypes.c_double()
-        _check(_lib.dgfas_norm(self._h, level, _ptr(v), ctypes.byref(out)))
-        return out.value
+        """Euclidean norm per right-hand side (numpy array of n_rhs values)."""
+        out = np.zeros(self.options.n_rhs)
+        _check(_lib.dgfas_norm(self._h, level, _ptr(v), out.ctypes.data_as(c_dp)))
+        return out

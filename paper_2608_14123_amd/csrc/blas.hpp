@@ -7,15 +7,19 @@ namespace dgfas {
 
 enum { kOpGamma = 0, kOpBeta = 1, kOpAlpha = 2, kOpNorm2 = 3, kOpStore = 4 };
 
-// second-stage reduction of one (or, for kOpBeta, two: partial[0..] and partial[1024..]) sums
-void finish(int nblocks, const double* partial, int op, double* scal, double* out, hipStream_t st);
+// All vectors are [nrhs][n]; partial sums live at partial[rhs * 1024 + block] and the SCG
+// scalars at scal[rhs * 8 + k].
+// second-stage reduction of one (or, for kOpBeta, two: partial and partial2) sums per rhs
+void finish(int nblocks, int nrhs, const double* partial, const double* partial2, int op, double* scal, double* out,
+            hipStream_t st);
 template <typename T>
-void pupdate(int64_t n, const T* z, T* p, const double* scal, int first, hipStream_t st);
+void pupdate(int64_t n, int nrhs, const T* z, T* p, const double* scal, int first, hipStream_t st);
 template <typename T>
-void cg_update(int64_t n, T* r, T* r0, const T* q, T* u, const T* p, const double* scal, double* partial,
+void cg_update(int64_t n, int nrhs, T* r, T* r0, const T* q, T* u, const T* p, const double* scal, double* partial,
                int nblocks, hipStream_t st);
 template <typename T>
-void dot_partials(int64_t n, const T* a, const T* b, const T* c, double* partial, int nblocks, hipStream_t st);
+void dot_partials(int64_t n, int nrhs, const T* a, const T* b, const T* c, double* partial, int nblocks,
+                  hipStream_t st);
 template <typename TI, typename TO>
 void convert(int64_t n, const TI* x, TO* y, int accumulate, hipStream_t st);
 void fill(int64_t n, double* y, double v, hipStream_t st);

@@ -107,12 +107,18 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return sh[0];
 }
 
-// partial[blk] = sum_i a_i (b_i - c_i)   (b, c may be null: b := a, c := 0); FP64 accumulation
+// Batched reductions: vectors are [nrhs][n]; block (blk, rhs) writes
+// partial[rhs * 1024 + blk] = sum_i a_i (b_i - c_i) over its strided share of right-hand
+// side rhs (b, c may be null: b := a, c := 0), accumulated in FP64.
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
 dot_partial_kernel(int64_t n, const T* __restrict__ a, const T* __restrict__ b, const T* __restrict__ c,
                    double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
+  const int64_t off = (int64_t)blockIdx.y * n;
+  a += off;
+  if (b) b += off;
+  if (c) c += off;
   double s = 0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
@@ -120,82 +126,92 @@ dot_partial_kernel(int64_t n, const T* __restrict__ a, const T* __restrict__ b, 
     s += (double)a[i] * (c ? bv - (double)c[i] : bv);
   }
   const double t = block_sum(s, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[blockIdx.y * 1024 + blockIdx.x] = t;
 }
 
 template <typename T>
-void dot_partials(int64_t n, const T* a, const T* b, const T* c, double* partial, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((dot_partial_kernel<T>), dim3(nblocks), dim3(kRedThreads), 0, st, n, a, b, c, partial);
+void dot_partials(int64_t n, int nrhs, const T* a, const T* b, const T* c, double* partial, int nblocks,
+                  hipStream_t st) {
+  hipLaunchKernelGGL((dot_partial_kernel<T>), dim3(nblocks, nrhs), dim3(kRedThreads), 0, st, n, a, b, c, partial);
 }
-template void dot_partials<double>(int64_t, const double*, const double*, const double*, double*, int, hipStream_t);
-template void dot_partials<float>(int64_t, const float*, const float*, const float*, double*, int, hipStream_t);
+template void dot_partials<double>(int64_t, int, const double*, const double*, const double*, double*, int,
+                                   hipStream_t);
+template void dot_partials<float>(int64_t, int, const float*, const float*, const float*, double*, int, hipStream_t);
 
-// Second stage: one block sums the partials of `nvals` reductions (stride 1024),
-// then applies the SCG scalar update selected by `op`.
-//   scal: [0] gamma (z^T r)  [1] beta  [2] alpha  [3] r^T r  [4] breakdown flag  [5] p^T q
-__global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double* __restrict__ partial, int op,
+// Second stage, one block per right-hand side: sums its partials (for kOpBeta also the
+// second set at partial2) and applies the SCG scalar update selected by `op`.
+//   scal[rhs * 8 + k]: 0 gamma (z^T r)  1 beta  2 alpha  3 r^T r  4 breakdown flag  5 p^T q
+__global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double* __restrict__ partial,
+                                                      const double* __restrict__ partial2, int op,
                                                       double* __restrict__ scal, double* __restrict__ out) {
   __shared__ double sh[1024];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, rhs = blockIdx.x;
   double v0 = 0, v1 = 0;
   for (int b = tid; b < nblocks; b += 1024) {
-    v0 += partial[b];
-    v1 += partial[1024 + b];
+    v0 += partial[rhs * 1024 + b];
+    if (op == kOpBeta) v1 += partial2[rhs * 1024 + b];
   }
   const double s0 = block_sum(v0, sh);
   __syncthreads();
   const double s1 = (op == kOpBeta) ? block_sum(v1, sh) : 0.0;
   if (tid != 0) return;
+  double* sc = scal + rhs * 8;
   switch (op) {
     case kOpGamma:          // first iteration: gamma = z^T r
-      scal[0] = s0;
-      scal[1] = 0.0;
+      sc[0] = s0;
+      sc[1] = 0.0;
       break;
     case kOpBeta: {         // beta = z^T (r - r0) / gamma_old ; gamma = z^T r
-      const double beta = s1 / scal[0];
-      scal[1] = beta;
-      scal[0] = s0;
-      if (!isfinite(beta)) scal[4] = 1.0;
+      const double beta = s1 / sc[0];
+      sc[1] = isfinite(beta) ? beta : 0.0;
+      sc[0] = s0;
+      if (!isfinite(beta)) sc[4] = 1.0;
       break;
     }
-    case kOpAlpha: {        // alpha = gamma / p^T q
-      scal[5] = s0;
-      const double alpha = scal[0] / s0;
-      scal[2] = alpha;
-      if (!(s0 > 0.0) || !isfinite(alpha)) { scal[4] = 1.0; scal[2] = 0.0; }
+    case kOpAlpha: {        // alpha = gamma / p^T q; a converged right-hand side (p = 0) takes alpha = 0
+      sc[5] = s0;
+      double alpha = (s0 != 0.0) ? sc[0] / s0 : 0.0;
+      if (s0 < 0.0 || !isfinite(alpha)) { sc[4] = 1.0; alpha = 0.0; }
+      sc[2] = alpha;
       break;
     }
     case kOpNorm2:          // r^T r
-      scal[3] = s0;
-      if (!isfinite(s0)) scal[4] = 1.0;
+      sc[3] = s0;
+      if (!isfinite(s0)) sc[4] = 1.0;
       break;
     case kOpStore:
-      out[0] = s0;
+      out[rhs] = s0;
       break;
   }
 }
 
-void finish(int nblocks, const double* partial, int op, double* scal, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, st, nblocks, partial, op, scal, out);
+void finish(int nblocks, int nrhs, const double* partial, const double* partial2, int op, double* scal, double* out,
+            hipStream_t st) {
+  hipLaunchKernelGGL(finish_kernel, dim3(nrhs), dim3(1024), 0, st, nblocks, partial, partial2, op, scal, out);
 }
 
-// p = beta p + z   (first: p = z)
+// p = beta p + z   (first: p = z), per right-hand side beta
 template <typename T>
-__global__ void pupdate_kernel(int64_t n, const T* __restrict__ z, T* __restrict__ p,
+__global__ void pupdate_kernel(int64_t n, int nrhs, const T* __restrict__ z, T* __restrict__ p,
                                const double* __restrict__ scal, int first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  p[i] = first ? z[i] : (T)scal[1] * p[i] + z[i];
+  if (i >= n * nrhs) return;
+  const int rhs = (int)(i / n);
+  p[i] = first ? z[i] : (T)scal[rhs * 8 + 1] * p[i] + z[i];
 }
 
-// r0 = r; r -= alpha q; u += alpha p; partial[blk] = sum r^2
+// r0 = r; r -= alpha q; u += alpha p; partial[rhs*1024 + blk] = sum r^2
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
 cg_update_kernel(int64_t n, T* __restrict__ r, T* __restrict__ r0, const T* __restrict__ q,
                  T* __restrict__ u, const T* __restrict__ p, const double* __restrict__ scal,
                  double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
-  const T alpha = (T)scal[2];
+  const int rhs = blockIdx.y;
+  const int64_t off = (int64_t)rhs * n;
+  r += off; q += off; u += off; p += off;
+  if (r0) r0 += off;
+  const T alpha = (T)scal[rhs * 8 + 2];
   double s = 0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
@@ -207,26 +223,28 @@ cg_update_kernel(int64_t n, T* __restrict__ r, T* __restrict__ r0, const T* __re
     s += (double)rn * (double)rn;
   }
   const double t = block_sum(s, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[rhs * 1024 + blockIdx.x] = t;
 }
 
 template <typename T>
-void pupdate(int64_t n, const T* z, T* p, const double* scal, int first, hipStream_t st) {
-  hipLaunchKernelGGL((pupdate_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, z, p, scal, first);
+void pupdate(int64_t n, int nrhs, const T* z, T* p, const double* scal, int first, hipStream_t st) {
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL((pupdate_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nrhs, z, p, scal,
+                     first);
 }
 
 template <typename T>
-void cg_update(int64_t n, T* r, T* r0, const T* q, T* u, const T* p, const double* scal, double* partial,
+void cg_update(int64_t n, int nrhs, T* r, T* r0, const T* q, T* u, const T* p, const double* scal, double* partial,
                int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblocks), dim3(kRedThreads), 0, st, n, r, r0, q, u, p, scal,
+  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblocks, nrhs), dim3(kRedThreads), 0, st, n, r, r0, q, u, p, scal,
                      partial);
 }
-template void pupdate<double>(int64_t, const double*, double*, const double*, int, hipStream_t);
-template void pupdate<float>(int64_t, const float*, float*, const double*, int, hipStream_t);
-template void cg_update<double>(int64_t, double*, double*, const double*, double*, const double*, const double*,
+template void pupdate<double>(int64_t, int, const double*, double*, const double*, int, hipStream_t);
+template void pupdate<float>(int64_t, int, const float*, float*, const double*, int, hipStream_t);
+template void cg_update<double>(int64_t, int, double*, double*, const double*, double*, const double*, const double*,
                                 double*, int, hipStream_t);
-template void cg_update<float>(int64_t, float*, float*, const float*, float*, const float*, const double*, double*,
-                               int, hipStream_t);
+template void cg_update<float>(int64_t, int, float*, float*, const float*, float*, const float*, const double*,
+                               double*, int, hipStream_t);
 
 // y = x (with optional conversion) / y += x
 template <typename TI, typename TO>

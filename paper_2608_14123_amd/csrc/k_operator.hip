@@ -25,21 +25,28 @@ struct OpShape {
 
 template <int N, typename T>
 __global__ void __launch_bounds__(OpShape<N>::THREADS)
-sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __restrict__ out, int mode,
+sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict__ g, T* __restrict__ out, int mode,
                   const T* __restrict__ G, const T* __restrict__ WJ, const T* __restrict__ pen,
                   const int* __restrict__ nbr, const int8_t* __restrict__ bc, const T* __restrict__ Dg,
                   T kappa, T inv_wend) {
   using S = OpShape<N>;
   constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
   constexpr int TPT = (6 * N2 + N3 - 1) / N3;     // face tasks per thread
-  const int lb = xcd_block((E + EPB - 1) / EPB);
-  if (lb < 0) return;
+  // logical block = (element block, right-hand side) with the right-hand side fastest, so
+  // that the batch of one element reads its geometry while it is resident in L2
+  const int lbr = xcd_block(((E + EPB - 1) / EPB) * nrhs);
+  if (lbr < 0) return;
+  const int lb = lbr / nrhs;
+  const int64_t ndof = (int64_t)E * N3;
+  const int64_t voff = (int64_t)(lbr - lb * nrhs) * ndof;
+  u += voff;
+  out += voff;
+  if (g) g += voff;
   const int tid = threadIdx.x;
   const int le = tid / N3;
   const int node = tid - le * N3;
   const int e = lb * EPB + le;
   const bool active = (le < EPB) && (e < E);
-  const int64_t ndof = (int64_t)E * N3;
 
   __shared__ T sD[N2];
   __shared__ T su[EPB][N3];
@@ -198,8 +205,8 @@ sipg_apply_kernel(int E, const T* __restrict__ u, const T* __restrict__ g, T* __
 template <int N, typename T>
 void launch_sipg(const OpArgs<T>& a, hipStream_t st) {
   using S = OpShape<N>;
-  const int nb = (a.E + S::EPB - 1) / S::EPB;
-  hipLaunchKernelGGL((sipg_apply_kernel<N, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a.E, a.u, a.g,
+  const int nb = ((a.E + S::EPB - 1) / S::EPB) * a.nrhs;
+  hipLaunchKernelGGL((sipg_apply_kernel<N, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a.E, a.nrhs, a.u, a.g,
                      a.out, a.mode, a.G, a.WJ, a.pen, a.nbr, a.bc, a.D, a.kappa, a.inv_wend);
 }
 

@@ -53,8 +53,12 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   using Sh = SzShape<N, M>;
   constexpr int NS = Sh::NS, LS = Sh::LS, N3 = N * N * N, THR = Sh::THREADS;
   constexpr Regions<N, M> R{};
-  const int e = xcd_block(a.E);
-  if (e < 0) return;
+  const int lbr = xcd_block(a.E * a.nrhs);
+  if (lbr < 0) return;
+  const int e = lbr / a.nrhs, rhs = lbr - e * a.nrhs;   // right-hand side fastest
+  a.r += (int64_t)rhs * a.E * N3;
+  a.z += (int64_t)rhs * a.E * N3;
+  a.O += (int64_t)rhs * a.E * R.size;
   const int tid = threadIdx.x;
 
   __shared__ T tA[Sh::TILE];
@@ -243,8 +247,11 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
   using Sh = AddShape<N>;
   constexpr int N3 = Sh::N3, EPB = Sh::EPB;
   constexpr Regions<N, M> R{};
-  const int lb = xcd_block((a.E + EPB - 1) / EPB);
-  if (lb < 0) return;
+  const int lbr = xcd_block(((a.E + EPB - 1) / EPB) * a.nrhs);
+  if (lbr < 0) return;
+  const int lb = lbr / a.nrhs, rhs = lbr - lb * a.nrhs;
+  a.z += (int64_t)rhs * a.E * N3;
+  a.O += (int64_t)rhs * a.E * R.size;
   const int tid = threadIdx.x;
   __shared__ int sOff[27];
   if (tid < 27) sOff[tid] = R.off[tid];
@@ -292,13 +299,14 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
 
 template <int N, int M, typename T>
 void launch_schwarz(const SchwarzArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL((schwarz_solve_kernel<N, M, T>), dim3(xcd_grid(a.E)), dim3(SzShape<N, M>::THREADS), 0, st, a);
+  hipLaunchKernelGGL((schwarz_solve_kernel<N, M, T>), dim3(xcd_grid(a.E * a.nrhs)), dim3(SzShape<N, M>::THREADS), 0,
+                     st, a);
 }
 
 template <int N, int M, typename T>
 void launch_overlap(const SchwarzArgs<T>& a, hipStream_t st) {
   using Sh = AddShape<N>;
-  const int nb = (a.E + Sh::EPB - 1) / Sh::EPB;
+  const int nb = ((a.E + Sh::EPB - 1) / Sh::EPB) * a.nrhs;
   hipLaunchKernelGGL((schwarz_overlap_add_kernel<N, M, T>), dim3(xcd_grid(nb)), dim3(Sh::THREADS), 0, st, a);
 }
 

@@ -8,6 +8,7 @@ namespace dgfas {
 template <typename T>
 struct OpArgs {
   int E = 0;
+  int nrhs = 1;               // vectors are [nrhs][E (p+1)^3]
   const T* u = nullptr;
   const T* g = nullptr;
   T* out = nullptr;
@@ -36,6 +37,7 @@ void penalty(int E, int p, double mu_star, double nu, const int* nbr, const int8
 template <typename T>
 struct SchwarzArgs {
   int E = 0;
+  int nrhs = 1;               // vectors are [nrhs][E (p+1)^3], inbox [nrhs][E][osz]
   const T* r = nullptr;       // input residual
   T* z = nullptr;             // output (mode 0: z = own part; mode 1: z += own part)
   int mode = 0;

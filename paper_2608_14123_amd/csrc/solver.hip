@@ -103,8 +103,10 @@ struct Solver {
   std::vector<int> h_nbr;
   std::vector<int8_t> h_bc;
   std::vector<Level> lv;   // lv[0] = root (level 1)
-  double* partial = nullptr;
-  double* scal = nullptr;
+  int nrhs = 1;            // right-hand sides per batch; vectors are [nrhs][ndof]
+  double* partial = nullptr;   // [2][nrhs][1024] first-stage sums
+  double* scal = nullptr;      // [nrhs][8] SCG scalars
+  double* partial2() { return partial + (size_t)1024 * nrhs; }
   double* scratch = nullptr;
   std::vector<void*> owned;
 
@@ -168,21 +170,22 @@ struct Solver {
   void was_mixed(Level& L, double* u, const double* g, int n) {
     if (n <= 0) return;
     residual(L, u, g, L.r);
-    convert<double, float>(L.ndof, L.r, L.r32, 0, st);
+    convert<double, float>(L.ndof * nrhs, L.r, L.r32, 0, st);
     schwarz32(L, L.r32, L.du32, 0);
     for (int i = 1; i < n; ++i) {
       residual32(L, L.du32, L.r32, L.rc32);
       schwarz32(L, L.rc32, L.du32, 1);
     }
-    convert<float, double>(L.ndof, L.du32, u, 1, st);
+    convert<float, double>(L.ndof * nrhs, L.du32, u, 1, st);
   }
 
-  double dot_sync(Level& L, const double* a, const double* b) {
+  // per right-hand side dot products a^T b, synchronously
+  std::vector<double> dots_sync(Level& L, const double* a, const double* b) {
     const int nb = reduction_blocks(L.ndof);
-    dot_partials<double>(L.ndof, a, b, nullptr, partial, nb, st);
-    finish(nb, partial, kOpStore, scal, scratch, st);
-    double h = 0;
-    HIPC(hipMemcpyAsync(&h, scratch, sizeof(double), hipMemcpyDeviceToHost, st));
+    dot_partials<double>(L.ndof, nrhs, a, b, nullptr, partial, nb, st);
+    finish(nb, nrhs, partial, nullptr, kOpStore, scal, scratch, st);
+    std::vector<double> h(nrhs);
+    HIPC(hipMemcpyAsync(h.data(), scratch, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     return h;
   }
@@ -197,45 +200,54 @@ struct Solver {
   void schwarz_t(Level& L, const double* r, double* z, int mode) { schwarz(L, r, z, mode); }
   void schwarz_t(Level& L, const float* r, float* z, int mode) { schwarz32(L, r, z, mode); }
 
-  // Alg. 6 with p = z in the first iteration.  r_max <= 0: exactly n iterations, no sync.
+  // Alg. 6 with p = z in the first iteration, every right-hand side with its own scalars.
+  // r_max empty: exactly n iterations, no synchronisation; otherwise stop once
+  // ||r_k|| <= r_max[k] for every right-hand side k (one synchronisation per iteration).
   // zero_start: x = 0 and r = f without an operator application (correction form).
   template <typename T>
-  int scg(Level& L, T* x, const T* f, int n, double r_max, bool* breakdown, bool zero_start = false) {
+  int scg(Level& L, T* x, const T* f, int n, const std::vector<double>& r_max, bool* breakdown,
+          bool zero_start = false) {
     const int nb = reduction_blocks(L.ndof);
+    const int64_t nv = L.ndof * nrhs;
     T *r, *z, *pv, *q, *r0;
     L.scg_vectors<T>(r, z, pv, q, r0);
     if (zero_start) {
-      fill(L.ndof, x, (T)0, st);
-      convert<T, T>(L.ndof, f, r, 0, st);
+      fill(nv, x, (T)0, st);
+      convert<T, T>(nv, f, r, 0, st);
     } else {
       residual_t(L, x, f, r);
     }
-    HIPC(hipMemsetAsync(scal, 0, 8 * sizeof(double), st));
+    HIPC(hipMemsetAsync(scal, 0, (size_t)8 * nrhs * sizeof(double), st));
+    std::vector<double> h((size_t)8 * nrhs);
     int it = 0;
     for (int i = 1; i <= n; ++i) {
       schwarz_t(L, r, z, 0);
       if (i > 1) {
-        dot_partials<T>(L.ndof, z, r, nullptr, partial, nb, st);
-        dot_partials<T>(L.ndof, z, r, r0, partial + 1024, nb, st);
-        finish(nb, partial, kOpBeta, scal, nullptr, st);
-        pupdate<T>(L.ndof, z, pv, scal, 0, st);
+        dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
+        dot_partials<T>(L.ndof, nrhs, z, r, r0, partial2(), nb, st);
+        finish(nb, nrhs, partial, partial2(), kOpBeta, scal, nullptr, st);
+        pupdate<T>(L.ndof, nrhs, z, pv, scal, 0, st);
       } else {
-        dot_partials<T>(L.ndof, z, r, nullptr, partial, nb, st);
-        finish(nb, partial, kOpGamma, scal, nullptr, st);
-        pupdate<T>(L.ndof, z, pv, scal, 1, st);
+        dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
+        finish(nb, nrhs, partial, nullptr, kOpGamma, scal, nullptr, st);
+        pupdate<T>(L.ndof, nrhs, z, pv, scal, 1, st);
       }
       apply_t(L, pv, q);
-      dot_partials<T>(L.ndof, pv, q, nullptr, partial, nb, st);
-      finish(nb, partial, kOpAlpha, scal, nullptr, st);
-      cg_update<T>(L.ndof, r, r0, q, x, pv, scal, partial, nb, st);
-      finish(nb, partial, kOpNorm2, scal, nullptr, st);
+      dot_partials<T>(L.ndof, nrhs, pv, q, nullptr, partial, nb, st);
+      finish(nb, nrhs, partial, nullptr, kOpAlpha, scal, nullptr, st);
+      cg_update<T>(L.ndof, nrhs, r, r0, q, x, pv, scal, partial, nb, st);
+      finish(nb, nrhs, partial, nullptr, kOpNorm2, scal, nullptr, st);
       it = i;
-      if (r_max > 0) {
-        double h[5];
-        HIPC(hipMemcpyAsync(h, scal, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+      if (!r_max.empty()) {
+        HIPC(hipMemcpyAsync(h.data(), scal, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPC(hipStreamSynchronize(st));
-        if (h[4] != 0.0) { if (breakdown) *breakdown = true; break; }
-        if (std::sqrt(h[3]) <= r_max) break;
+        bool done = true, bad = false;
+        for (int k = 0; k < nrhs; ++k) {
+          bad = bad || h[k * 8 + 4] != 0.0;
+          done = done && std::sqrt(h[k * 8 + 3]) <= r_max[k];
+        }
+        if (bad) { if (breakdown) *breakdown = true; break; }
+        if (done) break;
       }
     }
     return it;
@@ -245,9 +257,9 @@ struct Solver {
   // on A du = r in FP32 from du = 0, u += du (FP64).
   void scg_mixed(Level& L, double* u, const double* g, int n) {
     residual(L, u, g, L.r);
-    convert<double, float>(L.ndof, L.r, L.r32, 0, st);
-    scg<float>(L, L.du32, L.r32, n, 0.0, nullptr, true);
-    convert<float, double>(L.ndof, L.du32, u, 1, st);
+    convert<double, float>(L.ndof * nrhs, L.r, L.r32, 0, st);
+    scg<float>(L, L.du32, L.r32, n, {}, nullptr, true);
+    convert<float, double>(L.ndof * nrhs, L.du32, u, 1, st);
   }
 
   void smooth(Level& L, double* u, const double* g, int n) {
@@ -255,7 +267,7 @@ struct Solver {
     const bool mixed = opt.precision == DGFAS_FP32;
     if (opt.smoother == DGFAS_SCG) {
       if (mixed) scg_mixed(L, u, g, n);
-      else scg<double>(L, u, g, n, 0.0, nullptr);
+      else scg<double>(L, u, g, n, {}, nullptr);
     } else if (mixed) {
       was_mixed(L, u, g, n);
     } else {
@@ -266,9 +278,14 @@ struct Solver {
   int root_solve(double* u, const double* g, bool* breakdown) {
     Level& L = lv[0];
     residual(L, u, g, L.r);
-    const double r0 = std::sqrt(dot_sync(L, L.r, L.r));
-    if (r0 == 0.0) return 0;
-    return scg<double>(L, u, g, opt.root_max_iter, opt.root_rtol * r0, breakdown);
+    std::vector<double> rmax = dots_sync(L, L.r, L.r);
+    bool any = false;
+    for (double& v : rmax) {
+      v = opt.root_rtol * std::sqrt(v);
+      any = any || v > 0.0;
+    }
+    if (!any) return 0;
+    return scg<double>(L, u, g, opt.root_max_iter, rmax, breakdown);
   }
 
   // Alg. 2 with global p-coarsening.
@@ -285,16 +302,16 @@ struct Solver {
       Level& C = lv[l - 1];
       smooth(F, F.u, F.g, opt.ns1);
       residual(F, F.u, F.g, F.r);
-      xfer<double>(F.n, C.n, C.E, F.Pm, F.u, nullptr, C.ubar, 0, st);        // ubar = P u
-      HIPC(hipMemcpyAsync(C.u, C.ubar, C.ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+      xfer<double>(F.n, C.n, C.E * nrhs, F.Pm, F.u, nullptr, C.ubar, 0, st);   // ubar = P u
+      HIPC(hipMemcpyAsync(C.u, C.ubar, C.ndof * nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       apply(C, C.ubar, C.g);                                                     // g = A ubar
-      xfer<double>(F.n, C.n, C.E, F.Rm, F.r, nullptr, C.g, 1, st);           //   + R r
+      xfer<double>(F.n, C.n, C.E * nrhs, F.Rm, F.r, nullptr, C.g, 1, st);      //   + R r
     }
     root_solve(lv[0].u, lv[0].g, &bd);
     for (int l = 1; l < Lc; ++l) {
       Level& F = lv[l];
       Level& C = lv[l - 1];
-      xfer<double>(C.n, F.n, C.E, F.Im, C.u, C.ubar, F.u, 1, st);          // u += I (u_c - ubar)
+      xfer<double>(C.n, F.n, C.E * nrhs, F.Im, C.u, C.ubar, F.u, 1, st);   // u += I (u_c - ubar)
       smooth(F, F.u, F.g, opt.ns2);
     }
     T.u = u_save;
@@ -306,6 +323,7 @@ template <typename T>
 OpArgs<T> Solver::op_args(Level& L, int mode, const T* u, const T* g, T* out) {
   OpArgs<T> a;
   a.E = L.E;
+  a.nrhs = nrhs;
   a.u = u;
   a.g = g;
   a.out = out;
@@ -326,6 +344,7 @@ template <typename T>
 SchwarzArgs<T> Solver::sz_args(Level& L, const T* r, T* z, int mode) {
   SchwarzArgs<T> a;
   a.E = L.E;
+  a.nrhs = nrhs;
   a.r = r;
   a.z = z;
   a.mode = mode;
@@ -448,28 +467,35 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
   L.var = s.own(upload(var, st));
   L.nb27 = s.own(upload(nb27, st));
   const int osz = overlap_size(p, L.m);
-  L.O = s.own(dalloc<double>((size_t)L.E * osz));
-  L.O32 = s.own(dalloc<float>((size_t)L.E * osz));
+  const size_t nin = (size_t)L.E * osz * s.nrhs;
+  const bool fp32 = s.opt.precision == DGFAS_FP32;
+  L.O = s.own(dalloc<double>(nin));
+  if (fp32) L.O32 = s.own(dalloc<float>(nin));
   // inbox regions of absent neighbours are never written and must read as zero
   if (osz) {
-    HIPC(hipMemsetAsync(L.O, 0, (size_t)L.E * osz * sizeof(double), st));
-    HIPC(hipMemsetAsync(L.O32, 0, (size_t)L.E * osz * sizeof(float), st));
+    HIPC(hipMemsetAsync(L.O, 0, nin * sizeof(double), st));
+    if (fp32) HIPC(hipMemsetAsync(L.O32, 0, nin * sizeof(float), st));
   }
   // work vectors
-  L.r = s.own(dalloc<double>(L.ndof));
-  L.z = s.own(dalloc<double>(L.ndof));
-  L.pv = s.own(dalloc<double>(L.ndof));
-  L.q = s.own(dalloc<double>(L.ndof));
-  L.r0 = s.own(dalloc<double>(L.ndof));
-  if (s.opt.precision == DGFAS_FP32) {
-    L.r32 = s.own(dalloc<float>(L.ndof));
-    L.du32 = s.own(dalloc<float>(L.ndof));
-    L.rc32 = s.own(dalloc<float>(L.ndof));
+  const size_t nv = (size_t)L.ndof * s.nrhs;
+  L.r = s.own(dalloc<double>(nv));
+  const bool scg_here = s.opt.smoother == DGFAS_SCG || &L == &s.lv[0];
+  const bool dbl_scg = scg_here && !(fp32 && &L != &s.lv[0]);
+  if (dbl_scg || !fp32) L.z = s.own(dalloc<double>(nv));
+  if (dbl_scg) {
+    L.pv = s.own(dalloc<double>(nv));
+    L.q = s.own(dalloc<double>(nv));
+    L.r0 = s.own(dalloc<double>(nv));
+  }
+  if (fp32 && &L != &s.lv[0]) {
+    L.r32 = s.own(dalloc<float>(nv));
+    L.du32 = s.own(dalloc<float>(nv));
+    L.rc32 = s.own(dalloc<float>(nv));
     if (s.opt.smoother == DGFAS_SCG) {
-      L.z32 = s.own(dalloc<float>(L.ndof));
-      L.p32 = s.own(dalloc<float>(L.ndof));
-      L.q32 = s.own(dalloc<float>(L.ndof));
-      L.r0_32 = s.own(dalloc<float>(L.ndof));
+      L.z32 = s.own(dalloc<float>(nv));
+      L.p32 = s.own(dalloc<float>(nv));
+      L.q32 = s.own(dalloc<float>(nv));
+      L.r0_32 = s.own(dalloc<float>(nv));
     }
   }
   HIPC(hipStreamSynchronize(st));
@@ -499,6 +525,8 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
   if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32) throw Error(DGFAS_EINVAL, "unknown precision");
+  if (o->n_rhs < 1 || o->n_rhs > 64) throw Error(DGFAS_EINVAL, "n_rhs must be 1..64");
+  if ((int64_t)m->n_elem * o->n_rhs > (int64_t)1 << 30) throw Error(DGFAS_EUNSUPPORTED, "n_elem * n_rhs too large");
 }
 
 Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
@@ -515,9 +543,10 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
       if (s->h_nbr[e * 6 + f] >= 0) s->h_bc[e * 6 + f] = DGFAS_INTERIOR;
   s->nbr = s->own(upload(s->h_nbr, s->st));
   s->bc = s->own(upload(s->h_bc, s->st));
-  s->partial = s->own(dalloc<double>(2048));
-  s->scal = s->own(dalloc<double>(8));
-  s->scratch = s->own(dalloc<double>(8));
+  s->nrhs = o->n_rhs;
+  s->partial = s->own(dalloc<double>((size_t)2048 * s->nrhs));
+  s->scal = s->own(dalloc<double>((size_t)8 * s->nrhs));
+  s->scratch = s->own(dalloc<double>((size_t)8 * s->nrhs));
   std::vector<int> chain{p};
   while (chain.back() > 1) chain.push_back(std::max(1, chain.back() / 2));
   std::reverse(chain.begin(), chain.end());
@@ -549,9 +578,9 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
     build_level(*s, L, chain[li], X);
     L.X = X;
     if (li < Lc - 1) {
-      L.u = s->own(dalloc<double>(L.ndof));
-      L.g = s->own(dalloc<double>(L.ndof));
-      L.ubar = s->own(dalloc<double>(L.ndof));
+      L.u = s->own(dalloc<double>((size_t)L.ndof * s->nrhs));
+      L.g = s->own(dalloc<double>((size_t)L.ndof * s->nrhs));
+      L.ubar = s->own(dalloc<double>((size_t)L.ndof * s->nrhs));
     }
   }
   HIPC(hipStreamSynchronize(s->st));
@@ -605,6 +634,7 @@ void dgfas_default_options(dgfas_options* o) {
   o->root_max_iter = 500;
   o->root_rtol = 1e-12;
   o->precision = DGFAS_FP64;
+  o->n_rhs = 1;
 }
 
 dgfas_status dgfas_gll(int32_t p, double* x, double* w) {
@@ -665,7 +695,11 @@ dgfas_status dgfas_rhs(dgfas_solver sv, const double* f, const double* uD, const
   Solver* s = S_(sv);
   need(f, "f"); need(b, "b");
   Level& T = s->lv.back();
-  rhs(T.p, T.E, f, uD, qN, b, T.G, T.WJ, T.pen, T.ws, s->nbr, s->bc, T.D, T.inv_wend, s->st);
+  for (int k = 0; k < s->nrhs; ++k) {
+    const int64_t o = (int64_t)k * T.ndof;
+    rhs(T.p, T.E, f + o, uD ? uD + o : nullptr, qN ? qN + o : nullptr, b + o, T.G, T.WJ, T.pen, T.ws, s->nbr, s->bc,
+        T.D, T.inv_wend, s->st);
+  }
   HIPC(hipGetLastError());
   API_END
 }
@@ -714,7 +748,7 @@ dgfas_status dgfas_restrict(dgfas_solver sv, int32_t level, const double* rf, do
   if (level < 2) throw Error(DGFAS_EINVAL, "restrict needs level >= 2");
   Level& F = s->level(level);
   Level& C = s->level(level - 1);
-  xfer<double>(F.n, C.n, C.E, F.Rm, rf, nullptr, rc, 0, s->st);
+  xfer<double>(F.n, C.n, C.E * s->nrhs, F.Rm, rf, nullptr, rc, 0, s->st);
   HIPC(hipGetLastError());
   API_END
 }
@@ -726,7 +760,7 @@ dgfas_status dgfas_project(dgfas_solver sv, int32_t level, const double* uf, dou
   if (level < 2) throw Error(DGFAS_EINVAL, "project needs level >= 2");
   Level& F = s->level(level);
   Level& C = s->level(level - 1);
-  xfer<double>(F.n, C.n, C.E, F.Pm, uf, nullptr, uc, 0, s->st);
+  xfer<double>(F.n, C.n, C.E * s->nrhs, F.Pm, uf, nullptr, uc, 0, s->st);
   HIPC(hipGetLastError());
   API_END
 }
@@ -738,7 +772,7 @@ dgfas_status dgfas_prolong_add(dgfas_solver sv, int32_t level, const double* uc,
   if (level < 2) throw Error(DGFAS_EINVAL, "prolong needs level >= 2");
   Level& F = s->level(level);
   Level& C = s->level(level - 1);
-  xfer<double>(C.n, F.n, C.E, F.Im, uc, ubar, uf, 1, s->st);
+  xfer<double>(C.n, F.n, C.E * s->nrhs, F.Im, uc, ubar, uf, 1, s->st);
   HIPC(hipGetLastError());
   API_END
 }
@@ -772,14 +806,25 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
   if (max_cycles < 0) throw Error(DGFAS_EINVAL, "negative max_cycles");
   Level& T = s->lv.back();
   s->residual(T, u, f, T.r);
-  const double r0 = std::sqrt(s->dot_sync(T, T.r, T.r));
+  std::vector<double> r0 = s->dots_sync(T, T.r, T.r);
+  for (double& v : r0) v = std::sqrt(v);
   if (hist) hist[0] = 1.0;
   int k = 0;
-  bool conv = r0 == 0.0;
+  auto worst = [&](const std::vector<double>& rr) {
+    double w = 0.0;
+    for (int j = 0; j < s->nrhs; ++j) {
+      const double rel = r0[j] > 0.0 ? std::sqrt(rr[j]) / r0[j] : 0.0;
+      if (!std::isfinite(rel)) return rel;
+      w = std::max(w, rel);
+    }
+    return w;
+  };
+  bool conv = worst(std::vector<double>(s->nrhs, 0.0)) == 0.0 &&
+              *std::max_element(r0.begin(), r0.end()) == 0.0;
   while (!conv && k < max_cycles) {
     s->vcycle(u, f);
     s->residual(T, u, f, T.r);
-    const double rk = std::sqrt(s->dot_sync(T, T.r, T.r)) / r0;
+    const double rk = worst(s->dots_sync(T, T.r, T.r));
     ++k;
     if (hist) hist[k] = rk;
     if (!std::isfinite(rk)) throw Error(DGFAS_EBREAKDOWN, "non-finite residual");
@@ -794,7 +839,8 @@ dgfas_status dgfas_norm(dgfas_solver sv, int32_t level, const double* v, double*
   API_BEGIN
   Solver* s = S_(sv);
   need(v, "v"); need(out, "out");
-  *out = std::sqrt(s->dot_sync(s->level(level), v, v));
+  std::vector<double> d = s->dots_sync(s->level(level), v, v);
+  for (int k = 0; k < s->nrhs; ++k) out[k] = std::sqrt(d[k]);
   API_END
 }
 
