@@ -152,6 +152,33 @@ dgfas_status dgfas_solve(dgfas_solver s, double* u, const double* f, int32_t max
  * Synchronous. */
 dgfas_status dgfas_norm(dgfas_solver s, int32_t level, const double* v, double* out);
 
+/* ---- Learned subdomain correction (addition to the paper's method) -------------------
+ * A 3-layer MLP in -> hidden -> hidden -> out, ReLU after the first two layers, BF16
+ * weights with FP32 accumulation on the matrix cores, FP32 master weights.  Parameters
+ * (FP32, one array): W1[in][hidden] b1[hidden] W2[hidden][hidden] b2[hidden]
+ * W3[hidden][out] b3[out].  Device arrays X [rows][in], Y/T [rows][out] are FP32, row-major. */
+typedef struct dgfas_mlp_s* dgfas_mlp;
+
+/* Create with He-normal weights drawn from `seed` and zero biases; stream as in dgfas_create. */
+dgfas_status dgfas_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed, void* stream,
+                              dgfas_mlp* out);
+void dgfas_mlp_destroy(dgfas_mlp m);
+dgfas_status dgfas_mlp_num_params(dgfas_mlp m, int64_t* n);
+/* Host copies of the FP32 master parameters (n_params floats).  set resets Adam. Synchronous. */
+dgfas_status dgfas_mlp_get_params(dgfas_mlp m, float* host);
+dgfas_status dgfas_mlp_set_params(dgfas_mlp m, const float* host);
+/* Y = MLP(X) for `rows` rows. */
+dgfas_status dgfas_mlp_forward(dgfas_mlp m, const float* X, int32_t rows, float* Y);
+/* loss = mean((MLP(X) - T)^2) over rows*out values and its gradient with respect to the
+ * parameters (device, n_params floats; may be NULL).  Synchronous. */
+dgfas_status dgfas_mlp_gradient(dgfas_mlp m, const float* X, const float* T, int32_t rows, float* grad,
+                                double* loss);
+/* `steps` Adam steps (beta 0.9/0.999, eps 1e-8) on consecutive mini-batches of `batch` rows of
+ * (X, T) [n rows], learning rate lr_min + (lr0 - lr_min)(1 + cos(pi t / total_steps))/2 at
+ * global step t; losses (host, may be NULL) receives the loss of every step.  Synchronous. */
+dgfas_status dgfas_mlp_train(dgfas_mlp m, const float* X, const float* T, int64_t n, int32_t batch,
+                             int32_t steps, float lr0, float lr_min, int32_t total_steps, double* losses);
+
 /* Message of the last failed call on this thread. */
 const char* dgfas_last_error(void);
 

@@ -206,3 +206,70 @@ class Solver:
         out = np.zeros(self.options.n_rhs)
         _check(_lib.dgfas_norm(self._h, level, _ptr(v), out.ctypes.data_as(c_dp)))
         return out
+
+
+_mlp_sig = {
+    'dgfas_mlp_create': (_I, [_I, _I, _I, ctypes.c_uint64, _V, ctypes.POINTER(_V)]),
+    'dgfas_mlp_destroy': (None, [_V]),
+    'dgfas_mlp_num_params': (_I, [_V, ctypes.POINTER(ctypes.c_int64)]),
+    'dgfas_mlp_get_params': (_I, [_V, _V]),
+    'dgfas_mlp_set_params': (_I, [_V, _V]),
+    'dgfas_mlp_forward': (_I, [_V, _V, _I, _V]),
+    'dgfas_mlp_gradient': (_I, [_V, _V, _V, _I, _V, c_dp]),
+    'dgfas_mlp_train': (_I, [_V, _V, _V, ctypes.c_int64, _I, _I, ctypes.c_float, ctypes.c_float, _I, c_dp]),
+}
+for _name, (_res, _args) in _mlp_sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+EXPORTED = EXPORTED + tuple(_mlp_sig)
+
+
+class Mlp:
+    """Learned subdomain-correction network (dgfas_mlp_*); device arrays are torch float32 tensors."""
+
+    def __init__(self, n_in, n_hidden, n_out, seed=5, stream=None):
+        h = _V()
+        _check(_lib.dgfas_mlp_create(n_in, n_hidden, n_out, seed, None if stream is None else _V(stream),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.n_in, self.n_hidden, self.n_out = n_in, n_hidden, n_out
+        n = ctypes.c_int64()
+        _check(_lib.dgfas_mlp_num_params(self._h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, '_h', None):
+            _lib.dgfas_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(_lib.dgfas_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        if theta.size != self.n_params:
+            raise ValueError('wrong parameter count')
+        _check(_lib.dgfas_mlp_set_params(self._h, theta.ctypes.data))
+
+    def forward(self, X, Y):
+        _check(_lib.dgfas_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(Y)))
+
+    def gradient(self, X, T, grad=None):
+        loss = ctypes.c_double()
+        _check(_lib.dgfas_mlp_gradient(self._h, _ptr(X), _ptr(T), X.shape[0], _ptr(grad), ctypes.byref(loss)))
+        return loss.value
+
+    def train(self, X, T, batch, steps, lr0=1e-3, lr_min=1e-5, total_steps=None):
+        losses = np.zeros(max(steps, 1))
+        _check(_lib.dgfas_mlp_train(self._h, _ptr(X), _ptr(T), X.shape[0], batch, steps, lr0, lr_min,
+                                    total_steps or steps, losses.ctypes.data_as(c_dp)))
+        return losses[:steps]

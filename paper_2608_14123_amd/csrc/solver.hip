@@ -587,6 +587,15 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   return s.release();
 }
 
+}  // namespace
+
+const char* set_error(const std::string& m) {
+  g_err = m;
+  return g_err.c_str();
+}
+
+namespace {
+
 dgfas_status fail(const Error& e) {
   g_err = e.what();
   return e.code;

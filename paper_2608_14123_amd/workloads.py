@@ -47,12 +47,15 @@ def box_vertices(nx, ny, nz, lengths=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
 
 
 def perturb_vertices(V, fraction, seed):
-    """Displace every interior vertex by U[-fraction, fraction] * (local edge length) per axis."""
+    """Displace every coordinate of every interior vertex by U[-fraction, fraction] * h_min.
+
+    h_min is the shortest edge of the grid, so stretched elements keep their faces close to
+    the box planes (a per-axis scale would tilt the short faces of 1:100 elements by up to
+    ~88 degrees)."""
     rng = np.random.default_rng(seed)
     V = V.copy()
-    nz, ny, nx = (s - 1 for s in V.shape[:3])
-    h = [np.diff(V[0, 0, :, 0]).min(), np.diff(V[0, :, 0, 1]).min(), np.diff(V[:, 0, 0, 2]).min()]
-    disp = rng.uniform(-fraction, fraction, size=V.shape) * np.array(h)
+    h = min(np.diff(V[0, 0, :, 0]).min(), np.diff(V[0, :, 0, 1]).min(), np.diff(V[:, 0, 0, 2]).min())
+    disp = rng.uniform(-fraction, fraction, size=V.shape) * h
     interior = np.zeros(V.shape[:3], dtype=bool)
     interior[1:-1, 1:-1, 1:-1] = True
     V[interior] += disp[interior]
