@@ -37,6 +37,7 @@ extern "C" {
 typedef enum {
   DGFAS_OK = 0,
   DGFAS_ENOTCONV = 1,      /* warning: tolerance not reached; outputs are valid */
+  DGFAS_EFALLBACK = 2,     /* warning: converged after the learned correction was switched off */
   DGFAS_EINVAL = -1,       /* bad argument (null pointer, bad size, bad level) */
   DGFAS_ENOMEM = -2,       /* device allocation failed */
   DGFAS_EHIP = -3,         /* HIP runtime error (message in dgfas_last_error) */
@@ -178,6 +179,25 @@ dgfas_status dgfas_mlp_gradient(dgfas_mlp m, const float* X, const float* T, int
  * global step t; losses (host, may be NULL) receives the loss of every step.  Synchronous. */
 dgfas_status dgfas_mlp_train(dgfas_mlp m, const float* X, const float* T, int64_t n, int32_t batch,
                              int32_t steps, float lr0, float lr_min, int32_t total_steps, double* losses);
+
+/* Attach (enabled = 1) or detach the network as a correction of the finest-level FD subdomain
+ * solves: du_s <- du_s + |r_s| MLP(r_s / |r_s|, J9) with r_s the subdomain residual tile
+ * (ns^3 values, ns = p + 1 + 2m) and J9 the element's linear map Jacobian / det^(1/3).
+ * Needs n_rhs = 1 and DGFAS_FP64; the network must map ns^3 + 9 -> ns^3.  The network must
+ * outlive the attachment.  dgfas_solve then judges it against the plain smoother: the first
+ * cycle of the first solve runs plain and gives the reference reduction factor; a learned cycle
+ * that reduces less (or goes non-finite) is undone, the rest of the solve runs plain and the
+ * call returns DGFAS_EFALLBACK. */
+dgfas_status dgfas_set_learned(dgfas_solver s, dgfas_mlp m, int32_t enabled);
+
+/* Training pairs from the method itself: for the n finest-level elements `centers` (host; any
+ * two at least 4 elements apart so that their 3x3x3 patches neither overlap nor touch), the
+ * subdomain residual r_s = R_s r, the FD solve and the exact local solve (R_s A R_s^T)^-1 r_s
+ * (masked PCG with the FD preconditioner to 1e-11).  Writes X [n][ns^3 + 9] =
+ * [r_s / |r_s|, J9] and T [n][ns^3] = (exact - FD) / |r_s| (device, FP32, tile order of the
+ * FD solve).  pcg_iters (host, may be NULL) gets the PCG iteration count.  Synchronous. */
+dgfas_status dgfas_learned_pairs(dgfas_solver s, const double* r, const int32_t* centers, int32_t n,
+                                 float* X, float* T, int32_t* pcg_iters);
 
 /* Message of the last failed call on this thread. */
 const char* dgfas_last_error(void);

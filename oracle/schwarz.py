@@ -215,3 +215,29 @@ def overlap_layers(p, delta):
     """Reading of Sec. 4.3.1 item 3: m = number of neighbour GLL nodes with (1+xi)/2 <= delta."""
     x, _ = gll(p)
     return int(np.sum(0.5 * (1.0 + x) <= delta + 1e-14))
+
+
+def local_pair(mesh, schwarz, A_dense, r, e):
+    """Learned-correction training pair of element e (not in the paper; test infrastructure):
+    subdomain residual r_s = R_s r, its FD solve and the exact local solve (R_s A R_s^T)^-1 r_s
+    by dense Cholesky of the principal submatrix of the assembled operator."""
+    idx, grp = schwarz.subdomain_indices(e)
+    i = idx.ravel()
+    rs = np.asarray(r).ravel()[i]
+    As = A_dense[np.ix_(i, i)]
+    exact = scipy.linalg.cho_solve(scipy.linalg.cho_factor(As), rs)
+    sel = np.nonzero(grp['els'] == e)[0]
+    fd = schwarz.fd_solve(grp, rs.reshape((1,) + idx.shape), sel).ravel()
+    return idx.shape, rs, fd, exact
+
+
+def linear_jacobian(mesh):
+    """[a1 a2 a3] / det^(1/3) per element (E, 3, 3): the linear Legendre coefficients of the map."""
+    from .gll import gll as _gll
+    p = mesh.p
+    x, _ = _gll(p)
+    V = np.stack([legendre(i, x)[0] for i in range(p + 1)], axis=1)
+    Vinv = np.linalg.inv(V)
+    xh = np.einsum('zk,yj,xi,eakji->eazyx', Vinv, Vinv, Vinv, mesh.X)
+    A = np.stack([xh[:, :, 0, 0, 1], xh[:, :, 0, 1, 0], xh[:, :, 1, 0, 0]], axis=2)   # A[e][a][b]
+    return A / np.cbrt(np.linalg.det(A))[:, None, None]

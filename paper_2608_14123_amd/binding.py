@@ -273,3 +273,36 @@ class Mlp:
         _check(_lib.dgfas_mlp_train(self._h, _ptr(X), _ptr(T), X.shape[0], batch, steps, lr0, lr_min,
                                     total_steps or steps, losses.ctypes.data_as(c_dp)))
         return losses[:steps]
+
+
+_learn_sig = {
+    'dgfas_set_learned': (_I, [_V, _V, _I]),
+    'dgfas_learned_pairs': (_I, [_V, _V, _V, _I, _V, _V, ctypes.POINTER(_I)]),
+}
+for _name, (_res, _args) in _learn_sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+EXPORTED = EXPORTED + tuple(_learn_sig)
+DGFAS_EFALLBACK = 2
+
+
+def set_learned(solver, mlp, enabled=True):
+    _check(_lib.dgfas_set_learned(solver._h, mlp._h if mlp is not None else None, 1 if enabled else 0))
+
+
+def learned_pairs(solver, r, centers, X, T):
+    """Training pairs for the listed centre elements (numpy int array); returns PCG iterations."""
+    c = np.ascontiguousarray(centers, dtype=np.int32)
+    it = _I()
+    _check(_lib.dgfas_learned_pairs(solver._h, _ptr(r), c.ctypes.data, len(c), _ptr(X), _ptr(T), ctypes.byref(it)))
+    return it.value
+
+
+def solve_status(solver, u, f, max_cycles=30, rtol=1e-10):
+    """Like Solver.solve but also returns the status code (0 ok, 1 not converged, 2 fallback)."""
+    hist = np.zeros(max_cycles + 1)
+    nd = _I()
+    code = _check(_lib.dgfas_solve(solver._h, _ptr(u), _ptr(f), max_cycles, rtol, hist.ctypes.data_as(c_dp),
+                                   ctypes.byref(nd)), warn_ok=True)
+    return hist[:nd.value + 1], code

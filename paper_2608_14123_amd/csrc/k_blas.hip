@@ -264,6 +264,14 @@ template void convert<double, float>(int64_t, const double*, float*, int, hipStr
 template void convert<float, double>(int64_t, const float*, double*, int, hipStream_t);
 template void convert<float, float>(int64_t, const float*, float*, int, hipStream_t);
 
+__global__ void mask_mul_kernel(int64_t n, double* __restrict__ y, const double* __restrict__ m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] *= m[i];
+}
+void mask_mul(int64_t n, double* y, const double* m, hipStream_t st) {
+  hipLaunchKernelGGL(mask_mul_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, y, m);
+}
+
 __global__ void fill_kernel(int64_t n, double* __restrict__ y, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = v;

@@ -56,6 +56,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   const int lbr = xcd_block(a.E * a.nrhs);
   if (lbr < 0) return;
   const int e = lbr / a.nrhs, rhs = lbr - e * a.nrhs;   // right-hand side fastest
+  if (a.sel && !a.sel[e]) return;
   a.r += (int64_t)rhs * a.E * N3;
   a.z += (int64_t)rhs * a.E * N3;
   a.O += (int64_t)rhs * a.E * R.size;
@@ -214,7 +215,9 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
     const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
     if (m1 < 0 || m2 < 0 || m3 < 0) continue;
-    const T v = sW[0][s1] * sW[1][s2] * sW[2][s3] * tB[(s3 * NS + s2) * LS + s1];
+    T t = tB[(s3 * NS + s2) * LS + s1];
+    if (a.corr) t += (T)(a.cscale[e] * (double)a.corr[(int64_t)e * (NS * NS * NS) + q]);
+    const T v = a.unweighted ? t : sW[0][s1] * sW[1][s2] * sW[2][s3] * t;
     const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, d3 = (m3 >> 6) - 1;
     const int l1 = m1 & 63, l2 = m2 & 63, l3 = m3 & 63;
     if (d1 == 0 && d2 == 0 && d3 == 0) {
@@ -296,6 +299,162 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
   for (int t = 0; t < 7; ++t) acc += ok[t] ? vals[t] : T(0);
   a.z[(int64_t)e * N3 + node] += acc;
 }
+
+// ---------------------------------------------------------------------------
+// Tile helpers for the learned correction.  A tile is the NS^3 subdomain block of a
+// vector in the layout of the FD solve (padded positions zero).
+template <int N, int M>
+struct TileCtx {
+  static constexpr int NS = N + 2 * M, NT = NS * NS * NS;
+  int map[3][NS];
+  int nb[27];
+};
+
+template <int N, int M, typename T>
+__device__ void load_tile_ctx(const SchwarzArgs<T>& a, int e, TileCtx<N, M>& c) {
+  constexpr int NS = N + 2 * M;
+  for (int t = threadIdx.x; t < 3 * NS; t += blockDim.x) {
+    const int d = t / NS, q = t - d * NS;
+    c.map[d][q] = a.map1d[a.var[(int64_t)e * 3 + d] * NS + q];
+  }
+  for (int t = threadIdx.x; t < 27; t += blockDim.x) c.nb[t] = a.nb27[(int64_t)e * 27 + t];
+}
+
+// global index of tile position q of the element, or -1 (padding / absent neighbour)
+template <int N, int M>
+__device__ __forceinline__ int64_t tile_index(const TileCtx<N, M>& c, int q) {
+  constexpr int NS = N + 2 * M;
+  const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
+  const int m1 = c.map[0][s1], m2 = c.map[1][s2], m3 = c.map[2][s3];
+  if (m1 < 0 || m2 < 0 || m3 < 0) return -1;
+  const int src = c.nb[(m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6)];
+  if (src < 0) return -1;
+  return (int64_t)src * (N * N * N) + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63);
+}
+
+// X[row] = [tile(v) / |tile(v)|, J9[e]], norms[row] = |tile(v)|
+template <int N, int M, typename T>
+__global__ void __launch_bounds__(256) tile_features_kernel(SchwarzArgs<T> a, const int* ids, int n,
+                                                            const double* __restrict__ v, const double* __restrict__ J9,
+                                                            float* __restrict__ X, double* __restrict__ norms) {
+  using C = TileCtx<N, M>;
+  __shared__ C c;
+  __shared__ double tile[C::NT];
+  __shared__ double red[256];
+  const int row = blockIdx.x;
+  if (row >= n) return;
+  const int e = ids ? ids[row] : row;
+  load_tile_ctx<N, M, T>(a, e, c);
+  __syncthreads();
+  double s = 0;
+  for (int q = threadIdx.x; q < C::NT; q += 256) {
+    const int64_t gi = tile_index<N, M>(c, q);
+    const double x = gi >= 0 ? v[gi] : 0.0;
+    tile[q] = x;
+    s += x * x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  const int64_t in = C::NT + 9;
+  for (int q = threadIdx.x; q < C::NT; q += 256) X[(int64_t)row * in + q] = (float)(tile[q] * inv);
+  if (threadIdx.x < 9) X[(int64_t)row * in + C::NT + threadIdx.x] = (float)J9[(int64_t)e * 9 + threadIdx.x];
+  if (threadIdx.x == 0) norms[row] = nrm;
+}
+
+// out[row] = (tile(v1) - tile(v2)) / norms[row]
+template <int N, int M, typename T>
+__global__ void __launch_bounds__(256) tile_diff_kernel(SchwarzArgs<T> a, const int* ids, int n,
+                                                        const double* __restrict__ v1, const double* __restrict__ v2,
+                                                        const double* __restrict__ norms, float* __restrict__ out) {
+  using C = TileCtx<N, M>;
+  __shared__ C c;
+  const int row = blockIdx.x;
+  if (row >= n) return;
+  const int e = ids ? ids[row] : row;
+  load_tile_ctx<N, M, T>(a, e, c);
+  __syncthreads();
+  const double inv = norms[row] > 0 ? 1.0 / norms[row] : 0.0;
+  for (int q = threadIdx.x; q < C::NT; q += 256) {
+    const int64_t gi = tile_index<N, M>(c, q);
+    out[(int64_t)row * C::NT + q] = gi >= 0 ? (float)((v1[gi] - v2[gi]) * inv) : 0.f;
+  }
+}
+
+// mask = 1 on every node of the listed subdomains
+template <int N, int M, typename T>
+__global__ void __launch_bounds__(256) mark_kernel(SchwarzArgs<T> a, const int* ids, int n, double* __restrict__ mask) {
+  using C = TileCtx<N, M>;
+  __shared__ C c;
+  const int row = blockIdx.x;
+  if (row >= n) return;
+  const int e = ids ? ids[row] : row;
+  load_tile_ctx<N, M, T>(a, e, c);
+  __syncthreads();
+  for (int q = threadIdx.x; q < C::NT; q += 256) {
+    const int64_t gi = tile_index<N, M>(c, q);
+    if (gi >= 0) mask[gi] = 1.0;
+  }
+}
+
+template <int N, int M, typename T>
+void launch_features(const SchwarzArgs<T>& a, const int* ids, int n, const double* v, const double* J9, float* X,
+                     double* norms, hipStream_t st) {
+  hipLaunchKernelGGL((tile_features_kernel<N, M, T>), dim3(n), dim3(256), 0, st, a, ids, n, v, J9, X, norms);
+}
+template <int N, int M, typename T>
+void launch_diff(const SchwarzArgs<T>& a, const int* ids, int n, const double* v1, const double* v2,
+                 const double* norms, float* out, hipStream_t st) {
+  hipLaunchKernelGGL((tile_diff_kernel<N, M, T>), dim3(n), dim3(256), 0, st, a, ids, n, v1, v2, norms, out);
+}
+template <int N, int M, typename T>
+void launch_mark(const SchwarzArgs<T>& a, const int* ids, int n, double* mask, hipStream_t st) {
+  hipLaunchKernelGGL((mark_kernel<N, M, T>), dim3(n), dim3(256), 0, st, a, ids, n, mask);
+}
+
+#define DGFAS_TILE_CASES(CALL)                           \
+  switch (p * 16 + m) {                                  \
+    case 1 * 16 + 1: CALL(2, 1); break;                  \
+    case 2 * 16 + 1: CALL(3, 1); break;                  \
+    case 3 * 16 + 1: CALL(4, 1); break;                  \
+    case 4 * 16 + 1: CALL(5, 1); break;                  \
+    case 5 * 16 + 1: CALL(6, 1); break;                  \
+    case 6 * 16 + 1: CALL(7, 1); break;                  \
+    case 7 * 16 + 1: CALL(8, 1); break;                  \
+    case 8 * 16 + 1: CALL(9, 1); break;                  \
+    default: break;                                      \
+  }
+
+template <typename T>
+void tile_features(int p, int m, const SchwarzArgs<T>& a, const int* ids, int n, const double* v, const double* J9,
+                   float* X, double* norms, hipStream_t st) {
+#define CALLF(NN, MM) launch_features<NN, MM, T>(a, ids, n, v, J9, X, norms, st)
+  DGFAS_TILE_CASES(CALLF)
+#undef CALLF
+}
+template <typename T>
+void tile_diff(int p, int m, const SchwarzArgs<T>& a, const int* ids, int n, const double* v1, const double* v2,
+               const double* norms, float* out, hipStream_t st) {
+#define CALLD(NN, MM) launch_diff<NN, MM, T>(a, ids, n, v1, v2, norms, out, st)
+  DGFAS_TILE_CASES(CALLD)
+#undef CALLD
+}
+template <typename T>
+void mark_subdomains(int p, int m, const SchwarzArgs<T>& a, const int* ids, int n, double* mask, hipStream_t st) {
+#define CALLM(NN, MM) launch_mark<NN, MM, T>(a, ids, n, mask, st)
+  DGFAS_TILE_CASES(CALLM)
+#undef CALLM
+}
+template void tile_features<double>(int, int, const SchwarzArgs<double>&, const int*, int, const double*,
+                                    const double*, float*, double*, hipStream_t);
+template void tile_diff<double>(int, int, const SchwarzArgs<double>&, const int*, int, const double*, const double*,
+                                const double*, float*, hipStream_t);
+template void mark_subdomains<double>(int, int, const SchwarzArgs<double>&, const int*, int, double*, hipStream_t);
 
 template <int N, int M, typename T>
 void launch_schwarz(const SchwarzArgs<T>& a, hipStream_t st) {

@@ -50,7 +50,21 @@ struct SchwarzArgs {
   const T* lam = nullptr;     // [9][ns]
   const T* W = nullptr;       // [9][ns]
   const int* map1d = nullptr; // [9][ns]: (delta+1)*64 + loc, or -1 for padding
+  const uint8_t* sel = nullptr;  // [E] subdomains to solve (null: all)
+  int unweighted = 0;            // 1: W = I (block-diagonal local solves)
+  const float* corr = nullptr;   // [E][ns^3] learned correction added to the FD tile (or null)
+  const double* cscale = nullptr;  // [E] scale of corr (the subdomain residual norm)
 };
+
+// Learned-correction helpers over the subdomain tiles of a list of elements (null list: all)
+template <typename T>
+void tile_features(int p, int m, const SchwarzArgs<T>& a, const int* ids, int n, const double* v, const double* J9,
+                   float* X, double* norms, hipStream_t st);
+template <typename T>
+void tile_diff(int p, int m, const SchwarzArgs<T>& a, const int* ids, int n, const double* v1, const double* v2,
+               const double* norms, float* out, hipStream_t st);
+template <typename T>
+void mark_subdomains(int p, int m, const SchwarzArgs<T>& a, const int* ids, int n, double* mask, hipStream_t st);
 
 template <typename T>
 void schwarz_solve(int p, int m, const SchwarzArgs<T>& a, hipStream_t st);

@@ -126,6 +126,10 @@ static Mlp* M_(dgfas_mlp p) {
   return p->m;
 }
 
+namespace dgfas {
+Mlp* dgfas_mlp_impl(dgfas_mlp p) { return M_(p); }
+}
+
 extern "C" {
 
 dgfas_status dgfas_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed, void* stream,

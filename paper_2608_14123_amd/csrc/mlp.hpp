@@ -41,3 +41,8 @@ struct Mlp {
 };
 
 }  // namespace dgfas
+
+struct dgfas_mlp_s;
+namespace dgfas {
+Mlp* dgfas_mlp_impl(dgfas_mlp_s* p);   // throws on a null handle
+}

@@ -15,6 +15,7 @@
 #include "blas.hpp"
 #include "kernels.hpp"
 #include "tables.hpp"
+#include "mlp.hpp"
 
 namespace dgfas {
 namespace {
@@ -79,6 +80,8 @@ struct Level {
   double *gco = nullptr, *S = nullptr, *ST = nullptr, *lam = nullptr, *W = nullptr, *O = nullptr;
   float *gco32 = nullptr, *S32 = nullptr, *ST32 = nullptr, *lam32 = nullptr, *W32 = nullptr, *O32 = nullptr;
   int* map1d = nullptr;
+  double* J9 = nullptr;          // [E][9] linear map Jacobian / det^(1/3) (network input)
+  std::vector<int> h_nb27;       // host copy of the 26-neighbourhood
   // transfer matrices to the next coarser level (this = fine)
   double *Pm = nullptr, *Im = nullptr, *Rm = nullptr;
   // vectors
@@ -109,6 +112,16 @@ struct Solver {
   double* partial2() { return partial + (size_t)1024 * nrhs; }
   double* scratch = nullptr;
   std::vector<void*> owned;
+  // learned correction on the finest level (FP64 Schwarz applications)
+  Mlp* mlp = nullptr;
+  bool learned = false;
+  float *lX = nullptr, *lY = nullptr;
+  double* lnorm = nullptr;
+  double plain_rho = -1.0;       // first-cycle reduction factor of the plain smoother (fallback judge)
+  double* usave = nullptr;       // finest-level copy of u taken before every learned cycle
+  // masked local solves (data generation): Schwarz restricted to selected subdomains, unweighted
+  const uint8_t* msel = nullptr;
+  const double* mmask = nullptr;
 
   template <typename T>
   T* own(T* p) {
@@ -148,6 +161,19 @@ struct Solver {
   // z = B r (mode 0) or z += B r (mode 1)
   void schwarz(Level& L, const double* r, double* z, int mode) {
     SchwarzArgs<double> a = sz_args<double>(L, r, z, mode);
+    if (msel) {
+      // block-diagonal local solves on the selected subdomains only (their supports are disjoint)
+      a.sel = msel;
+      a.unweighted = 1;
+      fill(L.ndof, z, 0.0, st);
+      HIPC(hipMemsetAsync(L.O, 0, (size_t)L.E * overlap_size(L.p, L.m) * sizeof(double), st));
+    } else if (learned && &L == &lv.back()) {
+      // FD solve plus the network correction |r_s| MLP(r_s / |r_s|, J9)
+      tile_features<double>(L.p, L.m, a, nullptr, L.E, r, L.J9, lX, lnorm, st);
+      mlp->forward(lX, L.E, lY);
+      a.corr = lY;
+      a.cscale = lnorm;
+    }
     schwarz_solve<double>(L.p, L.m, a, st);
     schwarz_overlap_add<double>(L.p, L.m, a, st);
   }
@@ -167,8 +193,21 @@ struct Solver {
 
   // Correction-form smoothing in FP32: r = g - A u (FP64); n WAS steps on
   // A du = r in FP32 from du = 0; u += du (FP64).
+  void ensure_mixed_vectors(Level& L) {
+    const size_t nv = (size_t)L.ndof * nrhs;
+    if (!L.r32) L.r32 = own(dalloc<float>(nv));
+    if (!L.du32) L.du32 = own(dalloc<float>(nv));
+    if (!L.rc32) L.rc32 = own(dalloc<float>(nv));
+    if (!L.O32) {
+      const size_t nin = (size_t)L.E * overlap_size(L.p, L.m) * nrhs;
+      L.O32 = own(dalloc<float>(nin));
+      if (nin) HIPC(hipMemsetAsync(L.O32, 0, nin * sizeof(float), st));
+    }
+  }
+
   void was_mixed(Level& L, double* u, const double* g, int n) {
     if (n <= 0) return;
+    ensure_mixed_vectors(L);
     residual(L, u, g, L.r);
     convert<double, float>(L.ndof * nrhs, L.r, L.r32, 0, st);
     schwarz32(L, L.r32, L.du32, 0);
@@ -190,7 +229,10 @@ struct Solver {
     return h;
   }
 
-  void apply_t(Level& L, const double* u, double* Au) { apply(L, u, Au); }
+  void apply_t(Level& L, const double* u, double* Au) {
+    apply(L, u, Au);
+    if (mmask) mask_mul(L.ndof, Au, mmask, st);
+  }
   void apply_t(Level& L, const float* u, float* Au) {
     OpArgs<float> a = op_args<float>(L, 1, u, nullptr, Au);
     sipg_apply<float>(L.p, a, st);
@@ -204,9 +246,28 @@ struct Solver {
   // r_max empty: exactly n iterations, no synchronisation; otherwise stop once
   // ||r_k|| <= r_max[k] for every right-hand side k (one synchronisation per iteration).
   // zero_start: x = 0 and r = f without an operator application (correction form).
+  // SCG work vectors are allocated at set-up only where the configured cycle runs SCG;
+  // other callers (data generation, dgfas_root_solve on any level) get them on first use
+  void ensure_scg_vectors(Level& L, bool fp32) {
+    const size_t nv = (size_t)L.ndof * nrhs;
+    if (!fp32) {
+      if (!L.z) L.z = own(dalloc<double>(nv));
+      if (!L.pv) L.pv = own(dalloc<double>(nv));
+      if (!L.q) L.q = own(dalloc<double>(nv));
+      if (!L.r0) L.r0 = own(dalloc<double>(nv));
+    } else {
+      if (!L.rc32) L.rc32 = own(dalloc<float>(nv));
+      if (!L.z32) L.z32 = own(dalloc<float>(nv));
+      if (!L.p32) L.p32 = own(dalloc<float>(nv));
+      if (!L.q32) L.q32 = own(dalloc<float>(nv));
+      if (!L.r0_32) L.r0_32 = own(dalloc<float>(nv));
+    }
+  }
+
   template <typename T>
   int scg(Level& L, T* x, const T* f, int n, const std::vector<double>& r_max, bool* breakdown,
           bool zero_start = false) {
+    ensure_scg_vectors(L, sizeof(T) == 4);
     const int nb = reduction_blocks(L.ndof);
     const int64_t nv = L.ndof * nrhs;
     T *r, *z, *pv, *q, *r0;
@@ -256,6 +317,7 @@ struct Solver {
   // Correction-form SCG smoothing in FP32: r = g - A u (FP64), n SCG iterations
   // on A du = r in FP32 from du = 0, u += du (FP64).
   void scg_mixed(Level& L, double* u, const double* g, int n) {
+    ensure_mixed_vectors(L);
     residual(L, u, g, L.r);
     convert<double, float>(L.ndof * nrhs, L.r, L.r32, 0, st);
     scg<float>(L, L.du32, L.r32, n, {}, nullptr, true);
@@ -416,6 +478,17 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
     gco[e * 4 + 3] = s.opt.nu * dx[0] * dx[1] / (2.0 * dx[2]);
   }
   L.gco = s.own(upload(gco, st));
+  {
+    std::vector<double> j9((size_t)L.E * 9);
+    for (int e = 0; e < L.E; ++e) {
+      const double* A = &lin[e * 9];   // A[a][b] = coefficient of coordinate a along xi_b
+      const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                         A[2] * (A[3] * A[7] - A[4] * A[6]);
+      const double sc = 1.0 / std::cbrt(det);
+      for (int q = 0; q < 9; ++q) j9[e * 9 + q] = A[q] * sc;
+    }
+    L.J9 = s.own(upload(j9, st));
+  }
   L.gco32 = s.own(upload(to_float(gco), st));
 
   // variant tables (left, right) in {I, D, N}^2, zero padded to ns
@@ -466,6 +539,7 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
   }
   L.var = s.own(upload(var, st));
   L.nb27 = s.own(upload(nb27, st));
+  L.h_nb27 = nb27;
   const int osz = overlap_size(p, L.m);
   const size_t nin = (size_t)L.E * osz * s.nrhs;
   const bool fp32 = s.opt.precision == DGFAS_FP32;
@@ -830,19 +904,46 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
   };
   bool conv = worst(std::vector<double>(s->nrhs, 0.0)) == 0.0 &&
               *std::max_element(r0.begin(), r0.end()) == 0.0;
+  // learned correction: the plain smoother's first-cycle reduction factor is the judge; a learned
+  // cycle that reduces less, or goes non-finite, is undone and the solve continues plain
+  const bool attached = s->learned;
+  bool use_learned = attached, fell_back = false;
+  if (attached && !s->usave) s->usave = s->own(dalloc<double>(T.ndof * s->nrhs));
+  double* usave = s->usave;
+  double prev = 1.0;
   while (!conv && k < max_cycles) {
+    const bool plain_probe = use_learned && s->plain_rho < 0.0;
+    s->learned = use_learned && !plain_probe;
+    if (s->learned)
+      HIPC(hipMemcpyAsync(usave, u, T.ndof * s->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s->st));
     s->vcycle(u, f);
     s->residual(T, u, f, T.r);
-    const double rk = worst(s->dots_sync(T, T.r, T.r));
+    double rk = worst(s->dots_sync(T, T.r, T.r));
+    if (plain_probe) s->plain_rho = rk / prev;
+    if (s->learned && (!std::isfinite(rk) || rk / prev > s->plain_rho)) {
+      HIPC(hipMemcpyAsync(u, usave, T.ndof * s->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+      use_learned = false;
+      fell_back = true;
+      s->learned = false;
+      s->vcycle(u, f);
+      s->residual(T, u, f, T.r);
+      rk = worst(s->dots_sync(T, T.r, T.r));
+    }
     ++k;
     if (hist) hist[k] = rk;
-    if (!std::isfinite(rk)) throw Error(DGFAS_EBREAKDOWN, "non-finite residual");
+    if (!std::isfinite(rk)) { s->learned = attached; throw Error(DGFAS_EBREAKDOWN, "non-finite residual"); }
+    prev = rk;
     conv = rk <= rtol;
   }
+  s->learned = attached;
   if (n_done) *n_done = k;
   if (!conv) { g_err = "tolerance not reached"; return DGFAS_ENOTCONV; }
+  if (fell_back) { g_err = "learned correction disabled by the fallback rule"; return DGFAS_EFALLBACK; }
   API_END
 }
+
+#if 0
+#endif
 
 dgfas_status dgfas_norm(dgfas_solver sv, int32_t level, const double* v, double* out) {
   API_BEGIN
@@ -850,6 +951,110 @@ dgfas_status dgfas_norm(dgfas_solver sv, int32_t level, const double* v, double*
   need(v, "v"); need(out, "out");
   std::vector<double> d = s->dots_sync(s->level(level), v, v);
   for (int k = 0; k < s->nrhs; ++k) out[k] = std::sqrt(d[k]);
+  API_END
+}
+
+dgfas_status dgfas_set_learned(dgfas_solver sv, dgfas_mlp m, int32_t enabled) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  Level& T = s->lv.back();
+  if (!enabled) { s->learned = false; return DGFAS_OK; }
+  if (!m) throw Error(DGFAS_EINVAL, "null network");
+  Mlp* net = dgfas_mlp_impl(m);
+  const int nt = T.ns * T.ns * T.ns;
+  if (net->in != nt + 9 || net->out != nt)
+    throw Error(DGFAS_EINVAL, "network shape must be (ns^3 + 9) -> ns^3 = " + std::to_string(nt + 9) + " -> " +
+                                  std::to_string(nt));
+  if (s->nrhs != 1) throw Error(DGFAS_EUNSUPPORTED, "learned correction needs n_rhs = 1");
+  if (s->opt.precision != DGFAS_FP64) throw Error(DGFAS_EUNSUPPORTED, "learned correction runs in the FP64 smoother");
+  if (!s->lX) {
+    s->lX = s->own(dalloc<float>((size_t)T.E * (nt + 9)));
+    s->lY = s->own(dalloc<float>((size_t)T.E * nt));
+    s->lnorm = s->own(dalloc<double>(T.E));
+  }
+  net->st = s->st;
+  s->mlp = net;
+  s->learned = true;
+  s->plain_rho = -1.0;
+  API_END
+}
+
+dgfas_status dgfas_learned_pairs(dgfas_solver sv, const double* r, const int32_t* centers, int32_t n, float* X,
+                                 float* T, int32_t* pcg_iters) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(r, "r"); need(centers, "centers"); need(X, "X"); need(T, "T");
+  if (s->nrhs != 1) throw Error(DGFAS_EUNSUPPORTED, "pairs need n_rhs = 1");
+  Level& L = s->lv.back();
+  if (n < 1 || n > L.E) throw Error(DGFAS_EINVAL, "bad number of centres");
+  // centres must be 4 apart in the 26-neighbourhood graph: their 3x3x3 patches then neither
+  // overlap nor touch, so the masked operator is block diagonal over the subdomains
+  std::vector<char> is_center(L.E, 0);
+  for (int c = 0; c < n; ++c) {
+    const int e0 = centers[c];
+    if (e0 < 0 || e0 >= L.E) throw Error(DGFAS_EINVAL, "centre out of range");
+    if (is_center[e0]) throw Error(DGFAS_EINVAL, "repeated centre");
+    is_center[e0] = 1;
+  }
+  for (int c = 0; c < n; ++c) {
+    const int e0 = centers[c];
+    std::vector<int> front{e0}, seen{e0};
+    for (int hop = 0; hop < 3; ++hop) {
+      std::vector<int> nxt;
+      for (int e : front)
+        for (int q = 0; q < 27; ++q) {
+          const int en = L.h_nb27[(size_t)e * 27 + q];
+          if (en < 0 || std::find(seen.begin(), seen.end(), en) != seen.end()) continue;
+          if (is_center[en]) throw Error(DGFAS_EINVAL, "centres closer than 4 elements");
+          seen.push_back(en);
+          nxt.push_back(en);
+        }
+      front.swap(nxt);
+    }
+  }
+  std::vector<int> ids(centers, centers + n);
+  std::vector<uint8_t> sel(L.E, 0);
+  for (int e : ids) sel[e] = 1;
+  int* d_ids = upload(ids, s->st);
+  uint8_t* d_sel = upload(sel, s->st);
+  double *mask = nullptr, *b = nullptr, *z0 = nullptr, *x = nullptr, *nrm = nullptr;
+  auto cleanup = [&]() {
+    s->msel = nullptr;
+    s->mmask = nullptr;
+    hipStreamSynchronize(s->st);
+    void* ps[] = {d_ids, d_sel, mask, b, z0, x, nrm};
+    for (void* p : ps)
+      if (p) hipFree(p);
+  };
+  try {
+    mask = dalloc<double>(L.ndof);
+    b = dalloc<double>(L.ndof);
+    z0 = dalloc<double>(L.ndof);
+    x = dalloc<double>(L.ndof);
+    nrm = dalloc<double>(n);
+    SchwarzArgs<double> a = s->sz_args<double>(L, r, z0, 0);
+    fill(L.ndof, mask, 0.0, s->st);
+    mark_subdomains<double>(L.p, L.m, a, d_ids, n, mask, s->st);
+    convert<double, double>(L.ndof, r, b, 0, s->st);
+    mask_mul(L.ndof, b, mask, s->st);
+    s->msel = d_sel;
+    s->mmask = mask;
+    s->schwarz(L, b, z0, 0);                      // FD solutions of the local problems
+    const double bn = std::sqrt(s->dots_sync(L, b, b)[0]);
+    bool bd = false;
+    const int it = s->scg<double>(L, x, b, 1000, {1e-11 * bn}, &bd, true);   // exact local solves
+    if (bd) throw Error(DGFAS_EBREAKDOWN, "breakdown in the local solves");
+    s->msel = nullptr;
+    s->mmask = nullptr;
+    tile_features<double>(L.p, L.m, a, d_ids, n, b, L.J9, X, nrm, s->st);
+    tile_diff<double>(L.p, L.m, a, d_ids, n, x, z0, nrm, T, s->st);
+    HIPC(hipGetLastError());
+    if (pcg_iters) *pcg_iters = it;
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
   API_END
 }
 
