@@ -180,14 +180,15 @@ dgfas_status dgfas_mlp_gradient(dgfas_mlp m, const float* X, const float* T, int
 dgfas_status dgfas_mlp_train(dgfas_mlp m, const float* X, const float* T, int64_t n, int32_t batch,
                              int32_t steps, float lr0, float lr_min, int32_t total_steps, double* losses);
 
-/* Attach (enabled = 1) or detach the network as a correction of the finest-level FD subdomain
+/* Attach (enabled = 1; 2 = attach without the fallback rule, for diagnostics) or detach
+ * (enabled = 0) the network as a correction of the finest-level FD subdomain
  * solves: du_s <- du_s + |r_s| MLP(r_s / |r_s|, J9) with r_s the subdomain residual tile
  * (ns^3 values, ns = p + 1 + 2m) and J9 the element's linear map Jacobian / det^(1/3).
  * Needs n_rhs = 1 and DGFAS_FP64; the network must map ns^3 + 9 -> ns^3.  The network must
- * outlive the attachment.  dgfas_solve then judges it against the plain smoother: the first
- * cycle of the first solve runs plain and gives the reference reduction factor; a learned cycle
- * that reduces less (or goes non-finite) is undone, the rest of the solve runs plain and the
- * call returns DGFAS_EFALLBACK. */
+ * outlive the attachment.  dgfas_solve then judges it against the plain smoother: the first two
+ * cycles of the first solve after attaching run plain and the second one's reduction factor is
+ * the reference; a learned cycle that reduces less (or goes non-finite) is undone, the rest of
+ * the solve runs plain and the call returns DGFAS_EFALLBACK. */
 dgfas_status dgfas_set_learned(dgfas_solver s, dgfas_mlp m, int32_t enabled);
 
 /* Training pairs from the method itself: for the n finest-level elements `centers` (host; any

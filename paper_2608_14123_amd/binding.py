@@ -287,8 +287,9 @@ EXPORTED = EXPORTED + tuple(_learn_sig)
 DGFAS_EFALLBACK = 2
 
 
-def set_learned(solver, mlp, enabled=True):
-    _check(_lib.dgfas_set_learned(solver._h, mlp._h if mlp is not None else None, 1 if enabled else 0))
+def set_learned(solver, mlp, enabled=True, judge=True):
+    code = (1 if judge else 2) if enabled else 0
+    _check(_lib.dgfas_set_learned(solver._h, mlp._h if mlp is not None else None, code))
 
 
 def learned_pairs(solver, r, centers, X, T):

@@ -119,6 +119,7 @@ struct Solver {
   double* lnorm = nullptr;
   double plain_rho = -1.0;       // first-cycle reduction factor of the plain smoother (fallback judge)
   double* usave = nullptr;       // finest-level copy of u taken before every learned cycle
+  bool judge = true;             // apply the fallback rule (off only for diagnostics)
   // masked local solves (data generation): Schwarz restricted to selected subdomains, unweighted
   const uint8_t* msel = nullptr;
   const double* mmask = nullptr;
@@ -904,8 +905,10 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
   };
   bool conv = worst(std::vector<double>(s->nrhs, 0.0)) == 0.0 &&
               *std::max_element(r0.begin(), r0.end()) == 0.0;
-  // learned correction: the plain smoother's first-cycle reduction factor is the judge; a learned
-  // cycle that reduces less, or goes non-finite, is undone and the solve continues plain
+  // learned correction: the plain smoother is the judge.  The first solve after attaching runs
+  // its first two cycles plain; the second cycle's reduction factor is the reference (the first
+  // cycle of any solve reduces far more than later ones).  A learned cycle that reduces less than
+  // the reference, or goes non-finite, is undone and the solve continues plain.
   const bool attached = s->learned;
   bool use_learned = attached, fell_back = false;
   if (attached && !s->usave) s->usave = s->own(dalloc<double>(T.ndof * s->nrhs));
@@ -919,8 +922,8 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
     s->vcycle(u, f);
     s->residual(T, u, f, T.r);
     double rk = worst(s->dots_sync(T, T.r, T.r));
-    if (plain_probe) s->plain_rho = rk / prev;
-    if (s->learned && (!std::isfinite(rk) || rk / prev > s->plain_rho)) {
+    if (plain_probe && k == 1) s->plain_rho = rk / prev;
+    if (s->learned && s->judge && (!std::isfinite(rk) || rk / prev > s->plain_rho)) {
       HIPC(hipMemcpyAsync(u, usave, T.ndof * s->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s->st));
       use_learned = false;
       fell_back = true;
@@ -975,6 +978,7 @@ dgfas_status dgfas_set_learned(dgfas_solver sv, dgfas_mlp m, int32_t enabled) {
   net->st = s->st;
   s->mlp = net;
   s->learned = true;
+  s->judge = enabled != 2;
   s->plain_rho = -1.0;
   API_END
 }

@@ -91,6 +91,25 @@ def sine_bump_map(X, amplitude=0.1):
     return X + s[..., None]
 
 
+def seeded_bump_map(seed, amplitude=(0.04, 0.08)):
+    """A random member of the sine-bump family, zero on the boundary of the unit cube:
+    x'_a = x_a + c_a prod_d sin(pi k_ad x_d) with amplitudes c_a (random sign) and wave
+    numbers k_ad in {1, 2} drawn from `seed`."""
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(amplitude[0], amplitude[1], size=3) * rng.choice([-1.0, 1.0], size=3)
+    k = rng.integers(1, 3, size=(3, 3))
+
+    def fn(X):
+        Y = X.copy()
+        for a in range(3):
+            s = np.ones(X.shape[:-1])
+            for d in range(3):
+                s = s * np.sin(np.pi * k[a, d] * X[..., d])
+            Y[..., a] += amp[a] * s
+        return Y
+    return fn
+
+
 def uniform_nodal(shape, seed):
     """Nodal values ~ U[-1, 1] from numpy's PCG64 with the given seed."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=shape)
