@@ -19,6 +19,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# HBM bytes of one residual launch of the operator kernel at 32^3, p = 7 from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs, scaled by a 1 GiB copy (profiles/c2_curved_p7_hbm_traffic_pmc.md);
+# valid only for the kernel source it was measured on.
+OPERATOR_TRAFFIC = {'sha256_prefix': '6cfdf3e2503685ef', 'bytes': 1.675e9, 'ne': 32, 'p': 7}
 
 
 def parse():
@@ -150,9 +154,14 @@ def main():
             for c in sizes:
                 flops_fd += (4.0 * (a + b_ + c) + 1.0) * a * b_ * c
     ach_fd = flops_fd / (ms_sz * 1e-3) / 1e12
+    import hashlib
+    src = os.path.join(ROOT, 'paper_2608_14123_amd', 'csrc', 'k_operator.hip')
+    sha = hashlib.sha256(open(src, 'rb').read()).hexdigest()[:16]
+    traffic = (OPERATOR_TRAFFIC['bytes'] if sha == OPERATOR_TRAFFIC['sha256_prefix'] and ne == OPERATOR_TRAFFIC['ne']
+               and p == OPERATOR_TRAFFIC['p'] else None)
     roof_res = {'kernel': 'sipg_apply_kernel<8,double> (residual)', 'bound': 'hbm', 'achieved': round(ach_res, 1),
                 'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': round(ach_res / HBM_PEAK_GBS, 4),
-                'traffic': None}
+                'traffic': traffic, 'traffic_unit': 'bytes per launch', 'algorithmic_bytes': bytes_res}
     roof_fd = {'kernel': 'schwarz_solve_kernel<8,1,double> + overlap add', 'bound': 'alu',
                'achieved': round(ach_fd, 2), 'peak': FP64_PEAK_TFLOPS, 'unit': 'TFLOP/s',
                'frac': round(ach_fd / FP64_PEAK_TFLOPS, 4), 'traffic': None}
