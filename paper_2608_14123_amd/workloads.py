@@ -139,3 +139,50 @@ def stretched_perturbed(ne, aspect=100.0, fraction=0.2, seed=4):
     nbr, bc = box_topology(ne, ne, ne)
     V = box_vertices(ne, ne, ne, lengths=(1.0, 1.0, aspect))
     return perturb_vertices(V, fraction, seed), nbr, bc
+
+
+# --- hp-adaptive spherical front (degrees per element) ---------------------------------
+
+def front_degrees(ne, center=(0.0, 0.0, 0.0), r0=0.7, pmin=2, pmax=8):
+    """Degree per element of ne^3 cubes on [0,1]^3: d_e = distance of the element box from the
+    sphere |x - c| = r0, p_e = max(pmin, pmax - floor(d_e / h)); elements cut by the sphere get pmax."""
+    h = 1.0 / ne
+    idx = np.arange(ne)
+    ex, ey, ez = np.meshgrid(idx, idx, idx, indexing='ij')
+    ex, ey, ez = (a.transpose(2, 1, 0).ravel() for a in (ex, ey, ez))
+    lo = np.stack([ex, ey, ez], 1) * h - np.asarray(center)
+    hi = lo + h
+    near = np.where(lo > 0, lo, np.where(hi < 0, -hi, 0.0))       # closest point offsets
+    far = np.maximum(np.abs(lo), np.abs(hi))
+    rmin = np.linalg.norm(near, axis=1)
+    rmax = np.linalg.norm(far, axis=1)
+    d = np.where(rmax < r0, r0 - rmax, np.where(rmin > r0, rmin - r0, 0.0))
+    return np.maximum(pmin, pmax - np.floor(d / h + 1e-12).astype(np.int64)).astype(np.int32)
+
+
+def front_solution(X, alpha=50.0, r0=0.7, center=(0.0, 0.0, 0.0)):
+    """u = atan(alpha (|x - c| - r0)) at coordinates X (3, ...)."""
+    rho = np.sqrt(sum((X[a] - center[a]) ** 2 for a in range(3)))
+    return np.arctan(alpha * (rho - r0))
+
+
+def front_source(X, alpha=50.0, r0=0.7, center=(0.0, 0.0, 0.0), rho_min=1e-6):
+    """f = -laplace(u) for the spherical front, with rho clipped at rho_min at the centre."""
+    rho = np.maximum(np.sqrt(sum((X[a] - center[a]) ** 2 for a in range(3))), rho_min)
+    s = alpha * (rho - r0)
+    du = alpha / (1.0 + s * s)
+    d2u = -2.0 * alpha ** 3 * (rho - r0) / (1.0 + s * s) ** 2
+    return -(d2u + 2.0 * du / rho)
+
+
+def element_coords_mixed(V, degrees, xi_of, map_fn=None):
+    """Coordinates per element at the reference points xi_of(p) of its own degree (list of (3,n,n,n))."""
+    nz, ny, nx = (s - 1 for s in V.shape[:3])
+    out = []
+    cache = {}
+    for e, p in enumerate(np.asarray(degrees)):
+        p = int(p)
+        if p not in cache:
+            cache[p] = element_coords(V, xi_of(p), map_fn)
+        out.append(cache[p][e])
+    return out
