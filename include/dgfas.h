@@ -45,18 +45,28 @@ typedef enum {
   DGFAS_EBREAKDOWN = -5    /* non-finite value or p^T A p <= 0 inside SCG */
 } dgfas_status;
 
-enum { DGFAS_INTERIOR = 0, DGFAS_DIRICHLET = 1, DGFAS_NEUMANN = 2 };
+enum { DGFAS_INTERIOR = 0, DGFAS_DIRICHLET = 1, DGFAS_NEUMANN = 2,
+       /* Schwarz side code only: an interior face toward an element of another degree,
+          where the subdomain has no overlap (own half of the interior face terms) */
+       DGFAS_INTERIOR_NO_OVERLAP = 3 };
 enum { DGFAS_WAS = 0, DGFAS_SCG = 1 };
 enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1 };
 
 typedef struct dgfas_solver_s* dgfas_solver;
 
-/* Mesh (Sec. 2.2): host arrays, read during dgfas_create only. */
+/* Mesh (Sec. 2.2): host arrays, read during dgfas_create only.
+ * Degrees may differ between elements (an extension: the paper keeps one degree per level,
+ * Sec. 3.1).  A face between degrees p and p' is integrated with the GLL rule of the finer
+ * side, the penalty uses both degrees, the Schwarz subdomains do not overlap into an
+ * element of another degree, and p-coarsening p -> max(1, p / 2) is applied per element.
+ * Every vector is element-major: element e owns the (p_e+1)^3 entries after those of
+ * elements 0..e-1, its nodes lexicographic with xi_1 fastest. */
 typedef struct {
   int32_t n_elem;
-  const int32_t* degree;    /* [n_elem] polynomial degree per element, 1..8; all equal in this build */
-  const double* coords;     /* [n_elem][3][(p+1)^3] nodal x, y, z at the element's GLL nodes
-                               (the GLL nodes of dgfas_gll); the map must keep det J > 0 */
+  const int32_t* degree;    /* [n_elem] polynomial degree per element, 1..8 */
+  const double* coords;     /* per element, in element order, [3][(p_e+1)^3] nodal x, y, z at
+                               the element's GLL nodes (the GLL nodes of dgfas_gll); the map
+                               must keep det J > 0 */
   const int32_t* face_nbr;  /* [n_elem][6] neighbour element, or -1 on the boundary */
   const int8_t* face_bc;    /* [n_elem][6] DGFAS_DIRICHLET / DGFAS_NEUMANN on boundary faces */
 } dgfas_mesh_desc;
@@ -88,7 +98,7 @@ dgfas_status dgfas_gll(int32_t p, double* x, double* w);
 
 /* Host-only: 1D subdomain tables of the Schwarz method (Sec. 4.3.1) for degree p,
  * overlap m and face conditions (left, right) in {DGFAS_INTERIOR, DGFAS_DIRICHLET,
- * DGFAS_NEUMANN}.  Outputs (host, caller-sized): ns = number of subdomain nodes,
+ * DGFAS_NEUMANN, DGFAS_INTERIOR_NO_OVERLAP}.  Outputs (host, caller-sized): ns = number of subdomain nodes,
  * S [ns*ns] row-major with S^T M S = I and S^T L S = diag(lam), lam [ns], weights [ns].
  * ns <= p + 1 + 2m.  Usable without a GPU. */
 dgfas_status dgfas_schwarz_tables_1d(int32_t p, int32_t m, int32_t left, int32_t right,
@@ -101,7 +111,8 @@ dgfas_status dgfas_create(const dgfas_mesh_desc* mesh, const dgfas_options* opt,
                           dgfas_solver* out);
 void dgfas_destroy(dgfas_solver s);
 
-/* Number of levels L, and degree / DOF count of one level. */
+/* Number of levels L, and degree / DOF count of one level (the largest degree of the
+ * level when degrees differ; n_dof is the sum of (p_e+1)^3 over the elements). */
 dgfas_status dgfas_levels(dgfas_solver s, int32_t* n_levels);
 dgfas_status dgfas_level_info(dgfas_solver s, int32_t level, int32_t* degree, int64_t* n_dof);
 

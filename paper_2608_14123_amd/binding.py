@@ -131,9 +131,8 @@ class Solver:
         E = len(degree)
         if face_nbr.shape != (E, 6) or face_bc.shape != (E, 6):
             raise ValueError('face tables must be (n_elem, 6)')
-        n = int(degree[0]) + 1
-        if coords.size != E * 3 * n ** 3:
-            raise ValueError('coords must hold n_elem * 3 * (p+1)^3 values')
+        if coords.size != int(3 * np.sum((degree.astype(np.int64) + 1) ** 3)):
+            raise ValueError('coords must hold 3 (p_e+1)^3 values per element')
         self._keep = (degree, coords, face_nbr, face_bc)
         desc = MeshDesc(E, degree.ctypes.data, coords.ctypes.data, face_nbr.ctypes.data, face_bc.ctypes.data)
         self.options = options if options is not None else default_options()

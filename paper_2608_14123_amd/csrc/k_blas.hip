@@ -17,74 +17,90 @@ struct TrShape {
   static constexpr int THREADS = ((EPB * M3 + 63) / 64) * 64;
 };
 
+// Element e of the launch list, sub-block s = rhs * ncomp + comp:
+//   in  + rhs * stride_in  + off_in[e]  * ncomp + comp * NI^3
+//   out + rhs * stride_out + off_out[e] * ncomp + comp * NO^3
 template <int NI, int NO, typename T>
 __global__ void __launch_bounds__((TrShape<NI, NO>::THREADS))
-tensor3_kernel(int E, const T* __restrict__ Tm, const T* __restrict__ in, const T* __restrict__ in2,
-               T* __restrict__ out, int accumulate) {
+tensor3_kernel(XferArgs<T> a) {
   using S = TrShape<NI, NO>;
   constexpr int M3 = S::M3, EPB = S::EPB, I3 = NI * NI * NI, O3 = NO * NO * NO;
-  const int lb = xcd_block((E + EPB - 1) / EPB);
-  if (lb < 0) return;
+  const int nsub = a.nrhs * a.ncomp;
+  const int lbs = xcd_block(((a.nel + EPB - 1) / EPB) * nsub);
+  if (lbs < 0) return;
+  const int lb = lbs / nsub, sub = lbs - lb * nsub;
+  const int rhs = sub / a.ncomp, comp = sub - rhs * a.ncomp;
   const int tid = threadIdx.x;
   const int le = tid / M3, q = tid - le * M3;
-  const int e = lb * EPB + le;
-  const bool act = le < EPB && e < E;
+  const int li = lb * EPB + le;
+  const bool act = le < EPB && li < a.nel;
+  const int e = act ? (a.elist ? a.elist[li] : li) : 0;
+  const int64_t ib = (int64_t)rhs * a.stride_in + (a.off_in ? a.off_in[e] : (int64_t)e * I3) * a.ncomp +
+                     (int64_t)comp * I3;
+  const int64_t ob = (int64_t)rhs * a.stride_out + (a.off_out ? a.off_out[e] : (int64_t)e * O3) * a.ncomp +
+                     (int64_t)comp * O3;
   __shared__ T sT[NO * NI];
   __shared__ T s0[EPB][NI * NI * NI];
   __shared__ T s1[EPB][NI * NI * NO];
   __shared__ T s2[EPB][NI * NO * NO];
-  for (int t = tid; t < NO * NI; t += S::THREADS) sT[t] = Tm[t];
+  for (int t = tid; t < NO * NI; t += S::THREADS) sT[t] = a.Tm[t];
   if (act && q < I3) {
-    T v = in[(int64_t)e * I3 + q];
-    if (in2) v -= in2[(int64_t)e * I3 + q];
+    T v = a.in[ib + q];
+    if (a.in2) v -= a.in2[ib + q];
     s0[le][q] = v;
   }
   __syncthreads();
   if (act && q < NI * NI * NO) {   // [k][j][a]
-    const int a = q % NO, j = (q / NO) % NI, k = q / (NO * NI);
+    const int x = q % NO, j = (q / NO) % NI, k = q / (NO * NI);
     T s = 0;
-    for (int i = 0; i < NI; ++i) s += sT[a * NI + i] * s0[le][(k * NI + j) * NI + i];
+    for (int i = 0; i < NI; ++i) s += sT[x * NI + i] * s0[le][(k * NI + j) * NI + i];
     s1[le][q] = s;
   }
   __syncthreads();
   if (act && q < NI * NO * NO) {   // [k][b][a]
-    const int a = q % NO, b = (q / NO) % NO, k = q / (NO * NO);
+    const int x = q % NO, y = (q / NO) % NO, k = q / (NO * NO);
     T s = 0;
-    for (int j = 0; j < NI; ++j) s += sT[b * NI + j] * s1[le][(k * NI + j) * NO + a];
+    for (int j = 0; j < NI; ++j) s += sT[y * NI + j] * s1[le][(k * NI + j) * NO + x];
     s2[le][q] = s;
   }
   __syncthreads();
   if (act && q < O3) {             // [c][b][a]
-    const int a = q % NO, b = (q / NO) % NO, c = q / (NO * NO);
+    const int x = q % NO, y = (q / NO) % NO, c = q / (NO * NO);
     T s = 0;
-    for (int k = 0; k < NI; ++k) s += sT[c * NI + k] * s2[le][(k * NO + b) * NO + a];
-    const int64_t o = (int64_t)e * O3 + q;
-    out[o] = accumulate ? out[o] + s : s;
+    for (int k = 0; k < NI; ++k) s += sT[c * NI + k] * s2[le][(k * NO + y) * NO + x];
+    const int64_t o = ob + q;
+    a.out[o] = a.accumulate ? a.out[o] + s : s;
   }
 }
 
 template <int NI, int NO, typename T>
-void launch_t3(int E, const T* Tm, const T* in, const T* in2, T* out, int acc, hipStream_t st) {
+void launch_t3(const XferArgs<T>& a, hipStream_t st) {
   using S = TrShape<NI, NO>;
-  const int nb = (E + S::EPB - 1) / S::EPB;
-  hipLaunchKernelGGL((tensor3_kernel<NI, NO, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, E, Tm, in, in2, out,
-                     acc);
+  const int nb = ((a.nel + S::EPB - 1) / S::EPB) * a.nrhs * a.ncomp;
+  hipLaunchKernelGGL((tensor3_kernel<NI, NO, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
 }
 
 template <typename T>
-bool tensor3(int n_in, int n_out, int E, const T* Tm, const T* in, const T* in2, T* out, int acc, hipStream_t st) {
-#define T3C(a, b) \
-  if (n_in == a && n_out == b) { launch_t3<a, b, T>(E, Tm, in, in2, out, acc, st); return true; }
-  // p-coarsening pairs (p_c = max(1, p_f / 2)) and identity-degree copies
-  T3C(3, 2) T3C(2, 3) T3C(4, 2) T3C(2, 4) T3C(5, 3) T3C(3, 5) T3C(6, 3) T3C(3, 6)
-  T3C(7, 4) T3C(4, 7) T3C(8, 4) T3C(4, 8) T3C(9, 5) T3C(5, 9) T3C(2, 2)
-  T3C(3, 3) T3C(4, 4) T3C(5, 5) T3C(6, 6) T3C(7, 7) T3C(8, 8) T3C(9, 9)
+bool tensor3(int n_in, int n_out, const XferArgs<T>& a, hipStream_t st) {
+  if (a.nel <= 0) return true;
+#define T3C(x, y) \
+  if (n_in == x && n_out == y) { launch_t3<x, y, T>(a, st); return true; }
+  // p-coarsening pairs (p_c = max(1, p_f / 2)), identity-degree copies and the
+  // interpolations between any two degrees 1..8 used on mixed-degree meshes
+  T3C(2, 2) T3C(2, 3) T3C(2, 4) T3C(2, 5) T3C(2, 6) T3C(2, 7) T3C(2, 8) T3C(2, 9)
+  T3C(3, 2) T3C(3, 3) T3C(3, 4) T3C(3, 5) T3C(3, 6) T3C(3, 7) T3C(3, 8) T3C(3, 9)
+  T3C(4, 2) T3C(4, 3) T3C(4, 4) T3C(4, 5) T3C(4, 6) T3C(4, 7) T3C(4, 8) T3C(4, 9)
+  T3C(5, 2) T3C(5, 3) T3C(5, 4) T3C(5, 5) T3C(5, 6) T3C(5, 7) T3C(5, 8) T3C(5, 9)
+  T3C(6, 2) T3C(6, 3) T3C(6, 4) T3C(6, 5) T3C(6, 6) T3C(6, 7) T3C(6, 8) T3C(6, 9)
+  T3C(7, 2) T3C(7, 3) T3C(7, 4) T3C(7, 5) T3C(7, 6) T3C(7, 7) T3C(7, 8) T3C(7, 9)
+  T3C(8, 2) T3C(8, 3) T3C(8, 4) T3C(8, 5) T3C(8, 6) T3C(8, 7) T3C(8, 8) T3C(8, 9)
+  T3C(9, 2) T3C(9, 3) T3C(9, 4) T3C(9, 5) T3C(9, 6) T3C(9, 7) T3C(9, 8) T3C(9, 9)
 #undef T3C
   return false;
 }
 
-template bool tensor3<double>(int, int, int, const double*, const double*, const double*, double*, int, hipStream_t);
-template bool tensor3<float>(int, int, int, const float*, const float*, const float*, float*, int, hipStream_t);
+template bool tensor3<double>(int, int, const XferArgs<double>&, hipStream_t);
+template bool tensor3<float>(int, int, const XferArgs<float>&, hipStream_t);
 
 // ---------------------------------------------------------------------------
 constexpr int kRedThreads = 256;
@@ -141,6 +157,9 @@ template void dot_partials<float>(int64_t, int, const float*, const float*, cons
 // Second stage, one block per right-hand side: sums its partials (for kOpBeta also the
 // second set at partial2) and applies the SCG scalar update selected by `op`.
 //   scal[rhs * 8 + k]: 0 gamma (z^T r)  1 beta  2 alpha  3 r^T r  4 breakdown flag  5 p^T q
+//                      6 stopping threshold on |r| (0: none)  7 converged flag
+// A right-hand side whose |r| has reached its threshold is frozen (alpha = 0 from then on),
+// so that in a batch every right-hand side stops at the iteration it would stop at alone.
 __global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double* __restrict__ partial,
                                                       const double* __restrict__ partial2, int op,
                                                       double* __restrict__ scal, double* __restrict__ out) {
@@ -171,13 +190,15 @@ __global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double*
     case kOpAlpha: {        // alpha = gamma / p^T q; a converged right-hand side (p = 0) takes alpha = 0
       sc[5] = s0;
       double alpha = (s0 != 0.0) ? sc[0] / s0 : 0.0;
-      if (s0 < 0.0 || !isfinite(alpha)) { sc[4] = 1.0; alpha = 0.0; }
+      if (sc[7] != 0.0) alpha = 0.0;
+      else if (s0 < 0.0 || !isfinite(alpha)) { sc[4] = 1.0; alpha = 0.0; }
       sc[2] = alpha;
       break;
     }
     case kOpNorm2:          // r^T r
       sc[3] = s0;
       if (!isfinite(s0)) sc[4] = 1.0;
+      if (sc[6] > 0.0 && sqrt(s0) <= sc[6]) sc[7] = 1.0;
       break;
     case kOpStore:
       out[rhs] = s0;

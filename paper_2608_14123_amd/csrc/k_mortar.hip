@@ -1,0 +1,226 @@
+// K1m: SIPG face terms of faces between elements of different degree (mixed-degree
+// levels; the paper keeps one degree per level, so this is an extension of
+// eq. helmholtz:dgm).  Such a face is integrated with the GLL rule of the finer side:
+// each side's trace and normal flux nu n.grad u are interpolated from its own face nodes
+// to that grid, the penalty mu_F uses both degrees, and the test functions of the own
+// element are its basis on the finer grid, so row terms are restricted back with the
+// transposed interpolation.  The lifting term uses the restricted jump times the own
+// nu n.grad xi_c, written into the transposed volume contractions as in sipg_apply.
+//
+// One workgroup per (element, right-hand side) of the list; the element's faces are taken
+// one after another and every output node is written by one thread, so the result is
+// deterministic.  Degrees are runtime values (tables for p = 1..8 in global memory).
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace dgfas {
+
+namespace {
+
+constexpr int kMaxN = 9, kMaxN2 = 81, kMaxN3 = 729, kMortarThreads = 256;
+
+__device__ __forceinline__ int fnode(int n, int phi, int f, int t) {
+  const int a = f / n, b = f - a * n, ax = phi >> 1;
+  if (ax == 0) return (a * n + b) * n + t;
+  if (ax == 1) return (a * n + t) * n + b;
+  return (t * n + a) * n + b;
+}
+
+__device__ __forceinline__ int lstride(int n, int ax) { return ax == 0 ? 1 : (ax == 1 ? n : n * n); }
+
+// trace, normal flux (nu n_out . grad u, without omega s) and metric row G_ax. at the face
+// nodes of face phi of an element of size n: phase A (line derivative, trace, loads)
+// (u read at src[sbase + node], the metric at G[c * ndof + gbase + node])
+template <typename T>
+__device__ void face_phase_a(int n, int phi, int f, const T* __restrict__ src, int64_t sbase, int64_t gbase,
+                             const T* __restrict__ G, int64_t ndof, const double* __restrict__ D, T* tr, T* dn,
+                             T (*gr)[kMaxN2]) {
+  const int ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0, st = lstride(n, ax);
+  const int v0 = fnode(n, phi, f, 0);
+  T d = 0, t = 0;
+  for (int m = 0; m < n; ++m) {
+    const T v = src[sbase + v0 + m * st];
+    d += (T)D[endo * n + m] * v;
+    if (m == endo) t = v;
+  }
+  tr[f] = t;
+  dn[f] = d;
+  const int vi = v0 + endo * st;
+  for (int c = 0; c < 3; ++c) gr[c][f] = G[sym_index(ax, c) * ndof + gbase + vi];
+}
+
+// phase B (after the traces are in LDS): tangential derivatives and the flux
+template <typename T>
+__device__ T face_flux(int n, int phi, int f, const double* __restrict__ D, const T* tr, const T* dn,
+                       const T (*gr)[kMaxN2], T sgn, T inv_wend, T wsf) {
+  const int ax = phi >> 1, a = f / n, b = f - a * n;
+  T dlast = 0, dfirst = 0;
+  for (int m = 0; m < n; ++m) {
+    dlast += (T)D[b * n + m] * tr[a * n + m];
+    dfirst += (T)D[a * n + m] * tr[m * n + b];
+  }
+  T du0, du1, du2;
+  if (ax == 0) { du0 = dn[f]; du1 = dlast; du2 = dfirst; }
+  else if (ax == 1) { du0 = dlast; du1 = dn[f]; du2 = dfirst; }
+  else { du0 = dlast; du1 = dfirst; du2 = dn[f]; }
+  const T fl = gr[0][f] * du0 + gr[1][f] * du1 + gr[2][f] * du2;
+  return sgn * inv_wend * fl / wsf;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<T> a) {
+  const int lbr = xcd_block(a.nel * a.nrhs);
+  if (lbr < 0) return;
+  const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
+  const int e = a.elist[li];
+  const int tid = threadIdx.x;
+  const T* __restrict__ u = a.u + (int64_t)rhs * a.ndof;
+  T* __restrict__ out = a.out + (int64_t)rhs * a.ndof;
+  const int po = a.deg[e], n = po + 1, n2 = n * n, n3 = n2 * n;
+  const int64_t base = a.off[e], fbase = a.offF[e];
+  const double* __restrict__ Do = a.Dall + (po - 1) * kMaxN2;
+  const T inv_wend_o = (T)(0.5 * po * (po + 1));
+
+  __shared__ T su[kMaxN3];
+  __shared__ T acc[kMaxN3];
+  __shared__ T to[kMaxN2], dno[kMaxN2], qo[kMaxN2], wso[kMaxN2], go[3][kMaxN2];
+  __shared__ T tn[kMaxN2], dnn[kMaxN2], qn[kMaxN2], wsn[kMaxN2], gn[3][kMaxN2];
+  __shared__ T x1[4][kMaxN2];                 // half-interpolated own t, own q, nb t, nb q
+  __shared__ T rF[kMaxN2], sF[kMaxN2];     // row term and lifting weight on the finer grid
+  __shared__ T y1[2][kMaxN2];                 // half-restricted row and lifting weight
+  __shared__ T row[kMaxN2], lift[3][kMaxN2];
+
+  for (int t = tid; t < n3; t += kMortarThreads) {
+    su[t] = u[base + t];
+    acc[t] = 0;
+  }
+  __syncthreads();
+
+  for (int phi = 0; phi < 6; ++phi) {
+    const int en = a.nbr[(int64_t)e * 6 + phi];
+    if (en < 0) continue;
+    const int pn = a.deg[en];
+    if (pn == po) continue;                 // uniform over the workgroup
+    const int nn = pn + 1, nn2 = nn * nn, nF = nn > n ? nn : n, nF2 = nF * nF;
+    const int phin = phi ^ 1, ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0;
+    const double* __restrict__ Dn = a.Dall + (pn - 1) * kMaxN2;
+    const int pF = nF - 1;
+    const double* __restrict__ Io = a.Iall + ((po - 1) * 8 + (pF - 1)) * kMaxN2;   // nF x n
+    const double* __restrict__ In = a.Iall + ((pn - 1) * 8 + (pF - 1)) * kMaxN2;   // nF x nn
+    const T sgn = (phi & 1) ? T(1) : T(-1);
+    const T inv_wend_n = (T)(0.5 * pn * (pn + 1));
+    const T mu = (T)a.muf[(int64_t)e * 6 + phi];
+    const int64_t nbase = a.off[en], nfbase = a.offF[en];
+
+    // A: traces, normal-line derivatives, metric rows and omega s of both sides
+    for (int t = tid; t < n2 + nn2; t += kMortarThreads) {
+      if (t < n2) {
+        face_phase_a<T>(n, phi, t, su, 0, base, a.G, a.ndof, Do, to, dno, go);
+        wso[t] = (T)a.ws[fbase + phi * n2 + t];
+      } else {
+        const int f = t - n2;
+        face_phase_a<T>(nn, phin, f, u, nbase, nbase, a.G, a.ndof, Dn, tn, dnn, gn);
+        wsn[f] = (T)a.ws[nfbase + phin * nn2 + f];
+      }
+    }
+    __syncthreads();
+    // B: normal fluxes (each side's outward normal)
+    for (int t = tid; t < n2 + nn2; t += kMortarThreads) {
+      if (t < n2) qo[t] = face_flux<T>(n, phi, t, Do, to, dno, go, sgn, inv_wend_o, wso[t]);
+      else qn[t - n2] = face_flux<T>(nn, phin, t - n2, Dn, tn, dnn, gn, -sgn, inv_wend_n, wsn[t - n2]);
+    }
+    __syncthreads();
+    // C: first interpolation step X1[i][b] = sum_a I[i][a] X[a][b] for the four face fields
+    for (int t = tid; t < 2 * nF * n + 2 * nF * nn; t += kMortarThreads) {
+      int s = t, which, w;
+      if (s < 2 * nF * n) { which = s / (nF * n); s -= which * nF * n; w = n; }
+      else { s -= 2 * nF * n; which = 2 + s / (nF * nn); s -= (which - 2) * nF * nn; w = nn; }
+      const int i = s / w, b = s - i * w;
+      const double* I = which < 2 ? Io : In;
+      const T* X = which == 0 ? to : (which == 1 ? qo : (which == 2 ? tn : qn));
+      T v = 0;
+      for (int q = 0; q < w; ++q) v += (T)I[i * w + q] * X[q * w + b];
+      x1[which][i * w + b] = v;
+    }
+    __syncthreads();
+    // D: second step and the differences on the finer grid
+    for (int t = tid; t < nF2; t += kMortarThreads) {
+      const int i = t / nF, j = t - i * nF;
+      T t_o = 0, q_o = 0, t_n = 0, q_n = 0;
+      for (int b = 0; b < n; ++b) {
+        const T ij = (T)Io[j * n + b];
+        t_o += x1[0][i * n + b] * ij;
+        q_o += x1[1][i * n + b] * ij;
+      }
+      for (int b = 0; b < nn; ++b) {
+        const T ij = (T)In[j * nn + b];
+        t_n += x1[2][i * nn + b] * ij;
+        q_n += x1[3][i * nn + b] * ij;
+      }
+      // omega s of the finer side, in its own face-node order (shared orientation)
+      const T wF = n > nn ? wso[t] : wsn[t];
+      const T jt = t_o - t_n, jq = q_o - q_n;
+      rF[t] = wF * (mu * jt - T(0.5) * jq);
+      sF[t] = T(-0.5) * wF * jt;
+    }
+    __syncthreads();
+    // E: restriction, first step Y1[a][j] = sum_i I[i][a] F[i][j]
+    for (int t = tid; t < 2 * n * nF; t += kMortarThreads) {
+      const int which = t / (n * nF), s = t - which * n * nF;
+      const int aa = s / nF, j = s - aa * nF;
+      const T* F = which == 0 ? rF : sF;
+      T v = 0;
+      for (int i = 0; i < nF; ++i) v += (T)Io[i * n + aa] * F[i * nF + j];
+      y1[which][aa * nF + j] = v;
+    }
+    __syncthreads();
+    // F: second step; the lifting weight divided by the own omega s times the own metric row
+    for (int t = tid; t < n2; t += kMortarThreads) {
+      const int aa = t / n, b = t - aa * n;
+      T r = 0, sgm = 0;
+      for (int j = 0; j < nF; ++j) {
+        const T ij = (T)Io[j * n + b];
+        r += y1[0][aa * nF + j] * ij;
+        sgm += y1[1][aa * nF + j] * ij;
+      }
+      row[t] = r;
+      const T sc = sgm / wso[t] * sgn * inv_wend_o;
+      for (int c = 0; c < 3; ++c) lift[c][t] = sc * go[c][t];
+    }
+    __syncthreads();
+    // G: accumulate per output node: row at the face, lifting through D^T along every axis
+    const int tb = ax == 0 ? 1 : 0;   // axis of the fast face index b
+    const int ta = ax == 2 ? 1 : 2;   // axis of the slow face index a
+    for (int t = tid; t < n3; t += kMortarThreads) {
+      const int idx[3] = {t % n, (t / n) % n, t / n2};
+      const int l = idx[ax], fa = idx[ta], fb = idx[tb], f = fa * n + fb;
+      T v = (T)Do[endo * n + l] * lift[ax][f];
+      if (l == endo) {
+        v += row[f];
+        for (int m = 0; m < n; ++m) {
+          v += (T)Do[m * n + fb] * lift[tb][fa * n + m];
+          v += (T)Do[m * n + fa] * lift[ta][m * n + fb];
+        }
+      }
+      acc[t] += v;
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < n3; t += kMortarThreads) {
+    const T v = acc[t];
+    out[base + t] = a.mode == 0 ? out[base + t] - v : out[base + t] + v;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void sipg_mortar(const MortarArgs<T>& a, hipStream_t st) {
+  if (a.nel <= 0) return;
+  hipLaunchKernelGGL((sipg_mortar_kernel<T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(kMortarThreads), 0, st, a);
+}
+
+template void sipg_mortar<double>(const MortarArgs<double>&, hipStream_t);
+template void sipg_mortar<float>(const MortarArgs<float>&, hipStream_t);
+
+}  // namespace dgfas

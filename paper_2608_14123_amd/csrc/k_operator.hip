@@ -25,19 +25,27 @@ struct OpShape {
 
 template <int N, typename T>
 __global__ void __launch_bounds__(OpShape<N>::THREADS)
-sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict__ g, T* __restrict__ out, int mode,
-                  const T* __restrict__ G, const T* __restrict__ WJ, const T* __restrict__ pen,
-                  const int* __restrict__ nbr, const int8_t* __restrict__ bc, const T* __restrict__ Dg,
-                  T kappa, T inv_wend) {
+sipg_apply_kernel(OpArgs<T> a) {
   using S = OpShape<N>;
+  const int nrhs = a.nrhs, nel = a.nel, mode = a.mode;
+  const T* __restrict__ u = a.u;
+  const T* __restrict__ g = a.g;
+  T* __restrict__ out = a.out;
+  const T* __restrict__ G = a.G;
+  const T* __restrict__ WJ = a.WJ;
+  const T* __restrict__ pen = a.pen;
+  const int* __restrict__ nbr = a.nbr;
+  const int8_t* __restrict__ bc = a.bc;
+  const T* __restrict__ Dg = a.D;
+  const T kappa = a.kappa, inv_wend = a.inv_wend;
   constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
   constexpr int TPT = (6 * N2 + N3 - 1) / N3;     // face tasks per thread
   // logical block = (element block, right-hand side) with the right-hand side fastest, so
   // that the batch of one element reads its geometry while it is resident in L2
-  const int lbr = xcd_block(((E + EPB - 1) / EPB) * nrhs);
+  const int lbr = xcd_block(((nel + EPB - 1) / EPB) * nrhs);
   if (lbr < 0) return;
   const int lb = lbr / nrhs;
-  const int64_t ndof = (int64_t)E * N3;
+  const int64_t ndof = a.ndof;
   const int64_t voff = (int64_t)(lbr - lb * nrhs) * ndof;
   u += voff;
   out += voff;
@@ -45,8 +53,9 @@ sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict_
   const int tid = threadIdx.x;
   const int le = tid / N3;
   const int node = tid - le * N3;
-  const int e = lb * EPB + le;
-  const bool active = (le < EPB) && (e < E);
+  const int li = lb * EPB + le;
+  const bool active = (le < EPB) && (li < nel);
+  const int e = active ? (a.elist ? a.elist[li] : li) : 0;
 
   __shared__ T sD[N2];
   __shared__ T su[EPB][N3];
@@ -55,7 +64,8 @@ sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict_
   __shared__ T sRow[EPB][6][N2];   // direct face-row term
   __shared__ T sSig[EPB][6][N2];   // lifting weight sigma
 
-  const int64_t base = (int64_t)e * N3;
+  const int64_t base = a.off ? a.off[e] : (int64_t)e * N3;
+  const int64_t fbase = a.offF ? a.offF[e] : (int64_t)e * 6 * N2;
   // prologue: every independent load first (neighbour ids, penalties, boundary codes, u, metric, g)
   int en_t[TPT];
   T pen_t[TPT];
@@ -68,8 +78,10 @@ sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict_
     bc_t[k] = 0;
     if (active && t < 6 * N2) {
       const int phi = t / N2;
-      en_t[k] = nbr[(int64_t)e * 6 + phi];
-      pen_t[k] = pen[(int64_t)e * 6 * N2 + t];
+      int en = nbr[(int64_t)e * 6 + phi];
+      if (en >= 0 && a.deg && a.deg[en] != N - 1) en = -2;   // other degree: mortar kernel
+      en_t[k] = en;
+      pen_t[k] = pen[fbase + t];
       bc_t[k] = bc[(int64_t)e * 6 + phi];
     }
   }
@@ -97,9 +109,10 @@ sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict_
     if (en >= 0) {
       const int phio = phi ^ 1;
       const int endo = (phio & 1) ? N - 1 : 0;
-      const T* line = u + (int64_t)en * N3 + face_node<N>(phio, f, 0);
+      const int64_t nbase = a.off ? a.off[en] : (int64_t)en * N3;
+      const T* line = u + nbase + face_node<N>(phio, f, 0);
       const int st = axis_stride<N>(ax);
-      const int64_t gi = (int64_t)en * N3 + face_node<N>(phio, f, endo);
+      const int64_t gi = nbase + face_node<N>(phio, f, endo);
 #pragma unroll
       for (int c = 0; c < 3; ++c) gn[k][c] = G[sym_index(ax, c) * ndof + gi];
       T dn = 0;
@@ -160,7 +173,7 @@ sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict_
       const T jmp = uo - sTr[le][phi][f];
       row = pf * jmp - T(0.5) * (qo - qn);
       sigma = T(-0.5) * jmp;
-    } else if (bc_t[kk] == 1) {                      // Dirichlet: 2 mu nu omega s u - q, lifting -u
+    } else if (en_t[kk] == -1 && bc_t[kk] == 1) {    // Dirichlet: 2 mu nu omega s u - q, lifting -u
       row = pf * uo - qo;
       sigma = -uo;
     }
@@ -205,9 +218,8 @@ sipg_apply_kernel(int E, int nrhs, const T* __restrict__ u, const T* __restrict_
 template <int N, typename T>
 void launch_sipg(const OpArgs<T>& a, hipStream_t st) {
   using S = OpShape<N>;
-  const int nb = ((a.E + S::EPB - 1) / S::EPB) * a.nrhs;
-  hipLaunchKernelGGL((sipg_apply_kernel<N, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a.E, a.nrhs, a.u, a.g,
-                     a.out, a.mode, a.G, a.WJ, a.pen, a.nbr, a.bc, a.D, a.kappa, a.inv_wend);
+  const int nb = ((a.nel + S::EPB - 1) / S::EPB) * a.nrhs;
+  hipLaunchKernelGGL((sipg_apply_kernel<N, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
 }
 
 template <typename T>
@@ -235,23 +247,31 @@ template void sipg_apply<float>(int, const OpArgs<float>&, hipStream_t);
 // linear Legendre coefficients of the map (surrogate cuboid, Sec. 4.3.1).
 template <int N>
 __global__ void __launch_bounds__(OpShape<N>::THREADS)
-geometry_kernel(int E, const double* __restrict__ X, const double* __restrict__ Dg, const double* __restrict__ w1,
-                const double* __restrict__ x1, double nu, double* __restrict__ G, double* __restrict__ WJ,
-                double* __restrict__ ws, double* __restrict__ vol, double* __restrict__ area,
-                double* __restrict__ lin, int* __restrict__ bad) {
+geometry_kernel(GeoArgs g, const double* __restrict__ Dg, const double* __restrict__ w1,
+                const double* __restrict__ x1, double nu) {
   using S = OpShape<N>;
   constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
+  const double* __restrict__ X = g.X;
+  double* __restrict__ G = g.G;
+  double* __restrict__ WJ = g.WJ;
+  double* __restrict__ ws = g.ws;
+  double* __restrict__ vol = g.vol;
+  double* __restrict__ area = g.area;
+  double* __restrict__ lin = g.lin;
   const int lb = blockIdx.x;
   const int tid = threadIdx.x;
   const int le = tid / N3;
   const int node = tid - le * N3;
-  const int e = lb * EPB + le;
-  const bool active = (le < EPB) && (e < E);
+  const int li = lb * EPB + le;
+  const bool active = (le < EPB) && (li < g.nel);
+  const int e = active ? (g.elist ? g.elist[li] : li) : 0;
+  const int64_t base = g.off ? g.off[e] : (int64_t)e * N3;
+  const int64_t fbase = g.offF ? g.offF[e] : (int64_t)e * 6 * N2;
   __shared__ double sX[EPB][3][N3];
   __shared__ double sWJ[EPB][N3];
   __shared__ double sws[EPB][6][N2];
   if (active)
-    for (int a = 0; a < 3; ++a) sX[le][a][node] = X[((int64_t)e * 3 + a) * N3 + node];
+    for (int a = 0; a < 3; ++a) sX[le][a][node] = X[3 * base + (int64_t)a * N3 + node];
   __syncthreads();
   const int i = node % N, j = (node / N) % N, k = node / N2;
   if (active) {
@@ -277,10 +297,10 @@ geometry_kernel(int E, const double* __restrict__ X, const double* __restrict__ 
     C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
     C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
-    if (!(det > 0)) atomicOr(bad, 1);
+    if (!(det > 0)) atomicOr(g.bad, 1);
     const double wq = w1[i] * w1[j] * w1[k];
     // grad xi_b = C[:, b] / det  ->  G_bc = w nu (C[:,b] . C[:,c]) / det
-    const int64_t ndof = (int64_t)E * N3, gi = (int64_t)e * N3 + node;
+    const int64_t ndof = g.ndof, gi = base + node;
     const double sc = wq * nu / det;
     double Gb[6];
     Gb[0] = sc * (C[0][0] * C[0][0] + C[1][0] * C[1][0] + C[2][0] * C[2][0]);
@@ -316,7 +336,7 @@ geometry_kernel(int E, const double* __restrict__ X, const double* __restrict__ 
       double a = 0;
       for (int f = 0; f < N2; ++f) a += sws[le][task][f];
       area[(int64_t)e * 6 + task] = a;
-      for (int f = 0; f < N2; ++f) ws[((int64_t)e * 6 + task) * N2 + f] = sws[le][task][f];
+      for (int f = 0; f < N2; ++f) ws[fbase + task * N2 + f] = sws[le][task][f];
     } else if (task == 6) {
       double v = 0;
       for (int t = 0; t < N3; ++t) v += sWJ[le][t];
@@ -345,56 +365,62 @@ geometry_kernel(int E, const double* __restrict__ X, const double* __restrict__ 
 }
 
 template <int N>
-void launch_geometry(int E, const double* X, const double* D, const double* w, const double* x, double nu, double* G,
-                     double* WJ, double* ws, double* vol, double* area, double* lin, int* bad, hipStream_t st) {
+void launch_geometry(const GeoArgs& g, const double* D, const double* w, const double* x, double nu, hipStream_t st) {
   using S = OpShape<N>;
-  const int nb = (E + S::EPB - 1) / S::EPB;
-  hipLaunchKernelGGL((geometry_kernel<N>), dim3(nb), dim3(S::THREADS), 0, st, E, X, D, w, x, nu, G, WJ, ws, vol,
-                     area, lin, bad);
+  const int nb = (g.nel + S::EPB - 1) / S::EPB;
+  if (nb > 0) hipLaunchKernelGGL((geometry_kernel<N>), dim3(nb), dim3(S::THREADS), 0, st, g, D, w, x, nu);
 }
 
-void geometry(int p, int E, const double* X, const double* D, const double* w, const double* x, double nu,
-              double* G, double* WJ, double* ws, double* vol, double* area, double* lin, int* bad, hipStream_t st) {
+void geometry(int p, const GeoArgs& g, const double* D, const double* w, const double* x, double nu,
+              hipStream_t st) {
   switch (p) {
-    case 1: launch_geometry<2>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
-    case 2: launch_geometry<3>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
-    case 3: launch_geometry<4>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
-    case 4: launch_geometry<5>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
-    case 5: launch_geometry<6>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
-    case 6: launch_geometry<7>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
-    case 7: launch_geometry<8>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
-    case 8: launch_geometry<9>(E, X, D, w, x, nu, G, WJ, ws, vol, area, lin, bad, st); break;
+    case 1: launch_geometry<2>(g, D, w, x, nu, st); break;
+    case 2: launch_geometry<3>(g, D, w, x, nu, st); break;
+    case 3: launch_geometry<4>(g, D, w, x, nu, st); break;
+    case 4: launch_geometry<5>(g, D, w, x, nu, st); break;
+    case 5: launch_geometry<6>(g, D, w, x, nu, st); break;
+    case 6: launch_geometry<7>(g, D, w, x, nu, st); break;
+    case 7: launch_geometry<8>(g, D, w, x, nu, st); break;
+    case 8: launch_geometry<9>(g, D, w, x, nu, st); break;
     default: break;
   }
 }
 
 // Penalty factor per element-face node: interior mu_F nu omega s with
-// mu_F = mu_star avg(p(p+1)/(2 h_perp)), Dirichlet 2 mu nu omega s, Neumann 0;
-// h_perp = vol / area (eq. helmholtz:dgm).
-__global__ void penalty_kernel(int E, int N2, int p, double mu_star, double nu, const int* __restrict__ nbr,
+// mu_F = mu_star avg(p(p+1)/(2 h_perp)) over the two sides (each with its own degree),
+// Dirichlet 2 mu nu omega s, Neumann 0; h_perp = vol / area (eq. helmholtz:dgm).
+// muf[e][phi] = mu_F nu (Dirichlet: 2 mu nu) for the face integration on mixed-degree faces.
+__global__ void penalty_kernel(int E, int p, const int* __restrict__ deg, const int64_t* __restrict__ offF,
+                               double mu_star, double nu, const int* __restrict__ nbr,
                                const int8_t* __restrict__ bc, const double* __restrict__ vol,
                                const double* __restrict__ area, const double* __restrict__ ws,
-                               double* __restrict__ pen) {
+                               double* __restrict__ pen, double* __restrict__ muf) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)E * 6) return;
   const int e = (int)(t / 6), phi = (int)(t % 6);
-  const double own = p * (p + 1) / (2.0 * (vol[e] / area[t]));
+  const int pe = deg ? deg[e] : p;
+  const int N2 = (pe + 1) * (pe + 1);
+  const double own = pe * (pe + 1) / (2.0 * (vol[e] / area[t]));
   const int en = nbr[t];
   double fac = 0.0;
   if (en >= 0) {
-    const double oth = p * (p + 1) / (2.0 * (vol[en] / area[(int64_t)en * 6 + (phi ^ 1)]));
+    const int pn = deg ? deg[en] : p;
+    const double oth = pn * (pn + 1) / (2.0 * (vol[en] / area[(int64_t)en * 6 + (phi ^ 1)]));
     fac = mu_star * 0.5 * (own + oth) * nu;
   } else if (bc[t] == 1) {
     fac = 2.0 * mu_star * own * nu;
   }
-  for (int f = 0; f < N2; ++f) pen[t * N2 + f] = fac * ws[t * N2 + f];
+  if (muf) muf[t] = fac;
+  const int64_t fb = (offF ? offF[e] : (int64_t)e * 6 * N2) + (int64_t)phi * N2;
+  for (int f = 0; f < N2; ++f) pen[fb + f] = fac * ws[fb + f];
 }
 
-void penalty(int E, int p, double mu_star, double nu, const int* nbr, const int8_t* bc, const double* vol,
-             const double* area, const double* ws, double* pen, hipStream_t st) {
+void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const int* nbr,
+             const int8_t* bc, const double* vol, const double* area, const double* ws, double* pen, double* muf,
+             hipStream_t st) {
   const int64_t n = (int64_t)E * 6;
-  hipLaunchKernelGGL(penalty_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, E, (p + 1) * (p + 1), p,
-                     mu_star, nu, nbr, bc, vol, area, ws, pen);
+  hipLaunchKernelGGL(penalty_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, E, p, deg, offF, mu_star,
+                     nu, nbr, bc, vol, area, ws, pen, muf);
 }
 
 }  // namespace dgfas
@@ -406,22 +432,31 @@ namespace dgfas {
 //   -nu omega s u_D (n . grad phi_q)) + Neumann faces (omega s q_N).
 template <int N>
 __global__ void __launch_bounds__(OpShape<N>::THREADS)
-rhs_kernel(int E, const double* __restrict__ f, const double* __restrict__ uD, const double* __restrict__ qN,
-           double* __restrict__ b, const double* __restrict__ G, const double* __restrict__ WJ,
-           const double* __restrict__ pen, const double* __restrict__ ws, const int* __restrict__ nbr,
-           const int8_t* __restrict__ bc, const double* __restrict__ Dg, double inv_wend) {
+rhs_kernel(RhsArgs r, const double* __restrict__ Dg, double inv_wend) {
   using S = OpShape<N>;
   constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
+  const double* __restrict__ f = r.f;
+  const double* __restrict__ uD = r.uD;
+  const double* __restrict__ qN = r.qN;
+  double* __restrict__ b = r.b;
+  const double* __restrict__ G = r.G;
+  const double* __restrict__ WJ = r.WJ;
+  const double* __restrict__ pen = r.pen;
+  const double* __restrict__ ws = r.ws;
+  const int* __restrict__ nbr = r.nbr;
+  const int8_t* __restrict__ bc = r.bc;
   const int lb = blockIdx.x;
   const int tid = threadIdx.x;
   const int le = tid / N3, node = tid - le * N3;
-  const int e = lb * EPB + le;
-  const bool active = (le < EPB) && (e < E);
+  const int li = lb * EPB + le;
+  const bool active = (le < EPB) && (li < r.nel);
+  const int e = active ? (r.elist ? r.elist[li] : li) : 0;
   __shared__ double sD[N2];
   __shared__ double sL[EPB][3][N3];
   __shared__ double sRow[EPB][N3];
   for (int t = tid; t < N2; t += S::THREADS) sD[t] = Dg[t];
-  const int64_t base = (int64_t)e * N3, ndof = (int64_t)E * N3;
+  const int64_t base = r.off ? r.off[e] : (int64_t)e * N3, ndof = r.ndof;
+  const int64_t fbase = r.offF ? r.offF[e] : (int64_t)e * 6 * N2;
   if (active) {
     sL[le][0][node] = sL[le][1][node] = sL[le][2][node] = 0.0;
     sRow[le][node] = 0.0;
@@ -438,10 +473,10 @@ rhs_kernel(int E, const double* __restrict__ f, const double* __restrict__ uD, c
         if (code == 1 && uD) {
           const double ud = uD[base + vi];
           const double sgn = (phi & 1) ? 1.0 : -1.0;
-          sRow[le][vi] += pen[((int64_t)e * 6 + phi) * N2 + fn] * ud;
+          sRow[le][vi] += pen[fbase + phi * N2 + fn] * ud;
           for (int c = 0; c < 3; ++c) sL[le][c][vi] += -ud * sgn * inv_wend * G[sym_index(ax, c) * ndof + base + vi];
         } else if (code == 2 && qN) {
-          sRow[le][vi] += ws[((int64_t)e * 6 + phi) * N2 + fn] * qN[base + vi];
+          sRow[le][vi] += ws[fbase + phi * N2 + fn] * qN[base + vi];
         }
       }
     }
@@ -460,27 +495,22 @@ rhs_kernel(int E, const double* __restrict__ f, const double* __restrict__ uD, c
 }
 
 template <int N>
-void launch_rhs(int E, const double* f, const double* uD, const double* qN, double* b, const double* G,
-                const double* WJ, const double* pen, const double* ws, const int* nbr, const int8_t* bc,
-                const double* D, double inv_wend, hipStream_t st) {
+void launch_rhs(const RhsArgs& r, const double* D, double inv_wend, hipStream_t st) {
   using S = OpShape<N>;
-  const int nb = (E + S::EPB - 1) / S::EPB;
-  hipLaunchKernelGGL((rhs_kernel<N>), dim3(nb), dim3(S::THREADS), 0, st, E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D,
-                     inv_wend);
+  const int nb = (r.nel + S::EPB - 1) / S::EPB;
+  if (nb > 0) hipLaunchKernelGGL((rhs_kernel<N>), dim3(nb), dim3(S::THREADS), 0, st, r, D, inv_wend);
 }
 
-void rhs(int p, int E, const double* f, const double* uD, const double* qN, double* b, const double* G,
-         const double* WJ, const double* pen, const double* ws, const int* nbr, const int8_t* bc, const double* D,
-         double inv_wend, hipStream_t st) {
+void rhs(int p, const RhsArgs& r, const double* D, double inv_wend, hipStream_t st) {
   switch (p) {
-    case 1: launch_rhs<2>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
-    case 2: launch_rhs<3>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
-    case 3: launch_rhs<4>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
-    case 4: launch_rhs<5>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
-    case 5: launch_rhs<6>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
-    case 6: launch_rhs<7>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
-    case 7: launch_rhs<8>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
-    case 8: launch_rhs<9>(E, f, uD, qN, b, G, WJ, pen, ws, nbr, bc, D, inv_wend, st); break;
+    case 1: launch_rhs<2>(r, D, inv_wend, st); break;
+    case 2: launch_rhs<3>(r, D, inv_wend, st); break;
+    case 3: launch_rhs<4>(r, D, inv_wend, st); break;
+    case 4: launch_rhs<5>(r, D, inv_wend, st); break;
+    case 5: launch_rhs<6>(r, D, inv_wend, st); break;
+    case 6: launch_rhs<7>(r, D, inv_wend, st); break;
+    case 7: launch_rhs<8>(r, D, inv_wend, st); break;
+    case 8: launch_rhs<9>(r, D, inv_wend, st); break;
     default: break;
   }
 }

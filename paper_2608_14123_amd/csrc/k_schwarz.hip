@@ -42,6 +42,17 @@ struct Regions {
   }
 };
 
+// first DOF of element e, and first inbox slot of element e
+template <int N, typename T>
+__device__ __forceinline__ int64_t elem_base(const SchwarzArgs<T>& a, int e) {
+  return a.off ? a.off[e] : (int64_t)e * (N * N * N);
+}
+template <int N, int M, typename T>
+__device__ __forceinline__ int64_t inbox_base(const SchwarzArgs<T>& a, int e) {
+  constexpr Regions<N, M> R{};
+  return a.offO ? a.offO[e] : (int64_t)e * R.size;
+}
+
 int overlap_size(int p, int m) {
   const int n = p + 1;
   return 6 * m * n * n + 12 * m * m * n + 8 * m * m * m;
@@ -53,13 +64,14 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   using Sh = SzShape<N, M>;
   constexpr int NS = Sh::NS, LS = Sh::LS, N3 = N * N * N, THR = Sh::THREADS;
   constexpr Regions<N, M> R{};
-  const int lbr = xcd_block(a.E * a.nrhs);
+  const int lbr = xcd_block(a.nel * a.nrhs);
   if (lbr < 0) return;
-  const int e = lbr / a.nrhs, rhs = lbr - e * a.nrhs;   // right-hand side fastest
+  const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;   // right-hand side fastest
+  const int e = a.elist ? a.elist[li] : li;
   if (a.sel && !a.sel[e]) return;
-  a.r += (int64_t)rhs * a.E * N3;
-  a.z += (int64_t)rhs * a.E * N3;
-  a.O += (int64_t)rhs * a.E * R.size;
+  a.r += (int64_t)rhs * a.ndof;
+  a.z += (int64_t)rhs * a.ndof;
+  a.O += (int64_t)rhs * a.nin;
   const int tid = threadIdx.x;
 
   __shared__ T tA[Sh::TILE];
@@ -85,7 +97,9 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     sMap[d][q] = a.map1d[v * NS + q];
   }
   if (tid < 27) {
-    sNb[tid] = a.nb27[(int64_t)e * 27 + tid];
+    int nb = a.nb27[(int64_t)e * 27 + tid];
+    if (nb >= 0 && a.deg && a.deg[nb] != N - 1) nb = -1;   // another degree: zero fill, no scatter
+    sNb[tid] = nb;
     sOff[tid] = R.off[tid];
   }
   const T g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
@@ -105,7 +119,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
         const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
         if (m1 >= 0 && m2 >= 0 && m3 >= 0) {
           const int src = sNb[(m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6)];   // absent neighbour: zeros
-          if (src >= 0) vals[it] = a.r[(int64_t)src * N3 + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63)];
+          if (src >= 0) vals[it] = a.r[elem_base<N>(a, src) + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63)];
         }
       }
     }
@@ -221,7 +235,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, d3 = (m3 >> 6) - 1;
     const int l1 = m1 & 63, l2 = m2 & 63, l3 = m3 & 63;
     if (d1 == 0 && d2 == 0 && d3 == 0) {
-      const int64_t gi = (int64_t)e * N3 + (l3 * N + l2) * N + l1;
+      const int64_t gi = elem_base<N>(a, e) + (l3 * N + l2) * N + l1;
       if (a.mode == 0) a.z[gi] = v;
       else a.z[gi] += v;
     } else {
@@ -230,7 +244,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
       const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
       const int c1 = d1 < 0 ? l1 - (N - M) : l1, c2 = d2 < 0 ? l2 - (N - M) : l2, c3 = d3 < 0 ? l3 - (N - M) : l3;
       const int x1 = d1 ? M : N, x2 = d2 ? M : N;
-      a.O[(int64_t)dest * R.size + sOff[r] + (c3 * x2 + c2) * x1 + c1] = v;
+      a.O[inbox_base<N, M>(a, dest) + sOff[r] + (c3 * x2 + c2) * x1 + c1] = v;
     }
   }
 }
@@ -250,18 +264,19 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
   using Sh = AddShape<N>;
   constexpr int N3 = Sh::N3, EPB = Sh::EPB;
   constexpr Regions<N, M> R{};
-  const int lbr = xcd_block(((a.E + EPB - 1) / EPB) * a.nrhs);
+  const int lbr = xcd_block(((a.nel + EPB - 1) / EPB) * a.nrhs);
   if (lbr < 0) return;
   const int lb = lbr / a.nrhs, rhs = lbr - lb * a.nrhs;
-  a.z += (int64_t)rhs * a.E * N3;
-  a.O += (int64_t)rhs * a.E * R.size;
+  a.z += (int64_t)rhs * a.ndof;
+  a.O += (int64_t)rhs * a.nin;
   const int tid = threadIdx.x;
   __shared__ int sOff[27];
   if (tid < 27) sOff[tid] = R.off[tid];
   __syncthreads();
   const int le = tid / N3, node = tid - le * N3;
-  const int e = lb * EPB + le;
-  if (le >= EPB || e >= a.E) return;
+  const int li = lb * EPB + le;
+  if (le >= EPB || li >= a.nel) return;
+  const int e = a.elist ? a.elist[li] : li;
   const int l[3] = {node % N, (node / N) % N, node / (N * N)};
   // per direction the offset towards the one neighbour whose overlap can cover this node
   int od[3];
@@ -272,7 +287,7 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
     any = any || od[d] != 0;
   }
   if (!any) return;
-  const T* __restrict__ box = a.O + (int64_t)e * R.size;
+  const T* __restrict__ box = a.O + inbox_base<N, M>(a, e);
   // the up to 7 candidates (subsets of the non-zero directions): every load is issued
   // unconditionally (invalid ones read entry 0 and are masked) so that none waits on another
   T vals[7];
@@ -297,7 +312,7 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
   T acc = 0;
 #pragma unroll
   for (int t = 0; t < 7; ++t) acc += ok[t] ? vals[t] : T(0);
-  a.z[(int64_t)e * N3 + node] += acc;
+  a.z[elem_base<N>(a, e) + node] += acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -458,14 +473,14 @@ template void mark_subdomains<double>(int, int, const SchwarzArgs<double>&, cons
 
 template <int N, int M, typename T>
 void launch_schwarz(const SchwarzArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL((schwarz_solve_kernel<N, M, T>), dim3(xcd_grid(a.E * a.nrhs)), dim3(SzShape<N, M>::THREADS), 0,
+  hipLaunchKernelGGL((schwarz_solve_kernel<N, M, T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(SzShape<N, M>::THREADS), 0,
                      st, a);
 }
 
 template <int N, int M, typename T>
 void launch_overlap(const SchwarzArgs<T>& a, hipStream_t st) {
   using Sh = AddShape<N>;
-  const int nb = ((a.E + Sh::EPB - 1) / Sh::EPB) * a.nrhs;
+  const int nb = ((a.nel + Sh::EPB - 1) / Sh::EPB) * a.nrhs;
   hipLaunchKernelGGL((schwarz_overlap_add_kernel<N, M, T>), dim3(xcd_grid(nb)), dim3(Sh::THREADS), 0, st, a);
 }
 

@@ -8,7 +8,14 @@ namespace dgfas {
 template <typename T>
 struct OpArgs {
   int E = 0;
-  int nrhs = 1;               // vectors are [nrhs][E (p+1)^3]
+  int nrhs = 1;               // vectors are [nrhs][ndof]
+  int nel = 0;                // elements of this launch (the degree bucket)
+  const int* elist = nullptr; // [nel] element ids of the bucket (null: 0..nel-1)
+  const int64_t* off = nullptr;   // [E] first DOF of every element (null: e (p+1)^3)
+  const int64_t* offF = nullptr;  // [E] first face-node slot of every element (null: 6 e (p+1)^2)
+  const int* deg = nullptr;   // [E] degree of every element (null: all equal); faces to another
+                              // degree are left to the mortar kernel
+  int64_t ndof = 0;           // DOF per right-hand side (stride of G, WJ and of the batch)
   const T* u = nullptr;
   const T* g = nullptr;
   T* out = nullptr;
@@ -26,18 +33,74 @@ struct OpArgs {
 template <typename T>
 void sipg_apply(int p, const OpArgs<T>& a, hipStream_t st);
 
-void geometry(int p, int E, const double* X, const double* D, const double* w, const double* x, double nu,
-              double* G, double* WJ, double* ws, double* vol, double* area, double* lin, int* bad, hipStream_t st);
-void rhs(int p, int E, const double* f, const double* uD, const double* qN, double* b, const double* G,
-         const double* WJ, const double* pen, const double* ws, const int* nbr, const int8_t* bc, const double* D,
-         double inv_wend, hipStream_t st);
-void penalty(int E, int p, double mu_star, double nu, const int* nbr, const int8_t* bc, const double* vol,
-             const double* area, const double* ws, double* pen, hipStream_t st);
+// one-time geometry of a degree bucket (Sec. 2.2)
+struct GeoArgs {
+  int nel = 0;
+  const int* elist = nullptr;       // [nel] element ids (null: 0..nel-1)
+  const int64_t* off = nullptr;     // [E] first node per element (null: e (p+1)^3)
+  const int64_t* offF = nullptr;    // [E] first face-node slot per element (null: 6 e (p+1)^2)
+  int64_t ndof = 0;                 // nodes of the level (stride of G)
+  const double* X = nullptr;        // coordinates, element e at 3 off[e]: [3][(p+1)^3]
+  double *G = nullptr, *WJ = nullptr, *ws = nullptr, *vol = nullptr, *area = nullptr, *lin = nullptr;
+  int* bad = nullptr;               // set when det J <= 0 somewhere
+};
+void geometry(int p, const GeoArgs& g, const double* D, const double* w, const double* x, double nu,
+              hipStream_t st);
+
+struct RhsArgs {
+  int nel = 0;
+  const int* elist = nullptr;
+  const int64_t* off = nullptr;
+  const int64_t* offF = nullptr;
+  int64_t ndof = 0;
+  const double *f = nullptr, *uD = nullptr, *qN = nullptr;
+  double* b = nullptr;
+  const double *G = nullptr, *WJ = nullptr, *pen = nullptr, *ws = nullptr;
+  const int* nbr = nullptr;
+  const int8_t* bc = nullptr;
+};
+void rhs(int p, const RhsArgs& r, const double* D, double inv_wend, hipStream_t st);
+
+void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const int* nbr,
+             const int8_t* bc, const double* vol, const double* area, const double* ws, double* pen, double* muf,
+             hipStream_t st);
+
+// Face terms of the faces between elements of different degree (mixed-degree levels):
+// integrated on the finer side's face grid, added to (mode 1) or subtracted from (mode 0)
+// the output of sipg_apply, which leaves these faces out.
+template <typename T>
+struct MortarArgs {
+  int nel = 0;                      // elements with at least one such face
+  const int* elist = nullptr;       // [nel]
+  int nrhs = 1;
+  int64_t ndof = 0;
+  const T* u = nullptr;
+  T* out = nullptr;
+  int mode = 0;
+  const int* deg = nullptr;         // [E]
+  const int64_t* off = nullptr;     // [E]
+  const int64_t* offF = nullptr;    // [E]
+  const int* nbr = nullptr;         // [E][6]
+  const T* G = nullptr;             // [6][ndof]
+  const double* ws = nullptr;       // face omega s, [offF]
+  const double* muf = nullptr;      // [E][6] mu_F nu
+  const double* Dall = nullptr;     // differentiation matrices of degrees 1..8, degree p at kDoff[p]
+  const double* Iall = nullptr;     // interpolation degree q -> r at ((q-1) * 8 + (r-1)) * 81
+};
+template <typename T>
+void sipg_mortar(const MortarArgs<T>& a, hipStream_t st);
 
 template <typename T>
 struct SchwarzArgs {
   int E = 0;
-  int nrhs = 1;               // vectors are [nrhs][E (p+1)^3], inbox [nrhs][E][osz]
+  int nrhs = 1;               // vectors are [nrhs][ndof], inbox [nrhs][nin]
+  int nel = 0;                // subdomains of this launch (the degree bucket)
+  const int* elist = nullptr; // [nel] element ids (null: 0..nel-1)
+  const int64_t* off = nullptr;   // [E] first DOF per element (null: uniform)
+  const int64_t* offO = nullptr;  // [E] first inbox slot per element (null: uniform)
+  const int* deg = nullptr;   // [E] degree per element (null: uniform)
+  int64_t ndof = 0;           // DOF per right-hand side
+  int64_t nin = 0;            // inbox slots per right-hand side
   const T* r = nullptr;       // input residual
   T* z = nullptr;             // output (mode 0: z = own part; mode 1: z += own part)
   int mode = 0;
@@ -72,10 +135,24 @@ template <typename T>
 void schwarz_overlap_add(int p, int m, const SchwarzArgs<T>& a, hipStream_t st);
 int overlap_size(int p, int m);
 
-// transfers: out (=|+=) T(x)T(x)T (in - in2); T is n_out x n_in
+// transfers: out (=|+=) T(x)T(x)T (in - in2) per element; T is n_out x n_in
 template <typename T>
-bool tensor3(int n_in, int n_out, int E, const T* Tm, const T* in, const T* in2, T* out, int accumulate,
-             hipStream_t st);
+struct XferArgs {
+  int nel = 0;                       // elements of this launch
+  const int* elist = nullptr;        // [nel] element ids (null: 0..nel-1)
+  const int64_t* off_in = nullptr;   // [E] first input node per element (null: e n_in^3)
+  const int64_t* off_out = nullptr;  // [E] first output node per element (null: e n_out^3)
+  int ncomp = 1;                     // components stored per element (3 for coordinates)
+  int nrhs = 1;
+  int64_t stride_in = 0, stride_out = 0;  // right-hand-side strides
+  const T* Tm = nullptr;
+  const T* in = nullptr;
+  const T* in2 = nullptr;            // subtracted from in when non-null
+  T* out = nullptr;
+  int accumulate = 0;
+};
+template <typename T>
+bool tensor3(int n_in, int n_out, const XferArgs<T>& a, hipStream_t st);
 
 int reduction_blocks(int64_t n);
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -34,11 +35,6 @@ struct Error : std::runtime_error {
       throw Error(DGFAS_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));                    \
   } while (0)
 
-template <typename T>
-void xfer(int n_in, int n_out, int E, const T* Tm, const T* in, const T* in2, T* out, int acc, hipStream_t st) {
-  if (!tensor3<T>(n_in, n_out, E, Tm, in, in2, out, acc, st))
-    throw Error(DGFAS_EUNSUPPORTED, "no transfer kernel for this degree pair");
-}
 
 template <typename T>
 T* dalloc(size_t n) {
@@ -66,24 +62,54 @@ std::vector<T> download(const T* d, size_t n, hipStream_t st) {
 
 std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
 
-struct Level {
-  int p = 0, n = 0, N2 = 0, N3 = 0, E = 0, m = 0, ns = 0;
-  int64_t ndof = 0;
+// Tables of one polynomial degree, shared by every level holding elements of that degree:
+// GLL data, the differentiation matrix and the 16 Schwarz variants (side codes I, D, N, I0
+// per direction end, zero padded to ns = p + 1 + 2m).
+struct DegTab {
+  int p = 0, n = 0, m = 0, ns = 0;
   double inv_wend = 0;
+  double *D = nullptr, *w1 = nullptr, *x1 = nullptr;
+  float* D32 = nullptr;
+  double *S = nullptr, *ST = nullptr, *lam = nullptr, *W = nullptr;
+  float *S32 = nullptr, *ST32 = nullptr, *lam32 = nullptr, *W32 = nullptr;
+  int* map1d = nullptr;
+};
+
+// The elements of one degree on a level (the whole level when it is uniform, elist = null),
+// with the transfer matrices to the next coarser level.
+struct Bucket {
+  int p = 0, n = 0, nel = 0;
+  int* elist = nullptr;
+  std::vector<int> h_elist;
+  DegTab* t = nullptr;
+  int pc = 0;                                        // coarse degree of these elements
+  double *Pm = nullptr, *Im = nullptr, *Rm = nullptr;
+};
+
+struct Level {
+  int p = 0, n = 0, N2 = 0, N3 = 0, E = 0, m = 0, ns = 0;   // p: largest degree on the level
+  bool uniform = true;
+  int64_t ndof = 0, nfs = 0, nin = 0;   // nodes, face-node slots and inbox slots per right-hand side
+  double inv_wend = 0;
+  std::vector<int> h_deg;
+  std::vector<int64_t> h_off;
+  int* deg = nullptr;                   // device per-element data, null on uniform levels
+  int64_t *off = nullptr, *offF = nullptr, *offO = nullptr;
+  std::vector<Bucket> bk;
+  int nm = 0;                           // elements with a face to another degree
+  int* mlist = nullptr;
+  double* muf = nullptr;                // [E][6] mu_F nu
   // geometry
   double *X = nullptr, *G = nullptr, *WJ = nullptr, *ws = nullptr, *pen = nullptr;
-  double *vol = nullptr, *area = nullptr, *lin = nullptr, *D = nullptr;
-  float *G32 = nullptr, *WJ32 = nullptr, *pen32 = nullptr, *D32 = nullptr;
+  double *vol = nullptr, *area = nullptr, *lin = nullptr;
+  float *G32 = nullptr, *WJ32 = nullptr, *pen32 = nullptr;
   // Schwarz
   int* nb27 = nullptr;
   int8_t* var = nullptr;
-  double *gco = nullptr, *S = nullptr, *ST = nullptr, *lam = nullptr, *W = nullptr, *O = nullptr;
-  float *gco32 = nullptr, *S32 = nullptr, *ST32 = nullptr, *lam32 = nullptr, *W32 = nullptr, *O32 = nullptr;
-  int* map1d = nullptr;
+  double *gco = nullptr, *O = nullptr;
+  float *gco32 = nullptr, *O32 = nullptr;
   double* J9 = nullptr;          // [E][9] linear map Jacobian / det^(1/3) (network input)
   std::vector<int> h_nb27;       // host copy of the 26-neighbourhood
-  // transfer matrices to the next coarser level (this = fine)
-  double *Pm = nullptr, *Im = nullptr, *Rm = nullptr;
   // vectors
   double *u = nullptr, *g = nullptr, *ubar = nullptr, *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr,
          *r0 = nullptr;
@@ -106,6 +132,8 @@ struct Solver {
   std::vector<int> h_nbr;
   std::vector<int8_t> h_bc;
   std::vector<Level> lv;   // lv[0] = root (level 1)
+  std::map<int, DegTab> tabs;
+  double *Dall = nullptr, *Iall = nullptr;   // mixed-degree face tables for degrees 1..8
   int nrhs = 1;            // right-hand sides per batch; vectors are [nrhs][ndof]
   double* partial = nullptr;   // [2][nrhs][1024] first-stage sums
   double* scal = nullptr;      // [nrhs][8] SCG scalars
@@ -141,47 +169,94 @@ struct Solver {
 
   // ---------------------------------------------------------------- operator
   template <typename T>
-  OpArgs<T> op_args(Level& L, int mode, const T* u, const T* g, T* out);
+  OpArgs<T> op_args(Level& L, const Bucket& b, int mode, const T* u, const T* g, T* out);
 
-  void apply(Level& L, const double* u, double* Au) {
-    OpArgs<double> a = op_args<double>(L, 1, u, nullptr, Au);
-    sipg_apply<double>(L.p, a, st);
+  // out = A u (mode 1) or g - A u (mode 0): one launch per degree bucket, then the faces
+  // between degrees
+  template <typename T>
+  void op(Level& L, int mode, const T* u, const T* g, T* out) {
+    for (const Bucket& b : L.bk) {
+      OpArgs<T> a = op_args<T>(L, b, mode, u, g, out);
+      sipg_apply<T>(b.p, a, st);
+    }
+    if (L.nm) {
+      MortarArgs<T> m;
+      m.nel = L.nm; m.elist = L.mlist; m.nrhs = nrhs; m.ndof = L.ndof; m.u = u; m.out = out; m.mode = mode;
+      m.deg = L.deg; m.off = L.off; m.offF = L.offF; m.nbr = nbr; m.ws = L.ws; m.muf = L.muf;
+      m.Dall = Dall; m.Iall = Iall;
+      if constexpr (sizeof(T) == 8) m.G = L.G;
+      else m.G = L.G32;
+      sipg_mortar<T>(m, st);
+    }
   }
-  void residual(Level& L, const double* u, const double* g, double* r) {
-    OpArgs<double> a = op_args<double>(L, 0, u, g, r);
-    sipg_apply<double>(L.p, a, st);
-  }
-  void residual32(Level& L, const float* u, const float* g, float* r) {
-    OpArgs<float> a = op_args<float>(L, 0, u, g, r);
-    sipg_apply<float>(L.p, a, st);
-  }
+  void apply(Level& L, const double* u, double* Au) { op<double>(L, 1, u, nullptr, Au); }
+  void residual(Level& L, const double* u, const double* g, double* r) { op<double>(L, 0, u, g, r); }
+  void residual32(Level& L, const float* u, const float* g, float* r) { op<float>(L, 0, u, g, r); }
 
   template <typename T>
-  SchwarzArgs<T> sz_args(Level& L, const T* r, T* z, int mode);
+  SchwarzArgs<T> sz_args(Level& L, const Bucket& b, const T* r, T* z, int mode);
 
   // z = B r (mode 0) or z += B r (mode 1)
   void schwarz(Level& L, const double* r, double* z, int mode) {
-    SchwarzArgs<double> a = sz_args<double>(L, r, z, mode);
-    if (msel) {
-      // block-diagonal local solves on the selected subdomains only (their supports are disjoint)
-      a.sel = msel;
-      a.unweighted = 1;
-      fill(L.ndof, z, 0.0, st);
-      HIPC(hipMemsetAsync(L.O, 0, (size_t)L.E * overlap_size(L.p, L.m) * sizeof(double), st));
-    } else if (learned && &L == &lv.back()) {
-      // FD solve plus the network correction |r_s| MLP(r_s / |r_s|, J9)
-      tile_features<double>(L.p, L.m, a, nullptr, L.E, r, L.J9, lX, lnorm, st);
-      mlp->forward(lX, L.E, lY);
-      a.corr = lY;
-      a.cscale = lnorm;
+    if (msel || (learned && &L == &lv.back())) {   // uniform levels only (checked at set-up)
+      SchwarzArgs<double> a = sz_args<double>(L, L.bk[0], r, z, mode);
+      if (msel) {
+        // block-diagonal local solves on the selected subdomains only (their supports are disjoint)
+        a.sel = msel;
+        a.unweighted = 1;
+        fill(L.ndof, z, 0.0, st);
+        fill(L.nin, L.O, 0.0, st);
+      } else {
+        // FD solve plus the network correction |r_s| MLP(r_s / |r_s|, J9)
+        tile_features<double>(L.p, L.m, a, nullptr, L.E, r, L.J9, lX, lnorm, st);
+        mlp->forward(lX, L.E, lY);
+        a.corr = lY;
+        a.cscale = lnorm;
+      }
+      schwarz_solve<double>(L.p, L.m, a, st);
+      schwarz_overlap_add<double>(L.p, L.m, a, st);
+      return;
     }
-    schwarz_solve<double>(L.p, L.m, a, st);
-    schwarz_overlap_add<double>(L.p, L.m, a, st);
+    // buckets do not exchange overlap (another degree is zero filled), so each bucket's
+    // solve and overlap add form an independent pair
+    for (const Bucket& b : L.bk) {
+      SchwarzArgs<double> a = sz_args<double>(L, b, r, z, mode);
+      schwarz_solve<double>(b.p, b.t->m, a, st);
+      schwarz_overlap_add<double>(b.p, b.t->m, a, st);
+    }
   }
   void schwarz32(Level& L, const float* r, float* z, int mode) {
-    SchwarzArgs<float> a = sz_args<float>(L, r, z, mode);
-    schwarz_solve<float>(L.p, L.m, a, st);
-    schwarz_overlap_add<float>(L.p, L.m, a, st);
+    for (const Bucket& b : L.bk) {
+      SchwarzArgs<float> a = sz_args<float>(L, b, r, z, mode);
+      schwarz_solve<float>(b.p, b.t->m, a, st);
+      schwarz_overlap_add<float>(b.p, b.t->m, a, st);
+    }
+  }
+
+  // kind 0: out = P in (projection), 1: out (+)= R in (restriction), 2: out += I (in - in2)
+  // (prolongation), per element from the fine level's buckets
+  void transfer(Level& F, Level& C, int kind, const double* in, const double* in2, double* out, int acc) {
+    for (const Bucket& b : F.bk) {
+      XferArgs<double> a;
+      a.Tm = kind == 0 ? b.Pm : (kind == 1 ? b.Rm : b.Im);
+      a.in = in; a.in2 = in2; a.out = out; a.accumulate = acc;
+      int n_in, n_out;
+      if (F.uniform && C.uniform) {
+        a.nel = C.E * nrhs;   // right-hand sides follow each other element-major
+        n_in = kind < 2 ? F.n : C.n;
+        n_out = kind < 2 ? C.n : F.n;
+      } else {
+        a.nel = b.nel; a.elist = b.elist; a.nrhs = nrhs;
+        if (kind < 2) {
+          a.off_in = F.off; a.off_out = C.off; a.stride_in = F.ndof; a.stride_out = C.ndof;
+          n_in = b.n; n_out = b.pc + 1;
+        } else {
+          a.off_in = C.off; a.off_out = F.off; a.stride_in = C.ndof; a.stride_out = F.ndof;
+          n_in = b.pc + 1; n_out = b.n;
+        }
+      }
+      if (!tensor3<double>(n_in, n_out, a, st)) throw Error(DGFAS_EUNSUPPORTED, "no transfer kernel for this degree pair");
+    }
   }
 
   // ---------------------------------------------------------------- smoothers
@@ -200,7 +275,7 @@ struct Solver {
     if (!L.du32) L.du32 = own(dalloc<float>(nv));
     if (!L.rc32) L.rc32 = own(dalloc<float>(nv));
     if (!L.O32) {
-      const size_t nin = (size_t)L.E * overlap_size(L.p, L.m) * nrhs;
+      const size_t nin = (size_t)L.nin * nrhs;
       L.O32 = own(dalloc<float>(nin));
       if (nin) HIPC(hipMemsetAsync(L.O32, 0, nin * sizeof(float), st));
     }
@@ -234,10 +309,7 @@ struct Solver {
     apply(L, u, Au);
     if (mmask) mask_mul(L.ndof, Au, mmask, st);
   }
-  void apply_t(Level& L, const float* u, float* Au) {
-    OpArgs<float> a = op_args<float>(L, 1, u, nullptr, Au);
-    sipg_apply<float>(L.p, a, st);
-  }
+  void apply_t(Level& L, const float* u, float* Au) { op<float>(L, 1, u, nullptr, Au); }
   void residual_t(Level& L, const double* u, const double* g, double* r) { residual(L, u, g, r); }
   void residual_t(Level& L, const float* u, const float* g, float* r) { residual32(L, u, g, r); }
   void schwarz_t(Level& L, const double* r, double* z, int mode) { schwarz(L, r, z, mode); }
@@ -279,8 +351,13 @@ struct Solver {
     } else {
       residual_t(L, x, f, r);
     }
-    HIPC(hipMemsetAsync(scal, 0, (size_t)8 * nrhs * sizeof(double), st));
-    std::vector<double> h((size_t)8 * nrhs);
+    std::vector<double> h((size_t)8 * nrhs, 0.0);
+    if (r_max.empty()) {
+      fill((int64_t)8 * nrhs, scal, 0.0, st);
+    } else {
+      for (int k = 0; k < nrhs; ++k) h[k * 8 + 6] = r_max[k];
+      HIPC(hipMemcpyAsync(scal, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    }
     int it = 0;
     for (int i = 1; i <= n; ++i) {
       schwarz_t(L, r, z, 0);
@@ -365,16 +442,16 @@ struct Solver {
       Level& C = lv[l - 1];
       smooth(F, F.u, F.g, opt.ns1);
       residual(F, F.u, F.g, F.r);
-      xfer<double>(F.n, C.n, C.E * nrhs, F.Pm, F.u, nullptr, C.ubar, 0, st);   // ubar = P u
+      transfer(F, C, 0, F.u, nullptr, C.ubar, 0);                              // ubar = P u
       HIPC(hipMemcpyAsync(C.u, C.ubar, C.ndof * nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       apply(C, C.ubar, C.g);                                                     // g = A ubar
-      xfer<double>(F.n, C.n, C.E * nrhs, F.Rm, F.r, nullptr, C.g, 1, st);      //   + R r
+      transfer(F, C, 1, F.r, nullptr, C.g, 1);                                   //   + R r
     }
     root_solve(lv[0].u, lv[0].g, &bd);
     for (int l = 1; l < Lc; ++l) {
       Level& F = lv[l];
       Level& C = lv[l - 1];
-      xfer<double>(C.n, F.n, C.E * nrhs, F.Im, C.u, C.ubar, F.u, 1, st);   // u += I (u_c - ubar)
+      transfer(F, C, 2, C.u, C.ubar, F.u, 1);                                  // u += I (u_c - ubar)
       smooth(F, F.u, F.g, opt.ns2);
     }
     T.u = u_save;
@@ -383,9 +460,15 @@ struct Solver {
 };
 
 template <typename T>
-OpArgs<T> Solver::op_args(Level& L, int mode, const T* u, const T* g, T* out) {
+OpArgs<T> Solver::op_args(Level& L, const Bucket& b, int mode, const T* u, const T* g, T* out) {
   OpArgs<T> a;
   a.E = L.E;
+  a.nel = b.nel;
+  a.elist = b.elist;
+  a.off = L.off;
+  a.offF = L.offF;
+  a.deg = L.deg;
+  a.ndof = L.ndof;
   a.nrhs = nrhs;
   a.u = u;
   a.g = g;
@@ -394,77 +477,177 @@ OpArgs<T> Solver::op_args(Level& L, int mode, const T* u, const T* g, T* out) {
   a.nbr = nbr;
   a.bc = bc;
   a.kappa = (T)opt.kappa;
-  a.inv_wend = (T)L.inv_wend;
+  a.inv_wend = (T)b.t->inv_wend;
   if constexpr (sizeof(T) == 8) {
-    a.G = L.G; a.WJ = opt.kappa != 0.0 ? L.WJ : nullptr; a.pen = L.pen; a.D = L.D;
+    a.G = L.G; a.WJ = opt.kappa != 0.0 ? L.WJ : nullptr; a.pen = L.pen; a.D = b.t->D;
   } else {
-    a.G = L.G32; a.WJ = opt.kappa != 0.0 ? L.WJ32 : nullptr; a.pen = L.pen32; a.D = L.D32;
+    a.G = L.G32; a.WJ = opt.kappa != 0.0 ? L.WJ32 : nullptr; a.pen = L.pen32; a.D = b.t->D32;
   }
   return a;
 }
 
 template <typename T>
-SchwarzArgs<T> Solver::sz_args(Level& L, const T* r, T* z, int mode) {
+SchwarzArgs<T> Solver::sz_args(Level& L, const Bucket& b, const T* r, T* z, int mode) {
   SchwarzArgs<T> a;
   a.E = L.E;
+  a.nel = b.nel;
+  a.elist = b.elist;
+  a.off = L.off;
+  a.offO = L.offO;
+  a.deg = L.deg;
+  a.ndof = L.ndof;
+  a.nin = L.nin;
   a.nrhs = nrhs;
   a.r = r;
   a.z = z;
   a.mode = mode;
   a.nb27 = L.nb27;
   a.var = L.var;
-  a.map1d = L.map1d;
+  const DegTab& t = *b.t;
+  a.map1d = t.map1d;
   if constexpr (sizeof(T) == 8) {
-    a.O = L.O; a.gco = L.gco; a.S = L.S; a.ST = L.ST; a.lam = L.lam; a.W = L.W;
+    a.O = L.O; a.gco = L.gco; a.S = t.S; a.ST = t.ST; a.lam = t.lam; a.W = t.W;
   } else {
-    a.O = L.O32; a.gco = L.gco32; a.S = L.S32; a.ST = L.ST32; a.lam = L.lam32; a.W = L.W32;
+    a.O = L.O32; a.gco = L.gco32; a.S = t.S32; a.ST = t.ST32; a.lam = t.lam32; a.W = t.W32;
   }
   return a;
 }
 
 const int kFace[3][2] = {{0, 1}, {2, 3}, {4, 5}};
 
-void build_level(Solver& s, Level& L, int p, const double* dX) {
+// tables of degree p (built once per solver)
+DegTab& deg_tab(Solver& s, int p) {
+  auto it = s.tabs.find(p);
+  if (it != s.tabs.end()) return it->second;
   hipStream_t st = s.st;
+  DegTab& t = s.tabs[p];
   const Gll& gl = gll_table(p);
-  L.p = p; L.n = p + 1; L.N2 = L.n * L.n; L.N3 = L.N2 * L.n; L.E = s.E;
-  L.ndof = (int64_t)L.E * L.N3;
-  L.inv_wend = 1.0 / gl.w[0];
-  L.m = std::min(s.opt.overlap, p);
+  t.p = p; t.n = p + 1;
+  t.m = std::min(s.opt.overlap, p);
+  t.ns = t.n + 2 * t.m;
+  t.inv_wend = 1.0 / gl.w[0];
+  t.D = s.own(upload(gl.D, st));
+  t.D32 = s.own(upload(to_float(gl.D), st));
+  t.w1 = s.own(upload(gl.w, st));
+  t.x1 = s.own(upload(gl.x, st));
+  // variant tables (left, right) in {I, D, N, I0}^2, zero padded to ns
+  const int NS = t.ns, NV = kSides * kSides;
+  std::vector<double> S(NV * NS * NS, 0.0), lam(NV * NS, 1.0), W(NV * NS, 0.0);
+  std::vector<int> map(NV * NS, -1);
+  for (int left = 0; left < kSides; ++left)
+    for (int right = 0; right < kSides; ++right) {
+      const int v = left * kSides + right;
+      Variant1D vt = make_variant_1d(p, t.m, left, right, s.opt.mu_star);
+      for (int i = 0; i < vt.ns; ++i) {
+        for (int a = 0; a < vt.ns; ++a) S[v * NS * NS + i * NS + a] = vt.S[i * vt.ns + a];
+        lam[v * NS + i] = vt.lam[i];
+        W[v * NS + i] = vt.W[i];
+        map[v * NS + i] = (vt.delta[i] + 1) * 64 + vt.loc[i];
+      }
+    }
+  std::vector<double> ST(S.size());
+  for (int v = 0; v < NV; ++v)
+    for (int i = 0; i < NS; ++i)
+      for (int a = 0; a < NS; ++a) ST[v * NS * NS + a * NS + i] = S[v * NS * NS + i * NS + a];
+  t.S = s.own(upload(S, st)); t.S32 = s.own(upload(to_float(S), st));
+  t.ST = s.own(upload(ST, st)); t.ST32 = s.own(upload(to_float(ST), st));
+  t.lam = s.own(upload(lam, st)); t.lam32 = s.own(upload(to_float(lam), st));
+  t.W = s.own(upload(W, st)); t.W32 = s.own(upload(to_float(W), st));
+  t.map1d = s.own(upload(map, st));
+  return t;
+}
+
+// Level set-up from per-element degrees and device coordinates (element e at 3 off[e]).
+void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double* dX) {
+  hipStream_t st = s.st;
+  const int E = s.E;
+  L.E = E;
+  L.h_deg = deg;
+  L.p = *std::max_element(deg.begin(), deg.end());
+  L.uniform = *std::min_element(deg.begin(), deg.end()) == L.p;
+  L.n = L.p + 1; L.N2 = L.n * L.n; L.N3 = L.N2 * L.n;
+  L.m = std::min(s.opt.overlap, L.p);
   L.ns = L.n + 2 * L.m;
-  L.D = s.own(upload(gl.D, st));
-  L.D32 = s.own(upload(to_float(gl.D), st));
-  double* w1 = s.own(upload(gl.w, st));
-  double* x1 = s.own(upload(gl.x, st));
+  L.inv_wend = 1.0 / gll_table(L.p).w[0];
+  // element-major layout with offsets
+  std::vector<int64_t> off(E), offF(E), offO(E);
+  int64_t nd = 0, nf = 0, no = 0;
+  for (int e = 0; e < E; ++e) {
+    const int n = deg[e] + 1;
+    off[e] = nd; offF[e] = nf; offO[e] = no;
+    nd += (int64_t)n * n * n;
+    nf += 6 * (int64_t)n * n;
+    no += overlap_size(deg[e], std::min(s.opt.overlap, deg[e]));
+  }
+  L.ndof = nd; L.nfs = nf; L.nin = no;
+  L.h_off = off;
+  if (!L.uniform) {
+    L.deg = s.own(upload(deg, st));
+    L.off = s.own(upload(off, st));
+    L.offF = s.own(upload(offF, st));
+    L.offO = s.own(upload(offO, st));
+  }
+  // degree buckets
+  for (int p = 1; p <= 8; ++p) {
+    Bucket b;
+    for (int e = 0; e < E; ++e)
+      if (deg[e] == p) b.h_elist.push_back(e);
+    if (b.h_elist.empty()) continue;
+    b.p = p; b.n = p + 1; b.nel = (int)b.h_elist.size();
+    if (!L.uniform) b.elist = s.own(upload(b.h_elist, st));
+    b.t = &deg_tab(s, p);
+    L.bk.push_back(std::move(b));
+  }
+  // elements with a face to another degree
+  if (!L.uniform) {
+    std::vector<int> ml;
+    for (int e = 0; e < E; ++e) {
+      bool any = false;
+      for (int f = 0; f < 6; ++f) {
+        const int en = s.h_nbr[e * 6 + f];
+        any = any || (en >= 0 && deg[en] != deg[e]);
+      }
+      if (any) ml.push_back(e);
+    }
+    L.nm = (int)ml.size();
+    if (L.nm) L.mlist = s.own(upload(ml, st));
+  }
+  // geometry per bucket
   L.G = s.own(dalloc<double>(6 * L.ndof));
   L.WJ = s.own(dalloc<double>(L.ndof));
-  L.ws = s.own(dalloc<double>((size_t)L.E * 6 * L.N2));
-  L.pen = s.own(dalloc<double>((size_t)L.E * 6 * L.N2));
-  L.vol = s.own(dalloc<double>(L.E));
-  L.area = s.own(dalloc<double>((size_t)L.E * 6));
-  L.lin = s.own(dalloc<double>((size_t)L.E * 9));
+  L.ws = s.own(dalloc<double>(L.nfs));
+  L.pen = s.own(dalloc<double>(L.nfs));
+  L.muf = s.own(dalloc<double>((size_t)E * 6));
+  L.vol = s.own(dalloc<double>(E));
+  L.area = s.own(dalloc<double>((size_t)E * 6));
+  L.lin = s.own(dalloc<double>((size_t)E * 9));
   int* bad = s.own(dalloc<int>(1));
   HIPC(hipMemsetAsync(bad, 0, sizeof(int), st));
-  geometry(p, L.E, dX, L.D, w1, x1, s.opt.nu, L.G, L.WJ, L.ws, L.vol, L.area, L.lin, bad, st);
-  HIPC(hipGetLastError());
-  penalty(L.E, p, s.opt.mu_star, s.opt.nu, s.nbr, s.bc, L.vol, L.area, L.ws, L.pen, st);
+  for (const Bucket& b : L.bk) {
+    GeoArgs g;
+    g.nel = b.nel; g.elist = b.elist; g.off = L.off; g.offF = L.offF; g.ndof = L.ndof; g.X = dX;
+    g.G = L.G; g.WJ = L.WJ; g.ws = L.ws; g.vol = L.vol; g.area = L.area; g.lin = L.lin; g.bad = bad;
+    geometry(b.p, g, b.t->D, b.t->w1, b.t->x1, s.opt.nu, st);
+    HIPC(hipGetLastError());
+  }
+  penalty(E, L.p, L.deg, L.offF, s.opt.mu_star, s.opt.nu, s.nbr, s.bc, L.vol, L.area, L.ws, L.pen, L.muf, st);
   HIPC(hipGetLastError());
   int hbad = 0;
   HIPC(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
-  if (hbad) throw Error(DGFAS_EINVAL, "element map with det J <= 0 at degree " + std::to_string(p));
+  if (hbad) throw Error(DGFAS_EINVAL, "element map with det J <= 0 at degree " + std::to_string(L.p));
   // FP32 copies for the correction-form smoother
   L.G32 = s.own(dalloc<float>(6 * L.ndof));
   L.WJ32 = s.own(dalloc<float>(L.ndof));
-  L.pen32 = s.own(dalloc<float>((size_t)L.E * 6 * L.N2));
+  L.pen32 = s.own(dalloc<float>(L.nfs));
   convert<double, float>(6 * L.ndof, L.G, L.G32, 0, st);
   convert<double, float>(L.ndof, L.WJ, L.WJ32, 0, st);
-  convert<double, float>((int64_t)L.E * 6 * L.N2, L.pen, L.pen32, 0, st);
+  convert<double, float>(L.nfs, L.pen, L.pen32, 0, st);
 
   // surrogate cuboid (Sec. 4.3.1 steps 1-3): Delta x_b = 2|a_b| (vol / prod)^(1/3)
-  std::vector<double> vol = download(L.vol, L.E, st), lin = download(L.lin, (size_t)L.E * 9, st);
-  std::vector<double> gco((size_t)L.E * 4);
-  for (int e = 0; e < L.E; ++e) {
+  std::vector<double> vol = download(L.vol, E, st), lin = download(L.lin, (size_t)E * 9, st);
+  std::vector<double> gco((size_t)E * 4);
+  for (int e = 0; e < E; ++e) {
     double ell[3];
     for (int b = 0; b < 3; ++b) {
       double s2 = 0;
@@ -480,8 +663,8 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
   }
   L.gco = s.own(upload(gco, st));
   {
-    std::vector<double> j9((size_t)L.E * 9);
-    for (int e = 0; e < L.E; ++e) {
+    std::vector<double> j9((size_t)E * 9);
+    for (int e = 0; e < E; ++e) {
       const double* A = &lin[e * 9];   // A[a][b] = coefficient of coordinate a along xi_b
       const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
                          A[2] * (A[3] * A[7] - A[4] * A[6]);
@@ -492,41 +675,20 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
   }
   L.gco32 = s.own(upload(to_float(gco), st));
 
-  // variant tables (left, right) in {I, D, N}^2, zero padded to ns
-  const int NS = L.ns;
-  std::vector<double> S(9 * NS * NS, 0.0), lam(9 * NS, 1.0), W(9 * NS, 0.0);
-  std::vector<int> map(9 * NS, -1);
-  for (int left = 0; left < 3; ++left)
-    for (int right = 0; right < 3; ++right) {
-      const int v = left * 3 + right;
-      Variant1D t = make_variant_1d(p, L.m, left, right, s.opt.mu_star);
-      for (int i = 0; i < t.ns; ++i) {
-        for (int a = 0; a < t.ns; ++a) S[v * NS * NS + i * NS + a] = t.S[i * t.ns + a];
-        lam[v * NS + i] = t.lam[i];
-        W[v * NS + i] = t.W[i];
-        map[v * NS + i] = (t.delta[i] + 1) * 64 + t.loc[i];
-      }
-    }
-  std::vector<double> ST(S.size());
-  for (int v = 0; v < 9; ++v)
-    for (int i = 0; i < NS; ++i)
-      for (int a = 0; a < NS; ++a) ST[v * NS * NS + a * NS + i] = S[v * NS * NS + i * NS + a];
-  L.S = s.own(upload(S, st)); L.S32 = s.own(upload(to_float(S), st));
-  L.ST = s.own(upload(ST, st)); L.ST32 = s.own(upload(to_float(ST), st));
-  L.lam = s.own(upload(lam, st)); L.lam32 = s.own(upload(to_float(lam), st));
-  L.W = s.own(upload(W, st)); L.W32 = s.own(upload(to_float(W), st));
-  L.map1d = s.own(upload(map, st));
-  // per element: variant code per direction and the 27-neighbourhood
-  std::vector<int8_t> var((size_t)L.E * 3);
-  std::vector<int> nb27((size_t)L.E * 27, -1);
-  for (int e = 0; e < L.E; ++e) {
+  // per element: variant code per direction and the 27-neighbourhood; a side toward an
+  // element of another degree takes the no-overlap interior variant
+  std::vector<int8_t> var((size_t)E * 3);
+  std::vector<int> nb27((size_t)E * 27, -1);
+  for (int e = 0; e < E; ++e) {
     for (int d = 0; d < 3; ++d) {
       int code[2];
       for (int sd = 0; sd < 2; ++sd) {
         const int f = kFace[d][sd];
-        code[sd] = s.h_nbr[e * 6 + f] >= 0 ? kInterior : (s.h_bc[e * 6 + f] == DGFAS_NEUMANN ? kNeumann : kDirichlet);
+        const int en = s.h_nbr[e * 6 + f];
+        if (en >= 0) code[sd] = deg[en] == deg[e] ? kInterior : kInteriorNoOverlap;
+        else code[sd] = s.h_bc[e * 6 + f] == DGFAS_NEUMANN ? kNeumann : kDirichlet;
       }
-      var[e * 3 + d] = (int8_t)(code[0] * 3 + code[1]);
+      var[e * 3 + d] = (int8_t)(code[0] * kSides + code[1]);
     }
     for (int d3 = -1; d3 <= 1; ++d3)
       for (int d2 = -1; d2 <= 1; ++d2)
@@ -541,13 +703,13 @@ void build_level(Solver& s, Level& L, int p, const double* dX) {
   L.var = s.own(upload(var, st));
   L.nb27 = s.own(upload(nb27, st));
   L.h_nb27 = nb27;
-  const int osz = overlap_size(p, L.m);
-  const size_t nin = (size_t)L.E * osz * s.nrhs;
+  const size_t nin = (size_t)L.nin * s.nrhs;
   const bool fp32 = s.opt.precision == DGFAS_FP32;
   L.O = s.own(dalloc<double>(nin));
   if (fp32) L.O32 = s.own(dalloc<float>(nin));
-  // inbox regions of absent neighbours are never written and must read as zero
-  if (osz) {
+  // inbox regions of absent neighbours (and of neighbours of another degree) are never
+  // written and must read as zero
+  if (nin) {
     HIPC(hipMemsetAsync(L.O, 0, nin * sizeof(double), st));
     if (fp32) HIPC(hipMemsetAsync(L.O32, 0, nin * sizeof(float), st));
   }
@@ -581,9 +743,11 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (m->n_elem <= 0 || !m->degree || !m->coords || !m->face_nbr || !m->face_bc)
     throw Error(DGFAS_EINVAL, "mesh arrays missing or n_elem <= 0");
   const int p = m->degree[0];
-  for (int e = 0; e < m->n_elem; ++e)
-    if (m->degree[e] != p) throw Error(DGFAS_EUNSUPPORTED, "mixed degrees are not supported by dgfas_create");
-  if (p < 1 || p > 8) throw Error(DGFAS_EUNSUPPORTED, "degree must be 1..8");
+  bool uniform = true;
+  for (int e = 0; e < m->n_elem; ++e) {
+    if (m->degree[e] < 1 || m->degree[e] > 8) throw Error(DGFAS_EUNSUPPORTED, "degree must be 1..8");
+    uniform = uniform && m->degree[e] == p;
+  }
   for (int e = 0; e < m->n_elem; ++e)
     for (int f = 0; f < 6; ++f) {
       const int en = m->face_nbr[e * 6 + f];
@@ -596,7 +760,8 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (!(o->nu > 0) || !(o->kappa >= 0) || !(o->mu_star > 0)) throw Error(DGFAS_EINVAL, "bad coefficients");
   if (o->overlap < 0 || o->overlap > 1 + (p >= 4 ? 1 : 0))
     throw Error(DGFAS_EUNSUPPORTED, "overlap must be 0 or 1 (2 for p = 4, 8)");
-  if (o->overlap == 2 && p != 4 && p != 8) throw Error(DGFAS_EUNSUPPORTED, "overlap 2 needs p = 4 or 8");
+  if (o->overlap == 2 && (!uniform || (p != 4 && p != 8)))
+    throw Error(DGFAS_EUNSUPPORTED, "overlap 2 needs one degree, p = 4 or 8");
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
   if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32) throw Error(DGFAS_EINVAL, "unknown precision");
@@ -610,10 +775,10 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   s->opt = *o;
   s->st = (hipStream_t)stream;
   s->E = m->n_elem;
-  const int p = m->degree[0];
-  s->h_nbr.assign(m->face_nbr, m->face_nbr + (size_t)s->E * 6);
-  s->h_bc.assign(m->face_bc, m->face_bc + (size_t)s->E * 6);
-  for (int e = 0; e < s->E; ++e)
+  const int E = s->E;
+  s->h_nbr.assign(m->face_nbr, m->face_nbr + (size_t)E * 6);
+  s->h_bc.assign(m->face_bc, m->face_bc + (size_t)E * 6);
+  for (int e = 0; e < E; ++e)
     for (int f = 0; f < 6; ++f)
       if (s->h_nbr[e * 6 + f] >= 0) s->h_bc[e * 6 + f] = DGFAS_INTERIOR;
   s->nbr = s->own(upload(s->h_nbr, s->st));
@@ -622,35 +787,73 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   s->partial = s->own(dalloc<double>((size_t)2048 * s->nrhs));
   s->scal = s->own(dalloc<double>((size_t)8 * s->nrhs));
   s->scratch = s->own(dalloc<double>((size_t)8 * s->nrhs));
-  std::vector<int> chain{p};
-  while (chain.back() > 1) chain.push_back(std::max(1, chain.back() / 2));
-  std::reverse(chain.begin(), chain.end());
-  const int Lc = (int)chain.size();
+  // face tables of the mixed-degree kernel: D of degrees 1..8 (stride 81) and the
+  // interpolation from degree q to degree r at ((q - 1) 8 + r - 1) 81
+  {
+    std::vector<double> Dall(8 * 81, 0.0), Iall(64 * 81, 0.0);
+    for (int q = 1; q <= 8; ++q) {
+      const Gll& g = gll_table(q);
+      for (size_t i = 0; i < g.D.size(); ++i) Dall[(q - 1) * 81 + i] = g.D[i];
+      for (int r = 1; r <= 8; ++r) {
+        std::vector<double> I = interp_matrix(q, r);
+        for (size_t i = 0; i < I.size(); ++i) Iall[((q - 1) * 8 + (r - 1)) * 81 + i] = I[i];
+      }
+    }
+    s->Dall = s->own(upload(Dall, s->st));
+    s->Iall = s->own(upload(Iall, s->st));
+  }
+  // per-element degree chain p_{l-1} = max(1, floor(p_l / 2)); levels from the largest degree
+  std::vector<std::vector<int>> degs{std::vector<int>(m->degree, m->degree + E)};
+  while (*std::max_element(degs.back().begin(), degs.back().end()) > 1) {
+    std::vector<int> c(E);
+    for (int e = 0; e < E; ++e) c[e] = std::max(1, degs.back()[e] / 2);
+    degs.push_back(c);
+  }
+  std::reverse(degs.begin(), degs.end());
+  const int Lc = (int)degs.size();
   s->lv.resize(Lc);
-  const int n = p + 1;
-  const size_t nX = (size_t)s->E * 3 * n * n * n;
+  size_t nX = 0;
+  for (int e = 0; e < E; ++e) nX += (size_t)3 * (degs[Lc - 1][e] + 1) * (degs[Lc - 1][e] + 1) * (degs[Lc - 1][e] + 1);
   double* X = s->own(dalloc<double>(nX));
   HIPC(hipMemcpyAsync(X, m->coords, nX * sizeof(double), hipMemcpyHostToDevice, s->st));
   for (int li = Lc - 1; li >= 0; --li) {
     Level& L = s->lv[li];
     if (li < Lc - 1) {
+      // coarse geometry: fine coordinates evaluated at the coarse GLL nodes, per element
       Level& F = s->lv[li + 1];
-      const int pc = chain[li], pf = chain[li + 1];
-      std::vector<double> P = interp_matrix(pf, pc), I = interp_matrix(pc, pf);
-      std::vector<double> R((size_t)(pc + 1) * (pf + 1));
-      for (int a = 0; a <= pc; ++a)
-        for (int b = 0; b <= pf; ++b) R[a * (pf + 1) + b] = I[b * (pc + 1) + a];
-      F.Pm = s->own(upload(P, s->st));
-      F.Im = s->own(upload(I, s->st));
-      F.Rm = s->own(upload(R, s->st));
-      // coarse geometry: fine coordinates evaluated at the coarse GLL nodes
-      const size_t nXc = (size_t)s->E * 3 * (pc + 1) * (pc + 1) * (pc + 1);
+      size_t nXc = 0;
+      for (int e = 0; e < E; ++e) nXc += (size_t)3 * (degs[li][e] + 1) * (degs[li][e] + 1) * (degs[li][e] + 1);
       double* Xc = s->own(dalloc<double>(nXc));
-      xfer<double>(pf + 1, pc + 1, 3 * s->E, F.Pm, X, nullptr, Xc, 0, s->st);
-      HIPC(hipGetLastError());
+      std::vector<int64_t> offc(E);
+      int64_t o = 0;
+      for (int e = 0; e < E; ++e) { offc[e] = o; o += (int64_t)(degs[li][e] + 1) * (degs[li][e] + 1) * (degs[li][e] + 1); }
+      int64_t* d_offc = F.uniform ? nullptr : s->own(upload(offc, s->st));
+      const bool cu = *std::min_element(degs[li].begin(), degs[li].end()) ==
+                      *std::max_element(degs[li].begin(), degs[li].end());
+      for (Bucket& b : F.bk) {
+        const int pf = b.p, pc = std::max(1, pf / 2);
+        std::vector<double> P = interp_matrix(pf, pc), I = interp_matrix(pc, pf);
+        std::vector<double> R((size_t)(pc + 1) * (pf + 1));
+        for (int a = 0; a <= pc; ++a)
+          for (int c = 0; c <= pf; ++c) R[a * (pf + 1) + c] = I[c * (pc + 1) + a];
+        b.pc = pc;
+        b.Pm = s->own(upload(P, s->st));
+        b.Im = s->own(upload(I, s->st));
+        b.Rm = s->own(upload(R, s->st));
+        XferArgs<double> a;
+        a.Tm = b.Pm; a.in = X; a.out = Xc;
+        if (F.uniform) {
+          a.nel = 3 * E;
+        } else {
+          a.nel = b.nel; a.elist = b.elist; a.ncomp = 3; a.off_in = F.off; a.off_out = cu ? nullptr : d_offc;
+        }
+        if (!tensor3<double>(pf + 1, pc + 1, a, s->st))
+          throw Error(DGFAS_EUNSUPPORTED, "no transfer kernel for this degree pair");
+        HIPC(hipGetLastError());
+      }
       X = Xc;
     }
-    build_level(*s, L, chain[li], X);
+    build_level(*s, L, degs[li], X);
     L.X = X;
     if (li < Lc - 1) {
       L.u = s->own(dalloc<double>((size_t)L.ndof * s->nrhs));
@@ -736,7 +939,7 @@ dgfas_status dgfas_schwarz_tables_1d(int32_t p, int32_t m, int32_t left, int32_t
   API_BEGIN
   need(ns, "ns"); need(S, "S"); need(lam, "lam"); need(weights, "weights");
   if (p < 1 || p > kMaxDegree || m < 0 || m > p) throw Error(DGFAS_EINVAL, "p or m out of range");
-  if (left < 0 || left > 2 || right < 0 || right > 2) throw Error(DGFAS_EINVAL, "bad side code");
+  if (left < 0 || left > 3 || right < 0 || right > 3) throw Error(DGFAS_EINVAL, "bad side code");
   Variant1D v = make_variant_1d(p, m, left, right, mu_star);
   *ns = v.ns;
   for (int i = 0; i < v.ns * v.ns; ++i) S[i] = v.S[i];
@@ -781,8 +984,13 @@ dgfas_status dgfas_rhs(dgfas_solver sv, const double* f, const double* uD, const
   Level& T = s->lv.back();
   for (int k = 0; k < s->nrhs; ++k) {
     const int64_t o = (int64_t)k * T.ndof;
-    rhs(T.p, T.E, f + o, uD ? uD + o : nullptr, qN ? qN + o : nullptr, b + o, T.G, T.WJ, T.pen, T.ws, s->nbr, s->bc,
-        T.D, T.inv_wend, s->st);
+    for (const Bucket& bk : T.bk) {
+      RhsArgs a;
+      a.nel = bk.nel; a.elist = bk.elist; a.off = T.off; a.offF = T.offF; a.ndof = T.ndof;
+      a.f = f + o; a.uD = uD ? uD + o : nullptr; a.qN = qN ? qN + o : nullptr; a.b = b + o;
+      a.G = T.G; a.WJ = T.WJ; a.pen = T.pen; a.ws = T.ws; a.nbr = s->nbr; a.bc = s->bc;
+      rhs(bk.p, a, bk.t->D, bk.t->inv_wend, s->st);
+    }
   }
   HIPC(hipGetLastError());
   API_END
@@ -832,7 +1040,7 @@ dgfas_status dgfas_restrict(dgfas_solver sv, int32_t level, const double* rf, do
   if (level < 2) throw Error(DGFAS_EINVAL, "restrict needs level >= 2");
   Level& F = s->level(level);
   Level& C = s->level(level - 1);
-  xfer<double>(F.n, C.n, C.E * s->nrhs, F.Rm, rf, nullptr, rc, 0, s->st);
+  s->transfer(F, C, 1, rf, nullptr, rc, 0);
   HIPC(hipGetLastError());
   API_END
 }
@@ -844,7 +1052,7 @@ dgfas_status dgfas_project(dgfas_solver sv, int32_t level, const double* uf, dou
   if (level < 2) throw Error(DGFAS_EINVAL, "project needs level >= 2");
   Level& F = s->level(level);
   Level& C = s->level(level - 1);
-  xfer<double>(F.n, C.n, C.E * s->nrhs, F.Pm, uf, nullptr, uc, 0, s->st);
+  s->transfer(F, C, 0, uf, nullptr, uc, 0);
   HIPC(hipGetLastError());
   API_END
 }
@@ -856,7 +1064,7 @@ dgfas_status dgfas_prolong_add(dgfas_solver sv, int32_t level, const double* uc,
   if (level < 2) throw Error(DGFAS_EINVAL, "prolong needs level >= 2");
   Level& F = s->level(level);
   Level& C = s->level(level - 1);
-  xfer<double>(C.n, F.n, C.E * s->nrhs, F.Im, uc, ubar, uf, 1, s->st);
+  s->transfer(F, C, 2, uc, ubar, uf, 1);
   HIPC(hipGetLastError());
   API_END
 }
@@ -963,6 +1171,7 @@ dgfas_status dgfas_set_learned(dgfas_solver sv, dgfas_mlp m, int32_t enabled) {
   Level& T = s->lv.back();
   if (!enabled) { s->learned = false; return DGFAS_OK; }
   if (!m) throw Error(DGFAS_EINVAL, "null network");
+  if (!T.uniform) throw Error(DGFAS_EUNSUPPORTED, "learned correction needs one degree on the finest level");
   Mlp* net = dgfas_mlp_impl(m);
   const int nt = T.ns * T.ns * T.ns;
   if (net->in != nt + 9 || net->out != nt)
@@ -990,6 +1199,7 @@ dgfas_status dgfas_learned_pairs(dgfas_solver sv, const double* r, const int32_t
   need(r, "r"); need(centers, "centers"); need(X, "X"); need(T, "T");
   if (s->nrhs != 1) throw Error(DGFAS_EUNSUPPORTED, "pairs need n_rhs = 1");
   Level& L = s->lv.back();
+  if (!L.uniform) throw Error(DGFAS_EUNSUPPORTED, "pairs need one degree on the finest level");
   if (n < 1 || n > L.E) throw Error(DGFAS_EINVAL, "bad number of centres");
   // centres must be 4 apart in the 26-neighbourhood graph: their 3x3x3 patches then neither
   // overlap nor touch, so the masked operator is block diagonal over the subdomains
@@ -1036,7 +1246,7 @@ dgfas_status dgfas_learned_pairs(dgfas_solver sv, const double* r, const int32_t
     z0 = dalloc<double>(L.ndof);
     x = dalloc<double>(L.ndof);
     nrm = dalloc<double>(n);
-    SchwarzArgs<double> a = s->sz_args<double>(L, r, z0, 0);
+    SchwarzArgs<double> a = s->sz_args<double>(L, L.bk[0], r, z0, 0);
     fill(L.ndof, mask, 0.0, s->st);
     mark_subdomains<double>(L.p, L.m, a, d_ids, n, mask, s->st);
     convert<double, double>(L.ndof, r, b, 0, s->st);

@@ -163,6 +163,12 @@ Variant1D make_variant_1d(int p, int m, int left, int right, double mu_star) {
   const Gll& g = gll_table(p);
   const int n = p + 1;
   if (m < 0 || m > p) throw std::invalid_argument("overlap out of range");
+  if (left < 0 || left >= kSides || right < 0 || right >= kSides) throw std::invalid_argument("bad side code");
+  // overlap per side: an interior side without overlap keeps the patch element (its face
+  // terms) but selects none of its nodes
+  const int ml = left == kInterior ? m : 0, mr = right == kInterior ? m : 0;
+  if (left == kInteriorNoOverlap) left = kInterior;
+  if (right == kInteriorNoOverlap) right = kInterior;
   // Patch of reference elements (length 2, so d/dx = d/dxi and the mass is diag(w)).
   int nel = 1 + (left == kInterior) + (right == kInterior);
   int c0 = (left == kInterior) ? 1 : 0;   // index of the centre element in the patch
@@ -212,10 +218,10 @@ Variant1D make_variant_1d(int p, int m, int left, int right, double mu_star) {
   Variant1D v;
   std::vector<int> sel;
   if (left == kInterior)
-    for (int l = n - m; l < n; ++l) { v.delta.push_back(-1); v.loc.push_back(l); sel.push_back(l); }
+    for (int l = n - ml; l < n; ++l) { v.delta.push_back(-1); v.loc.push_back(l); sel.push_back(l); }
   for (int l = 0; l < n; ++l) { v.delta.push_back(0); v.loc.push_back(l); sel.push_back(c0 * n + l); }
   if (right == kInterior)
-    for (int l = 0; l < m; ++l) { v.delta.push_back(1); v.loc.push_back(l); sel.push_back((c0 + 1) * n + l); }
+    for (int l = 0; l < mr; ++l) { v.delta.push_back(1); v.loc.push_back(l); sel.push_back((c0 + 1) * n + l); }
   const int ns = (int)sel.size();
   v.ns = ns;
   // C = M^-1/2 L M^-1/2 on the selected nodes
@@ -241,11 +247,11 @@ Variant1D make_variant_1d(int p, int m, int left, int right, double mu_star) {
     for (int s = 0; s < ns; ++s) {
       double w = 1.0;
       const double xl = g.x[v.loc[s]];
-      if (left == kInterior) {
+      if (ml > 0) {
         if (v.delta[s] == 0) w *= smoothstep5((0.5 * (1.0 + xl) + a) / (2 * a));
         else if (v.delta[s] == -1) w *= smoothstep5((-0.5 * (1.0 - xl) + a) / (2 * a));
       }
-      if (right == kInterior) {
+      if (mr > 0) {
         if (v.delta[s] == 0) w *= smoothstep5((0.5 * (1.0 - xl) + a) / (2 * a));
         else if (v.delta[s] == 1) w *= smoothstep5((-0.5 * (1.0 + xl) + a) / (2 * a));
       }

@@ -20,8 +20,11 @@ const Gll& gll_table(int p);
 // polynomial at the GLL nodes of degree p_to.
 std::vector<double> interp_matrix(int p_from, int p_to);
 
-// Face condition of one side of a 1D subdomain.
-enum Side { kInterior = 0, kDirichlet = 1, kNeumann = 2 };
+// Face condition of one side of a 1D subdomain; kInteriorNoOverlap is an interior face
+// whose subdomain stops at the face (neighbour of another degree): the 1D matrix keeps
+// the own element's half of the interior face terms and no node of the neighbour.
+enum Side { kInterior = 0, kDirichlet = 1, kNeumann = 2, kInteriorNoOverlap = 3 };
+constexpr int kSides = 4;   // variant index = left * kSides + right
 
 // 1D subdomain data of a face-condition variant (Sec. 4.3.1): node map, generalized
 // eigen-decomposition L s = lambda M s (S^T M S = I, S^T L S = diag lambda) and weights.

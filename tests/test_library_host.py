@@ -58,6 +58,22 @@ def test_schwarz_tables_match_oracle(lib, p, m, lr):
     assert np.abs(np.sort(lam) - np.sort(v['lam'])).max() < 1e-11 * np.abs(lam).max()
 
 
+@pytest.mark.parametrize('p,m', [(2, 1), (3, 1), (8, 1)])
+@pytest.mark.parametrize('lr', [(3, 3), (3, 0), (0, 3), (3, 1), (2, 3)])
+def test_no_overlap_interior_side_matches_oracle(lib, p, m, lr):
+    """Side code 3: interior face toward another degree, no overlap (mixed-degree levels)."""
+    from oracle.mixed import variant_1d_sides
+    code = {0: 'i', 1: 'd', 2: 'n', 3: 'i'}
+    ms = [0 if c == 3 else (m if c == 0 else 0) for c in lr]
+    v = variant_1d_sides(p, ms[0], ms[1], code[lr[0]], code[lr[1]], 2.0)
+    S, lam, W = lib.schwarz_tables_1d(p, m, lr[0], lr[1], 2.0)
+    assert len(lam) == len(v['nodes'])
+    assert np.allclose(W, v['W'], atol=1e-15)
+    Linv_lib = S @ np.diag(1 / lam) @ S.T
+    Linv_or = v['S'] @ np.diag(1 / v['lam']) @ v['S'].T
+    assert np.abs(Linv_lib - Linv_or).max() < 1e-11 * np.abs(Linv_or).max()
+
+
 def test_argument_errors_are_reported_without_gpu(lib):
     with pytest.raises(lib.DgfasError) as ei:
         lib.gll(0)
