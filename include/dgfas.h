@@ -51,6 +51,7 @@ enum { DGFAS_INTERIOR = 0, DGFAS_DIRICHLET = 1, DGFAS_NEUMANN = 2,
        DGFAS_INTERIOR_NO_OVERLAP = 3 };
 enum { DGFAS_WAS = 0, DGFAS_SCG = 1 };
 enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1 };
+enum { DGFAS_BATCH_PER_DEGREE = 0, DGFAS_BATCH_ONE_LAUNCH = 1, DGFAS_BATCH_TUNED = 2 };
 
 typedef struct dgfas_solver_s* dgfas_solver;
 
@@ -87,7 +88,16 @@ typedef struct {
   int32_t n_rhs;            /* right-hand sides solved together, 1..64: every vector argument is then
                                [n_rhs][n_dof] (each right-hand side contiguous) and every SCG scalar is
                                kept per right-hand side; the geometry is shared */
-  int32_t reserved[6];
+  int32_t batch;            /* mixed-degree levels: DGFAS_BATCH_PER_DEGREE (one launch per degree
+                               bucket and stage), DGFAS_BATCH_ONE_LAUNCH (one launch per sweep
+                               stage over all buckets) or DGFAS_BATCH_TUNED (the choice per level
+                               and stage made by dgfas_autotune; per-degree until it has run).
+                               Levels with one degree always take one launch per stage */
+  int32_t graph;            /* 1: dgfas_solve replays each V-cycle's smoothing and transfer legs
+                               as two captured HIP graphs (the root solve between them runs
+                               eagerly); results are bitwise those of the eager cycle.  Not with
+                               the learned correction */
+  int32_t reserved[4];
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);
@@ -159,6 +169,16 @@ dgfas_status dgfas_vcycle(dgfas_solver s, double* u, const double* f);
  * Returns DGFAS_ENOTCONV (a warning) if the tolerance was not reached. */
 dgfas_status dgfas_solve(dgfas_solver s, double* u, const double* f, int32_t max_cycles, double rtol,
                          double* hist, int32_t* n_done);
+
+/* Autotuner of the mixed-degree launch shape: for every level with more than one degree and
+ * each sweep stage (operator, subdomain solves, overlap add) it times the per-degree launches
+ * against the one-launch batch with HIP events (median of `reps` runs on the solver's stream,
+ * on scratch vectors) and keeps the faster one; it then sets opt.batch = DGFAS_BATCH_TUNED.
+ * cache_path (may be NULL): a JSON file of earlier choices keyed by device architecture,
+ * level degree histogram, precision and n_rhs; entries found there are used without timing
+ * and new ones are appended.  report (host, may be NULL): [n_levels][3][2] times in ms,
+ * per-degree then one-launch, 0 where a level has one degree.  Synchronous. */
+dgfas_status dgfas_autotune(dgfas_solver s, const char* cache_path, int32_t reps, double* report);
 
 /* Euclidean norm of a level-l vector per right-hand side, written to out (host, n_rhs doubles).
  * Synchronous. */

@@ -23,6 +23,7 @@ DGFAS_EINVAL, DGFAS_ENOMEM, DGFAS_EHIP, DGFAS_EUNSUPPORTED, DGFAS_EBREAKDOWN = -
 INTERIOR, DIRICHLET, NEUMANN = 0, 1, 2
 WAS, SCG = 0, 1
 FP64, FP32 = 0, 1
+BATCH_PER_DEGREE, BATCH_ONE_LAUNCH, BATCH_TUNED = 0, 1, 2
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -36,7 +37,8 @@ class Options(ctypes.Structure):
     _fields_ = [('kappa', ctypes.c_double), ('nu', ctypes.c_double), ('mu_star', ctypes.c_double),
                 ('overlap', ctypes.c_int32), ('smoother', ctypes.c_int32), ('ns1', ctypes.c_int32),
                 ('ns2', ctypes.c_int32), ('root_max_iter', ctypes.c_int32), ('root_rtol', ctypes.c_double),
-                ('precision', ctypes.c_int32), ('n_rhs', ctypes.c_int32), ('reserved', ctypes.c_int32 * 6)]
+                ('precision', ctypes.c_int32), ('n_rhs', ctypes.c_int32), ('batch', ctypes.c_int32),
+                ('graph', ctypes.c_int32), ('reserved', ctypes.c_int32 * 4)]
 
 
 class DgfasError(RuntimeError):
@@ -67,6 +69,7 @@ _sig = {
     'dgfas_vcycle': (_I, [_V, _V, _V]),
     'dgfas_solve': (_I, [_V, _V, _V, _I, ctypes.c_double, c_dp, ctypes.POINTER(_I)]),
     'dgfas_norm': (_I, [_V, _I, _V, c_dp]),
+    'dgfas_autotune': (_I, [_V, ctypes.c_char_p, _I, c_dp]),
     'dgfas_last_error': (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -199,6 +202,14 @@ class Solver:
         code = _check(_lib.dgfas_solve(self._h, _ptr(u), _ptr(f), max_cycles, rtol, hist.ctypes.data_as(c_dp),
                                        ctypes.byref(nd)), warn_ok=True)
         return hist[:nd.value + 1], code == DGFAS_OK
+
+    def autotune(self, cache_path=None, reps=10):
+        """Time per-degree against one-launch batches per level and stage (see dgfas_autotune);
+        returns [n_levels][3][2] median times in ms."""
+        rep = np.zeros((self.n_levels, 3, 2))
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(_lib.dgfas_autotune(self._h, path, reps, rep.ctypes.data_as(c_dp)))
+        return rep
 
     def norm(self, level, v):
         """Euclidean norm per right-hand side (numpy array of n_rhs values)."""

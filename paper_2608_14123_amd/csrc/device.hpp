@@ -17,6 +17,14 @@ __device__ __forceinline__ int xcd_block(int n_logical) {
 
 inline int xcd_grid(int n_logical) { return 8 * ((n_logical + 7) / 8); }
 
+// bucket of tile t (buckets ordered by their first tile; uniform over the workgroup)
+template <typename D>
+__device__ __forceinline__ int find_bucket(const D* __restrict__ bd, int nb, int stage, int t) {
+  int k = 0;
+  while (k + 1 < nb && bd[k + 1].tile0[stage] <= t) ++k;
+  return k;
+}
+
 // Volume index of face node f = (a, b) of face phi (layout: phi 0/1 -> (k, j),
 // 2/3 -> (k, i), 4/5 -> (j, i)) with the normal index set to `t`.
 template <int N>

@@ -24,8 +24,21 @@ struct OpShape {
 };
 
 template <int N, typename T>
-__global__ void __launch_bounds__(OpShape<N>::THREADS)
-sipg_apply_kernel(OpArgs<T> a) {
+struct OpSmem {
+  using S = OpShape<N>;
+  T sD[S::N2];
+  T su[S::EPB][S::N3];
+  T sF[S::EPB][3][S::N3];
+  T sTr[S::EPB][6][S::N2];    // neighbour trace
+  T sRow[S::EPB][6][S::N2];   // direct face-row term
+  T sSig[S::EPB][6][S::N2];   // lifting weight sigma
+};
+
+// One tile: EPB elements of one right-hand side (logical block lbr).  Every thread of the
+// workgroup passes every barrier; threads beyond EPB n^3 only take part in them, so the
+// tile also runs inside wider batched workgroups.
+template <int N, typename T>
+__device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpSmem<N, T>& sm) {
   using S = OpShape<N>;
   const int nrhs = a.nrhs, nel = a.nel, mode = a.mode;
   const T* __restrict__ u = a.u;
@@ -42,8 +55,6 @@ sipg_apply_kernel(OpArgs<T> a) {
   constexpr int TPT = (6 * N2 + N3 - 1) / N3;     // face tasks per thread
   // logical block = (element block, right-hand side) with the right-hand side fastest, so
   // that the batch of one element reads its geometry while it is resident in L2
-  const int lbr = xcd_block(((nel + EPB - 1) / EPB) * nrhs);
-  if (lbr < 0) return;
   const int lb = lbr / nrhs;
   const int64_t ndof = a.ndof;
   const int64_t voff = (int64_t)(lbr - lb * nrhs) * ndof;
@@ -57,12 +68,12 @@ sipg_apply_kernel(OpArgs<T> a) {
   const bool active = (le < EPB) && (li < nel);
   const int e = active ? (a.elist ? a.elist[li] : li) : 0;
 
-  __shared__ T sD[N2];
-  __shared__ T su[EPB][N3];
-  __shared__ T sF[EPB][3][N3];
-  __shared__ T sTr[EPB][6][N2];    // neighbour trace
-  __shared__ T sRow[EPB][6][N2];   // direct face-row term
-  __shared__ T sSig[EPB][6][N2];   // lifting weight sigma
+  T(&sD)[N2] = sm.sD;
+  T(&su)[EPB][N3] = sm.su;
+  T(&sF)[EPB][3][N3] = sm.sF;
+  T(&sTr)[EPB][6][N2] = sm.sTr;
+  T(&sRow)[EPB][6][N2] = sm.sRow;
+  T(&sSig)[EPB][6][N2] = sm.sSig;
 
   const int64_t base = a.off ? a.off[e] : (int64_t)e * N3;
   const int64_t fbase = a.offF ? a.offF[e] : (int64_t)e * 6 * N2;
@@ -93,7 +104,7 @@ sipg_apply_kernel(OpArgs<T> a) {
     for (int c = 0; c < 6; ++c) gl[c] = G[c * ndof + base + node];
     if (mode == 0) gval = g[base + node];
   }
-  for (int t = tid; t < N2; t += S::THREADS) sD[t] = Dg[t];
+  if (tid < N2) sD[tid] = Dg[tid];
   if (active) su[le][node] = uval;
   // phase 0: neighbour data of every face node: trace, normal derivative and metric row
   T dn_nb[TPT], gn[TPT][3];
@@ -216,11 +227,88 @@ sipg_apply_kernel(OpArgs<T> a) {
 }
 
 template <int N, typename T>
+__global__ void __launch_bounds__(OpShape<N>::THREADS)
+sipg_apply_kernel(OpArgs<T> a) {
+  using S = OpShape<N>;
+  __shared__ OpSmem<N, T> sm;
+  const int lbr = xcd_block(((a.nel + S::EPB - 1) / S::EPB) * a.nrhs);
+  if (lbr < 0) return;
+  sipg_tile<N, T>(a, lbr, sm);
+}
+
+template <int N, typename T>
 void launch_sipg(const OpArgs<T>& a, hipStream_t st) {
   using S = OpShape<N>;
   const int nb = ((a.nel + S::EPB - 1) / S::EPB) * a.nrhs;
   hipLaunchKernelGGL((sipg_apply_kernel<N, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
 }
+
+// largest tile workspace of the degrees with n <= N
+template <typename T, int N>
+constexpr size_t op_smem_upto() {
+  if constexpr (N < 2) {
+    return 0;
+  } else {
+    constexpr size_t a = sizeof(OpSmem<N, T>), b = op_smem_upto<T, N - 1>();
+    return a > b ? a : b;
+  }
+}
+
+// all degrees up to NMAX - 1 in one launch; the workgroup is the widest tile's
+template <int NMAX, typename T>
+__global__ void __launch_bounds__(OpShape<NMAX>::THREADS)
+sipg_batched_kernel(OpArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
+  __shared__ __align__(16) char smem[op_smem_upto<T, NMAX>()];
+  const int t = xcd_block(ntiles);
+  if (t < 0) return;
+  {
+    const int k = find_bucket(bd, nb, kStageOp, t);
+    OpArgs<T> x = a;
+    x.nel = bd[k].nel;
+    x.elist = bd[k].elist;
+    x.D = bd[k].D;
+    x.inv_wend = bd[k].inv_wend;
+    const int lbr = t - bd[k].tile0[kStageOp];
+    switch (bd[k].p) {
+#define DGFAS_OPB(P)                                                                        \
+  case P:                                                                                   \
+    if constexpr (P + 1 <= NMAX) sipg_tile<P + 1, T>(x, lbr, *reinterpret_cast<OpSmem<P + 1, T>*>(smem)); \
+    break;
+      DGFAS_OPB(1) DGFAS_OPB(2) DGFAS_OPB(3) DGFAS_OPB(4) DGFAS_OPB(5) DGFAS_OPB(6) DGFAS_OPB(7) DGFAS_OPB(8)
+#undef DGFAS_OPB
+      default: break;
+    }
+  }
+}
+
+int stage_tiles(int stage, int p, int nel, int nrhs) {
+  const int n3 = (p + 1) * (p + 1) * (p + 1);
+  const int epb = n3 >= 256 ? 1 : 256 / n3;   // elements per tile of the operator and overlap add
+  if (stage == kStageSolve) return nel * nrhs;
+  return ((nel + epb - 1) / epb) * nrhs;
+}
+
+int stage_threads(int stage, int pmax) {
+  const int n = pmax + 1, n3 = n * n * n;
+  if (stage == kStageSolve) return n + 2 >= 9 ? 128 : 64;   // overlap 1: ns^2 lines, rounded to waves
+  if (n3 >= 256) return ((n3 + 63) / 64) * 64;
+  return 256;
+}
+
+template <typename T>
+void sipg_apply_batched(int pmax, const OpArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l, hipStream_t st) {
+  if (l.ntiles <= 0) return;
+  const dim3 g(l.grid), b(stage_threads(kStageOp, pmax));
+  if (pmax <= 5) hipLaunchKernelGGL((sipg_batched_kernel<6, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+  else if (pmax == 6) hipLaunchKernelGGL((sipg_batched_kernel<7, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+  else if (pmax == 7) hipLaunchKernelGGL((sipg_batched_kernel<8, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+  else hipLaunchKernelGGL((sipg_batched_kernel<9, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+}
+
+template void sipg_apply_batched<double>(int, const OpArgs<double>&, const BucketDesc<double>*, const BatchLaunch&,
+                                         hipStream_t);
+template void sipg_apply_batched<float>(int, const OpArgs<float>&, const BucketDesc<float>*, const BatchLaunch&,
+                                        hipStream_t);
 
 template <typename T>
 void sipg_apply(int p, const OpArgs<T>& a, hipStream_t st) {

@@ -59,13 +59,23 @@ int overlap_size(int p, int m) {
 }
 
 template <int N, int M, typename T>
-__global__ void __launch_bounds__((SzShape<N, M>::THREADS))
-schwarz_solve_kernel(SchwarzArgs<T> a) {
+struct SzSmem {
+  using Sh = SzShape<N, M>;
+  T tA[Sh::TILE];
+  T tB[Sh::TILE];
+  T sW[3][Sh::NS];
+  int sMap[3][Sh::NS];
+  int sNb[27];
+  int sOff[27];
+};
+
+// One subdomain solve (logical block lbr = element in the list, right-hand side fastest).
+// Threads at or beyond THR (wider batched workgroups) only pass the barriers.
+template <int N, int M, typename T>
+__device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, SzSmem<N, M, T>& sm) {
   using Sh = SzShape<N, M>;
   constexpr int NS = Sh::NS, LS = Sh::LS, N3 = N * N * N, THR = Sh::THREADS;
   constexpr Regions<N, M> R{};
-  const int lbr = xcd_block(a.nel * a.nrhs);
-  if (lbr < 0) return;
   const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;   // right-hand side fastest
   const int e = a.elist ? a.elist[li] : li;
   if (a.sel && !a.sel[e]) return;
@@ -73,13 +83,14 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
   a.z += (int64_t)rhs * a.ndof;
   a.O += (int64_t)rhs * a.nin;
   const int tid = threadIdx.x;
+  const bool inb = tid < THR;
 
-  __shared__ T tA[Sh::TILE];
-  __shared__ T tB[Sh::TILE];
-  __shared__ T sW[3][NS];
-  __shared__ int sMap[3][NS];
-  __shared__ int sNb[27];
-  __shared__ int sOff[27];
+  T(&tA)[Sh::TILE] = sm.tA;
+  T(&tB)[Sh::TILE] = sm.tB;
+  T(&sW)[3][NS] = sm.sW;
+  int(&sMap)[3][NS] = sm.sMap;
+  int(&sNb)[27] = sm.sNb;
+  int(&sOff)[27] = sm.sOff;
 
   // variant per direction: uniform over the workgroup, so the eigenvector tables
   // are read through the scalar cache straight into SGPR operands
@@ -114,7 +125,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
     for (int it = 0; it < GIT; ++it) {
       const int q = tid + it * THR;
       vals[it] = 0;
-      if (q < NS * NS * NS) {
+      if (inb && q < NS * NS * NS) {
         const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
         const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
         if (m1 >= 0 && m2 >= 0 && m3 >= 0) {
@@ -126,7 +137,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
 #pragma unroll
     for (int it = 0; it < GIT; ++it) {
       const int q = tid + it * THR;
-      if (q < NS * NS * NS) {
+      if (inb && q < NS * NS * NS) {
         const int s1 = q % NS, s23 = q / NS;
         tA[s23 * LS + s1] = vals[it];
       }
@@ -225,7 +236,7 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
 #pragma unroll
   for (int it = 0; it < GIT; ++it) {
     const int q = tid + it * THR;
-    if (q >= NS * NS * NS) continue;
+    if (!inb || q >= NS * NS * NS) continue;
     const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
     const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
     if (m1 < 0 || m2 < 0 || m3 < 0) continue;
@@ -256,21 +267,31 @@ struct AddShape {
   static constexpr int THREADS = ((EPB * N3 + 63) / 64) * 64;
 };
 
+template <int N, int M, typename T>
+__global__ void __launch_bounds__((SzShape<N, M>::THREADS))
+schwarz_solve_kernel(SchwarzArgs<T> a) {
+  __shared__ SzSmem<N, M, T> sm;
+  const int lbr = xcd_block(a.nel * a.nrhs);
+  if (lbr < 0) return;
+  schwarz_tile<N, M, T>(a, lbr, sm);
+}
+
+struct AddSmem {
+  int sOff[27];
+};
+
 // z[node] += sum of the neighbours' overlap contributions in the element's own
 // inbox, in a fixed order.  Inbox regions of absent neighbours stay zero.
 template <int N, int M, typename T>
-__global__ void __launch_bounds__(AddShape<N>::THREADS)
-schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
+__device__ __forceinline__ void overlap_add_tile(SchwarzArgs<T> a, const int lbr, AddSmem& sm) {
   using Sh = AddShape<N>;
   constexpr int N3 = Sh::N3, EPB = Sh::EPB;
   constexpr Regions<N, M> R{};
-  const int lbr = xcd_block(((a.nel + EPB - 1) / EPB) * a.nrhs);
-  if (lbr < 0) return;
   const int lb = lbr / a.nrhs, rhs = lbr - lb * a.nrhs;
   a.z += (int64_t)rhs * a.ndof;
   a.O += (int64_t)rhs * a.nin;
   const int tid = threadIdx.x;
-  __shared__ int sOff[27];
+  int(&sOff)[27] = sm.sOff;
   if (tid < 27) sOff[tid] = R.off[tid];
   __syncthreads();
   const int le = tid / N3, node = tid - le * N3;
@@ -313,6 +334,16 @@ schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
 #pragma unroll
   for (int t = 0; t < 7; ++t) acc += ok[t] ? vals[t] : T(0);
   a.z[elem_base<N>(a, e) + node] += acc;
+}
+
+template <int N, int M, typename T>
+__global__ void __launch_bounds__(AddShape<N>::THREADS)
+schwarz_overlap_add_kernel(SchwarzArgs<T> a) {
+  using Sh = AddShape<N>;
+  __shared__ AddSmem sm;
+  const int lbr = xcd_block(((a.nel + Sh::EPB - 1) / Sh::EPB) * a.nrhs);
+  if (lbr < 0) return;
+  overlap_add_tile<N, M, T>(a, lbr, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -516,6 +547,100 @@ void schwarz_overlap_add(int p, int m, const SchwarzArgs<T>& a, hipStream_t st) 
   if (m == 0) return;
   DGFAS_SZ_CASES(launch_overlap)
 }
+
+// ---------------------------------------------------------------------------
+// Batched launches over the degree buckets of a mixed-degree level (overlap m = 1).
+template <typename T, int N>
+constexpr size_t sz_smem_upto() {
+  if constexpr (N < 2) {
+    return 0;
+  } else {
+    constexpr size_t a = sizeof(SzSmem<N, 1, T>), b = sz_smem_upto<T, N - 1>();
+    return a > b ? a : b;
+  }
+}
+
+template <int NMAX, typename T>
+__global__ void __launch_bounds__((SzShape<NMAX, 1>::THREADS))
+schwarz_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
+  __shared__ __align__(16) char smem[sz_smem_upto<T, NMAX>()];
+  const int t = xcd_block(ntiles);
+  if (t < 0) return;
+  {
+    const int k = find_bucket(bd, nb, kStageSolve, t);
+    SchwarzArgs<T> x = a;
+    x.nel = bd[k].nel;
+    x.elist = bd[k].elist;
+    x.S = bd[k].S;
+    x.ST = bd[k].ST;
+    x.lam = bd[k].lam;
+    x.W = bd[k].W;
+    x.map1d = bd[k].map1d;
+    const int lbr = t - bd[k].tile0[kStageSolve];
+    switch (bd[k].p) {
+#define DGFAS_SZB(P)                                                                                  \
+  case P:                                                                                             \
+    if constexpr (P + 1 <= NMAX) schwarz_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<SzSmem<P + 1, 1, T>*>(smem)); \
+    break;
+      DGFAS_SZB(1) DGFAS_SZB(2) DGFAS_SZB(3) DGFAS_SZB(4) DGFAS_SZB(5) DGFAS_SZB(6) DGFAS_SZB(7) DGFAS_SZB(8)
+#undef DGFAS_SZB
+      default: break;
+    }
+  }
+}
+
+template <int NMAX, typename T>
+__global__ void __launch_bounds__(AddShape<NMAX>::THREADS)
+overlap_add_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
+  __shared__ AddSmem sm;
+  const int t = xcd_block(ntiles);
+  if (t < 0) return;
+  {
+    const int k = find_bucket(bd, nb, kStageAdd, t);
+    SchwarzArgs<T> x = a;
+    x.nel = bd[k].nel;
+    x.elist = bd[k].elist;
+    const int lbr = t - bd[k].tile0[kStageAdd];
+    switch (bd[k].p) {
+#define DGFAS_ADB(P)                                                          \
+  case P:                                                                     \
+    if constexpr (P + 1 <= NMAX) overlap_add_tile<P + 1, 1, T>(x, lbr, sm);  \
+    break;
+      DGFAS_ADB(1) DGFAS_ADB(2) DGFAS_ADB(3) DGFAS_ADB(4) DGFAS_ADB(5) DGFAS_ADB(6) DGFAS_ADB(7) DGFAS_ADB(8)
+#undef DGFAS_ADB
+      default: break;
+    }
+  }
+}
+
+#define DGFAS_BATCH_LAUNCH(KERNEL, STAGE)                                                              \
+  if (l.ntiles <= 0) return;                                                                           \
+  const dim3 g(l.grid), b(stage_threads(STAGE, pmax));                                                 \
+  if (pmax <= 5) hipLaunchKernelGGL((KERNEL<6, T>), g, b, 0, st, a, bd, l.nb, l.ntiles); \
+  else if (pmax == 6) hipLaunchKernelGGL((KERNEL<7, T>), g, b, 0, st, a, bd, l.nb, l.ntiles); \
+  else if (pmax == 7) hipLaunchKernelGGL((KERNEL<8, T>), g, b, 0, st, a, bd, l.nb, l.ntiles); \
+  else hipLaunchKernelGGL((KERNEL<9, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+
+template <typename T>
+void schwarz_solve_batched(int pmax, const SchwarzArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l,
+                           hipStream_t st) {
+  DGFAS_BATCH_LAUNCH(schwarz_batched_kernel, kStageSolve)
+}
+template <typename T>
+void schwarz_overlap_add_batched(int pmax, const SchwarzArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l,
+                                 hipStream_t st) {
+  DGFAS_BATCH_LAUNCH(overlap_add_batched_kernel, kStageAdd)
+}
+#undef DGFAS_BATCH_LAUNCH
+
+template void schwarz_solve_batched<double>(int, const SchwarzArgs<double>&, const BucketDesc<double>*,
+                                            const BatchLaunch&, hipStream_t);
+template void schwarz_solve_batched<float>(int, const SchwarzArgs<float>&, const BucketDesc<float>*,
+                                           const BatchLaunch&, hipStream_t);
+template void schwarz_overlap_add_batched<double>(int, const SchwarzArgs<double>&, const BucketDesc<double>*,
+                                                  const BatchLaunch&, hipStream_t);
+template void schwarz_overlap_add_batched<float>(int, const SchwarzArgs<float>&, const BucketDesc<float>*,
+                                                 const BatchLaunch&, hipStream_t);
 
 template void schwarz_solve<double>(int, int, const SchwarzArgs<double>&, hipStream_t);
 template void schwarz_solve<float>(int, int, const SchwarzArgs<float>&, hipStream_t);

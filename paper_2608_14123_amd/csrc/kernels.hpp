@@ -33,6 +33,33 @@ struct OpArgs {
 template <typename T>
 void sipg_apply(int p, const OpArgs<T>& a, hipStream_t st);
 
+// Batched launches of mixed-degree levels: one launch per sweep stage covers a work list of
+// tiles over all degree buckets (largest degree first), one tile per workgroup, so the
+// hardware dispatcher balances the load.  Per-bucket data lives in a device table; the
+// per-call vectors come with the stage's argument block.
+template <typename T>
+struct BucketDesc {
+  int p = 0, m = 0, nel = 0, pad0 = 0;
+  int tile0[4] = {0, 0, 0, 0};      // first tile in the operator / solve / overlap-add lists
+  const int* elist = nullptr;
+  const T* D = nullptr;
+  const T *S = nullptr, *ST = nullptr, *lam = nullptr, *W = nullptr;
+  const int* map1d = nullptr;
+  T inv_wend = 0;
+};
+struct BatchLaunch {
+  int nb = 0;           // buckets
+  int ntiles = 0;       // tiles of the stage
+  int grid = 0;         // workgroups (a multiple of 8)
+};
+enum { kStageOp = 0, kStageSolve = 1, kStageAdd = 2 };
+// tiles per bucket of each stage (elements per tile times right-hand sides)
+int stage_tiles(int stage, int p, int nel, int nrhs);
+// workgroup size of the batched kernel of a stage for largest degree pmax
+int stage_threads(int stage, int pmax);
+template <typename T>
+void sipg_apply_batched(int pmax, const OpArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l, hipStream_t st);
+
 // one-time geometry of a degree bucket (Sec. 2.2)
 struct GeoArgs {
   int nel = 0;
@@ -134,6 +161,12 @@ void schwarz_solve(int p, int m, const SchwarzArgs<T>& a, hipStream_t st);
 template <typename T>
 void schwarz_overlap_add(int p, int m, const SchwarzArgs<T>& a, hipStream_t st);
 int overlap_size(int p, int m);
+template <typename T>
+void schwarz_solve_batched(int pmax, const SchwarzArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l,
+                           hipStream_t st);
+template <typename T>
+void schwarz_overlap_add_batched(int pmax, const SchwarzArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l,
+                                 hipStream_t st);
 
 // transfers: out (=|+=) T(x)T(x)T (in - in2) per element; T is n_out x n_in
 template <typename T>

@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -14,6 +16,7 @@
 
 #include "../../include/dgfas.h"
 #include "blas.hpp"
+#include "device.hpp"
 #include "kernels.hpp"
 #include "tables.hpp"
 #include "mlp.hpp"
@@ -96,6 +99,12 @@ struct Level {
   int* deg = nullptr;                   // device per-element data, null on uniform levels
   int64_t *off = nullptr, *offF = nullptr, *offO = nullptr;
   std::vector<Bucket> bk;
+  // one-launch batches over the buckets (levels with several degrees)
+  BucketDesc<double>* bd64 = nullptr;
+  BucketDesc<float>* bd32 = nullptr;
+  int tiles[3] = {0, 0, 0};             // work-list length per stage
+  int one_launch[3] = {0, 0, 0};        // tuned choice per stage
+  std::string hist;                     // degree histogram "p:count,..." (autotuner key)
   int nm = 0;                           // elements with a face to another degree
   int* mlist = nullptr;
   double* muf = nullptr;                // [E][6] mu_F nu
@@ -134,6 +143,12 @@ struct Solver {
   std::vector<Level> lv;   // lv[0] = root (level 1)
   std::map<int, DegTab> tabs;
   double *Dall = nullptr, *Iall = nullptr;   // mixed-degree face tables for degrees 1..8
+  int force_batch = -1;                      // autotuner: -1 options, 0 per degree, 1 one launch
+  // captured V-cycle legs (smoothing and transfers above the root, down and up)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gdown = nullptr, gup = nullptr;
+  const double *gu = nullptr, *gf = nullptr;
+  int graph_epoch = 0, graph_built_epoch = -1;
   int nrhs = 1;            // right-hand sides per batch; vectors are [nrhs][ndof]
   double* partial = nullptr;   // [2][nrhs][1024] first-stage sums
   double* scal = nullptr;      // [nrhs][8] SCG scalars
@@ -159,7 +174,30 @@ struct Solver {
   }
   ~Solver() {
     if (st) hipStreamSynchronize(st);
+    drop_graphs();
+    if (cap) hipStreamDestroy(cap);
     for (void* p : owned) hipFree(p);
+  }
+  void drop_graphs() {
+    if (gdown) hipGraphExecDestroy(gdown);
+    if (gup) hipGraphExecDestroy(gup);
+    gdown = gup = nullptr;
+    gu = gf = nullptr;
+  }
+
+  // one launch over all buckets for this level and stage?
+  bool use_batch(const Level& L, int stage) const {
+    if (L.uniform || L.bk.size() < 2) return false;
+    if (stage != kStageOp && opt.overlap != 1) return false;   // batched Schwarz tiles take m = 1
+    if (force_batch >= 0) return force_batch == 1;
+    if (opt.batch == DGFAS_BATCH_ONE_LAUNCH) return true;
+    if (opt.batch == DGFAS_BATCH_TUNED) return L.one_launch[stage] != 0;
+    return false;
+  }
+  template <typename T>
+  const BucketDesc<T>* bdesc(const Level& L) const {
+    if constexpr (sizeof(T) == 8) return L.bd64;
+    else return L.bd32;
   }
 
   Level& level(int l) {
@@ -175,9 +213,16 @@ struct Solver {
   // between degrees
   template <typename T>
   void op(Level& L, int mode, const T* u, const T* g, T* out) {
-    for (const Bucket& b : L.bk) {
-      OpArgs<T> a = op_args<T>(L, b, mode, u, g, out);
-      sipg_apply<T>(b.p, a, st);
+    if (use_batch(L, kStageOp)) {
+      OpArgs<T> a = op_args<T>(L, L.bk[0], mode, u, g, out);
+      BatchLaunch bl;
+      bl.nb = (int)L.bk.size(); bl.ntiles = L.tiles[kStageOp]; bl.grid = xcd_grid(bl.ntiles);
+      sipg_apply_batched<T>(L.p, a, bdesc<T>(L), bl, st);
+    } else {
+      for (const Bucket& b : L.bk) {
+        OpArgs<T> a = op_args<T>(L, b, mode, u, g, out);
+        sipg_apply<T>(b.p, a, st);
+      }
     }
     if (L.nm) {
       MortarArgs<T> m;
@@ -217,20 +262,33 @@ struct Solver {
       schwarz_overlap_add<double>(L.p, L.m, a, st);
       return;
     }
-    // buckets do not exchange overlap (another degree is zero filled), so each bucket's
-    // solve and overlap add form an independent pair
+    schwarz_t2<double>(L, r, z, mode);
+  }
+  void schwarz32(Level& L, const float* r, float* z, int mode) { schwarz_t2<float>(L, r, z, mode); }
+
+  // Buckets do not exchange overlap (another degree is zero filled), so the subdomain
+  // solves of all buckets may run before or beside any overlap add; every stage is either
+  // one launch per bucket or one launch over all buckets.
+  template <typename T>
+  void schwarz_stage(Level& L, int stage, const T* r, T* z, int mode) {
+    if (use_batch(L, stage)) {
+      SchwarzArgs<T> a = sz_args<T>(L, L.bk[0], r, z, mode);
+      BatchLaunch bl;
+      bl.nb = (int)L.bk.size(); bl.ntiles = L.tiles[stage]; bl.grid = xcd_grid(bl.ntiles);
+      if (stage == kStageSolve) schwarz_solve_batched<T>(L.p, a, bdesc<T>(L), bl, st);
+      else schwarz_overlap_add_batched<T>(L.p, a, bdesc<T>(L), bl, st);
+      return;
+    }
     for (const Bucket& b : L.bk) {
-      SchwarzArgs<double> a = sz_args<double>(L, b, r, z, mode);
-      schwarz_solve<double>(b.p, b.t->m, a, st);
-      schwarz_overlap_add<double>(b.p, b.t->m, a, st);
+      SchwarzArgs<T> a = sz_args<T>(L, b, r, z, mode);
+      if (stage == kStageSolve) schwarz_solve<T>(b.p, b.t->m, a, st);
+      else schwarz_overlap_add<T>(b.p, b.t->m, a, st);
     }
   }
-  void schwarz32(Level& L, const float* r, float* z, int mode) {
-    for (const Bucket& b : L.bk) {
-      SchwarzArgs<float> a = sz_args<float>(L, b, r, z, mode);
-      schwarz_solve<float>(b.p, b.t->m, a, st);
-      schwarz_overlap_add<float>(b.p, b.t->m, a, st);
-    }
+  template <typename T>
+  void schwarz_t2(Level& L, const T* r, T* z, int mode) {
+    schwarz_stage<T>(L, kStageSolve, r, z, mode);
+    schwarz_stage<T>(L, kStageAdd, r, z, mode);
   }
 
   // kind 0: out = P in (projection), 1: out (+)= R in (restriction), 2: out += I (in - in2)
@@ -428,7 +486,8 @@ struct Solver {
     return scg<double>(L, u, g, opt.root_max_iter, rmax, breakdown);
   }
 
-  // Alg. 2 with global p-coarsening.
+  // Alg. 2 with p-coarsening (per element on mixed-degree levels): the leg above the root
+  // solve going down (pre-smoothing, tau-correction), the root solve, the leg going up.
   void vcycle(double* u_top, const double* f_top) {
     const int Lc = (int)lv.size();
     Level& T = lv[Lc - 1];
@@ -437,6 +496,82 @@ struct Solver {
     T.u = u_top;
     T.g = const_cast<double*>(f_top);
     bool bd = false;
+    leg_down();
+    root_solve(lv[0].u, lv[0].g, &bd);
+    leg_up();
+    T.u = u_save;
+    T.g = const_cast<double*>(g_save);
+  }
+
+  // The same cycle with both legs replayed from captured graphs (bitwise the same work).
+  void vcycle_graphed(double* u_top, const double* f_top) {
+    if (!gdown || gu != u_top || gf != f_top || graph_built_epoch != graph_epoch) build_graphs(u_top, f_top);
+    bool bd = false;
+    HIPC(hipGraphLaunch(gdown, st));
+    root_solve(lv[0].u, lv[0].g, &bd);
+    HIPC(hipGraphLaunch(gup, st));
+  }
+
+  // every work vector a leg may touch, allocated before capture
+  void prepare_legs() {
+    const bool fp32 = opt.precision == DGFAS_FP32;
+    for (size_t l = 1; l < lv.size(); ++l) {
+      Level& L = lv[l];
+      if (fp32) ensure_mixed_vectors(L);
+      if (opt.smoother == DGFAS_SCG) ensure_scg_vectors(L, fp32);
+      if (!fp32 && !L.z) L.z = own(dalloc<double>((size_t)L.ndof * nrhs));
+    }
+  }
+
+  void build_graphs(double* u_top, const double* f_top) {
+    drop_graphs();
+    prepare_legs();
+    if (!cap) HIPC(hipStreamCreate(&cap));
+    HIPC(hipStreamSynchronize(st));
+    const int Lc = (int)lv.size();
+    Level& T = lv[Lc - 1];
+    double* u_save = T.u;
+    const double* g_save = T.g;
+    hipStream_t saved = st;
+    T.u = u_top;
+    T.g = const_cast<double*>(f_top);
+    st = cap;
+    hipGraphExec_t* dst[2] = {&gdown, &gup};
+    try {
+      for (int leg = 0; leg < 2; ++leg) {
+        HIPC(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        try {
+          if (leg == 0) leg_down();
+          else leg_up();
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          hipStreamEndCapture(cap, &g);
+          if (g) hipGraphDestroy(g);
+          throw;
+        }
+        hipGraph_t g = nullptr;
+        HIPC(hipStreamEndCapture(cap, &g));
+        const hipError_t e = hipGraphInstantiate(dst[leg], g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        HIPC(e);
+      }
+    } catch (...) {
+      st = saved;
+      T.u = u_save;
+      T.g = const_cast<double*>(g_save);
+      drop_graphs();
+      throw;
+    }
+    st = saved;
+    T.u = u_save;
+    T.g = const_cast<double*>(g_save);
+    gu = u_top;
+    gf = f_top;
+    graph_built_epoch = graph_epoch;
+  }
+
+  void leg_down() {
+    const int Lc = (int)lv.size();
     for (int l = Lc - 1; l >= 1; --l) {
       Level& F = lv[l];
       Level& C = lv[l - 1];
@@ -447,16 +582,19 @@ struct Solver {
       apply(C, C.ubar, C.g);                                                     // g = A ubar
       transfer(F, C, 1, F.r, nullptr, C.g, 1);                                   //   + R r
     }
-    root_solve(lv[0].u, lv[0].g, &bd);
+  }
+
+  void leg_up() {
+    const int Lc = (int)lv.size();
     for (int l = 1; l < Lc; ++l) {
       Level& F = lv[l];
       Level& C = lv[l - 1];
       transfer(F, C, 2, C.u, C.ubar, F.u, 1);                                  // u += I (u_c - ubar)
       smooth(F, F.u, F.g, opt.ns2);
     }
-    T.u = u_save;
-    T.g = const_cast<double*>(g_save);
   }
+
+  void autotune(const char* path, int reps, double* report);
 };
 
 template <typename T>
@@ -598,6 +736,33 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     b.t = &deg_tab(s, p);
     L.bk.push_back(std::move(b));
   }
+  // degree histogram and the one-launch work lists (largest degree first)
+  for (const Bucket& b : L.bk) L.hist += std::to_string(b.p) + ":" + std::to_string(b.nel) + ",";
+  if (!L.uniform) {
+    std::vector<BucketDesc<double>> d64;
+    std::vector<BucketDesc<float>> d32;
+    int t0[3] = {0, 0, 0};
+    for (int k = (int)L.bk.size() - 1; k >= 0; --k) {
+      const Bucket& b = L.bk[k];
+      const DegTab& t = *b.t;
+      BucketDesc<double> x;
+      BucketDesc<float> y;
+      x.p = y.p = b.p; x.m = y.m = t.m; x.nel = y.nel = b.nel;
+      x.elist = y.elist = b.elist;
+      for (int sg = 0; sg < 3; ++sg) {
+        x.tile0[sg] = y.tile0[sg] = t0[sg];
+        t0[sg] += stage_tiles(sg, b.p, b.nel, s.nrhs);
+      }
+      x.D = t.D; x.S = t.S; x.ST = t.ST; x.lam = t.lam; x.W = t.W; x.map1d = t.map1d; x.inv_wend = t.inv_wend;
+      y.D = t.D32; y.S = t.S32; y.ST = t.ST32; y.lam = t.lam32; y.W = t.W32; y.map1d = t.map1d;
+      y.inv_wend = (float)t.inv_wend;
+      d64.push_back(x);
+      d32.push_back(y);
+    }
+    for (int sg = 0; sg < 3; ++sg) L.tiles[sg] = t0[sg];
+    L.bd64 = s.own(upload(d64, st));
+    L.bd32 = s.own(upload(d32, st));
+  }
   // elements with a face to another degree
   if (!L.uniform) {
     std::vector<int> ml;
@@ -738,6 +903,130 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   HIPC(hipStreamSynchronize(st));
 }
 
+// ---------------------------------------------------------------------------------- autotuner
+namespace {
+
+// flat JSON object of string keys and integer values (the autotuner cache)
+std::map<std::string, int> read_cache(const char* path) {
+  std::map<std::string, int> m;
+  if (!path) return m;
+  std::ifstream in(path);
+  if (!in) return m;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string t = ss.str();
+  size_t i = 0;
+  while ((i = t.find('"', i)) != std::string::npos) {
+    const size_t j = t.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = t.substr(i + 1, j - i - 1);
+    const size_t c = t.find(':', j);
+    if (c == std::string::npos) break;
+    m[key] = std::atoi(t.c_str() + c + 1);
+    i = t.find_first_of(",}", c);
+    if (i == std::string::npos) break;
+  }
+  return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, int>& m) {
+  if (!path) return;
+  std::ofstream out(path);
+  if (!out) throw Error(DGFAS_EINVAL, std::string("cannot write the autotuner cache ") + path);
+  out << "{\n";
+  size_t k = 0;
+  for (const auto& kv : m) out << "  \"" << kv.first << "\": " << kv.second << (++k < m.size() ? ",\n" : "\n");
+  out << "}\n";
+}
+
+}  // namespace
+
+void Solver::autotune(const char* path, int reps, double* report) {
+  if (reps < 1) throw Error(DGFAS_EINVAL, "reps must be >= 1");
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPC(hipGetDeviceProperties(&prop, dev));
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  std::map<std::string, int> cache = read_cache(path);
+  const char* stage_name[3] = {"operator", "solve", "add"};
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  double *x = nullptr, *y = nullptr, *w = nullptr;
+  auto cleanup = [&]() {
+    force_batch = -1;
+    hipStreamSynchronize(st);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (x) hipFree(x);
+    if (y) hipFree(y);
+    if (w) hipFree(w);
+  };
+  try {
+    for (size_t li = 0; li < lv.size(); ++li) {
+      Level& L = lv[li];
+      for (int sg = 0; sg < 3; ++sg)
+        if (report) report[(li * 3 + sg) * 2] = report[(li * 3 + sg) * 2 + 1] = 0.0;
+      if (L.uniform || L.bk.size() < 2) continue;
+      const size_t nv = (size_t)L.ndof * nrhs;
+      if (x) { hipStreamSynchronize(st); hipFree(x); hipFree(y); hipFree(w); x = y = w = nullptr; }
+      x = dalloc<double>(nv);
+      y = dalloc<double>(nv);
+      w = dalloc<double>(nv);
+      fill((int64_t)nv, x, 0.5, st);
+      fill((int64_t)nv, y, 0.25, st);
+      for (int sg = 0; sg < 3; ++sg) {
+        const std::string key = arch + "|" + L.hist + "|" + (opt.precision == DGFAS_FP32 ? "fp32" : "fp64") + "|rhs" +
+                                std::to_string(nrhs) + "|" + stage_name[sg];
+        if (sg != kStageOp && opt.overlap != 1) continue;
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+          L.one_launch[sg] = it->second;
+          continue;
+        }
+        double med[2];
+        for (int v = 0; v < 2; ++v) {
+          force_batch = v;
+          auto run = [&]() {
+            if (sg == kStageOp) op<double>(L, 0, x, y, w);
+            else schwarz_stage<double>(L, sg, x, w, 1);
+          };
+          run();   // warm-up
+          std::vector<double> ts;
+          for (int k = 0; k < reps; ++k) {
+            HIPC(hipEventRecord(e0, st));
+            run();
+            HIPC(hipEventRecord(e1, st));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            ts.push_back(ms);
+          }
+          std::sort(ts.begin(), ts.end());
+          med[v] = ts[ts.size() / 2];
+          HIPC(hipGetLastError());
+        }
+        force_batch = -1;
+        L.one_launch[sg] = med[1] < med[0] ? 1 : 0;
+        cache[key] = L.one_launch[sg];
+        if (report) {
+          report[(li * 3 + sg) * 2] = med[0];
+          report[(li * 3 + sg) * 2 + 1] = med[1];
+        }
+      }
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+  write_cache(path, cache);
+  opt.batch = DGFAS_BATCH_TUNED;
+  ++graph_epoch;
+}
+
 void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (!m || !o) throw Error(DGFAS_EINVAL, "null mesh or options");
   if (m->n_elem <= 0 || !m->degree || !m->coords || !m->face_nbr || !m->face_bc)
@@ -766,6 +1055,8 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
   if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32) throw Error(DGFAS_EINVAL, "unknown precision");
   if (o->n_rhs < 1 || o->n_rhs > 64) throw Error(DGFAS_EINVAL, "n_rhs must be 1..64");
+  if (o->batch < DGFAS_BATCH_PER_DEGREE || o->batch > DGFAS_BATCH_TUNED) throw Error(DGFAS_EINVAL, "unknown batch mode");
+  if (o->graph != 0 && o->graph != 1) throw Error(DGFAS_EINVAL, "graph must be 0 or 1");
   if ((int64_t)m->n_elem * o->n_rhs > (int64_t)1 << 30) throw Error(DGFAS_EUNSUPPORTED, "n_elem * n_rhs too large");
 }
 
@@ -1127,7 +1418,8 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
     s->learned = use_learned && !plain_probe;
     if (s->learned)
       HIPC(hipMemcpyAsync(usave, u, T.ndof * s->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s->st));
-    s->vcycle(u, f);
+    if (s->opt.graph && !attached) s->vcycle_graphed(u, f);
+    else s->vcycle(u, f);
     s->residual(T, u, f, T.r);
     double rk = worst(s->dots_sync(T, T.r, T.r));
     if (plain_probe && k == 1) s->plain_rho = rk / prev;
@@ -1269,6 +1561,13 @@ dgfas_status dgfas_learned_pairs(dgfas_solver sv, const double* r, const int32_t
     throw;
   }
   cleanup();
+  API_END
+}
+
+dgfas_status dgfas_autotune(dgfas_solver sv, const char* cache_path, int32_t reps, double* report) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  s->autotune(cache_path, reps, report);
   API_END
 }
 

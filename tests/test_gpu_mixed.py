@@ -223,3 +223,89 @@ def test_front_workload_converges(binding, front27):
     u = torch.zeros_like(b)
     hist, _ = lib.solve(u, b, max_cycles=4, rtol=0.0)
     assert all(np.isfinite(hist)) and all(hist[k + 1] < 0.2 * hist[k] for k in range(len(hist) - 1)), hist
+
+
+@pytest.mark.parametrize('case', CASES, ids=repr)
+def test_one_launch_batches_match_per_degree_launches(binding, case):
+    """The one-launch batch of every sweep stage computes every element as its degree's own
+    launch does: bitwise equal results on every level, FP64 and FP32."""
+    print('one-launch batches', case, flush=True)
+    lv = case.oracle_levels()
+    per = case.library(binding)
+    one = case.library(binding, batch=binding.BATCH_ONE_LAUNCH)
+    rng = np.random.default_rng(15)
+    for l in range(1, per.n_levels + 1):
+        n = lv[l - 1].mesh.n_dof()
+        u, g = dev(rng.uniform(-1, 1, n)), dev(rng.uniform(-1, 1, n))
+        outs = []
+        for lib in (per, one):
+            a = torch.empty(n, dtype=torch.float64, device='cuda')
+            r = torch.empty_like(a)
+            z = torch.empty_like(a)
+            lib.apply(l, u, a)
+            lib.residual(l, u, g, r)
+            lib.schwarz(l, g, z)
+            outs.append([host(a), host(r), host(z)])
+        for x, y in zip(*outs):
+            assert np.array_equal(x, y), (l, np.abs(x - y).max())
+        assert rel(outs[1][2], lv[l - 1].B(host(g))) <= 1e-11
+    per.close()
+    one.close()
+
+
+@pytest.mark.parametrize('batch,precision', [(0, 'fp64'), (1, 'fp64'), (1, 'fp32')])
+def test_graph_replayed_cycles_are_bitwise_eager(binding, batch, precision):
+    """dgfas_solve with the captured legs replays them once per cycle, with the eager root
+    solve and residual norms between replays: histories and iterates are bitwise those of
+    the eager cycles."""
+    print('graph replay', batch, precision, flush=True)
+    case = CASES[2]
+    prec = binding.FP64 if precision == 'fp64' else binding.FP32
+    n = int(case.off[-1])
+    f = np.random.default_rng(16).uniform(-1, 1, n)
+    res = []
+    for graph in (0, 1):
+        lib = case.library(binding, smoother=binding.SCG, ns1=3, ns2=2, root_rtol=1e-1, precision=prec,
+                           batch=batch, graph=graph)
+        b = torch.empty(n, dtype=torch.float64, device='cuda')
+        lib.rhs(dev(f), b)
+        u = torch.zeros_like(b)
+        h1, _ = lib.solve(u, b, max_cycles=4, rtol=0.0)
+        u1 = host(u).copy()
+        h2, _ = lib.solve(u, b, max_cycles=3, rtol=0.0)     # replays continue from the current iterate
+        res.append((h1, u1, h2, host(u)))
+        lib.close()
+    for x, y in zip(*res):
+        assert np.array_equal(x, y)
+    assert res[0][0][-1] < 1e-2
+
+
+def test_autotuner_times_choices_and_reuses_its_cache(binding, tmp_path):
+    print('autotune', flush=True)
+    case = CASES[1]
+    lv = case.oracle_levels()
+    cache = tmp_path / 'tune.json'
+    lib = case.library(binding)
+    rep = lib.autotune(cache, reps=3)
+    mixed = [l for l in range(lib.n_levels) if len(np.unique(lv[l].mesh.p)) > 1]
+    assert mixed and all((rep[l] > 0).all() for l in mixed)
+    assert all((rep[l] == 0).all() for l in range(lib.n_levels) if l not in mixed)
+    text = cache.read_text()
+    assert text.count('operator') == len(mixed) and text.count('solve') == len(mixed)
+    # tuned launches give the oracle's results
+    rng = np.random.default_rng(17)
+    for l in range(1, lib.n_levels + 1):
+        nl = lv[l - 1].mesh.n_dof()
+        u = rng.uniform(-1, 1, nl)
+        out = torch.empty(nl, dtype=torch.float64, device='cuda')
+        lib.apply(l, dev(u), out)
+        assert rel(host(out), lv[l - 1].A(u)) <= 1e-12
+        lib.schwarz(l, dev(u), out)
+        assert rel(host(out), lv[l - 1].B(u)) <= 1e-11
+    lib.close()
+    # a second solver finds every choice in the cache and times nothing
+    lib2 = case.library(binding)
+    rep2 = lib2.autotune(cache, reps=3)
+    assert (rep2 == 0).all()
+    assert cache.read_text() == text
+    lib2.close()
