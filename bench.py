@@ -36,6 +36,8 @@ def parse():
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle cpu_baseline leg')
     ap.add_argument('--no-t10', action='store_true', help='skip the time-to-tolerance solves')
     ap.add_argument('--calib-copy', action='store_true', help='also run a plain copy kernel (PMC calibration)')
+    ap.add_argument('--workload', default='curved', choices=['curved', 'front'],
+                    help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8)')
     return ap.parse_args()
 
 
@@ -74,6 +76,99 @@ def cpu_baseline(ne, p, budget_s=20.0):
                       '(%d DOF) of the same mesh, numpy FP64 single thread' % (reps, sub, nd)}
 
 
+def front_bench(args, torch, B):
+    """The hp front workload (27^3 unit cubes, degrees 2..8 from the front distance, 3,217,284
+    DOF, alpha = 50): per-degree launches, one-launch batches, and autotuned launches with the
+    cycle legs replayed from HIP graphs.  Prints one JSON line."""
+    from paper_2608_14123_amd import workloads as W
+    ne = 27
+    degs, X, nbr, bc, f_host, uD_host = W.front_workload(ne, lambda p: B.gll(p)[0])
+    flat = np.concatenate([x.ravel() for x in X])
+    ndof = int(((degs.astype(np.int64) + 1) ** 3).sum())
+    stream = torch.cuda.current_stream()
+    cyc = dict(smoother=B.SCG, ns1=3, ns2=2, root_rtol=0.1)
+    f = torch.from_numpy(f_host).cuda()
+    uD = torch.from_numpy(uD_host).cuda()
+    modes = [('per_degree', dict(batch=B.BATCH_PER_DEGREE)), ('one_launch', dict(batch=B.BATCH_ONE_LAUNCH)),
+             ('tuned_graph', dict(batch=B.BATCH_TUNED, graph=1))]
+    out_modes = {}
+    tune = None
+
+    def timed(fn, reps):
+        fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    for name, extra in modes:
+        for prec in ('fp64', 'fp32'):
+            if prec == 'fp32' and name != 'tuned_graph':
+                continue
+            o = B.default_options(precision=B.FP64 if prec == 'fp64' else B.FP32, **cyc, **extra)
+            lib = B.Solver(degs, flat, nbr, bc, o, stream=stream.cuda_stream)
+            L = lib.n_levels
+            if name == 'tuned_graph' and tune is None:
+                tune = lib.autotune(None, reps=10)
+            elif name == 'tuned_graph':
+                lib.autotune(None, reps=10)
+            b = torch.empty_like(f)
+            lib.rhs(f, b, uD=uD)
+            u = torch.zeros_like(b)
+            rec = {}
+            if prec == 'fp64':
+                g = torch.from_numpy(W.uniform_nodal(ndof, 3)).cuda()
+                r = torch.empty_like(g)
+                uu = torch.from_numpy(W.uniform_nodal(ndof, 4)).cuda()
+                rec['residual_ms'] = round(timed(lambda: lib.residual(L, uu, g, r), args.reps), 4)
+                rec['schwarz_ms'] = round(timed(lambda: lib.schwarz(L, g, r), args.reps), 4)
+                ms_sweep = timed(lambda: lib.smooth(L, uu, g, 1), args.reps)
+                rec['residual_plus_scg_iteration_ms'] = round(ms_sweep, 4)
+                rec['sweep_gdofs'] = round(ndof / (ms_sweep * 1e-3) / 1e9, 3)
+                lib.solve(u.zero_(), b, max_cycles=args.warmup, rtol=0.0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lib.solve(u.zero_(), b, max_cycles=args.steps, rtol=0.0)
+                torch.cuda.synchronize()
+                rec['ms_per_cycle'] = round((time.perf_counter() - t0) * 1e3 / args.steps, 4)
+            hist, ok = lib.solve(u.zero_(), b, max_cycles=40, rtol=1e-10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hist, ok = lib.solve(u.zero_(), b, max_cycles=40, rtol=1e-10)
+            torch.cuda.synchronize()
+            rec['t10_s'] = round(time.perf_counter() - t0, 4)
+            rec['n10'] = len(hist) - 1
+            rec['converged'] = bool(ok)
+            lib.close()
+            out_modes[name if prec == 'fp64' else name + '_fp32_smoother'] = rec
+            print(name, prec, rec, file=sys.stderr, flush=True)
+    best = out_modes['tuned_graph']
+    sweeps = cyc['ns1'] + cyc['ns2']
+    bytes_res = 48.0 * ndof
+    ach = bytes_res / (best['residual_ms'] * 1e-3) / 1e9
+    levels = ['%d' % int(x) for x in np.unique(degs)]
+    out = {
+        'metric': 'GDOF/s per Schwarz sweep; time-to-1e-10 residual, plain FP64 vs mixed/learned',
+        'value': round(ndof * sweeps / (best['ms_per_cycle'] * 1e-3) / 1e9, 3), 'unit': 'GDOF/s', 'n_gpus': 1,
+        'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': best['ms_per_cycle'], 'higher_is_better': True,
+        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64', 'data': 'synthetic',
+        'config': {'workload': 'hp_front_27^3_degrees_2to8_alpha50', 'n_dof': ndof,
+                   'degrees': dict(zip(levels, np.unique(degs, return_counts=True)[1].tolist())),
+                   'cycle': 'FAS-MG-SCG(3,2), per-element p-coarsening, root SCG to 1e-1', 'overlap': 1,
+                   'mu_star': 2.0},
+        'roofline': {'kernel': 'operator stage (residual), tuned launches', 'bound': 'hbm', 'achieved': round(ach, 1),
+                     'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': round(ach / HBM_PEAK_GBS, 4), 'traffic': None},
+        'modes': out_modes,
+        'autotune_ms': {'level%d' % (l + 1): {st: tune[l][k].round(4).tolist()
+                                              for k, st in enumerate(('operator', 'solve', 'add'))}
+                        for l in range(tune.shape[0]) if tune[l].any()},
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -83,6 +178,9 @@ def main():
     import torch
     from paper_2608_14123_amd import binding as B
     assert torch.cuda.is_available(), 'needs a GPU'
+    if args.workload == 'front':
+        front_bench(args, torch, B)
+        return
     ne, p = args.ne, args.p
     E = ne ** 3
     n3 = (p + 1) ** 3

@@ -9,7 +9,8 @@
 //
 // One workgroup per (element, right-hand side) of the list; the element's faces are taken
 // one after another and every output node is written by one thread, so the result is
-// deterministic.  Degrees are runtime values (tables for p = 1..8 in global memory).
+// deterministic.  Degrees are runtime values; the face's D and interpolation tables are
+// staged in LDS.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -28,36 +29,16 @@ __device__ __forceinline__ int fnode(int n, int phi, int f, int t) {
 
 __device__ __forceinline__ int lstride(int n, int ax) { return ax == 0 ? 1 : (ax == 1 ? n : n * n); }
 
-// trace, normal flux (nu n_out . grad u, without omega s) and metric row G_ax. at the face
-// nodes of face phi of an element of size n: phase A (line derivative, trace, loads)
-// (u read at src[sbase + node], the metric at G[c * ndof + gbase + node])
+// phase B (traces, line derivatives and tables in LDS): tangential derivatives and the
+// normal flux nu n_out . grad u (without omega s) at face node f
 template <typename T>
-__device__ void face_phase_a(int n, int phi, int f, const T* __restrict__ src, int64_t sbase, int64_t gbase,
-                             const T* __restrict__ G, int64_t ndof, const double* __restrict__ D, T* tr, T* dn,
-                             T (*gr)[kMaxN2]) {
-  const int ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0, st = lstride(n, ax);
-  const int v0 = fnode(n, phi, f, 0);
-  T d = 0, t = 0;
-  for (int m = 0; m < n; ++m) {
-    const T v = src[sbase + v0 + m * st];
-    d += (T)D[endo * n + m] * v;
-    if (m == endo) t = v;
-  }
-  tr[f] = t;
-  dn[f] = d;
-  const int vi = v0 + endo * st;
-  for (int c = 0; c < 3; ++c) gr[c][f] = G[sym_index(ax, c) * ndof + gbase + vi];
-}
-
-// phase B (after the traces are in LDS): tangential derivatives and the flux
-template <typename T>
-__device__ T face_flux(int n, int phi, int f, const double* __restrict__ D, const T* tr, const T* dn,
-                       const T (*gr)[kMaxN2], T sgn, T inv_wend, T wsf) {
+__device__ T face_flux(int n, int phi, int f, const T* D, const T* tr, const T* dn, const T (*gr)[kMaxN2], T sgn,
+                       T inv_wend, T wsf) {
   const int ax = phi >> 1, a = f / n, b = f - a * n;
   T dlast = 0, dfirst = 0;
   for (int m = 0; m < n; ++m) {
-    dlast += (T)D[b * n + m] * tr[a * n + m];
-    dfirst += (T)D[a * n + m] * tr[m * n + b];
+    dlast += D[b * n + m] * tr[a * n + m];
+    dfirst += D[a * n + m] * tr[m * n + b];
   }
   T du0, du1, du2;
   if (ax == 0) { du0 = dn[f]; du1 = dlast; du2 = dfirst; }
@@ -78,15 +59,15 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
   T* __restrict__ out = a.out + (int64_t)rhs * a.ndof;
   const int po = a.deg[e], n = po + 1, n2 = n * n, n3 = n2 * n;
   const int64_t base = a.off[e], fbase = a.offF[e];
-  const double* __restrict__ Do = a.Dall + (po - 1) * kMaxN2;
   const T inv_wend_o = (T)(0.5 * po * (po + 1));
 
   __shared__ T su[kMaxN3];
   __shared__ T acc[kMaxN3];
+  __shared__ T sDo[kMaxN2], sDn[kMaxN2], sIo[kMaxN2], sIn[kMaxN2];
   __shared__ T to[kMaxN2], dno[kMaxN2], qo[kMaxN2], wso[kMaxN2], go[3][kMaxN2];
   __shared__ T tn[kMaxN2], dnn[kMaxN2], qn[kMaxN2], wsn[kMaxN2], gn[3][kMaxN2];
   __shared__ T x1[4][kMaxN2];                 // half-interpolated own t, own q, nb t, nb q
-  __shared__ T rF[kMaxN2], sF[kMaxN2];     // row term and lifting weight on the finer grid
+  __shared__ T rF[kMaxN2], sF[kMaxN2];        // row term and lifting weight on the finer grid
   __shared__ T y1[2][kMaxN2];                 // half-restricted row and lifting weight
   __shared__ T row[kMaxN2], lift[3][kMaxN2];
 
@@ -94,6 +75,7 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
     su[t] = u[base + t];
     acc[t] = 0;
   }
+  if (tid < n2) sDo[tid] = (T)a.Dall[(po - 1) * kMaxN2 + tid];
   __syncthreads();
 
   for (int phi = 0; phi < 6; ++phi) {
@@ -102,33 +84,63 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
     const int pn = a.deg[en];
     if (pn == po) continue;                 // uniform over the workgroup
     const int nn = pn + 1, nn2 = nn * nn, nF = nn > n ? nn : n, nF2 = nF * nF;
-    const int phin = phi ^ 1, ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0;
-    const double* __restrict__ Dn = a.Dall + (pn - 1) * kMaxN2;
+    const int phin = phi ^ 1, ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0, endn = (phin & 1) ? nn - 1 : 0;
     const int pF = nF - 1;
-    const double* __restrict__ Io = a.Iall + ((po - 1) * 8 + (pF - 1)) * kMaxN2;   // nF x n
-    const double* __restrict__ In = a.Iall + ((pn - 1) * 8 + (pF - 1)) * kMaxN2;   // nF x nn
     const T sgn = (phi & 1) ? T(1) : T(-1);
     const T inv_wend_n = (T)(0.5 * pn * (pn + 1));
     const T mu = (T)a.muf[(int64_t)e * 6 + phi];
     const int64_t nbase = a.off[en], nfbase = a.offF[en];
 
-    // A: traces, normal-line derivatives, metric rows and omega s of both sides
-    for (int t = tid; t < n2 + nn2; t += kMortarThreads) {
-      if (t < n2) {
-        face_phase_a<T>(n, phi, t, su, 0, base, a.G, a.ndof, Do, to, dno, go);
-        wso[t] = (T)a.ws[fbase + phi * n2 + t];
-      } else {
-        const int f = t - n2;
-        face_phase_a<T>(nn, phin, f, u, nbase, nbase, a.G, a.ndof, Dn, tn, dnn, gn);
-        wsn[f] = (T)a.ws[nfbase + phin * nn2 + f];
+    // 0: every global load of the face first (neighbour normal lines, metric rows, omega s)
+    // and the face's tables into LDS; one face-node task per thread (n^2 + nn^2 <= 162)
+    const bool own_t = tid < n2, nb_t = !own_t && tid < n2 + nn2;
+    const int f = own_t ? tid : tid - n2;
+    T line[kMaxN], g3[3] = {0, 0, 0}, wsv = 0;
+    if (nb_t) {
+      const int v0 = fnode(nn, phin, f, 0), st = lstride(nn, ax);
+#pragma unroll
+      for (int m = 0; m < kMaxN; ++m) line[m] = m < nn ? u[nbase + v0 + m * st] : T(0);
+      const int vi = v0 + endn * st;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + nbase + vi];
+      wsv = (T)a.ws[nfbase + phin * nn2 + f];
+    } else if (own_t) {
+      const int vi = fnode(n, phi, f, endo);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + base + vi];
+      wsv = (T)a.ws[fbase + phi * n2 + f];
+    }
+    for (int t = tid; t < kMaxN2; t += kMortarThreads) {
+      if (t < nn2) sDn[t] = (T)a.Dall[(pn - 1) * kMaxN2 + t];
+      if (t < nF * n) sIo[t] = (T)a.Iall[((po - 1) * 8 + (pF - 1)) * kMaxN2 + t];     // nF x n
+      if (t < nF * nn) sIn[t] = (T)a.Iall[((pn - 1) * 8 + (pF - 1)) * kMaxN2 + t];    // nF x nn
+    }
+    __syncthreads();
+    // A: traces and normal-line derivatives of both sides
+    if (own_t) {
+      const int v0 = fnode(n, phi, f, 0), st = lstride(n, ax);
+      T d = 0;
+      for (int m = 0; m < n; ++m) d += sDo[endo * n + m] * su[v0 + m * st];
+      to[f] = su[v0 + endo * st];
+      dno[f] = d;
+      wso[f] = wsv;
+      for (int c = 0; c < 3; ++c) go[c][f] = g3[c];
+    } else if (nb_t) {
+      T d = 0, tv = 0;
+#pragma unroll
+      for (int m = 0; m < kMaxN; ++m) {
+        if (m < nn) d += sDn[endn * nn + m] * line[m];
+        if (m == endn) tv = line[m];
       }
+      tn[f] = tv;
+      dnn[f] = d;
+      wsn[f] = wsv;
+      for (int c = 0; c < 3; ++c) gn[c][f] = g3[c];
     }
     __syncthreads();
     // B: normal fluxes (each side's outward normal)
-    for (int t = tid; t < n2 + nn2; t += kMortarThreads) {
-      if (t < n2) qo[t] = face_flux<T>(n, phi, t, Do, to, dno, go, sgn, inv_wend_o, wso[t]);
-      else qn[t - n2] = face_flux<T>(nn, phin, t - n2, Dn, tn, dnn, gn, -sgn, inv_wend_n, wsn[t - n2]);
-    }
+    if (own_t) qo[f] = face_flux<T>(n, phi, f, sDo, to, dno, go, sgn, inv_wend_o, wso[f]);
+    else if (nb_t) qn[f] = face_flux<T>(nn, phin, f, sDn, tn, dnn, gn, -sgn, inv_wend_n, wsn[f]);
     __syncthreads();
     // C: first interpolation step X1[i][b] = sum_a I[i][a] X[a][b] for the four face fields
     for (int t = tid; t < 2 * nF * n + 2 * nF * nn; t += kMortarThreads) {
@@ -136,10 +148,10 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
       if (s < 2 * nF * n) { which = s / (nF * n); s -= which * nF * n; w = n; }
       else { s -= 2 * nF * n; which = 2 + s / (nF * nn); s -= (which - 2) * nF * nn; w = nn; }
       const int i = s / w, b = s - i * w;
-      const double* I = which < 2 ? Io : In;
+      const T* I = which < 2 ? sIo : sIn;
       const T* X = which == 0 ? to : (which == 1 ? qo : (which == 2 ? tn : qn));
       T v = 0;
-      for (int q = 0; q < w; ++q) v += (T)I[i * w + q] * X[q * w + b];
+      for (int q = 0; q < w; ++q) v += I[i * w + q] * X[q * w + b];
       x1[which][i * w + b] = v;
     }
     __syncthreads();
@@ -148,12 +160,12 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
       const int i = t / nF, j = t - i * nF;
       T t_o = 0, q_o = 0, t_n = 0, q_n = 0;
       for (int b = 0; b < n; ++b) {
-        const T ij = (T)Io[j * n + b];
+        const T ij = sIo[j * n + b];
         t_o += x1[0][i * n + b] * ij;
         q_o += x1[1][i * n + b] * ij;
       }
       for (int b = 0; b < nn; ++b) {
-        const T ij = (T)In[j * nn + b];
+        const T ij = sIn[j * nn + b];
         t_n += x1[2][i * nn + b] * ij;
         q_n += x1[3][i * nn + b] * ij;
       }
@@ -170,7 +182,7 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
       const int aa = s / nF, j = s - aa * nF;
       const T* F = which == 0 ? rF : sF;
       T v = 0;
-      for (int i = 0; i < nF; ++i) v += (T)Io[i * n + aa] * F[i * nF + j];
+      for (int i = 0; i < nF; ++i) v += sIo[i * n + aa] * F[i * nF + j];
       y1[which][aa * nF + j] = v;
     }
     __syncthreads();
@@ -179,7 +191,7 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
       const int aa = t / n, b = t - aa * n;
       T r = 0, sgm = 0;
       for (int j = 0; j < nF; ++j) {
-        const T ij = (T)Io[j * n + b];
+        const T ij = sIo[j * n + b];
         r += y1[0][aa * nF + j] * ij;
         sgm += y1[1][aa * nF + j] * ij;
       }
@@ -193,13 +205,13 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
     const int ta = ax == 2 ? 1 : 2;   // axis of the slow face index a
     for (int t = tid; t < n3; t += kMortarThreads) {
       const int idx[3] = {t % n, (t / n) % n, t / n2};
-      const int l = idx[ax], fa = idx[ta], fb = idx[tb], f = fa * n + fb;
-      T v = (T)Do[endo * n + l] * lift[ax][f];
+      const int l = idx[ax], fa = idx[ta], fb = idx[tb], ff = fa * n + fb;
+      T v = sDo[endo * n + l] * lift[ax][ff];
       if (l == endo) {
-        v += row[f];
+        v += row[ff];
         for (int m = 0; m < n; ++m) {
-          v += (T)Do[m * n + fb] * lift[tb][fa * n + m];
-          v += (T)Do[m * n + fa] * lift[ta][m * n + fb];
+          v += sDo[m * n + fb] * lift[tb][fa * n + m];
+          v += sDo[m * n + fa] * lift[ta][m * n + fb];
         }
       }
       acc[t] += v;

@@ -186,3 +186,15 @@ def element_coords_mixed(V, degrees, xi_of, map_fn=None):
             cache[p] = element_coords(V, xi_of(p), map_fn)
         out.append(cache[p][e])
     return out
+
+
+def front_workload(ne, xi_of, center=(0.0, 0.0, 0.0), r0=0.7, alpha=50.0):
+    """The hp front problem on ne^3 unit cubes: degrees by `front_degrees`, coordinates per
+    element at xi_of(p_e), f = -laplace(u) and u_D = u of the spherical front, nodal."""
+    degrees = front_degrees(ne, center=center, r0=r0)
+    nbr, bc = box_topology(ne, ne, ne)
+    X = element_coords_mixed(box_vertices(ne, ne, ne), degrees, xi_of)
+    f = np.concatenate([front_source(x, alpha=alpha, r0=r0, center=center).ravel() for x in X])
+    uD = np.concatenate([front_solution(x, alpha=alpha, r0=r0, center=center).ravel() for x in X])
+    return degrees, X, nbr, bc, f, uD
+
