@@ -52,6 +52,7 @@ enum { DGFAS_INTERIOR = 0, DGFAS_DIRICHLET = 1, DGFAS_NEUMANN = 2,
 enum { DGFAS_WAS = 0, DGFAS_SCG = 1 };
 enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1 };
 enum { DGFAS_BATCH_PER_DEGREE = 0, DGFAS_BATCH_ONE_LAUNCH = 1, DGFAS_BATCH_TUNED = 2 };
+enum { DGFAS_ORDER_NATURAL = 0, DGFAS_ORDER_MORTON = 1 };
 
 typedef struct dgfas_solver_s* dgfas_solver;
 
@@ -97,7 +98,12 @@ typedef struct {
                                as two captured HIP graphs (the root solve between them runs
                                eagerly); results are bitwise those of the eager cycle.  Not with
                                the learned correction */
-  int32_t reserved[4];
+  int32_t order;            /* element processing order of the sweep kernels: DGFAS_ORDER_NATURAL
+                               (element index) or DGFAS_ORDER_MORTON (Morton order of the element
+                               centroids, so that concurrently running workgroups of one XCD take
+                               a compact 3D block and share their neighbours' data in L2).
+                               Results are bitwise the same */
+  int32_t reserved[3];
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);

@@ -24,6 +24,7 @@ INTERIOR, DIRICHLET, NEUMANN = 0, 1, 2
 WAS, SCG = 0, 1
 FP64, FP32 = 0, 1
 BATCH_PER_DEGREE, BATCH_ONE_LAUNCH, BATCH_TUNED = 0, 1, 2
+ORDER_NATURAL, ORDER_MORTON = 0, 1
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -38,7 +39,7 @@ class Options(ctypes.Structure):
                 ('overlap', ctypes.c_int32), ('smoother', ctypes.c_int32), ('ns1', ctypes.c_int32),
                 ('ns2', ctypes.c_int32), ('root_max_iter', ctypes.c_int32), ('root_rtol', ctypes.c_double),
                 ('precision', ctypes.c_int32), ('n_rhs', ctypes.c_int32), ('batch', ctypes.c_int32),
-                ('graph', ctypes.c_int32), ('reserved', ctypes.c_int32 * 4)]
+                ('graph', ctypes.c_int32), ('order', ctypes.c_int32), ('reserved', ctypes.c_int32 * 3)]
 
 
 class DgfasError(RuntimeError):

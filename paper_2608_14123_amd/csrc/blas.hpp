@@ -11,7 +11,7 @@ enum { kOpGamma = 0, kOpBeta = 1, kOpAlpha = 2, kOpNorm2 = 3, kOpStore = 4 };
 // scalars at scal[rhs * 8 + k].
 // second-stage reduction of one (or, for kOpBeta, two: partial and partial2) sums per rhs
 void finish(int nblocks, int nrhs, const double* partial, const double* partial2, int op, double* scal, double* out,
-            hipStream_t st);
+            hipStream_t st, int pstride = 1024);
 template <typename T>
 void pupdate(int64_t n, int nrhs, const T* z, T* p, const double* scal, int first, hipStream_t st);
 template <typename T>

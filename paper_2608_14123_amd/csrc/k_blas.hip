@@ -156,19 +156,21 @@ template void dot_partials<float>(int64_t, int, const float*, const float*, cons
 
 // Second stage, one block per right-hand side: sums its partials (for kOpBeta also the
 // second set at partial2) and applies the SCG scalar update selected by `op`.
-//   scal[rhs * 8 + k]: 0 gamma (z^T r)  1 beta  2 alpha  3 r^T r  4 breakdown flag  5 p^T q
-//                      6 stopping threshold on |r| (0: none)  7 converged flag
+//   scal[rhs * 8 + k]: 0 gamma (z^T r)  1 beta  2 alpha  3 r^T r  4 breakdown flag
+//                      5 iterations run before convergence  6 stopping threshold on |r|
+//                      (0: none)  7 converged flag
 // A right-hand side whose |r| has reached its threshold is frozen (alpha = 0 from then on),
 // so that in a batch every right-hand side stops at the iteration it would stop at alone.
 __global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double* __restrict__ partial,
                                                       const double* __restrict__ partial2, int op,
-                                                      double* __restrict__ scal, double* __restrict__ out) {
+                                                      double* __restrict__ scal, double* __restrict__ out,
+                                                      int pstride) {
   __shared__ double sh[1024];
   const int tid = threadIdx.x, rhs = blockIdx.x;
   double v0 = 0, v1 = 0;
   for (int b = tid; b < nblocks; b += 1024) {
-    v0 += partial[rhs * 1024 + b];
-    if (op == kOpBeta) v1 += partial2[rhs * 1024 + b];
+    v0 += partial[(int64_t)rhs * pstride + b];
+    if (op == kOpBeta) v1 += partial2[(int64_t)rhs * pstride + b];
   }
   const double s0 = block_sum(v0, sh);
   __syncthreads();
@@ -188,7 +190,6 @@ __global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double*
       break;
     }
     case kOpAlpha: {        // alpha = gamma / p^T q; a converged right-hand side (p = 0) takes alpha = 0
-      sc[5] = s0;
       double alpha = (s0 != 0.0) ? sc[0] / s0 : 0.0;
       if (sc[7] != 0.0) alpha = 0.0;
       else if (s0 < 0.0 || !isfinite(alpha)) { sc[4] = 1.0; alpha = 0.0; }
@@ -198,7 +199,10 @@ __global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double*
     case kOpNorm2:          // r^T r
       sc[3] = s0;
       if (!isfinite(s0)) sc[4] = 1.0;
-      if (sc[6] > 0.0 && sqrt(s0) <= sc[6]) sc[7] = 1.0;
+      if (sc[7] == 0.0) {
+        sc[5] += 1.0;
+        if (sc[6] > 0.0 && sqrt(s0) <= sc[6]) sc[7] = 1.0;
+      }
       break;
     case kOpStore:
       out[rhs] = s0;
@@ -207,8 +211,9 @@ __global__ void __launch_bounds__(1024) finish_kernel(int nblocks, const double*
 }
 
 void finish(int nblocks, int nrhs, const double* partial, const double* partial2, int op, double* scal, double* out,
-            hipStream_t st) {
-  hipLaunchKernelGGL(finish_kernel, dim3(nrhs), dim3(1024), 0, st, nblocks, partial, partial2, op, scal, out);
+            hipStream_t st, int pstride) {
+  hipLaunchKernelGGL(finish_kernel, dim3(nrhs), dim3(1024), 0, st, nblocks, partial, partial2, op, scal, out,
+                     pstride);
 }
 
 // p = beta p + z   (first: p = z), per right-hand side beta

@@ -19,6 +19,9 @@ namespace dgfas {
 template <int N>
 struct OpShape {
   static constexpr int N2 = N * N, N3 = N * N * N;
+  // LDS pitch of the xi_1 rows of volume tiles and of face rows: odd, so that the lanes of a
+  // wavefront that read one column of rows hit distinct banks
+  static constexpr int P = N | 1, V3 = N2 * P, F2 = N * P;
   static constexpr int EPB = (N3 >= 256) ? 1 : (256 / N3);
   static constexpr int THREADS = ((EPB * N3 + 63) / 64) * 64;
 };
@@ -26,12 +29,14 @@ struct OpShape {
 template <int N, typename T>
 struct OpSmem {
   using S = OpShape<N>;
-  T sD[S::N2];
-  T su[S::EPB][S::N3];
-  T sF[S::EPB][3][S::N3];
-  T sTr[S::EPB][6][S::N2];    // neighbour trace
-  T sRow[S::EPB][6][S::N2];   // direct face-row term
-  T sSig[S::EPB][6][S::N2];   // lifting weight sigma
+  T sD[S::N2];                // D[i][m] at i N + m
+  T sDT[S::N2];               // D[i][m] at m N + i
+  T su[S::EPB][S::V3];
+  T sF[S::EPB][3][S::V3];
+  T sTr[S::EPB][6][S::F2];    // neighbour trace
+  T sRow[S::EPB][6][S::F2];   // direct face-row term
+  T sSig[S::EPB][6][S::F2];   // lifting weight sigma
+  double red[(S::THREADS + 63) / 64];   // per-wavefront partial sums of the fused dot product
 };
 
 // One tile: EPB elements of one right-hand side (logical block lbr).  Every thread of the
@@ -51,7 +56,7 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   const int8_t* __restrict__ bc = a.bc;
   const T* __restrict__ Dg = a.D;
   const T kappa = a.kappa, inv_wend = a.inv_wend;
-  constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB;
+  constexpr int N2 = S::N2, N3 = S::N3, EPB = S::EPB, P = S::P, V3 = S::V3, F2 = S::F2;
   constexpr int TPT = (6 * N2 + N3 - 1) / N3;     // face tasks per thread
   // logical block = (element block, right-hand side) with the right-hand side fastest, so
   // that the batch of one element reads its geometry while it is resident in L2
@@ -69,11 +74,14 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   const int e = active ? (a.elist ? a.elist[li] : li) : 0;
 
   T(&sD)[N2] = sm.sD;
-  T(&su)[EPB][N3] = sm.su;
-  T(&sF)[EPB][3][N3] = sm.sF;
-  T(&sTr)[EPB][6][N2] = sm.sTr;
-  T(&sRow)[EPB][6][N2] = sm.sRow;
-  T(&sSig)[EPB][6][N2] = sm.sSig;
+  T(&sDT)[N2] = sm.sDT;
+  T(&su)[EPB][V3] = sm.su;
+  T(&sF)[EPB][3][V3] = sm.sF;
+  T(&sTr)[EPB][6][F2] = sm.sTr;
+  T(&sRow)[EPB][6][F2] = sm.sRow;
+  T(&sSig)[EPB][6][F2] = sm.sSig;
+  const int i = node % N, j = (node / N) % N, k = node / N2;
+  const int lnode = (k * N + j) * P + i;          // padded LDS slot of the thread's node
 
   const int64_t base = a.off ? a.off[e] : (int64_t)e * N3;
   const int64_t fbase = a.offF ? a.offF[e] : (int64_t)e * 6 * N2;
@@ -104,8 +112,12 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     for (int c = 0; c < 6; ++c) gl[c] = G[c * ndof + base + node];
     if (mode == 0) gval = g[base + node];
   }
-  if (tid < N2) sD[tid] = Dg[tid];
-  if (active) su[le][node] = uval;
+  if (tid < N2) {
+    const T dv = Dg[tid];
+    sD[tid] = dv;
+    sDT[(tid % N) * N + tid / N] = dv;
+  }
+  if (active) su[le][lnode] = uval;
   // phase 0: neighbour data of every face node: trace, normal derivative and metric row
   T dn_nb[TPT], gn[TPT][3];
 #pragma unroll
@@ -135,23 +147,22 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
       }
       dn_nb[k] = dn;
     }
-    sTr[le][phi][f] = tr;
+    sTr[le][phi][(f / N) * P + f % N] = tr;
   }
   __syncthreads();
 
   // phase 1: reference derivatives and contravariant fluxes F_b = sum_c G_bc d_c u
-  const int i = node % N, j = (node / N) % N, k = node / N2;
   if (active) {
     T d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      d0 += sD[i * N + m] * su[le][(k * N + j) * N + m];
-      d1 += sD[j * N + m] * su[le][(k * N + m) * N + i];
-      d2 += sD[k * N + m] * su[le][(m * N + j) * N + i];
+      d0 += sDT[m * N + i] * su[le][(k * N + j) * P + m];
+      d1 += sDT[m * N + j] * su[le][(k * N + m) * P + i];
+      d2 += sDT[m * N + k] * su[le][(m * N + j) * P + i];
     }
-    sF[le][0][node] = gl[0] * d0 + gl[1] * d1 + gl[2] * d2;
-    sF[le][1][node] = gl[1] * d0 + gl[3] * d1 + gl[4] * d2;
-    sF[le][2][node] = gl[2] * d0 + gl[4] * d1 + gl[5] * d2;
+    sF[le][0][lnode] = gl[0] * d0 + gl[1] * d1 + gl[2] * d2;
+    sF[le][1][lnode] = gl[1] * d0 + gl[3] * d1 + gl[4] * d2;
+    sF[le][2][lnode] = gl[2] * d0 + gl[4] * d1 + gl[5] * d2;
   }
   __syncthreads();
 
@@ -162,18 +173,19 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     if (!active || t >= 6 * N2) continue;
     const int phi = t / N2, f = t - phi * N2, ax = phi >> 1;
     const int vi = face_node<N>(phi, f, (phi & 1) ? N - 1 : 0);
+    const int lvi = (vi / N) * P + vi % N;
+    const int fa = f / N, fb = f - fa * N, lf = fa * P + fb;
     const T sgn = (phi & 1) ? T(1) : T(-1);
-    const T uo = su[le][vi];
-    const T qo = sgn * inv_wend * sF[le][ax][vi];    // nu omega s n_out . grad u
+    const T uo = su[le][lvi];
+    const T qo = sgn * inv_wend * sF[le][ax][lvi];   // nu omega s n_out . grad u
     const T pf = pen_t[kk];
     T row = 0, sigma = 0;
     if (en_t[kk] >= 0) {
-      const int a = f / N, b = f - a * N;
       T dlast = 0, dfirst = 0;
 #pragma unroll
       for (int m = 0; m < N; ++m) {
-        dlast += sD[b * N + m] * sTr[le][phi][a * N + m];
-        dfirst += sD[a * N + m] * sTr[le][phi][m * N + b];
+        dlast += sDT[m * N + fb] * sTr[le][phi][fa * P + m];
+        dfirst += sDT[m * N + fa] * sTr[le][phi][m * P + fb];
       }
       T du0, du1, du2;
       if (ax == 0) { du0 = dn_nb[kk]; du1 = dlast; du2 = dfirst; }
@@ -181,22 +193,22 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
       else { du0 = dlast; du1 = dfirst; du2 = dn_nb[kk]; }
       const T fl = gn[kk][0] * du0 + gn[kk][1] * du1 + gn[kk][2] * du2;
       const T qn = -sgn * inv_wend * fl;             // neighbour's outward flux
-      const T jmp = uo - sTr[le][phi][f];
+      const T jmp = uo - sTr[le][phi][lf];
       row = pf * jmp - T(0.5) * (qo - qn);
       sigma = T(-0.5) * jmp;
     } else if (en_t[kk] == -1 && bc_t[kk] == 1) {    // Dirichlet: 2 mu nu omega s u - q, lifting -u
       row = pf * uo - qo;
       sigma = -uo;
     }
-    sRow[le][phi][f] = row;
-    sSig[le][phi][f] = sigma;
+    sRow[le][phi][lf] = row;
+    sSig[le][phi][lf] = sigma;
   }
   __syncthreads();
 
   // phase 3: every node collects the terms of the faces it lies on (its own slots)
   T rowsum = 0;
   if (active) {
-    const int fidx[3] = {k * N + j, k * N + i, j * N + i};
+    const int fidx[3] = {k * P + j, k * P + i, j * P + i};
     const int idx[3] = {i, j, k};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -206,23 +218,38 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
       if (phi < 0) continue;
       rowsum += sRow[le][phi][fidx[ax]];
       const T sg = sSig[le][phi][fidx[ax]] * ((phi & 1) ? inv_wend : -inv_wend);
-      sF[le][0][node] += sg * gl[sym_index(ax, 0)];
-      sF[le][1][node] += sg * gl[sym_index(ax, 1)];
-      sF[le][2][node] += sg * gl[sym_index(ax, 2)];
+      sF[le][0][lnode] += sg * gl[sym_index(ax, 0)];
+      sF[le][1][lnode] += sg * gl[sym_index(ax, 1)];
+      sF[le][2][lnode] += sg * gl[sym_index(ax, 2)];
     }
   }
   __syncthreads();
 
+  double pq = 0;
   if (active) {
     T acc = rowsum;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      acc += sD[m * N + i] * sF[le][0][(k * N + j) * N + m];
-      acc += sD[m * N + j] * sF[le][1][(k * N + m) * N + i];
-      acc += sD[m * N + k] * sF[le][2][(m * N + j) * N + i];
+      acc += sD[m * N + i] * sF[le][0][(k * N + j) * P + m];
+      acc += sD[m * N + j] * sF[le][1][(k * N + m) * P + i];
+      acc += sD[m * N + k] * sF[le][2][(m * N + j) * P + i];
     }
     if (WJ) acc += kappa * WJ[base + node] * uval;
     out[base + node] = mode == 0 ? gval - acc : acc;
+    if (a.dotp) pq = (double)uval * (double)acc;
+  }
+  if (a.dotp) {
+    // u^T (A u) over the tile: wavefront butterfly, then the waves in order (deterministic)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) pq += __shfl_xor(pq, off);
+    if ((tid & 63) == 0 && tid < S::THREADS) sm.red[tid >> 6] = pq;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0;
+      for (int w = 0; w < (S::THREADS + 63) / 64; ++w) s += sm.red[w];
+      const int nlb = (nel + EPB - 1) / EPB;
+      a.dotp[(int64_t)(lbr - lb * nrhs) * nlb + lb] = s;
+    }
   }
 }
 

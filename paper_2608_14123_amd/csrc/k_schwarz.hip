@@ -61,8 +61,7 @@ int overlap_size(int p, int m) {
 template <int N, int M, typename T>
 struct SzSmem {
   using Sh = SzShape<N, M>;
-  T tA[Sh::TILE];
-  T tB[Sh::TILE];
+  T tA[Sh::TILE];             // the subdomain tile; every contraction updates its own lines in place
   T sW[3][Sh::NS];
   int sMap[3][Sh::NS];
   int sNb[27];
@@ -74,7 +73,7 @@ struct SzSmem {
 template <int N, int M, typename T>
 __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, SzSmem<N, M, T>& sm) {
   using Sh = SzShape<N, M>;
-  constexpr int NS = Sh::NS, LS = Sh::LS, N3 = N * N * N, THR = Sh::THREADS;
+  constexpr int NS = Sh::NS, LS = Sh::LS, THR = Sh::THREADS;
   constexpr Regions<N, M> R{};
   const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;   // right-hand side fastest
   const int e = a.elist ? a.elist[li] : li;
@@ -83,10 +82,8 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
   a.z += (int64_t)rhs * a.ndof;
   a.O += (int64_t)rhs * a.nin;
   const int tid = threadIdx.x;
-  const bool inb = tid < THR;
 
   T(&tA)[Sh::TILE] = sm.tA;
-  T(&tB)[Sh::TILE] = sm.tB;
   T(&sW)[3][NS] = sm.sW;
   int(&sMap)[3][NS] = sm.sMap;
   int(&sNb)[27] = sm.sNb;
@@ -117,38 +114,44 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
   const T g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
   __syncthreads();
 
-  // gather r_s = R_s r: all loads of a thread are issued before the LDS stores
-  constexpr int GIT = (NS * NS * NS + THR - 1) / THR;
-  {
-    T vals[GIT];
+  // gather r_s = R_s r, one thread per xi_3 column (s1, s2) of the tile: the column's
+  // node (l1, l2) in each of the three elements it crosses is found once, the xi_3
+  // positions (uniform over the workgroup) then only select the element and the layer.
+  // Every load of a thread is issued before its LDS stores.
+  const bool act = tid < NS * NS;
+  const int c1 = tid % NS, c2 = tid / NS;
+  int m3u[NS];
 #pragma unroll
-    for (int it = 0; it < GIT; ++it) {
-      const int q = tid + it * THR;
-      vals[it] = 0;
-      if (inb && q < NS * NS * NS) {
-        const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
-        const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
-        if (m1 >= 0 && m2 >= 0 && m3 >= 0) {
-          const int src = sNb[(m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6)];   // absent neighbour: zeros
-          if (src >= 0) vals[it] = a.r[elem_base<N>(a, src) + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63)];
-        }
+  for (int s3 = 0; s3 < NS; ++s3) m3u[s3] = __builtin_amdgcn_readfirstlane(sMap[2][s3]);
+  if (act) {
+    const int m1 = sMap[0][c1], m2 = sMap[1][c2];
+    int64_t cb[3];
+#pragma unroll
+    for (int d3 = 0; d3 < 3; ++d3) {
+      cb[d3] = -1;
+      if (m1 >= 0 && m2 >= 0) {
+        const int src = sNb[d3 * 9 + (m2 >> 6) * 3 + (m1 >> 6)];   // absent neighbour: zeros
+        if (src >= 0) cb[d3] = elem_base<N>(a, src) + (m2 & 63) * N + (m1 & 63);
+      }
+    }
+    T vals[NS];
+#pragma unroll
+    for (int s3 = 0; s3 < NS; ++s3) {
+      const int m3 = m3u[s3];
+      vals[s3] = 0;
+      if (m3 >= 0) {
+        const int64_t cbase = cb[m3 >> 6];
+        if (cbase >= 0) vals[s3] = a.r[cbase + (m3 & 63) * (N * N)];
       }
     }
 #pragma unroll
-    for (int it = 0; it < GIT; ++it) {
-      const int q = tid + it * THR;
-      if (inb && q < NS * NS * NS) {
-        const int s1 = q % NS, s23 = q / NS;
-        tA[s23 * LS + s1] = vals[it];
-      }
-    }
+    for (int s3 = 0; s3 < NS; ++s3) tA[(s3 * NS + c2) * LS + c1] = vals[s3];
   }
   __syncthreads();
 
   // Each contraction: one thread per tile line, out_c = sum_q M[c][q] line_q with the
   // row M[c][:] read through the scalar cache (uniform over the workgroup).
-  const bool act = tid < NS * NS;
-  const int tlo = tid % NS, thi = tid / NS;
+  const int tlo = c1, thi = c2;
   const T* __restrict__ S1T = a.ST + v0 * NS * NS;
   const T* __restrict__ S2T = a.ST + v1 * NS * NS;
   const T* __restrict__ S3T = a.ST + v2 * NS * NS;
@@ -163,14 +166,14 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
       T s = 0;
 #pragma unroll
       for (int q = 0; q < NS; ++q) s += S1T[c * NS + q] * line[q];
-      tB[b + c] = s;
+      tA[b + c] = s;
     }
   }
   __syncthreads();
   // phase 2: xi_2 with S2^T   (thread: s1 = tlo, s3 = thi)
   if (act) {
 #pragma unroll
-    for (int q = 0; q < NS; ++q) line[q] = tB[(thi * NS + q) * LS + tlo];
+    for (int q = 0; q < NS; ++q) line[q] = tA[(thi * NS + q) * LS + tlo];
 #pragma unroll 1
     for (int c = 0; c < NS; ++c) {
       T s = 0;
@@ -200,14 +203,14 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
       T s = 0;
 #pragma unroll
       for (int q = 0; q < NS; ++q) s += S3[c * NS + q] * line[q];
-      tB[(c * NS + thi) * LS + tlo] = s;
+      tA[(c * NS + thi) * LS + tlo] = s;
     }
   }
   __syncthreads();
   // phase 4: xi_2 with S2   (thread: s1 = tlo, s3 = thi)
   if (act) {
 #pragma unroll
-    for (int q = 0; q < NS; ++q) line[q] = tB[(thi * NS + q) * LS + tlo];
+    for (int q = 0; q < NS; ++q) line[q] = tA[(thi * NS + q) * LS + tlo];
 #pragma unroll 1
     for (int c = 0; c < NS; ++c) {
       T s = 0;
@@ -227,35 +230,59 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
       T s = 0;
 #pragma unroll
       for (int q = 0; q < NS; ++q) s += S1[c * NS + q] * line[q];
-      tB[b + c] = s;
+      tA[b + c] = s;
     }
   }
   __syncthreads();
-  // weighted scatter: own part to z, each overlap part into the receiving
-  // element's inbox (region seen from the receiver), read back by overlap_add
+  // weighted scatter, one thread per xi_3 column (s1, s2): own part to z, each overlap part
+  // into the receiving element's inbox (region seen from the receiver), read back by
+  // overlap_add.  The destination of the column in each of the three xi_3 elements is
+  // found once; the xi_3 positions select it.
+  if (act) {
+    const int m1 = sMap[0][c1], m2 = sMap[1][c2];
+    if (m1 >= 0 && m2 >= 0) {
+      const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, l1 = m1 & 63, l2 = m2 & 63;
+      const T w12 = sW[0][c1] * sW[1][c2];
+      int64_t db[3];
+      int ds[3];
 #pragma unroll
-  for (int it = 0; it < GIT; ++it) {
-    const int q = tid + it * THR;
-    if (!inb || q >= NS * NS * NS) continue;
-    const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
-    const int m1 = sMap[0][s1], m2 = sMap[1][s2], m3 = sMap[2][s3];
-    if (m1 < 0 || m2 < 0 || m3 < 0) continue;
-    T t = tB[(s3 * NS + s2) * LS + s1];
-    if (a.corr) t += (T)(a.cscale[e] * (double)a.corr[(int64_t)e * (NS * NS * NS) + q]);
-    const T v = a.unweighted ? t : sW[0][s1] * sW[1][s2] * sW[2][s3] * t;
-    const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, d3 = (m3 >> 6) - 1;
-    const int l1 = m1 & 63, l2 = m2 & 63, l3 = m3 & 63;
-    if (d1 == 0 && d2 == 0 && d3 == 0) {
-      const int64_t gi = elem_base<N>(a, e) + (l3 * N + l2) * N + l1;
-      if (a.mode == 0) a.z[gi] = v;
-      else a.z[gi] += v;
-    } else {
-      const int dest = sNb[(d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1)];
-      if (dest < 0) continue;
-      const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
-      const int c1 = d1 < 0 ? l1 - (N - M) : l1, c2 = d2 < 0 ? l2 - (N - M) : l2, c3 = d3 < 0 ? l3 - (N - M) : l3;
-      const int x1 = d1 ? M : N, x2 = d2 ? M : N;
-      a.O[inbox_base<N, M>(a, dest) + sOff[r] + (c3 * x2 + c2) * x1 + c1] = v;
+      for (int d3i = 0; d3i < 3; ++d3i) {
+        const int d3 = d3i - 1;
+        db[d3i] = -1;
+        ds[d3i] = 0;
+        if (d1 == 0 && d2 == 0 && d3 == 0) {
+          db[d3i] = elem_base<N>(a, e) + l2 * N + l1;
+          ds[d3i] = N * N;
+        } else {
+          const int dest = sNb[d3i * 9 + (d2 + 1) * 3 + (d1 + 1)];
+          if (dest >= 0) {
+            const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
+            const int cc1 = d1 < 0 ? l1 - (N - M) : l1, cc2 = d2 < 0 ? l2 - (N - M) : l2;
+            const int x1 = d1 ? M : N, x2 = d2 ? M : N;
+            ds[d3i] = x2 * x1;
+            db[d3i] = inbox_base<N, M>(a, dest) + sOff[r] + cc2 * x1 + cc1;
+          }
+        }
+      }
+#pragma unroll
+      for (int s3 = 0; s3 < NS; ++s3) {
+        const int m3 = m3u[s3];
+        if (m3 < 0) continue;
+        const int d3i = m3 >> 6, l3 = m3 & 63;
+        T t = tA[(s3 * NS + c2) * LS + c1];
+        if (a.corr) t += (T)(a.cscale[e] * (double)a.corr[(int64_t)e * (NS * NS * NS) + (s3 * NS + c2) * NS + c1]);
+        const T v = a.unweighted ? t : w12 * sW[2][s3] * t;
+        const int64_t base = db[d3i];
+        if (base < 0) continue;
+        const int c3 = d3i == 0 ? l3 - (N - M) : l3;   // layer index inside the receiver's region
+        const int64_t gi = base + (int64_t)c3 * ds[d3i];
+        if (d1 == 0 && d2 == 0 && d3i == 1) {
+          if (a.mode == 0) a.z[gi] = v;
+          else a.z[gi] += v;
+        } else {
+          a.O[gi] = v;
+        }
+      }
     }
   }
 }
@@ -278,10 +305,12 @@ schwarz_solve_kernel(SchwarzArgs<T> a) {
 
 struct AddSmem {
   int sOff[27];
+  double red[2][16];   // per-wavefront partial sums of the fused dot products
 };
 
 // z[node] += sum of the neighbours' overlap contributions in the element's own
-// inbox, in a fixed order.  Inbox regions of absent neighbours stay zero.
+// inbox, in a fixed order.  Inbox regions of absent neighbours stay zero.  With dotz set,
+// also the tile's sums of z dr and z (dr - dr0) over every node (deterministic order).
 template <int N, int M, typename T>
 __device__ __forceinline__ void overlap_add_tile(SchwarzArgs<T> a, const int lbr, AddSmem& sm) {
   using Sh = AddShape<N>;
@@ -296,44 +325,80 @@ __device__ __forceinline__ void overlap_add_tile(SchwarzArgs<T> a, const int lbr
   __syncthreads();
   const int le = tid / N3, node = tid - le * N3;
   const int li = lb * EPB + le;
-  if (le >= EPB || li >= a.nel) return;
-  const int e = a.elist ? a.elist[li] : li;
-  const int l[3] = {node % N, (node / N) % N, node / (N * N)};
-  // per direction the offset towards the one neighbour whose overlap can cover this node
-  int od[3];
-  bool any = false;
+  double pz = 0, pz2 = 0;
+  if (le < EPB && li < a.nel) {
+    const int e = a.elist ? a.elist[li] : li;
+    const int64_t gi = elem_base<N>(a, e) + node;
+    const int l[3] = {node % N, (node / N) % N, node / (N * N)};
+    // per direction the offset towards the one neighbour whose overlap can cover this node
+    int od[3];
+    bool any = false;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    od[d] = (l[d] < M) ? -1 : ((l[d] >= N - M) ? 1 : 0);
-    any = any || od[d] != 0;
-  }
-  if (!any) return;
-  const T* __restrict__ box = a.O + inbox_base<N, M>(a, e);
-  // the up to 7 candidates (subsets of the non-zero directions): every load is issued
-  // unconditionally (invalid ones read entry 0 and are masked) so that none waits on another
-  T vals[7];
-  bool ok[7];
-#pragma unroll
-  for (int bits = 1; bits < 8; ++bits) {
-    const int dd[3] = {(bits & 1) ? od[0] : 0, (bits & 2) ? od[1] : 0, (bits & 4) ? od[2] : 0};
-    const bool valid = ((bits & 1) == 0 || od[0] != 0) && ((bits & 2) == 0 || od[1] != 0) &&
-                       ((bits & 4) == 0 || od[2] != 0);
-    int off = 0;
-    if (valid) {
-      const int r = (dd[2] + 1) * 9 + (dd[1] + 1) * 3 + (dd[0] + 1);
-      const int c1 = dd[0] > 0 ? l[0] - (N - M) : l[0];
-      const int c2 = dd[1] > 0 ? l[1] - (N - M) : l[1];
-      const int c3 = dd[2] > 0 ? l[2] - (N - M) : l[2];
-      const int x1 = dd[0] ? M : N, x2 = dd[1] ? M : N;
-      off = sOff[r] + (c3 * x2 + c2) * x1 + c1;
+    for (int d = 0; d < 3; ++d) {
+      od[d] = (l[d] < M) ? -1 : ((l[d] >= N - M) ? 1 : 0);
+      any = any || od[d] != 0;
     }
-    ok[bits - 1] = valid;
-    vals[bits - 1] = box[off];
-  }
-  T acc = 0;
+    T zv = 0;
+    if (any) {
+      const T* __restrict__ box = a.O + inbox_base<N, M>(a, e);
+      // the up to 7 candidates (subsets of the non-zero directions): every load is issued
+      // unconditionally (invalid ones read entry 0 and are masked) so that none waits on another
+      T vals[7];
+      bool ok[7];
 #pragma unroll
-  for (int t = 0; t < 7; ++t) acc += ok[t] ? vals[t] : T(0);
-  a.z[elem_base<N>(a, e) + node] += acc;
+      for (int bits = 1; bits < 8; ++bits) {
+        const int dd[3] = {(bits & 1) ? od[0] : 0, (bits & 2) ? od[1] : 0, (bits & 4) ? od[2] : 0};
+        const bool valid = ((bits & 1) == 0 || od[0] != 0) && ((bits & 2) == 0 || od[1] != 0) &&
+                           ((bits & 4) == 0 || od[2] != 0);
+        int off = 0;
+        if (valid) {
+          const int r = (dd[2] + 1) * 9 + (dd[1] + 1) * 3 + (dd[0] + 1);
+          const int c1 = dd[0] > 0 ? l[0] - (N - M) : l[0];
+          const int c2 = dd[1] > 0 ? l[1] - (N - M) : l[1];
+          const int c3 = dd[2] > 0 ? l[2] - (N - M) : l[2];
+          const int x1 = dd[0] ? M : N, x2 = dd[1] ? M : N;
+          off = sOff[r] + (c3 * x2 + c2) * x1 + c1;
+        }
+        ok[bits - 1] = valid;
+        vals[bits - 1] = box[off];
+      }
+      T acc = 0;
+#pragma unroll
+      for (int t = 0; t < 7; ++t) acc += ok[t] ? vals[t] : T(0);
+      zv = a.z[gi] + acc;
+      a.z[gi] = zv;
+    } else if (a.dotz) {
+      zv = a.z[gi];
+    }
+    if (a.dotz) {
+      const int64_t ri = (int64_t)rhs * a.ndof + gi;
+      const double rv = (double)a.dr[ri];
+      pz = (double)zv * rv;
+      if (a.dr0) pz2 = (double)zv * (rv - (double)a.dr0[ri]);
+    }
+  }
+  if (a.dotz) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      pz += __shfl_xor(pz, off);
+      pz2 += __shfl_xor(pz2, off);
+    }
+    if ((tid & 63) == 0 && tid < Sh::THREADS) {
+      sm.red[0][tid >> 6] = pz;
+      sm.red[1][tid >> 6] = pz2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0, s2 = 0;
+      for (int w = 0; w < Sh::THREADS / 64; ++w) {
+        s += sm.red[0][w];
+        s2 += sm.red[1][w];
+      }
+      const int ntiles = (a.nel + EPB - 1) / EPB;
+      a.dotz[(int64_t)rhs * ntiles + lb] = s;
+      if (a.dotz2) a.dotz2[(int64_t)rhs * ntiles + lb] = s2;
+    }
+  }
 }
 
 template <int N, int M, typename T>

@@ -28,6 +28,7 @@ struct OpArgs {
   const T* D = nullptr;       // [n][n]
   T kappa = 0;
   T inv_wend = 0;             // 1 / w_0 = p (p + 1) / 2
+  double* dotp = nullptr;     // mode 1 only: per tile u^T (A u) partial sums, [nrhs][tiles]
 };
 
 template <typename T>
@@ -111,7 +112,7 @@ struct MortarArgs {
   const T* G = nullptr;             // [6][ndof]
   const double* ws = nullptr;       // face omega s, [offF]
   const double* muf = nullptr;      // [E][6] mu_F nu
-  const double* Dall = nullptr;     // differentiation matrices of degrees 1..8, degree p at kDoff[p]
+  const double* Dall = nullptr;     // differentiation matrices of degrees 1..8, degree p at (p-1) * 81
   const double* Iall = nullptr;     // interpolation degree q -> r at ((q-1) * 8 + (r-1)) * 81
 };
 template <typename T>
@@ -133,17 +134,23 @@ struct SchwarzArgs {
   int mode = 0;
   T* O = nullptr;             // overlap buffer [E][osz]
   const int* nb27 = nullptr;  // [E][27]
-  const int8_t* var = nullptr;   // [E][3] variant index (left*3+right)
+  const int8_t* var = nullptr;   // [E][3] variant index (left * 4 + right, sides I, D, N, I0)
   const T* gco = nullptr;     // [E][4] g0..g3
-  const T* S = nullptr;       // [9][ns*ns] padded eigenvector tables, S[i*ns + a] = (s_a)_i
-  const T* ST = nullptr;      // [9][ns*ns] transposes
-  const T* lam = nullptr;     // [9][ns]
-  const T* W = nullptr;       // [9][ns]
-  const int* map1d = nullptr; // [9][ns]: (delta+1)*64 + loc, or -1 for padding
+  const T* S = nullptr;       // [16][ns*ns] padded eigenvector tables, S[i*ns + a] = (s_a)_i
+  const T* ST = nullptr;      // [16][ns*ns] transposes
+  const T* lam = nullptr;     // [16][ns]
+  const T* W = nullptr;       // [16][ns]
+  const int* map1d = nullptr; // [16][ns]: (delta+1)*64 + loc, or -1 for padding
   const uint8_t* sel = nullptr;  // [E] subdomains to solve (null: all)
   int unweighted = 0;            // 1: W = I (block-diagonal local solves)
   const float* corr = nullptr;   // [E][ns^3] learned correction added to the FD tile (or null)
   const double* cscale = nullptr;  // [E] scale of corr (the subdomain residual norm)
+  // overlap add only: z^T dr and z^T (dr - dr0) of the final z summed per tile into
+  // dotz / dotz2 [nrhs][tiles] (dotz null: no dot products; dr0 null: z^T dr only)
+  const T* dr = nullptr;
+  const T* dr0 = nullptr;
+  double* dotz = nullptr;
+  double* dotz2 = nullptr;
 };
 
 // Learned-correction helpers over the subdomain tiles of a list of elements (null list: all)

@@ -106,6 +106,10 @@ struct Level {
   int one_launch[3] = {0, 0, 0};        // tuned choice per stage
   std::string hist;                     // degree histogram "p:count,..." (autotuner key)
   int nm = 0;                           // elements with a face to another degree
+  int nlb = 0;                          // operator tiles per right-hand side (uniform levels)
+  double* kpart = nullptr;              // [nrhs][nlb] fused p^T A p partial sums (uniform levels)
+  int nla = 0;                          // overlap-add tiles per right-hand side (uniform levels)
+  double* zpart = nullptr;              // [2][nrhs][nla] fused z^T r, z^T (r - r0) partial sums
   int* mlist = nullptr;
   double* muf = nullptr;                // [E][6] mu_F nu
   // geometry
@@ -141,6 +145,7 @@ struct Solver {
   std::vector<int> h_nbr;
   std::vector<int8_t> h_bc;
   std::vector<Level> lv;   // lv[0] = root (level 1)
+  std::vector<int64_t> rank;   // processing rank of every element (empty: natural order)
   std::map<int, DegTab> tabs;
   double *Dall = nullptr, *Iall = nullptr;   // mixed-degree face tables for degrees 1..8
   int force_batch = -1;                      // autotuner: -1 options, 0 per degree, 1 one launch
@@ -241,6 +246,15 @@ struct Solver {
   template <typename T>
   SchwarzArgs<T> sz_args(Level& L, const Bucket& b, const T* r, T* z, int mode);
 
+  // FD solve plus the network correction |r_s| MLP(r_s / |r_s|, J9) (finest level, FP64)
+  void add_learned(Level& L, SchwarzArgs<double>& a, const double* r) {
+    tile_features<double>(L.p, L.m, a, nullptr, L.E, r, L.J9, lX, lnorm, st);
+    mlp->forward(lX, L.E, lY);
+    a.corr = lY;
+    a.cscale = lnorm;
+  }
+  void add_learned(Level&, SchwarzArgs<float>&, const float*) {}
+
   // z = B r (mode 0) or z += B r (mode 1)
   void schwarz(Level& L, const double* r, double* z, int mode) {
     if (msel || (learned && &L == &lv.back())) {   // uniform levels only (checked at set-up)
@@ -252,11 +266,7 @@ struct Solver {
         fill(L.ndof, z, 0.0, st);
         fill(L.nin, L.O, 0.0, st);
       } else {
-        // FD solve plus the network correction |r_s| MLP(r_s / |r_s|, J9)
-        tile_features<double>(L.p, L.m, a, nullptr, L.E, r, L.J9, lX, lnorm, st);
-        mlp->forward(lX, L.E, lY);
-        a.corr = lY;
-        a.cscale = lnorm;
+        add_learned(L, a, r);
       }
       schwarz_solve<double>(L.p, L.m, a, st);
       schwarz_overlap_add<double>(L.p, L.m, a, st);
@@ -395,6 +405,8 @@ struct Solver {
     }
   }
 
+  static constexpr int kCheck = 4;   // iterations between host convergence checks
+
   template <typename T>
   int scg(Level& L, T* x, const T* f, int n, const std::vector<double>& r_max, bool* breakdown,
           bool zero_start = false) {
@@ -417,34 +429,63 @@ struct Solver {
       HIPC(hipMemcpyAsync(scal, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
     }
     int it = 0;
+    const bool fused = L.zpart && !msel;
+    const bool with_net = learned && &L == &lv.back() && sizeof(T) == 8;
     for (int i = 1; i <= n; ++i) {
-      schwarz_t(L, r, z, 0);
-      if (i > 1) {
+      if (fused) {
+        // z = B r with z^T r (and z^T (r - r0)) summed by the overlap-add kernel
+        SchwarzArgs<T> a = sz_args<T>(L, L.bk[0], r, z, 0);
+        if (with_net) add_learned(L, a, r);
+        schwarz_solve<T>(L.p, L.m, a, st);
+        a.dr = r;
+        a.dr0 = i > 1 ? r0 : nullptr;
+        a.dotz = L.zpart;
+        a.dotz2 = i > 1 ? L.zpart + (size_t)L.nla * nrhs : nullptr;
+        schwarz_overlap_add<T>(L.p, L.m, a, st);
+        finish(L.nla, nrhs, a.dotz, a.dotz2, i > 1 ? kOpBeta : kOpGamma, scal, nullptr, st, L.nla);
+        pupdate<T>(L.ndof, nrhs, z, pv, scal, i > 1 ? 0 : 1, st);
+      } else if (i > 1) {
+        schwarz_t(L, r, z, 0);
         dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
         dot_partials<T>(L.ndof, nrhs, z, r, r0, partial2(), nb, st);
         finish(nb, nrhs, partial, partial2(), kOpBeta, scal, nullptr, st);
         pupdate<T>(L.ndof, nrhs, z, pv, scal, 0, st);
       } else {
+        schwarz_t(L, r, z, 0);
         dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
         finish(nb, nrhs, partial, nullptr, kOpGamma, scal, nullptr, st);
         pupdate<T>(L.ndof, nrhs, z, pv, scal, 1, st);
       }
-      apply_t(L, pv, q);
-      dot_partials<T>(L.ndof, nrhs, pv, q, nullptr, partial, nb, st);
-      finish(nb, nrhs, partial, nullptr, kOpAlpha, scal, nullptr, st);
+      if (L.kpart && !mmask) {
+        // q = A p with p^T q summed by the operator kernel itself
+        OpArgs<T> a = op_args<T>(L, L.bk[0], 1, pv, nullptr, q);
+        a.dotp = L.kpart;
+        sipg_apply<T>(L.p, a, st);
+        finish(L.nlb, nrhs, L.kpart, nullptr, kOpAlpha, scal, nullptr, st, L.nlb);
+      } else {
+        apply_t(L, pv, q);
+        dot_partials<T>(L.ndof, nrhs, pv, q, nullptr, partial, nb, st);
+        finish(nb, nrhs, partial, nullptr, kOpAlpha, scal, nullptr, st);
+      }
       cg_update<T>(L.ndof, nrhs, r, r0, q, x, pv, scal, partial, nb, st);
       finish(nb, nrhs, partial, nullptr, kOpNorm2, scal, nullptr, st);
       it = i;
-      if (!r_max.empty()) {
+      // A converged right-hand side is frozen on the device at the iteration where it
+      // converged, so the host needs to look only every kCheck iterations: the iterates are
+      // those of a check after every iteration, at a fraction of the synchronisations.
+      if (!r_max.empty() && (i % kCheck == 0 || i == n)) {
         HIPC(hipMemcpyAsync(h.data(), scal, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPC(hipStreamSynchronize(st));
         bool done = true, bad = false;
+        it = 0;
         for (int k = 0; k < nrhs; ++k) {
           bad = bad || h[k * 8 + 4] != 0.0;
-          done = done && std::sqrt(h[k * 8 + 3]) <= r_max[k];
+          done = done && (h[k * 8 + 7] != 0.0 || std::sqrt(h[k * 8 + 3]) <= r_max[k]);
+          it = std::max(it, (int)h[k * 8 + 5]);
         }
         if (bad) { if (breakdown) *breakdown = true; break; }
         if (done) break;
+        it = i;
       }
     }
     return it;
@@ -732,7 +773,9 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       if (deg[e] == p) b.h_elist.push_back(e);
     if (b.h_elist.empty()) continue;
     b.p = p; b.n = p + 1; b.nel = (int)b.h_elist.size();
-    if (!L.uniform) b.elist = s.own(upload(b.h_elist, st));
+    if (!s.rank.empty())
+      std::stable_sort(b.h_elist.begin(), b.h_elist.end(), [&](int x, int y) { return s.rank[x] < s.rank[y]; });
+    if (!L.uniform || !s.rank.empty()) b.elist = s.own(upload(b.h_elist, st));
     b.t = &deg_tab(s, p);
     L.bk.push_back(std::move(b));
   }
@@ -877,6 +920,14 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   if (nin) {
     HIPC(hipMemsetAsync(L.O, 0, nin * sizeof(double), st));
     if (fp32) HIPC(hipMemsetAsync(L.O32, 0, nin * sizeof(float), st));
+  }
+  if (L.uniform) {
+    L.nlb = stage_tiles(kStageOp, L.p, E, 1);
+    L.kpart = s.own(dalloc<double>((size_t)L.nlb * s.nrhs));
+    if (L.m > 0) {
+      L.nla = stage_tiles(kStageAdd, L.p, E, 1);
+      L.zpart = s.own(dalloc<double>((size_t)2 * L.nla * s.nrhs));
+    }
   }
   // work vectors
   const size_t nv = (size_t)L.ndof * s.nrhs;
@@ -1057,7 +1108,45 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (o->n_rhs < 1 || o->n_rhs > 64) throw Error(DGFAS_EINVAL, "n_rhs must be 1..64");
   if (o->batch < DGFAS_BATCH_PER_DEGREE || o->batch > DGFAS_BATCH_TUNED) throw Error(DGFAS_EINVAL, "unknown batch mode");
   if (o->graph != 0 && o->graph != 1) throw Error(DGFAS_EINVAL, "graph must be 0 or 1");
+  if (o->order != DGFAS_ORDER_NATURAL && o->order != DGFAS_ORDER_MORTON) throw Error(DGFAS_EINVAL, "unknown order");
   if ((int64_t)m->n_elem * o->n_rhs > (int64_t)1 << 30) throw Error(DGFAS_EUNSUPPORTED, "n_elem * n_rhs too large");
+}
+
+// Morton (Z-order) rank of the element centroids on a 2^10 grid over their bounding box
+std::vector<int64_t> morton_rank(const dgfas_mesh_desc* m) {
+  const int E = m->n_elem;
+  std::vector<double> c((size_t)E * 3);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  size_t o = 0;
+  for (int e = 0; e < E; ++e) {
+    const int n = m->degree[e] + 1, n3 = n * n * n;
+    for (int a = 0; a < 3; ++a) {
+      double sum = 0;
+      for (int q = 0; q < n3; ++q) sum += m->coords[o + (size_t)a * n3 + q];
+      c[e * 3 + a] = sum / n3;
+      lo[a] = std::min(lo[a], c[e * 3 + a]);
+      hi[a] = std::max(hi[a], c[e * 3 + a]);
+    }
+    o += (size_t)3 * n3;
+  }
+  std::vector<int64_t> key(E);
+  for (int e = 0; e < E; ++e) {
+    uint64_t k = 0;
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      const double w = hi[a] > lo[a] ? (c[e * 3 + a] - lo[a]) / (hi[a] - lo[a]) : 0.0;
+      q[a] = (uint32_t)std::min(1023.0, std::max(0.0, w * 1024.0));
+    }
+    for (int bit = 9; bit >= 0; --bit)
+      for (int a = 2; a >= 0; --a) k = (k << 1) | ((q[a] >> bit) & 1u);
+    key[e] = (int64_t)k * E + e;   // ties broken by the element index
+  }
+  std::vector<int> idx(E);
+  for (int e = 0; e < E; ++e) idx[e] = e;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return key[x] < key[y]; });
+  std::vector<int64_t> rank(E);
+  for (int r = 0; r < E; ++r) rank[idx[r]] = r;
+  return rank;
 }
 
 Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
@@ -1075,6 +1164,7 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   s->nbr = s->own(upload(s->h_nbr, s->st));
   s->bc = s->own(upload(s->h_bc, s->st));
   s->nrhs = o->n_rhs;
+  if (o->order == DGFAS_ORDER_MORTON) s->rank = morton_rank(m);
   s->partial = s->own(dalloc<double>((size_t)2048 * s->nrhs));
   s->scal = s->own(dalloc<double>((size_t)8 * s->nrhs));
   s->scratch = s->own(dalloc<double>((size_t)8 * s->nrhs));
