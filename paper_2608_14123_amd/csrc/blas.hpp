@@ -12,10 +12,15 @@ enum { kOpGamma = 0, kOpBeta = 1, kOpAlpha = 2, kOpNorm2 = 3, kOpStore = 4 };
 // second-stage reduction of one (or, for kOpBeta, two: partial and partial2) sums per rhs
 void finish(int nblocks, int nrhs, const double* partial, const double* partial2, int op, double* scal, double* out,
             hipStream_t st, int pstride = 1024);
+// p = z (first) or p = beta p + z, with the previous iteration's x += alpha p_old when x is set
 template <typename T>
-void pupdate(int64_t n, int nrhs, const T* z, T* p, const double* scal, int first, hipStream_t st);
+void pupdate(int64_t n, int nrhs, const T* z, T* p, T* x, const double* scal, int first, hipStream_t st);
+// x += alpha p
 template <typename T>
-void cg_update(int64_t n, int nrhs, T* r, T* r0, const T* q, T* u, const T* p, const double* scal, double* partial,
+void xupdate(int64_t n, int nrhs, T* x, const T* p, const double* scal, hipStream_t st);
+// rout = rin - alpha q with sum rout^2 partials
+template <typename T>
+void cg_update(int64_t n, int nrhs, const T* rin, T* rout, const T* q, const double* scal, double* partial,
                int nblocks, hipStream_t st);
 template <typename T>
 void dot_partials(int64_t n, int nrhs, const T* a, const T* b, const T* c, double* partial, int nblocks,

@@ -218,34 +218,44 @@ void finish(int nblocks, int nrhs, const double* partial, const double* partial2
 
 // p = beta p + z   (first: p = z), per right-hand side beta
 template <typename T>
-__global__ void pupdate_kernel(int64_t n, int nrhs, const T* __restrict__ z, T* __restrict__ p,
+__global__ void pupdate_kernel(int64_t n, int nrhs, const T* __restrict__ z, T* __restrict__ p, T* __restrict__ x,
                                const double* __restrict__ scal, int first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
   const int rhs = (int)(i / n);
-  p[i] = first ? z[i] : (T)scal[rhs * 8 + 1] * p[i] + z[i];
+  if (first) {
+    p[i] = z[i];
+    return;
+  }
+  const T po = p[i];
+  if (x) x[i] += (T)scal[rhs * 8 + 2] * po;     // the previous iteration's u += alpha p
+  p[i] = (T)scal[rhs * 8 + 1] * po + z[i];
 }
 
-// r0 = r; r -= alpha q; u += alpha p; partial[rhs*1024 + blk] = sum r^2
+// x += alpha p (the last iteration's update)
+template <typename T>
+__global__ void xupdate_kernel(int64_t n, int nrhs, T* __restrict__ x, const T* __restrict__ p,
+                               const double* __restrict__ scal) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  x[i] += (T)scal[(i / n) * 8 + 2] * p[i];
+}
+
+// rout = rin - alpha q (rout may be rin); partial[rhs*1024 + blk] = sum rout^2
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
-cg_update_kernel(int64_t n, T* __restrict__ r, T* __restrict__ r0, const T* __restrict__ q,
-                 T* __restrict__ u, const T* __restrict__ p, const double* __restrict__ scal,
-                 double* __restrict__ partial) {
+cg_update_kernel(int64_t n, const T* __restrict__ rin, T* __restrict__ rout, const T* __restrict__ q,
+                 const double* __restrict__ scal, double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
   const int rhs = blockIdx.y;
   const int64_t off = (int64_t)rhs * n;
-  r += off; q += off; u += off; p += off;
-  if (r0) r0 += off;
+  rin += off; rout += off; q += off;
   const T alpha = (T)scal[rhs * 8 + 2];
   double s = 0;
   const int64_t stride = (int64_t)gridDim.x * kRedThreads;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += stride) {
-    const T rv = r[i];
-    if (r0) r0[i] = rv;
-    const T rn = rv - alpha * q[i];
-    r[i] = rn;
-    u[i] += alpha * p[i];
+    const T rn = rin[i] - alpha * q[i];
+    rout[i] = rn;
     s += (double)rn * (double)rn;
   }
   const double t = block_sum(s, sh);
@@ -253,24 +263,32 @@ cg_update_kernel(int64_t n, T* __restrict__ r, T* __restrict__ r0, const T* __re
 }
 
 template <typename T>
-void pupdate(int64_t n, int nrhs, const T* z, T* p, const double* scal, int first, hipStream_t st) {
+void pupdate(int64_t n, int nrhs, const T* z, T* p, T* x, const double* scal, int first, hipStream_t st) {
   const int64_t tot = n * nrhs;
-  hipLaunchKernelGGL((pupdate_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nrhs, z, p, scal,
-                     first);
+  hipLaunchKernelGGL((pupdate_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nrhs, z, p, x,
+                     scal, first);
 }
 
 template <typename T>
-void cg_update(int64_t n, int nrhs, T* r, T* r0, const T* q, T* u, const T* p, const double* scal, double* partial,
+void xupdate(int64_t n, int nrhs, T* x, const T* p, const double* scal, hipStream_t st) {
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL((xupdate_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nrhs, x, p, scal);
+}
+
+template <typename T>
+void cg_update(int64_t n, int nrhs, const T* rin, T* rout, const T* q, const double* scal, double* partial,
                int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblocks, nrhs), dim3(kRedThreads), 0, st, n, r, r0, q, u, p, scal,
+  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblocks, nrhs), dim3(kRedThreads), 0, st, n, rin, rout, q, scal,
                      partial);
 }
-template void pupdate<double>(int64_t, int, const double*, double*, const double*, int, hipStream_t);
-template void pupdate<float>(int64_t, int, const float*, float*, const double*, int, hipStream_t);
-template void cg_update<double>(int64_t, int, double*, double*, const double*, double*, const double*, const double*,
-                                double*, int, hipStream_t);
-template void cg_update<float>(int64_t, int, float*, float*, const float*, float*, const float*, const double*,
-                               double*, int, hipStream_t);
+template void pupdate<double>(int64_t, int, const double*, double*, double*, const double*, int, hipStream_t);
+template void pupdate<float>(int64_t, int, const float*, float*, float*, const double*, int, hipStream_t);
+template void xupdate<double>(int64_t, int, double*, const double*, const double*, hipStream_t);
+template void xupdate<float>(int64_t, int, float*, const float*, const double*, hipStream_t);
+template void cg_update<double>(int64_t, int, const double*, double*, const double*, const double*, double*, int,
+                                hipStream_t);
+template void cg_update<float>(int64_t, int, const float*, float*, const float*, const double*, double*, int,
+                               hipStream_t);
 
 // y = x (with optional conversion) / y += x
 template <typename TI, typename TO>

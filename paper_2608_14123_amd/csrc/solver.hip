@@ -428,7 +428,7 @@ struct Solver {
       for (int k = 0; k < nrhs; ++k) h[k * 8 + 6] = r_max[k];
       HIPC(hipMemcpyAsync(scal, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
     }
-    int it = 0;
+    int it = 0, ran = 0;
     const bool fused = L.zpart && !msel;
     const bool with_net = learned && &L == &lv.back() && sizeof(T) == 8;
     for (int i = 1; i <= n; ++i) {
@@ -443,18 +443,18 @@ struct Solver {
         a.dotz2 = i > 1 ? L.zpart + (size_t)L.nla * nrhs : nullptr;
         schwarz_overlap_add<T>(L.p, L.m, a, st);
         finish(L.nla, nrhs, a.dotz, a.dotz2, i > 1 ? kOpBeta : kOpGamma, scal, nullptr, st, L.nla);
-        pupdate<T>(L.ndof, nrhs, z, pv, scal, i > 1 ? 0 : 1, st);
+        pupdate<T>(L.ndof, nrhs, z, pv, i > 1 ? x : nullptr, scal, i > 1 ? 0 : 1, st);
       } else if (i > 1) {
         schwarz_t(L, r, z, 0);
         dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
         dot_partials<T>(L.ndof, nrhs, z, r, r0, partial2(), nb, st);
         finish(nb, nrhs, partial, partial2(), kOpBeta, scal, nullptr, st);
-        pupdate<T>(L.ndof, nrhs, z, pv, scal, 0, st);
+        pupdate<T>(L.ndof, nrhs, z, pv, x, scal, 0, st);
       } else {
         schwarz_t(L, r, z, 0);
         dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
         finish(nb, nrhs, partial, nullptr, kOpGamma, scal, nullptr, st);
-        pupdate<T>(L.ndof, nrhs, z, pv, scal, 1, st);
+        pupdate<T>(L.ndof, nrhs, z, pv, nullptr, scal, 1, st);
       }
       if (L.kpart && !mmask) {
         // q = A p with p^T q summed by the operator kernel itself
@@ -467,9 +467,13 @@ struct Solver {
         dot_partials<T>(L.ndof, nrhs, pv, q, nullptr, partial, nb, st);
         finish(nb, nrhs, partial, nullptr, kOpAlpha, scal, nullptr, st);
       }
-      cg_update<T>(L.ndof, nrhs, r, r0, q, x, pv, scal, partial, nb, st);
+      // r_new = r - alpha q goes to the other residual buffer, which then holds r0; the
+      // update u += alpha p rides on the next iteration's p update (or follows the loop)
+      cg_update<T>(L.ndof, nrhs, r, r0, q, scal, partial, nb, st);
+      std::swap(r, r0);
       finish(nb, nrhs, partial, nullptr, kOpNorm2, scal, nullptr, st);
       it = i;
+      ran = i;
       // A converged right-hand side is frozen on the device at the iteration where it
       // converged, so the host needs to look only every kCheck iterations: the iterates are
       // those of a check after every iteration, at a fraction of the synchronisations.
@@ -488,6 +492,7 @@ struct Solver {
         it = i;
       }
     }
+    if (ran) xupdate<T>(L.ndof, nrhs, x, pv, scal, st);
     return it;
   }
 
