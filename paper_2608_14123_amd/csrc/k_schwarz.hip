@@ -287,6 +287,140 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
   }
 }
 
+// Small subdomains (n <= 3, ns^3 <= 125): one thread per tile point, looping over the
+// points when the workgroup is narrower than the tile; the three directions' tables are
+// staged in LDS.  The contraction order and arithmetic are those of schwarz_tile.
+template <int N, int M, typename T>
+struct PtSmem {
+  static constexpr int NS = N + 2 * M, NT = NS * NS * NS;
+  T tile[NT];
+  T S[3][NS * NS];
+  T lam[3][NS];
+  T W[3][NS];
+  int map[3][NS];
+  int nb[27];
+  int off[27];
+};
+
+template <int N, int M, typename T>
+__device__ __forceinline__ void schwarz_point_tile(SchwarzArgs<T> a, const int lbr, PtSmem<N, M, T>& sm,
+                                                   const int nthr) {
+  constexpr int NS = N + 2 * M, NT = NS * NS * NS, MAXP = (NT + 63) / 64;
+  constexpr Regions<N, M> R{};
+  const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
+  const int e = a.elist ? a.elist[li] : li;
+  if (a.sel && !a.sel[e]) return;
+  a.r += (int64_t)rhs * a.ndof;
+  a.z += (int64_t)rhs * a.ndof;
+  a.O += (int64_t)rhs * a.nin;
+  const int tid = threadIdx.x;
+  const int vv[3] = {__builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 0]),
+                     __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 1]),
+                     __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 2])};
+  for (int t = tid; t < 3 * NS * NS; t += nthr) {
+    const int d = t / (NS * NS), q = t - d * NS * NS;
+    sm.S[d][q] = a.S[vv[d] * NS * NS + q];
+  }
+  for (int t = tid; t < 3 * NS; t += nthr) {
+    const int d = t / NS, q = t - d * NS;
+    sm.lam[d][q] = a.lam[vv[d] * NS + q];
+    sm.W[d][q] = a.W[vv[d] * NS + q];
+    sm.map[d][q] = a.map1d[vv[d] * NS + q];
+  }
+  if (tid < 27) {
+    int nb = a.nb27[(int64_t)e * 27 + tid];
+    if (nb >= 0 && a.deg && a.deg[nb] != N - 1) nb = -1;   // another degree: zero fill, no scatter
+    sm.nb[tid] = nb;
+    sm.off[tid] = R.off[tid];
+  }
+  const T g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
+  const T g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
+  __syncthreads();
+  T v[MAXP];
+  // gather r_s = R_s r
+#pragma unroll
+  for (int pp = 0; pp < MAXP; ++pp) {
+    const int q = tid + pp * nthr;
+    v[pp] = 0;
+    if (q < NT) {
+      const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
+      const int m1 = sm.map[0][s1], m2 = sm.map[1][s2], m3 = sm.map[2][s3];
+      if (m1 >= 0 && m2 >= 0 && m3 >= 0) {
+        const int src = sm.nb[(m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6)];
+        if (src >= 0) v[pp] = a.r[elem_base<N>(a, src) + ((m3 & 63) * N + (m2 & 63)) * N + (m1 & 63)];
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < MAXP; ++pp) {
+    const int q = tid + pp * nthr;
+    if (q < NT) sm.tile[q] = v[pp];
+  }
+  __syncthreads();
+  // six contractions: xi_1 S1^T, xi_2 S2^T, xi_3 S3^T and 1/D, xi_3 S3, xi_2 S2, xi_1 S1
+#pragma unroll 1
+  for (int step = 0; step < 6; ++step) {
+    const int dir = step < 3 ? step : 5 - step;
+    const bool tr = step < 3;
+#pragma unroll
+    for (int pp = 0; pp < MAXP; ++pp) {
+      const int q = tid + pp * nthr;
+      if (q >= NT) continue;
+      const int s[3] = {q % NS, (q / NS) % NS, q / (NS * NS)};
+      const int c = s[dir];
+      const int stride = dir == 0 ? 1 : (dir == 1 ? NS : NS * NS);
+      const int q0 = q - c * stride;
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) acc += (tr ? sm.S[dir][k * NS + c] : sm.S[dir][c * NS + k]) * sm.tile[q0 + k * stride];
+      if (step == 2) acc = acc / (g0 + g1 * sm.lam[0][s[0]] + g2 * sm.lam[1][s[1]] + g3 * sm.lam[2][s[2]]);
+      v[pp] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pp = 0; pp < MAXP; ++pp) {
+      const int q = tid + pp * nthr;
+      if (q < NT) sm.tile[q] = v[pp];
+    }
+    __syncthreads();
+  }
+  // weighted scatter: own part to z, overlap parts into the receivers' inboxes
+#pragma unroll
+  for (int pp = 0; pp < MAXP; ++pp) {
+    const int q = tid + pp * nthr;
+    if (q >= NT) continue;
+    const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
+    const int m1 = sm.map[0][s1], m2 = sm.map[1][s2], m3 = sm.map[2][s3];
+    if (m1 < 0 || m2 < 0 || m3 < 0) continue;
+    T t = sm.tile[q];
+    if (a.corr) t += (T)(a.cscale[e] * (double)a.corr[(int64_t)e * NT + q]);
+    const T val = a.unweighted ? t : sm.W[0][s1] * sm.W[1][s2] * sm.W[2][s3] * t;
+    const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, d3 = (m3 >> 6) - 1;
+    const int l1 = m1 & 63, l2 = m2 & 63, l3 = m3 & 63;
+    if (d1 == 0 && d2 == 0 && d3 == 0) {
+      const int64_t gi = elem_base<N>(a, e) + (l3 * N + l2) * N + l1;
+      if (a.mode == 0) a.z[gi] = val;
+      else a.z[gi] += val;
+    } else {
+      const int dest = sm.nb[(d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1)];
+      if (dest < 0) continue;
+      const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
+      const int c1 = d1 < 0 ? l1 - (N - M) : l1, c2 = d2 < 0 ? l2 - (N - M) : l2, c3 = d3 < 0 ? l3 - (N - M) : l3;
+      const int x1 = d1 ? M : N, x2 = d2 ? M : N;
+      a.O[inbox_base<N, M>(a, dest) + sm.off[r] + (c3 * x2 + c2) * x1 + c1] = val;
+    }
+  }
+}
+
+template <int N, int M, typename T>
+__global__ void __launch_bounds__(((N + 2 * M) * (N + 2 * M) * (N + 2 * M) + 63) / 64 * 64)
+schwarz_point_kernel(SchwarzArgs<T> a) {
+  __shared__ PtSmem<N, M, T> sm;
+  const int lbr = xcd_block(a.nel * a.nrhs);
+  if (lbr < 0) return;
+  schwarz_point_tile<N, M, T>(a, lbr, sm, blockDim.x);
+}
+
 template <int N>
 struct AddShape {
   static constexpr int N3 = N * N * N;
@@ -569,8 +703,13 @@ template void mark_subdomains<double>(int, int, const SchwarzArgs<double>&, cons
 
 template <int N, int M, typename T>
 void launch_schwarz(const SchwarzArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL((schwarz_solve_kernel<N, M, T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(SzShape<N, M>::THREADS), 0,
-                     st, a);
+  if constexpr (N <= 3) {
+    constexpr int NS = N + 2 * M, THR = (NS * NS * NS + 63) / 64 * 64;
+    hipLaunchKernelGGL((schwarz_point_kernel<N, M, T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(THR), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((schwarz_solve_kernel<N, M, T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(SzShape<N, M>::THREADS),
+                       0, st, a);
+  }
 }
 
 template <int N, int M, typename T>
@@ -620,7 +759,7 @@ constexpr size_t sz_smem_upto() {
   if constexpr (N < 2) {
     return 0;
   } else {
-    constexpr size_t a = sizeof(SzSmem<N, 1, T>), b = sz_smem_upto<T, N - 1>();
+    constexpr size_t a = N <= 3 ? sizeof(PtSmem<N, 1, T>) : sizeof(SzSmem<N, 1, T>), b = sz_smem_upto<T, N - 1>();
     return a > b ? a : b;
   }
 }
@@ -645,7 +784,8 @@ schwarz_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, i
     switch (bd[k].p) {
 #define DGFAS_SZB(P)                                                                                  \
   case P:                                                                                             \
-    if constexpr (P + 1 <= NMAX) schwarz_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<SzSmem<P + 1, 1, T>*>(smem)); \
+    if constexpr (P + 1 <= 3) schwarz_point_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<PtSmem<P + 1, 1, T>*>(smem), blockDim.x); \
+    else if constexpr (P + 1 <= NMAX) schwarz_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<SzSmem<P + 1, 1, T>*>(smem)); \
     break;
       DGFAS_SZB(1) DGFAS_SZB(2) DGFAS_SZB(3) DGFAS_SZB(4) DGFAS_SZB(5) DGFAS_SZB(6) DGFAS_SZB(7) DGFAS_SZB(8)
 #undef DGFAS_SZB
