@@ -36,8 +36,10 @@ def parse():
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle cpu_baseline leg')
     ap.add_argument('--no-t10', action='store_true', help='skip the time-to-tolerance solves')
     ap.add_argument('--calib-copy', action='store_true', help='also run a plain copy kernel (PMC calibration)')
-    ap.add_argument('--workload', default='curved', choices=['curved', 'front'],
-                    help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8)')
+    ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched'],
+                    help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8); '
+                         'stretched: 48^3, p = 8, aspect 1:100, 16 right-hand sides')
+    ap.add_argument('--cycles', type=int, default=8, help='stretched workload: V-cycles per solve')
     return ap.parse_args()
 
 
@@ -169,6 +171,80 @@ def front_bench(args, torch, B):
     print(json.dumps(out))
 
 
+def stretched_bench(args, torch, B):
+    """The anisotropic stress workload: 48^3 elements on [0,1]^2 x [0,100] (aspect 1:100),
+    interior vertices perturbed by U[-0.2, 0.2] h_min (seed 4), p = 8 (80,621,568 DOF), 16
+    right-hand sides (nodal U[-1,1], seeds 4000..4015) in one batch, FAS-MG-SCG(12,4).
+    Reports the Schwarz application and one SCG iteration over all 16 right-hand sides, and
+    the first cycles' history and time, FP64 and FP32 smoothers.  Prints one JSON line."""
+    from paper_2608_14123_amd import workloads as W
+    ne, p, R = 48, 8, 16
+    E = ne ** 3
+    V, nbr, bc = W.stretched_perturbed(ne, seed=4)
+    X = W.element_coords(V, B.gll(p)[0])
+    ndof = E * (p + 1) ** 3
+    stream = torch.cuda.current_stream()
+    f = torch.empty(R * ndof, dtype=torch.float64, device='cuda')
+    for k in range(R):
+        f[k * ndof:(k + 1) * ndof].copy_(torch.from_numpy(W.uniform_nodal(ndof, 4000 + k)))
+    cyc = dict(smoother=B.SCG, ns1=12, ns2=4, mu_star=5.0, root_rtol=0.1, n_rhs=R)
+
+    def timed(fn, reps):
+        fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    modes = {}
+    for prec in ('fp64', 'fp32'):
+        o = B.default_options(precision=B.FP64 if prec == 'fp64' else B.FP32, **cyc)
+        t0 = time.perf_counter()
+        lib = B.Solver(np.full(E, p, np.int32), X, nbr, bc, o, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        rec = {'setup_s': round(time.perf_counter() - t0, 3)}
+        L = lib.n_levels
+        b = torch.empty_like(f)
+        lib.rhs(f, b)
+        if prec == 'fp64':
+            z = torch.empty_like(f)
+            ms_sz = timed(lambda: lib.schwarz(L, b, z), max(2, args.reps // 4))
+            del z
+            u = torch.zeros_like(f)
+            ms1 = timed(lambda: lib.smooth(L, u, b, 1), 2)
+            ms3 = timed(lambda: lib.smooth(L, u, b, 3), 2)
+            rec['schwarz_gdofs_all_rhs'] = round(R * ndof / (ms_sz * 1e-3) / 1e9, 3)
+            rec['scg_iteration_ms'] = round((ms3 - ms1) / 2, 3)
+            rec['scg_iteration_gdofs_all_rhs'] = round(R * ndof / ((ms3 - ms1) / 2 * 1e-3) / 1e9, 3)
+            del u
+        u = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist, ok = lib.solve(u, b, max_cycles=args.cycles, rtol=1e-10)
+        torch.cuda.synchronize()
+        rec['cycles'] = len(hist) - 1
+        rec['s_per_cycle'] = round((time.perf_counter() - t0) / max(1, len(hist) - 1), 4)
+        rec['converged_1e-10'] = bool(ok)
+        rec['hist'] = ['%.3e' % h for h in hist]
+        print(prec, rec, file=sys.stderr, flush=True)
+        modes[prec] = rec
+        del u, b
+        lib.close()
+    out = {
+        'metric': 'GDOF/s per Schwarz sweep; time-to-1e-10 residual, plain FP64 vs mixed/learned',
+        'value': modes['fp64']['schwarz_gdofs_all_rhs'], 'unit': 'GDOF/s', 'n_gpus': 1, 'steps': args.cycles,
+        'warmup': 1, 'ms_per_step': round(modes['fp64']['s_per_cycle'] * 1e3, 2), 'higher_is_better': True,
+        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64', 'data': 'synthetic',
+        'config': {'workload': 'stretched_perturbed_48^3_p8_aspect100_16rhs', 'n_dof_per_rhs': ndof, 'n_rhs': R,
+                   'cycle': 'FAS-MG-SCG(12,4), p-levels 8->4->2->1, root SCG to 1e-1', 'mu_star': 5.0},
+        'modes': modes,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -180,6 +256,9 @@ def main():
     assert torch.cuda.is_available(), 'needs a GPU'
     if args.workload == 'front':
         front_bench(args, torch, B)
+        return
+    if args.workload == 'stretched':
+        stretched_bench(args, torch, B)
         return
     ne, p = args.ne, args.p
     E = ne ** 3

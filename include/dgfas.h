@@ -102,7 +102,8 @@ typedef struct {
                                (element index) or DGFAS_ORDER_MORTON (Morton order of the element
                                centroids, so that concurrently running workgroups of one XCD take
                                a compact 3D block and share their neighbours' data in L2).
-                               Results are bitwise the same */
+                               Operator and Schwarz results are bitwise the same; dot products
+                               fused into the kernels sum their partials in another order */
   int32_t reserved[3];
 } dgfas_options;
 
