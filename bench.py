@@ -366,6 +366,17 @@ def main():
                                 'converged': bool(ok), 'final_rho': float(hist[-1])}
         print('t10 fp32', t10['fp32_smoother'], file=sys.stderr, flush=True)
         lib32.close()
+        optsb = B.default_options(precision=B.BF16, **cyc)
+        libb = B.Solver(np.full(E, p, np.int32), X, nbr, bc, optsb, stream=stream.cuda_stream)
+        hist, ok = libb.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        hist, ok = libb.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+        torch.cuda.synchronize()
+        t10['bf16_matrix_core_smoother'] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1,
+                                            'converged': bool(ok), 'final_rho': float(hist[-1])}
+        print('t10 bf16', t10['bf16_matrix_core_smoother'], file=sys.stderr, flush=True)
+        libb.close()
     else:
         lib.close()
 

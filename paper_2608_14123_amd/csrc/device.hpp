@@ -47,4 +47,21 @@ __device__ __forceinline__ constexpr int sym_index(int b, int c) {
   return (b > c) ? sym_index(c, b) : (b == 0 ? c : (b == 1 ? 2 + c : 5));
 }
 
+// offsets of the 26 overlap regions (region index (d3+1)*9 + (d2+1)*3 + (d1+1); 13 unused)
+template <int N, int M>
+struct Regions {
+  int off[27];
+  int size;
+  __host__ __device__ constexpr Regions() : off(), size(0) {
+    int o = 0;
+    for (int r = 0; r < 27; ++r) {
+      off[r] = o;
+      if (r == 13) continue;
+      const int d1 = r % 3 - 1, d2 = (r / 3) % 3 - 1, d3 = r / 9 - 1;
+      o += (d1 ? M : N) * (d2 ? M : N) * (d3 ? M : N);
+    }
+    size = o;
+  }
+};
+
 }  // namespace dgfas

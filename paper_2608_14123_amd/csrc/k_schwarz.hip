@@ -25,23 +25,6 @@ struct SzShape {
   static constexpr int THREADS = ((NS * NS + 63) / 64) * 64 < 64 ? 64 : ((NS * NS + 63) / 64) * 64;
 };
 
-// offsets of the 26 overlap regions (region index (d3+1)*9 + (d2+1)*3 + (d1+1); 13 unused)
-template <int N, int M>
-struct Regions {
-  int off[27];
-  int size;
-  __host__ __device__ constexpr Regions() : off(), size(0) {
-    int o = 0;
-    for (int r = 0; r < 27; ++r) {
-      off[r] = o;
-      if (r == 13) continue;
-      const int d1 = r % 3 - 1, d2 = (r / 3) % 3 - 1, d3 = r / 9 - 1;
-      o += (d1 ? M : N) * (d2 ? M : N) * (d3 ? M : N);
-    }
-    size = o;
-  }
-};
-
 // first DOF of element e, and first inbox slot of element e
 template <int N, typename T>
 __device__ __forceinline__ int64_t elem_base(const SchwarzArgs<T>& a, int e) {

@@ -1,0 +1,222 @@
+// K2m: the subdomain solve of the FP32 correction-form smoother with its six tensor
+// contractions (Sec. 4.3.1, fast diagonalisation) on the matrix cores:
+// v_mfma_f32_16x16x16bf16_1k, operands rounded to BF16, products accumulated in FP32.
+// One wavefront per subdomain (overlap m = 1, ns <= 16).  The tile stays in LDS in FP32;
+// a contraction along direction d is OUT(c, line) = sum_q M(c, q) IN(q, line) over the
+// ns^2 tile lines of that direction, 16 lines per MFMA (M = S_d^T going forward, S_d coming
+// back).  Gather, the division by the surrogate eigenvalue sums and the weighted scatter
+// follow the vector kernel.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace dgfas {
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 with round-to-nearest-even
+__device__ __forceinline__ short to_bf16s(float f) {
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x7fffffu)) return (short)((b >> 16) | 0x40);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (short)(b >> 16);
+}
+
+// tile slot of position q along direction dir of tile line `line` (pitch LS of xi_1 rows)
+template <int NS, int LS>
+__device__ __forceinline__ int tslot(int dir, int line, int q) {
+  const int lo = line % NS, hi = line / NS;
+  if (dir == 0) return (hi * NS + lo) * LS + q;
+  if (dir == 1) return (hi * NS + q) * LS + lo;
+  return (q * NS + hi) * LS + lo;
+}
+
+template <int N, int M>
+__global__ void __launch_bounds__(64) schwarz_mfma_kernel(SchwarzArgs<float> a) {
+  constexpr int NS = N + 2 * M, LS = NS | 1, NL = NS * NS, NCB = (NL + 15) / 16;
+  constexpr Regions<N, M> R{};
+  static_assert(NS <= 16, "one 16x16x16 MFMA covers a tile line");
+  const int lbr = xcd_block(a.nel * a.nrhs);
+  if (lbr < 0) return;
+  const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
+  const int e = a.elist ? a.elist[li] : li;
+  a.r += (int64_t)rhs * a.ndof;
+  a.z += (int64_t)rhs * a.ndof;
+  a.O += (int64_t)rhs * a.nin;
+  const int lane = threadIdx.x;
+  const int64_t ebase = a.off ? a.off[e] : (int64_t)e * (N * N * N);
+
+  __shared__ float tile[NS * NS * LS];
+  __shared__ float sW[3][NS];
+  __shared__ float sLam[3][NS];
+  __shared__ int sMap[3][NS];
+  __shared__ int sNb[27];
+  __shared__ int sOff[27];
+
+  int vv[3];
+  for (int d = 0; d < 3; ++d) vv[d] = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + d]);
+  for (int t = lane; t < 3 * NS; t += 64) {
+    const int d = t / NS, q = t - d * NS;
+    sW[d][q] = a.W[vv[d] * NS + q];
+    sLam[d][q] = a.lam[vv[d] * NS + q];
+    sMap[d][q] = a.map1d[vv[d] * NS + q];
+  }
+  if (lane < 27) {
+    int nb = a.nb27[(int64_t)e * 27 + lane];
+    if (nb >= 0 && a.deg && a.deg[nb] != N - 1) nb = -1;   // another degree: zero fill, no scatter
+    sNb[lane] = nb;
+    sOff[lane] = R.off[lane];
+  }
+  const float g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
+  const float g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
+  __syncthreads();
+  int m3u[NS];
+#pragma unroll
+  for (int s3 = 0; s3 < NS; ++s3) m3u[s3] = __builtin_amdgcn_readfirstlane(sMap[2][s3]);
+
+  // gather r_s = R_s r, one xi_3 column (c1, c2) per lane and pass
+  for (int col = lane; col < NL; col += 64) {
+    const int c1 = col % NS, c2 = col / NS;
+    const int m1 = sMap[0][c1], m2 = sMap[1][c2];
+    int64_t cb[3];
+#pragma unroll
+    for (int d3 = 0; d3 < 3; ++d3) {
+      cb[d3] = -1;
+      if (m1 >= 0 && m2 >= 0) {
+        const int src = sNb[d3 * 9 + (m2 >> 6) * 3 + (m1 >> 6)];
+        if (src >= 0)
+          cb[d3] = (a.off ? a.off[src] : (int64_t)src * (N * N * N)) + (m2 & 63) * N + (m1 & 63);
+      }
+    }
+    float vals[NS];
+#pragma unroll
+    for (int s3 = 0; s3 < NS; ++s3) {
+      const int m3 = m3u[s3];
+      vals[s3] = 0.f;
+      if (m3 >= 0) {
+        const int64_t b = cb[m3 >> 6];
+        if (b >= 0) vals[s3] = a.r[b + (m3 & 63) * (N * N)];
+      }
+    }
+#pragma unroll
+    for (int s3 = 0; s3 < NS; ++s3) tile[(s3 * NS + c2) * LS + c1] = vals[s3];
+  }
+  __syncthreads();
+
+  // six contractions: xi_1 S1^T, xi_2 S2^T, xi_3 S3^T (then 1/D), xi_3 S3, xi_2 S2, xi_1 S1
+  const int row = lane & 15, kq = 4 * (lane >> 4);
+#pragma unroll 1
+  for (int step = 0; step < 6; ++step) {
+    const int dir = step < 3 ? step : 5 - step;
+    const bool tr = step < 3;
+    const float* __restrict__ Sv = a.S + vv[dir] * NS * NS;
+    // A operand: lane holds M[row][kq + i]
+    v4s av;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = kq + i;
+      const float mv = (row < NS && q < NS) ? (tr ? Sv[q * NS + row] : Sv[row * NS + q]) : 0.f;
+      av[i] = to_bf16s(mv);
+    }
+#pragma unroll 1
+    for (int cbk = 0; cbk < NCB; ++cbk) {
+      const int line = cbk * 16 + row;
+      v4s bv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = kq + i;
+        bv[i] = to_bf16s((line < NL && q < NS) ? tile[tslot<NS, LS>(dir, line, q)] : 0.f);
+      }
+      const v4f acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      // result: lane holds OUT[kq + j][line]; the lines of this block are read above, so the
+      // block is updated in place
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = kq + j;
+        if (line < NL && c < NS) tile[tslot<NS, LS>(dir, line, c)] = acc[j];
+      }
+    }
+    __syncthreads();
+    if (step == 2) {
+      for (int q = lane; q < NS * NS * NS; q += 64) {
+        const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
+        const int t = (s3 * NS + s2) * LS + s1;
+        tile[t] = tile[t] / (g0 + g1 * sLam[0][s1] + g2 * sLam[1][s2] + g3 * sLam[2][s3]);
+      }
+      __syncthreads();
+    }
+  }
+
+  // weighted scatter, one xi_3 column per lane and pass
+  for (int col = lane; col < NL; col += 64) {
+    const int c1 = col % NS, c2 = col / NS;
+    const int m1 = sMap[0][c1], m2 = sMap[1][c2];
+    if (m1 < 0 || m2 < 0) continue;
+    const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, l1 = m1 & 63, l2 = m2 & 63;
+    const float w12 = sW[0][c1] * sW[1][c2];
+    int64_t db[3];
+    int ds[3];
+#pragma unroll
+    for (int d3i = 0; d3i < 3; ++d3i) {
+      const int d3 = d3i - 1;
+      db[d3i] = -1;
+      ds[d3i] = 0;
+      if (d1 == 0 && d2 == 0 && d3 == 0) {
+        db[d3i] = ebase + l2 * N + l1;
+        ds[d3i] = N * N;
+      } else {
+        const int dest = sNb[d3i * 9 + (d2 + 1) * 3 + (d1 + 1)];
+        if (dest >= 0) {
+          const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);
+          const int cc1 = d1 < 0 ? l1 - (N - M) : l1, cc2 = d2 < 0 ? l2 - (N - M) : l2;
+          const int x1 = d1 ? M : N, x2 = d2 ? M : N;
+          ds[d3i] = x2 * x1;
+          db[d3i] = (a.offO ? a.offO[dest] : (int64_t)dest * R.size) + sOff[r] + cc2 * x1 + cc1;
+        }
+      }
+    }
+#pragma unroll
+    for (int s3 = 0; s3 < NS; ++s3) {
+      const int m3 = m3u[s3];
+      if (m3 < 0) continue;
+      const int d3i = m3 >> 6, l3 = m3 & 63;
+      const float v = w12 * sW[2][s3] * tile[(s3 * NS + c2) * LS + c1];
+      const int64_t base = db[d3i];
+      if (base < 0) continue;
+      const int c3 = d3i == 0 ? l3 - (N - M) : l3;
+      const int64_t gi = base + (int64_t)c3 * ds[d3i];
+      if (d1 == 0 && d2 == 0 && d3i == 1) {
+        if (a.mode == 0) a.z[gi] = v;
+        else a.z[gi] += v;
+      } else {
+        a.O[gi] = v;
+      }
+    }
+  }
+}
+
+template <int N>
+void launch_mfma(const SchwarzArgs<float>& a, hipStream_t st) {
+  hipLaunchKernelGGL((schwarz_mfma_kernel<N, 1>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(64), 0, st, a);
+}
+
+}  // namespace
+
+bool schwarz_solve_mfma(int p, int m, const SchwarzArgs<float>& a, hipStream_t st) {
+  if (m != 1 || a.sel || a.corr || a.unweighted) return false;
+  switch (p) {
+    case 1: launch_mfma<2>(a, st); return true;
+    case 2: launch_mfma<3>(a, st); return true;
+    case 3: launch_mfma<4>(a, st); return true;
+    case 4: launch_mfma<5>(a, st); return true;
+    case 5: launch_mfma<6>(a, st); return true;
+    case 6: launch_mfma<7>(a, st); return true;
+    case 7: launch_mfma<8>(a, st); return true;
+    case 8: launch_mfma<9>(a, st); return true;
+    default: return false;
+  }
+}
+
+}  // namespace dgfas

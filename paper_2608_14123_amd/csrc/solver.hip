@@ -194,6 +194,7 @@ struct Solver {
   bool use_batch(const Level& L, int stage) const {
     if (L.uniform || L.bk.size() < 2) return false;
     if (stage != kStageOp && opt.overlap != 1) return false;   // batched Schwarz tiles take m = 1
+    if (stage == kStageSolve && opt.precision == DGFAS_BF16) return false;   // matrix-core tiles per degree
     if (force_batch >= 0) return force_batch == 1;
     if (opt.batch == DGFAS_BATCH_ONE_LAUNCH) return true;
     if (opt.batch == DGFAS_BATCH_TUNED) return L.one_launch[stage] != 0;
@@ -291,8 +292,14 @@ struct Solver {
     }
     for (const Bucket& b : L.bk) {
       SchwarzArgs<T> a = sz_args<T>(L, b, r, z, mode);
-      if (stage == kStageSolve) schwarz_solve<T>(b.p, b.t->m, a, st);
-      else schwarz_overlap_add<T>(b.p, b.t->m, a, st);
+      if (stage == kStageSolve) {
+        if constexpr (sizeof(T) == 4) {
+          if (opt.precision == DGFAS_BF16 && schwarz_solve_mfma(b.p, b.t->m, a, st)) continue;
+        }
+        schwarz_solve<T>(b.p, b.t->m, a, st);
+      } else {
+        schwarz_overlap_add<T>(b.p, b.t->m, a, st);
+      }
     }
   }
   template <typename T>
@@ -436,7 +443,9 @@ struct Solver {
         // z = B r with z^T r (and z^T (r - r0)) summed by the overlap-add kernel
         SchwarzArgs<T> a = sz_args<T>(L, L.bk[0], r, z, 0);
         if (with_net) add_learned(L, a, r);
-        schwarz_solve<T>(L.p, L.m, a, st);
+        bool done = false;
+        if constexpr (sizeof(T) == 4) done = opt.precision == DGFAS_BF16 && schwarz_solve_mfma(L.p, L.m, a, st);
+        if (!done) schwarz_solve<T>(L.p, L.m, a, st);
         a.dr = r;
         a.dr0 = i > 1 ? r0 : nullptr;
         a.dotz = L.zpart;
@@ -508,7 +517,7 @@ struct Solver {
 
   void smooth(Level& L, double* u, const double* g, int n) {
     if (n <= 0) return;
-    const bool mixed = opt.precision == DGFAS_FP32;
+    const bool mixed = opt.precision != DGFAS_FP64;
     if (opt.smoother == DGFAS_SCG) {
       if (mixed) scg_mixed(L, u, g, n);
       else scg<double>(L, u, g, n, {}, nullptr);
@@ -560,7 +569,7 @@ struct Solver {
 
   // every work vector a leg may touch, allocated before capture
   void prepare_legs() {
-    const bool fp32 = opt.precision == DGFAS_FP32;
+    const bool fp32 = opt.precision != DGFAS_FP64;
     for (size_t l = 1; l < lv.size(); ++l) {
       Level& L = lv[l];
       if (fp32) ensure_mixed_vectors(L);
@@ -917,7 +926,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   L.nb27 = s.own(upload(nb27, st));
   L.h_nb27 = nb27;
   const size_t nin = (size_t)L.nin * s.nrhs;
-  const bool fp32 = s.opt.precision == DGFAS_FP32;
+  const bool fp32 = s.opt.precision != DGFAS_FP64;
   L.O = s.own(dalloc<double>(nin));
   if (fp32) L.O32 = s.own(dalloc<float>(nin));
   // inbox regions of absent neighbours (and of neighbours of another degree) are never
@@ -1034,7 +1043,7 @@ void Solver::autotune(const char* path, int reps, double* report) {
       fill((int64_t)nv, x, 0.5, st);
       fill((int64_t)nv, y, 0.25, st);
       for (int sg = 0; sg < 3; ++sg) {
-        const std::string key = arch + "|" + L.hist + "|" + (opt.precision == DGFAS_FP32 ? "fp32" : "fp64") + "|rhs" +
+        const std::string key = arch + "|" + L.hist + "|" + (opt.precision == DGFAS_BF16 ? "bf16" : (opt.precision == DGFAS_FP32 ? "fp32" : "fp64")) + "|rhs" +
                                 std::to_string(nrhs) + "|" + stage_name[sg];
         if (sg != kStageOp && opt.overlap != 1) continue;
         auto it = cache.find(key);
@@ -1109,7 +1118,8 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
     throw Error(DGFAS_EUNSUPPORTED, "overlap 2 needs one degree, p = 4 or 8");
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
-  if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32) throw Error(DGFAS_EINVAL, "unknown precision");
+  if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32 && o->precision != DGFAS_BF16)
+    throw Error(DGFAS_EINVAL, "unknown precision");
   if (o->n_rhs < 1 || o->n_rhs > 64) throw Error(DGFAS_EINVAL, "n_rhs must be 1..64");
   if (o->batch < DGFAS_BATCH_PER_DEGREE || o->batch > DGFAS_BATCH_TUNED) throw Error(DGFAS_EINVAL, "unknown batch mode");
   if (o->graph != 0 && o->graph != 1) throw Error(DGFAS_EINVAL, "graph must be 0 or 1");
