@@ -1,11 +1,14 @@
 // K2m: the subdomain solve of the FP32 correction-form smoother with its six tensor
 // contractions (Sec. 4.3.1, fast diagonalisation) on the matrix cores:
 // v_mfma_f32_16x16x16bf16_1k, operands rounded to BF16, products accumulated in FP32.
-// One wavefront per subdomain (overlap m = 1, ns <= 16).  The tile stays in LDS in FP32;
+// Two wavefronts per subdomain: one xi_3 column per thread in gather and scatter, alternate
+// blocks of 16 tile lines per wavefront in the contractions (overlap m = 1, ns <= 16,
+// ns^2 <= 128).  The tile stays in LDS in FP32;
 // a contraction along direction d is OUT(c, line) = sum_q M(c, q) IN(q, line) over the
 // ns^2 tile lines of that direction, 16 lines per MFMA (M = S_d^T going forward, S_d coming
-// back).  Gather, the division by the surrogate eigenvalue sums and the weighted scatter
-// follow the vector kernel.
+// back); the eigenvector tables sit in LDS zero-padded to 16 x 16.  Gather and weighted
+// scatter follow the vector kernel; the division by the surrogate eigenvalue sums is done
+// on the registers between the two xi_3 contractions.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -16,28 +19,18 @@ namespace {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16 with round-to-nearest-even
+// FP32 -> BF16 with round-to-nearest-even (the hardware conversion on gfx950)
 __device__ __forceinline__ short to_bf16s(float f) {
-  uint32_t b = __float_as_uint(f);
-  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x7fffffu)) return (short)((b >> 16) | 0x40);
-  b += 0x7fffu + ((b >> 16) & 1u);
-  return (short)(b >> 16);
+  return __builtin_bit_cast(short, (__bf16)f);
 }
 
-// tile slot of position q along direction dir of tile line `line` (pitch LS of xi_1 rows)
-template <int NS, int LS>
-__device__ __forceinline__ int tslot(int dir, int line, int q) {
-  const int lo = line % NS, hi = line / NS;
-  if (dir == 0) return (hi * NS + lo) * LS + q;
-  if (dir == 1) return (hi * NS + q) * LS + lo;
-  return (q * NS + hi) * LS + lo;
-}
+constexpr int kMfThreads = 128;   // two wavefronts per subdomain
 
 template <int N, int M>
-__global__ void __launch_bounds__(64) schwarz_mfma_kernel(SchwarzArgs<float> a) {
-  constexpr int NS = N + 2 * M, LS = NS | 1, NL = NS * NS, NCB = (NL + 15) / 16;
+__global__ void __launch_bounds__(kMfThreads) schwarz_mfma_kernel(SchwarzArgs<float> a) {
+  constexpr int NS = N + 2 * M, LS = NS | 1, NL = NS * NS, NCB = (NL + 15) / 16, NCW = (NCB + 1) / 2;
   constexpr Regions<N, M> R{};
-  static_assert(NS <= 16, "one 16x16x16 MFMA covers a tile line");
+  static_assert(NS <= 16 && NL <= kMfThreads, "one 16x16x16 MFMA per tile line, one column per thread");
   const int lbr = xcd_block(a.nel * a.nrhs);
   if (lbr < 0) return;
   const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
@@ -45,29 +38,37 @@ __global__ void __launch_bounds__(64) schwarz_mfma_kernel(SchwarzArgs<float> a) 
   a.r += (int64_t)rhs * a.ndof;
   a.z += (int64_t)rhs * a.ndof;
   a.O += (int64_t)rhs * a.nin;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
   const int64_t ebase = a.off ? a.off[e] : (int64_t)e * (N * N * N);
 
-  __shared__ float tile[NS * NS * LS];
+  constexpr int TILE = NS * NS * LS;
+  __shared__ float tile[TILE + kMfThreads];   // the tile, then one dump slot per thread
+  __shared__ float sS[3][16 * 16];            // eigenvector tables zero-padded to 16 x 16
   __shared__ float sW[3][NS];
-  __shared__ float sLam[3][NS];
+  __shared__ float sLam[3][16];
   __shared__ int sMap[3][NS];
   __shared__ int sNb[27];
   __shared__ int sOff[27];
 
   int vv[3];
   for (int d = 0; d < 3; ++d) vv[d] = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + d]);
-  for (int t = lane; t < 3 * NS; t += 64) {
+  for (int t = tid; t < 3 * NS; t += kMfThreads) {
     const int d = t / NS, q = t - d * NS;
     sW[d][q] = a.W[vv[d] * NS + q];
     sLam[d][q] = a.lam[vv[d] * NS + q];
     sMap[d][q] = a.map1d[vv[d] * NS + q];
   }
-  if (lane < 27) {
-    int nb = a.nb27[(int64_t)e * 27 + lane];
+  for (int t = tid; t < 3 * 256; t += kMfThreads) {
+    const int d = t >> 8, i = (t >> 4) & 15, j = t & 15;
+    sS[d][t & 255] = (i < NS && j < NS) ? a.S[vv[d] * NS * NS + i * NS + j] : 0.f;
+  }
+  for (int t = tid; t < 3 * 16; t += kMfThreads)
+    if ((t & 15) >= NS) sLam[t >> 4][t & 15] = 0.f;
+  if (tid < 27) {
+    int nb = a.nb27[(int64_t)e * 27 + tid];
     if (nb >= 0 && a.deg && a.deg[nb] != N - 1) nb = -1;   // another degree: zero fill, no scatter
-    sNb[lane] = nb;
-    sOff[lane] = R.off[lane];
+    sNb[tid] = nb;
+    sOff[tid] = R.off[tid];
   }
   const float g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
   const float g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(64) schwarz_mfma_kernel(SchwarzArgs<float> a) 
   for (int s3 = 0; s3 < NS; ++s3) m3u[s3] = __builtin_amdgcn_readfirstlane(sMap[2][s3]);
 
   // gather r_s = R_s r, one xi_3 column (c1, c2) per lane and pass
-  for (int col = lane; col < NL; col += 64) {
+  for (int col = tid; col < NL; col += kMfThreads) {
     const int c1 = col % NS, c2 = col / NS;
     const int m1 = sMap[0][c1], m2 = sMap[1][c2];
     int64_t cb[3];
@@ -105,52 +106,83 @@ __global__ void __launch_bounds__(64) schwarz_mfma_kernel(SchwarzArgs<float> a) 
   }
   __syncthreads();
 
-  // six contractions: xi_1 S1^T, xi_2 S2^T, xi_3 S3^T (then 1/D), xi_3 S3, xi_2 S2, xi_1 S1
+  // six contractions: xi_1 S1^T, xi_2 S2^T, xi_3 S3^T (then 1/D), xi_3 S3, xi_2 S2, xi_1 S1,
+  // in five phases: the two xi_3 contractions share their lines, and the MFMA result layout
+  // (lane holds OUT[kq + j][line]) is the B operand layout, so the second one takes the
+  // first one's result from registers.
   const int row = lane & 15, kq = 4 * (lane >> 4);
-#pragma unroll 1
-  for (int step = 0; step < 6; ++step) {
-    const int dir = step < 3 ? step : 5 - step;
-    const bool tr = step < 3;
-    const float* __restrict__ Sv = a.S + vv[dir] * NS * NS;
-    // A operand: lane holds M[row][kq + i]
+  // A operand: lane holds M[row][kq + i], M = S_d^T (fwd) or S_d
+  auto a_operand = [&](int dir, bool fwd) {
     v4s av;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int q = kq + i;
-      const float mv = (row < NS && q < NS) ? (tr ? Sv[q * NS + row] : Sv[row * NS + q]) : 0.f;
-      av[i] = to_bf16s(mv);
+      av[i] = to_bf16s(fwd ? sS[dir][q * 16 + row] : sS[dir][row * 16 + q]);
     }
+    return av;
+  };
 #pragma unroll 1
-    for (int cbk = 0; cbk < NCB; ++cbk) {
-      const int line = cbk * 16 + row;
-      v4s bv;
+  for (int ph = 0; ph < 5; ++ph) {
+    const int dir = ph < 3 ? ph : 4 - ph;
+    const v4s av = a_operand(dir, ph <= 2);
+    // slot of position q on the line (hi, lo) of direction dir: hi * sh + lo * sl + q * sq
+    const int sh = dir == 2 ? LS : NS * LS, sl = dir == 0 ? LS : 1;
+    const int sq = dir == 0 ? 1 : (dir == 1 ? LS : NS * LS);
+    int lb[NCW];
+    bool lok[NCW];
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) {
+      const int line = (2 * k + wv) * 16 + row;
+      lok[k] = line < NL;
+      lb[k] = lok[k] ? (line / NS) * sh + (line % NS) * sl + kq * sq : 0;
+    }
+    // all column blocks are read before any is written: the lines of a direction partition
+    // the tile, so the contraction is done in place; the two wavefronts take alternate blocks
+    v4s bv[NCW];
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int q = kq + i;
-        bv[i] = to_bf16s((line < NL && q < NS) ? tile[tslot<NS, LS>(dir, line, q)] : 0.f);
+        const bool ok = lok[k] && kq + i < NS;
+        const float v = tile[ok ? lb[k] + i * sq : 0];
+        bv[k][i] = to_bf16s(ok ? v : 0.f);
       }
-      const v4f acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      // result: lane holds OUT[kq + j][line]; the lines of this block are read above, so the
-      // block is updated in place
+    }
+    v4f acc[NCW];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = kq + j;
-        if (line < NL && c < NS) tile[tslot<NS, LS>(dir, line, c)] = acc[j];
+    for (int k = 0; k < NCW; ++k)
+      acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[k], v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    if (ph == 2) {
+      // divide by the surrogate eigenvalue sums of (s1, s2, s3) = (line % ns, line / ns, c),
+      // then contract with S3
+      const v4s av3 = a_operand(2, false);
+      float l3[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) l3[j] = g3 * sLam[2][kq + j];
+#pragma unroll
+      for (int k = 0; k < NCW; ++k) {
+        const int line = (2 * k + wv) * 16 + row;
+        const bool okl = line < NL;
+        const float base = g0 + g1 * sLam[0][okl ? line % NS : 0] + g2 * sLam[1][okl ? line / NS : 0];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // the quotient is rounded to BF16 next, so the hardware reciprocal (1 ulp) suffices
+          const float v = acc[k][j] * __builtin_amdgcn_rcpf(base + l3[j]);
+          bv[k][j] = to_bf16s(okl && kq + j < NS ? v : 0.f);
+        }
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av3, bv[k], v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       }
+    }
+#pragma unroll
+    for (int k = 0; k < NCW; ++k) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tile[(lok[k] && kq + j < NS) ? lb[k] + j * sq : TILE + tid] = acc[k][j];
     }
     __syncthreads();
-    if (step == 2) {
-      for (int q = lane; q < NS * NS * NS; q += 64) {
-        const int s1 = q % NS, s2 = (q / NS) % NS, s3 = q / (NS * NS);
-        const int t = (s3 * NS + s2) * LS + s1;
-        tile[t] = tile[t] / (g0 + g1 * sLam[0][s1] + g2 * sLam[1][s2] + g3 * sLam[2][s3]);
-      }
-      __syncthreads();
-    }
   }
 
   // weighted scatter, one xi_3 column per lane and pass
-  for (int col = lane; col < NL; col += 64) {
+  for (int col = tid; col < NL; col += kMfThreads) {
     const int c1 = col % NS, c2 = col / NS;
     const int m1 = sMap[0][c1], m2 = sMap[1][c2];
     if (m1 < 0 || m2 < 0) continue;
@@ -199,7 +231,7 @@ __global__ void __launch_bounds__(64) schwarz_mfma_kernel(SchwarzArgs<float> a) 
 
 template <int N>
 void launch_mfma(const SchwarzArgs<float>& a, hipStream_t st) {
-  hipLaunchKernelGGL((schwarz_mfma_kernel<N, 1>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(64), 0, st, a);
+  hipLaunchKernelGGL((schwarz_mfma_kernel<N, 1>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(kMfThreads), 0, st, a);
 }
 
 }  // namespace
