@@ -1,9 +1,9 @@
 // K2m: the subdomain solve of the FP32 correction-form smoother with its six tensor
 // contractions (Sec. 4.3.1, fast diagonalisation) on the matrix cores:
 // v_mfma_f32_16x16x16bf16_1k, operands rounded to BF16, products accumulated in FP32.
-// Two wavefronts per subdomain: one xi_3 column per thread in gather and scatter, alternate
-// blocks of 16 tile lines per wavefront in the contractions (overlap m = 1, ns <= 16,
-// ns^2 <= 128).  The tile stays in LDS in FP32;
+// One xi_3 column per thread in gather and scatter (one wavefront per subdomain for
+// ns^2 <= 64, else two taking alternate blocks of 16 tile lines in the contractions;
+// overlap m = 1, ns <= 11).  The tile stays in LDS in FP32;
 // a contraction along direction d is OUT(c, line) = sum_q M(c, q) IN(q, line) over the
 // ns^2 tile lines of that direction, 16 lines per MFMA (M = S_d^T going forward, S_d coming
 // back); the eigenvector tables sit in LDS zero-padded to 16 x 16.  Gather and weighted
@@ -24,11 +24,14 @@ __device__ __forceinline__ short to_bf16s(float f) {
   return __builtin_bit_cast(short, (__bf16)f);
 }
 
-constexpr int kMfThreads = 128;   // two wavefronts per subdomain
+// one wavefront per subdomain while a thread per xi_3 column fits in it, else two
+template <int NS>
+constexpr int mf_threads() { return NS * NS <= 64 ? 64 : 128; }
 
 template <int N, int M>
-__global__ void __launch_bounds__(kMfThreads) schwarz_mfma_kernel(SchwarzArgs<float> a) {
-  constexpr int NS = N + 2 * M, LS = NS | 1, NL = NS * NS, NCB = (NL + 15) / 16, NCW = (NCB + 1) / 2;
+__global__ void __launch_bounds__(mf_threads<N + 2 * M>()) schwarz_mfma_kernel(SchwarzArgs<float> a) {
+  constexpr int NS = N + 2 * M, LS = NS | 1, NL = NS * NS, NCB = (NL + 15) / 16;
+  constexpr int kMfThreads = mf_threads<NS>(), NW = kMfThreads / 64, NCW = (NCB + NW - 1) / NW;
   constexpr Regions<N, M> R{};
   static_assert(NS <= 16 && NL <= kMfThreads, "one 16x16x16 MFMA per tile line, one column per thread");
   const int lbr = xcd_block(a.nel * a.nrhs);
@@ -132,12 +135,12 @@ __global__ void __launch_bounds__(kMfThreads) schwarz_mfma_kernel(SchwarzArgs<fl
     bool lok[NCW];
 #pragma unroll
     for (int k = 0; k < NCW; ++k) {
-      const int line = (2 * k + wv) * 16 + row;
+      const int line = (NW * k + wv) * 16 + row;
       lok[k] = line < NL;
       lb[k] = lok[k] ? (line / NS) * sh + (line % NS) * sl + kq * sq : 0;
     }
     // all column blocks are read before any is written: the lines of a direction partition
-    // the tile, so the contraction is done in place; the two wavefronts take alternate blocks
+    // the tile, so the contraction is done in place; the wavefronts take alternate blocks
     v4s bv[NCW];
 #pragma unroll
     for (int k = 0; k < NCW; ++k) {
@@ -161,7 +164,7 @@ __global__ void __launch_bounds__(kMfThreads) schwarz_mfma_kernel(SchwarzArgs<fl
       for (int j = 0; j < 4; ++j) l3[j] = g3 * sLam[2][kq + j];
 #pragma unroll
       for (int k = 0; k < NCW; ++k) {
-        const int line = (2 * k + wv) * 16 + row;
+        const int line = (NW * k + wv) * 16 + row;
         const bool okl = line < NL;
         const float base = g0 + g1 * sLam[0][okl ? line % NS : 0] + g2 * sLam[1][okl ? line / NS : 0];
 #pragma unroll
@@ -231,7 +234,7 @@ __global__ void __launch_bounds__(kMfThreads) schwarz_mfma_kernel(SchwarzArgs<fl
 
 template <int N>
 void launch_mfma(const SchwarzArgs<float>& a, hipStream_t st) {
-  hipLaunchKernelGGL((schwarz_mfma_kernel<N, 1>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(kMfThreads), 0, st, a);
+  hipLaunchKernelGGL((schwarz_mfma_kernel<N, 1>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(mf_threads<N + 2>()), 0, st, a);
 }
 
 }  // namespace
