@@ -128,6 +128,9 @@ struct Level {
          *r0 = nullptr;
   float *r32 = nullptr, *du32 = nullptr, *rc32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr,
         *r0_32 = nullptr;
+  // after an FP64 SCG smoothing call: the buffer holding its recurrence residual g - A u of
+  // the smoothed u (r or r0, by the parity of the iteration count); null otherwise
+  const double* rsm = nullptr;
 
   template <typename T>
   void scg_vectors(T*& r_, T*& z_, T*& p_, T*& q_, T*& r0_) {
@@ -154,6 +157,11 @@ struct Solver {
   hipGraphExec_t gdown = nullptr, gup = nullptr;
   const double *gu = nullptr, *gf = nullptr;
   int graph_epoch = 0, graph_built_epoch = -1;
+  // set by the solve loop right before a cycle: the finest level's r already holds g - A u for
+  // the cycle's (u, g), so the first smoothing step need not recompute it (one-shot; cleared
+  // once the cycle's pre-smoothing on the finest level has run)
+  bool rhint = false;
+  bool graph_hint = false;
   int nrhs = 1;            // right-hand sides per batch; vectors are [nrhs][ndof]
   double* partial = nullptr;   // [2][nrhs][1024] first-stage sums
   double* scal = nullptr;      // [nrhs][8] SCG scalars
@@ -335,9 +343,19 @@ struct Solver {
   }
 
   // ---------------------------------------------------------------- smoothers
+  // r = g - A u into L.r at the start of a smoothing call
+  void first_residual(Level& L, const double* u, const double* g) {
+    if (rhint && &L == &lv.back() && u == L.u && g == L.g) {
+      rhint = false;
+      return;
+    }
+    residual(L, u, g, L.r);
+  }
+
   void was(Level& L, double* u, const double* g, int n) {
     for (int i = 0; i < n; ++i) {
-      residual(L, u, g, L.r);
+      if (i == 0) first_residual(L, u, g);
+      else residual(L, u, g, L.r);
       schwarz(L, L.r, u, 1);
     }
   }
@@ -359,7 +377,7 @@ struct Solver {
   void was_mixed(Level& L, double* u, const double* g, int n) {
     if (n <= 0) return;
     ensure_mixed_vectors(L);
-    residual(L, u, g, L.r);
+    first_residual(L, u, g);
     convert<double, float>(L.ndof * nrhs, L.r, L.r32, 0, st);
     schwarz32(L, L.r32, L.du32, 0);
     for (int i = 1; i < n; ++i) {
@@ -425,6 +443,9 @@ struct Solver {
     if (zero_start) {
       fill(nv, x, (T)0, st);
       convert<T, T>(nv, f, r, 0, st);
+    } else if constexpr (sizeof(T) == 8) {
+      if (r == L.r && r_max.empty()) first_residual(L, x, f);
+      else residual_t(L, x, f, r);
     } else {
       residual_t(L, x, f, r);
     }
@@ -502,6 +523,9 @@ struct Solver {
       }
     }
     if (ran) xupdate<T>(L.ndof, nrhs, x, pv, scal, st);
+    if constexpr (sizeof(T) == 8) {
+      if (ran && r_max.empty() && !msel && !mmask) L.rsm = r;
+    }
     return it;
   }
 
@@ -509,13 +533,14 @@ struct Solver {
   // on A du = r in FP32 from du = 0, u += du (FP64).
   void scg_mixed(Level& L, double* u, const double* g, int n) {
     ensure_mixed_vectors(L);
-    residual(L, u, g, L.r);
+    first_residual(L, u, g);
     convert<double, float>(L.ndof * nrhs, L.r, L.r32, 0, st);
     scg<float>(L, L.du32, L.r32, n, {}, nullptr, true);
     convert<float, double>(L.ndof * nrhs, L.du32, u, 1, st);
   }
 
   void smooth(Level& L, double* u, const double* g, int n) {
+    L.rsm = nullptr;
     if (n <= 0) return;
     const bool mixed = opt.precision != DGFAS_FP64;
     if (opt.smoother == DGFAS_SCG) {
@@ -552,6 +577,7 @@ struct Solver {
     T.g = const_cast<double*>(f_top);
     bool bd = false;
     leg_down();
+    rhint = false;
     root_solve(lv[0].u, lv[0].g, &bd);
     leg_up();
     T.u = u_save;
@@ -560,7 +586,9 @@ struct Solver {
 
   // The same cycle with both legs replayed from captured graphs (bitwise the same work).
   void vcycle_graphed(double* u_top, const double* f_top) {
-    if (!gdown || gu != u_top || gf != f_top || graph_built_epoch != graph_epoch) build_graphs(u_top, f_top);
+    if (!gdown || gu != u_top || gf != f_top || graph_built_epoch != graph_epoch || graph_hint != rhint)
+      build_graphs(u_top, f_top);
+    rhint = false;
     bool bd = false;
     HIPC(hipGraphLaunch(gdown, st));
     root_solve(lv[0].u, lv[0].g, &bd);
@@ -590,6 +618,7 @@ struct Solver {
     hipStream_t saved = st;
     T.u = u_top;
     T.g = const_cast<double*>(f_top);
+    const bool hint = rhint;   // the captured down leg starts from r, as the replays will
     st = cap;
     hipGraphExec_t* dst[2] = {&gdown, &gup};
     try {
@@ -623,6 +652,7 @@ struct Solver {
     gu = u_top;
     gf = f_top;
     graph_built_epoch = graph_epoch;
+    graph_hint = hint;
   }
 
   void leg_down() {
@@ -631,11 +661,19 @@ struct Solver {
       Level& F = lv[l];
       Level& C = lv[l - 1];
       smooth(F, F.u, F.g, opt.ns1);
-      residual(F, F.u, F.g, F.r);
+      rhint = false;
+      // r = g - A u: an FP64 SCG smoother leaves it as its recurrence residual (the same
+      // vector up to rounding), any other smoother has it computed here
+      const double* rF = F.rsm;
+      if (!rF) {
+        residual(F, F.u, F.g, F.r);
+        rF = F.r;
+      }
+      F.rsm = nullptr;
       transfer(F, C, 0, F.u, nullptr, C.ubar, 0);                              // ubar = P u
       HIPC(hipMemcpyAsync(C.u, C.ubar, C.ndof * nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       apply(C, C.ubar, C.g);                                                     // g = A ubar
-      transfer(F, C, 1, F.r, nullptr, C.g, 1);                                   //   + R r
+      transfer(F, C, 1, rF, nullptr, C.g, 1);                                    //   + R r
     }
   }
 
@@ -1492,6 +1530,10 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
   Solver* s = S_(sv);
   need(u, "u"); need(f, "f");
   if (max_cycles < 0) throw Error(DGFAS_EINVAL, "negative max_cycles");
+  struct HintReset {   // no residual hint survives the call, also when a cycle throws
+    Solver* s;
+    ~HintReset() { s->rhint = false; }
+  } hint_reset{s};
   Level& T = s->lv.back();
   s->residual(T, u, f, T.r);
   std::vector<double> r0 = s->dots_sync(T, T.r, T.r);
@@ -1523,8 +1565,10 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
     s->learned = use_learned && !plain_probe;
     if (s->learned)
       HIPC(hipMemcpyAsync(usave, u, T.ndof * s->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    s->rhint = true;   // T.r holds f - A u of this u (computed before the loop or below)
     if (s->opt.graph && !attached) s->vcycle_graphed(u, f);
     else s->vcycle(u, f);
+    s->rhint = false;
     s->residual(T, u, f, T.r);
     double rk = worst(s->dots_sync(T, T.r, T.r));
     if (plain_probe && k == 1) s->plain_rho = rk / prev;
