@@ -241,7 +241,7 @@ __global__ void xupdate_kernel(int64_t n, int nrhs, T* __restrict__ x, const T* 
   x[i] += (T)scal[(i / n) * 8 + 2] * p[i];
 }
 
-// rout = rin - alpha q (rout may be rin); partial[rhs*1024 + blk] = sum rout^2
+// rout = rin - alpha q (rout may be rin); partial[rhs*1024 + blk] = sum rout^2 (partial null: no sums)
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
 cg_update_kernel(int64_t n, const T* __restrict__ rin, T* __restrict__ rout, const T* __restrict__ q,
@@ -258,6 +258,7 @@ cg_update_kernel(int64_t n, const T* __restrict__ rin, T* __restrict__ rout, con
     rout[i] = rn;
     s += (double)rn * (double)rn;
   }
+  if (!partial) return;   // no norm wanted (uniform over the grid)
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) partial[rhs * 1024 + blockIdx.x] = t;
 }

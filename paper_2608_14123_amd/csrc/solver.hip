@@ -499,9 +499,11 @@ struct Solver {
       }
       // r_new = r - alpha q goes to the other residual buffer, which then holds r0; the
       // update u += alpha p rides on the next iteration's p update (or follows the loop)
-      cg_update<T>(L.ndof, nrhs, r, r0, q, scal, partial, nb, st);
+      // ||r||^2 feeds only the convergence test, so a fixed-count smoothing call skips it
+      const bool track = !r_max.empty();
+      cg_update<T>(L.ndof, nrhs, r, r0, q, scal, track ? partial : nullptr, nb, st);
       std::swap(r, r0);
-      finish(nb, nrhs, partial, nullptr, kOpNorm2, scal, nullptr, st);
+      if (track) finish(nb, nrhs, partial, nullptr, kOpNorm2, scal, nullptr, st);
       it = i;
       ran = i;
       // A converged right-hand side is frozen on the device at the iteration where it
