@@ -7,10 +7,11 @@
 // transposed interpolation.  The lifting term uses the restricted jump times the own
 // nu n.grad xi_c, written into the transposed volume contractions as in sipg_apply.
 //
-// One workgroup per (element, right-hand side) of the list; the element's faces are taken
-// one after another and every output node is written by one thread, so the result is
-// deterministic.  Degrees are runtime values; the face's D and interpolation tables are
-// staged in LDS.
+// Two launches: one workgroup per (face between degrees, right-hand side) computes the
+// face's row and lifting terms on the own face grid into a result slot, then one workgroup
+// per (element, right-hand side) adds its faces' terms in face order, every output node
+// written by one thread, so the result is deterministic.  Degrees are runtime values; the
+// face's D and interpolation tables are staged in LDS.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -48,179 +49,210 @@ __device__ T face_flux(int n, int phi, int f, const T* D, const T* tr, const T* 
   return sgn * inv_wend * fl / wsf;
 }
 
+// Face results per (right-hand side, face task): the row term and the three lifting rows
+// on the own element's face grid
+constexpr int kFaceRes = 4 * kMaxN2;
+
+// One workgroup per (face between degrees, right-hand side): phases 0 to F of the face.
 template <typename T>
-__global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<T> a) {
-  const int lbr = xcd_block(a.nel * a.nrhs);
+__global__ void __launch_bounds__(kMortarThreads) mortar_face_kernel(MortarArgs<T> a) {
+  const int lbr = xcd_block(a.nface * a.nrhs);
   if (lbr < 0) return;
-  const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
-  const int e = a.elist[li];
+  const int task = lbr / a.nrhs, rhs = lbr - task * a.nrhs;
+  const int ep = a.ftask[task], e = ep / 6, phi = ep - e * 6;
   const int tid = threadIdx.x;
   const T* __restrict__ u = a.u + (int64_t)rhs * a.ndof;
-  T* __restrict__ out = a.out + (int64_t)rhs * a.ndof;
-  const int po = a.deg[e], n = po + 1, n2 = n * n, n3 = n2 * n;
+  T* __restrict__ res = reinterpret_cast<T*>(a.fres) + ((int64_t)rhs * a.nface + task) * kFaceRes;
+  const int po = a.deg[e], n = po + 1, n2 = n * n;
   const int64_t base = a.off[e], fbase = a.offF[e];
   const T inv_wend_o = (T)(0.5 * po * (po + 1));
 
-  __shared__ T su[kMaxN3];
-  __shared__ T acc[kMaxN3];
   __shared__ T sDo[kMaxN2], sDn[kMaxN2], sIo[kMaxN2], sIn[kMaxN2];
   __shared__ T to[kMaxN2], dno[kMaxN2], qo[kMaxN2], wso[kMaxN2], go[3][kMaxN2];
   __shared__ T tn[kMaxN2], dnn[kMaxN2], qn[kMaxN2], wsn[kMaxN2], gn[3][kMaxN2];
   __shared__ T x1[4][kMaxN2];                 // half-interpolated own t, own q, nb t, nb q
   __shared__ T rF[kMaxN2], sF[kMaxN2];        // row term and lifting weight on the finer grid
   __shared__ T y1[2][kMaxN2];                 // half-restricted row and lifting weight
-  __shared__ T row[kMaxN2], lift[3][kMaxN2];
 
-  for (int t = tid; t < n3; t += kMortarThreads) {
-    su[t] = u[base + t];
-    acc[t] = 0;
+  const int en = a.nbr[(int64_t)e * 6 + phi];
+  const int pn = a.deg[en];
+  const int nn = pn + 1, nn2 = nn * nn, nF = nn > n ? nn : n, nF2 = nF * nF;
+  const int phin = phi ^ 1, ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0, endn = (phin & 1) ? nn - 1 : 0;
+  const int pF = nF - 1;
+  const T sgn = (phi & 1) ? T(1) : T(-1);
+  const T inv_wend_n = (T)(0.5 * pn * (pn + 1));
+  const T mu = (T)a.muf[(int64_t)e * 6 + phi];
+  const int64_t nbase = a.off[en], nfbase = a.offF[en];
+
+  // 0: every global load of the face first (both sides' normal lines, metric rows, omega s)
+  // and the face's tables into LDS; one face-node task per thread (n^2 + nn^2 <= 162)
+  const bool own_t = tid < n2, nb_t = !own_t && tid < n2 + nn2;
+  const int f = own_t ? tid : tid - n2;
+  T line[kMaxN], g3[3] = {0, 0, 0}, wsv = 0;
+  if (nb_t) {
+    const int v0 = fnode(nn, phin, f, 0), st = lstride(nn, ax);
+#pragma unroll
+    for (int m = 0; m < kMaxN; ++m) line[m] = m < nn ? u[nbase + v0 + m * st] : T(0);
+    const int vi = v0 + endn * st;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + nbase + vi];
+    wsv = (T)a.ws[nfbase + phin * nn2 + f];
+  } else if (own_t) {
+    const int v0 = fnode(n, phi, f, 0), st = lstride(n, ax);
+#pragma unroll
+    for (int m = 0; m < kMaxN; ++m) line[m] = m < n ? u[base + v0 + m * st] : T(0);
+    const int vi = v0 + endo * st;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + base + vi];
+    wsv = (T)a.ws[fbase + phi * n2 + f];
   }
+  for (int t = tid; t < kMaxN2; t += kMortarThreads) {
+    if (t < n2) sDo[t] = (T)a.Dall[(po - 1) * kMaxN2 + t];
+    if (t < nn2) sDn[t] = (T)a.Dall[(pn - 1) * kMaxN2 + t];
+    if (t < nF * n) sIo[t] = (T)a.Iall[((po - 1) * 8 + (pF - 1)) * kMaxN2 + t];     // nF x n
+    if (t < nF * nn) sIn[t] = (T)a.Iall[((pn - 1) * 8 + (pF - 1)) * kMaxN2 + t];    // nF x nn
+  }
+  __syncthreads();
+  // A: traces and normal-line derivatives of both sides
+  if (own_t) {
+    T d = 0, tv = 0;
+#pragma unroll
+    for (int m = 0; m < kMaxN; ++m) {
+      if (m < n) d += sDo[endo * n + m] * line[m];
+      if (m == endo) tv = line[m];
+    }
+    to[f] = tv;
+    dno[f] = d;
+    wso[f] = wsv;
+    for (int c = 0; c < 3; ++c) go[c][f] = g3[c];
+  } else if (nb_t) {
+    T d = 0, tv = 0;
+#pragma unroll
+    for (int m = 0; m < kMaxN; ++m) {
+      if (m < nn) d += sDn[endn * nn + m] * line[m];
+      if (m == endn) tv = line[m];
+    }
+    tn[f] = tv;
+    dnn[f] = d;
+    wsn[f] = wsv;
+    for (int c = 0; c < 3; ++c) gn[c][f] = g3[c];
+  }
+  __syncthreads();
+  // B: normal fluxes (each side's outward normal)
+  if (own_t) qo[f] = face_flux<T>(n, phi, f, sDo, to, dno, go, sgn, inv_wend_o, wso[f]);
+  else if (nb_t) qn[f] = face_flux<T>(nn, phin, f, sDn, tn, dnn, gn, -sgn, inv_wend_n, wsn[f]);
+  __syncthreads();
+  // C: first interpolation step X1[i][b] = sum_a I[i][a] X[a][b] for the four face fields
+  for (int t = tid; t < 2 * nF * n + 2 * nF * nn; t += kMortarThreads) {
+    int s = t, which, w;
+    if (s < 2 * nF * n) { which = s / (nF * n); s -= which * nF * n; w = n; }
+    else { s -= 2 * nF * n; which = 2 + s / (nF * nn); s -= (which - 2) * nF * nn; w = nn; }
+    const int i = s / w, b = s - i * w;
+    const T* I = which < 2 ? sIo : sIn;
+    const T* X = which == 0 ? to : (which == 1 ? qo : (which == 2 ? tn : qn));
+    T v = 0;
+    for (int q = 0; q < w; ++q) v += I[i * w + q] * X[q * w + b];
+    x1[which][i * w + b] = v;
+  }
+  __syncthreads();
+  // D: second step and the differences on the finer grid
+  for (int t = tid; t < nF2; t += kMortarThreads) {
+    const int i = t / nF, j = t - i * nF;
+    T t_o = 0, q_o = 0, t_n = 0, q_n = 0;
+    for (int b = 0; b < n; ++b) {
+      const T ij = sIo[j * n + b];
+      t_o += x1[0][i * n + b] * ij;
+      q_o += x1[1][i * n + b] * ij;
+    }
+    for (int b = 0; b < nn; ++b) {
+      const T ij = sIn[j * nn + b];
+      t_n += x1[2][i * nn + b] * ij;
+      q_n += x1[3][i * nn + b] * ij;
+    }
+    // omega s of the finer side, in its own face-node order (shared orientation)
+    const T wF = n > nn ? wso[t] : wsn[t];
+    const T jt = t_o - t_n, jq = q_o - q_n;
+    rF[t] = wF * (mu * jt - T(0.5) * jq);
+    sF[t] = T(-0.5) * wF * jt;
+  }
+  __syncthreads();
+  // E: restriction, first step Y1[a][j] = sum_i I[i][a] F[i][j]
+  for (int t = tid; t < 2 * n * nF; t += kMortarThreads) {
+    const int which = t / (n * nF), s = t - which * n * nF;
+    const int aa = s / nF, j = s - aa * nF;
+    const T* F = which == 0 ? rF : sF;
+    T v = 0;
+    for (int i = 0; i < nF; ++i) v += sIo[i * n + aa] * F[i * nF + j];
+    y1[which][aa * nF + j] = v;
+  }
+  __syncthreads();
+  // F: second step; the lifting weight divided by the own omega s times the own metric row;
+  // row and lifting rows go to the face's result slot
+  for (int t = tid; t < n2; t += kMortarThreads) {
+    const int aa = t / n, b = t - aa * n;
+    T r = 0, sgm = 0;
+    for (int j = 0; j < nF; ++j) {
+      const T ij = sIo[j * n + b];
+      r += y1[0][aa * nF + j] * ij;
+      sgm += y1[1][aa * nF + j] * ij;
+    }
+    res[t] = r;
+    const T sc = sgm / wso[t] * sgn * inv_wend_o;
+    for (int c = 0; c < 3; ++c) res[(1 + c) * kMaxN2 + t] = sc * go[c][t];
+  }
+}
+
+// One workgroup per (element with faces between degrees, right-hand side): the faces'
+// results in face order, row at the face and lifting through D^T along every axis, added to
+// (mode 1) or subtracted from (mode 0) the element's output.
+template <typename T>
+__global__ void __launch_bounds__(kMortarThreads) mortar_gather_kernel(MortarArgs<T> a) {
+  const int lbr = xcd_block(a.nel * a.nrhs);
+  if (lbr < 0) return;
+  const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
+  const int e = a.elist[li];
+  const int tid = threadIdx.x;
+  T* __restrict__ out = a.out + (int64_t)rhs * a.ndof;
+  const T* __restrict__ fres = reinterpret_cast<const T*>(a.fres) + (int64_t)rhs * a.nface * kFaceRes;
+  const int po = a.deg[e], n = po + 1, n2 = n * n, n3 = n2 * n;
+  const int64_t base = a.off[e];
+
+  __shared__ T sDo[kMaxN2];
+  __shared__ T row[6][kMaxN2], lift[6][3][kMaxN2];
+  __shared__ int ftk[6];
+  if (tid < 6) ftk[tid] = a.fmap[(int64_t)li * 6 + tid];
   if (tid < n2) sDo[tid] = (T)a.Dall[(po - 1) * kMaxN2 + tid];
   __syncthreads();
-
   for (int phi = 0; phi < 6; ++phi) {
-    const int en = a.nbr[(int64_t)e * 6 + phi];
-    if (en < 0) continue;
-    const int pn = a.deg[en];
-    if (pn == po) continue;                 // uniform over the workgroup
-    const int nn = pn + 1, nn2 = nn * nn, nF = nn > n ? nn : n, nF2 = nF * nF;
-    const int phin = phi ^ 1, ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0, endn = (phin & 1) ? nn - 1 : 0;
-    const int pF = nF - 1;
-    const T sgn = (phi & 1) ? T(1) : T(-1);
-    const T inv_wend_n = (T)(0.5 * pn * (pn + 1));
-    const T mu = (T)a.muf[(int64_t)e * 6 + phi];
-    const int64_t nbase = a.off[en], nfbase = a.offF[en];
-
-    // 0: every global load of the face first (neighbour normal lines, metric rows, omega s)
-    // and the face's tables into LDS; one face-node task per thread (n^2 + nn^2 <= 162)
-    const bool own_t = tid < n2, nb_t = !own_t && tid < n2 + nn2;
-    const int f = own_t ? tid : tid - n2;
-    T line[kMaxN], g3[3] = {0, 0, 0}, wsv = 0;
-    if (nb_t) {
-      const int v0 = fnode(nn, phin, f, 0), st = lstride(nn, ax);
-#pragma unroll
-      for (int m = 0; m < kMaxN; ++m) line[m] = m < nn ? u[nbase + v0 + m * st] : T(0);
-      const int vi = v0 + endn * st;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + nbase + vi];
-      wsv = (T)a.ws[nfbase + phin * nn2 + f];
-    } else if (own_t) {
-      const int vi = fnode(n, phi, f, endo);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + base + vi];
-      wsv = (T)a.ws[fbase + phi * n2 + f];
-    }
-    for (int t = tid; t < kMaxN2; t += kMortarThreads) {
-      if (t < nn2) sDn[t] = (T)a.Dall[(pn - 1) * kMaxN2 + t];
-      if (t < nF * n) sIo[t] = (T)a.Iall[((po - 1) * 8 + (pF - 1)) * kMaxN2 + t];     // nF x n
-      if (t < nF * nn) sIn[t] = (T)a.Iall[((pn - 1) * 8 + (pF - 1)) * kMaxN2 + t];    // nF x nn
-    }
-    __syncthreads();
-    // A: traces and normal-line derivatives of both sides
-    if (own_t) {
-      const int v0 = fnode(n, phi, f, 0), st = lstride(n, ax);
-      T d = 0;
-      for (int m = 0; m < n; ++m) d += sDo[endo * n + m] * su[v0 + m * st];
-      to[f] = su[v0 + endo * st];
-      dno[f] = d;
-      wso[f] = wsv;
-      for (int c = 0; c < 3; ++c) go[c][f] = g3[c];
-    } else if (nb_t) {
-      T d = 0, tv = 0;
-#pragma unroll
-      for (int m = 0; m < kMaxN; ++m) {
-        if (m < nn) d += sDn[endn * nn + m] * line[m];
-        if (m == endn) tv = line[m];
-      }
-      tn[f] = tv;
-      dnn[f] = d;
-      wsn[f] = wsv;
-      for (int c = 0; c < 3; ++c) gn[c][f] = g3[c];
-    }
-    __syncthreads();
-    // B: normal fluxes (each side's outward normal)
-    if (own_t) qo[f] = face_flux<T>(n, phi, f, sDo, to, dno, go, sgn, inv_wend_o, wso[f]);
-    else if (nb_t) qn[f] = face_flux<T>(nn, phin, f, sDn, tn, dnn, gn, -sgn, inv_wend_n, wsn[f]);
-    __syncthreads();
-    // C: first interpolation step X1[i][b] = sum_a I[i][a] X[a][b] for the four face fields
-    for (int t = tid; t < 2 * nF * n + 2 * nF * nn; t += kMortarThreads) {
-      int s = t, which, w;
-      if (s < 2 * nF * n) { which = s / (nF * n); s -= which * nF * n; w = n; }
-      else { s -= 2 * nF * n; which = 2 + s / (nF * nn); s -= (which - 2) * nF * nn; w = nn; }
-      const int i = s / w, b = s - i * w;
-      const T* I = which < 2 ? sIo : sIn;
-      const T* X = which == 0 ? to : (which == 1 ? qo : (which == 2 ? tn : qn));
-      T v = 0;
-      for (int q = 0; q < w; ++q) v += I[i * w + q] * X[q * w + b];
-      x1[which][i * w + b] = v;
-    }
-    __syncthreads();
-    // D: second step and the differences on the finer grid
-    for (int t = tid; t < nF2; t += kMortarThreads) {
-      const int i = t / nF, j = t - i * nF;
-      T t_o = 0, q_o = 0, t_n = 0, q_n = 0;
-      for (int b = 0; b < n; ++b) {
-        const T ij = sIo[j * n + b];
-        t_o += x1[0][i * n + b] * ij;
-        q_o += x1[1][i * n + b] * ij;
-      }
-      for (int b = 0; b < nn; ++b) {
-        const T ij = sIn[j * nn + b];
-        t_n += x1[2][i * nn + b] * ij;
-        q_n += x1[3][i * nn + b] * ij;
-      }
-      // omega s of the finer side, in its own face-node order (shared orientation)
-      const T wF = n > nn ? wso[t] : wsn[t];
-      const T jt = t_o - t_n, jq = q_o - q_n;
-      rF[t] = wF * (mu * jt - T(0.5) * jq);
-      sF[t] = T(-0.5) * wF * jt;
-    }
-    __syncthreads();
-    // E: restriction, first step Y1[a][j] = sum_i I[i][a] F[i][j]
-    for (int t = tid; t < 2 * n * nF; t += kMortarThreads) {
-      const int which = t / (n * nF), s = t - which * n * nF;
-      const int aa = s / nF, j = s - aa * nF;
-      const T* F = which == 0 ? rF : sF;
-      T v = 0;
-      for (int i = 0; i < nF; ++i) v += sIo[i * n + aa] * F[i * nF + j];
-      y1[which][aa * nF + j] = v;
-    }
-    __syncthreads();
-    // F: second step; the lifting weight divided by the own omega s times the own metric row
+    const int k = ftk[phi];
+    if (k < 0) continue;                      // uniform over the workgroup
+    const T* r = fres + (int64_t)k * kFaceRes;
     for (int t = tid; t < n2; t += kMortarThreads) {
-      const int aa = t / n, b = t - aa * n;
-      T r = 0, sgm = 0;
-      for (int j = 0; j < nF; ++j) {
-        const T ij = sIo[j * n + b];
-        r += y1[0][aa * nF + j] * ij;
-        sgm += y1[1][aa * nF + j] * ij;
-      }
-      row[t] = r;
-      const T sc = sgm / wso[t] * sgn * inv_wend_o;
-      for (int c = 0; c < 3; ++c) lift[c][t] = sc * go[c][t];
+      row[phi][t] = r[t];
+      for (int c = 0; c < 3; ++c) lift[phi][c][t] = r[(1 + c) * kMaxN2 + t];
     }
-    __syncthreads();
-    // G: accumulate per output node: row at the face, lifting through D^T along every axis
-    const int tb = ax == 0 ? 1 : 0;   // axis of the fast face index b
-    const int ta = ax == 2 ? 1 : 2;   // axis of the slow face index a
-    for (int t = tid; t < n3; t += kMortarThreads) {
-      const int idx[3] = {t % n, (t / n) % n, t / n2};
+  }
+  __syncthreads();
+  for (int t = tid; t < n3; t += kMortarThreads) {
+    const int idx[3] = {t % n, (t / n) % n, t / n2};
+    T acc = 0;
+    for (int phi = 0; phi < 6; ++phi) {
+      if (ftk[phi] < 0) continue;
+      const int ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0;
+      const int tb = ax == 0 ? 1 : 0;   // axis of the fast face index b
+      const int ta = ax == 2 ? 1 : 2;   // axis of the slow face index a
       const int l = idx[ax], fa = idx[ta], fb = idx[tb], ff = fa * n + fb;
-      T v = sDo[endo * n + l] * lift[ax][ff];
+      T v = sDo[endo * n + l] * lift[phi][ax][ff];
       if (l == endo) {
-        v += row[ff];
+        v += row[phi][ff];
         for (int m = 0; m < n; ++m) {
-          v += sDo[m * n + fb] * lift[tb][fa * n + m];
-          v += sDo[m * n + fa] * lift[ta][m * n + fb];
+          v += sDo[m * n + fb] * lift[phi][tb][fa * n + m];
+          v += sDo[m * n + fa] * lift[phi][ta][m * n + fb];
         }
       }
-      acc[t] += v;
+      acc += v;
     }
-    __syncthreads();
-  }
-  for (int t = tid; t < n3; t += kMortarThreads) {
-    const T v = acc[t];
-    out[base + t] = a.mode == 0 ? out[base + t] - v : out[base + t] + v;
+    out[base + t] = a.mode == 0 ? out[base + t] - acc : out[base + t] + acc;
   }
 }
 
@@ -228,8 +260,9 @@ __global__ void __launch_bounds__(kMortarThreads) sipg_mortar_kernel(MortarArgs<
 
 template <typename T>
 void sipg_mortar(const MortarArgs<T>& a, hipStream_t st) {
-  if (a.nel <= 0) return;
-  hipLaunchKernelGGL((sipg_mortar_kernel<T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(kMortarThreads), 0, st, a);
+  if (a.nel <= 0 || a.nface <= 0) return;
+  hipLaunchKernelGGL((mortar_face_kernel<T>), dim3(xcd_grid(a.nface * a.nrhs)), dim3(kMortarThreads), 0, st, a);
+  hipLaunchKernelGGL((mortar_gather_kernel<T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(kMortarThreads), 0, st, a);
 }
 
 template void sipg_mortar<double>(const MortarArgs<double>&, hipStream_t);

@@ -111,6 +111,10 @@ struct Level {
   int nla = 0;                          // overlap-add tiles per right-hand side (uniform levels)
   double* zpart = nullptr;              // [2][nrhs][nla] fused z^T r, z^T (r - r0) partial sums
   int* mlist = nullptr;
+  int nmf = 0;                          // faces to another degree (own side)
+  int* mftask = nullptr;                // [nmf] e * 6 + phi
+  int* mfmap = nullptr;                 // [nm][6] face task of (list element, phi), or -1
+  double* mfres = nullptr;              // [nrhs][nmf][4][81] face results
   double* muf = nullptr;                // [E][6] mu_F nu
   // geometry
   double *X = nullptr, *G = nullptr, *WJ = nullptr, *ws = nullptr, *pen = nullptr;
@@ -243,6 +247,7 @@ struct Solver {
       m.nel = L.nm; m.elist = L.mlist; m.nrhs = nrhs; m.ndof = L.ndof; m.u = u; m.out = out; m.mode = mode;
       m.deg = L.deg; m.off = L.off; m.offF = L.offF; m.nbr = nbr; m.ws = L.ws; m.muf = L.muf;
       m.Dall = Dall; m.Iall = Iall;
+      m.nface = L.nmf; m.ftask = L.mftask; m.fmap = L.mfmap; m.fres = L.mfres;
       if constexpr (sizeof(T) == 8) m.G = L.G;
       else m.G = L.G32;
       sipg_mortar<T>(m, st);
@@ -872,7 +877,24 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       if (any) ml.push_back(e);
     }
     L.nm = (int)ml.size();
-    if (L.nm) L.mlist = s.own(upload(ml, st));
+    if (L.nm) {
+      L.mlist = s.own(upload(ml, st));
+      std::vector<int> ft, fm((size_t)L.nm * 6, -1);
+      for (int li = 0; li < L.nm; ++li) {
+        const int e = ml[li];
+        for (int f = 0; f < 6; ++f) {
+          const int en = s.h_nbr[e * 6 + f];
+          if (en >= 0 && deg[en] != deg[e]) {
+            fm[(size_t)li * 6 + f] = (int)ft.size();
+            ft.push_back(e * 6 + f);
+          }
+        }
+      }
+      L.nmf = (int)ft.size();
+      L.mftask = s.own(upload(ft, st));
+      L.mfmap = s.own(upload(fm, st));
+      L.mfres = s.own(dalloc<double>((size_t)s.nrhs * L.nmf * 4 * 81));
+    }
   }
   // geometry per bucket
   L.G = s.own(dalloc<double>(6 * L.ndof));
