@@ -19,7 +19,9 @@ namespace dgfas {
 
 namespace {
 
-constexpr int kMaxN = 9, kMaxN2 = 81, kMaxN3 = 729, kMortarThreads = 256;
+constexpr int kMaxN = 9, kMaxN2 = 81, kMortarThreads = 256;
+// face kernel: one thread per face node of both sides in its first phases (n^2 + nn^2 <= 162)
+constexpr int kFaceThreads = 192;
 
 __device__ __forceinline__ int fnode(int n, int phi, int f, int t) {
   const int a = f / n, b = f - a * n, ax = phi >> 1;
@@ -55,7 +57,7 @@ constexpr int kFaceRes = 4 * kMaxN2;
 
 // One workgroup per (face between degrees, right-hand side): phases 0 to F of the face.
 template <typename T>
-__global__ void __launch_bounds__(kMortarThreads) mortar_face_kernel(MortarArgs<T> a) {
+__global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T> a) {
   const int lbr = xcd_block(a.nface * a.nrhs);
   if (lbr < 0) return;
   const int task = lbr / a.nrhs, rhs = lbr - task * a.nrhs;
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(kMortarThreads) mortar_face_kernel(MortarArgs<
     for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + base + vi];
     wsv = (T)a.ws[fbase + phi * n2 + f];
   }
-  for (int t = tid; t < kMaxN2; t += kMortarThreads) {
+  for (int t = tid; t < kMaxN2; t += kFaceThreads) {
     if (t < n2) sDo[t] = (T)a.Dall[(po - 1) * kMaxN2 + t];
     if (t < nn2) sDn[t] = (T)a.Dall[(pn - 1) * kMaxN2 + t];
     if (t < nF * n) sIo[t] = (T)a.Iall[((po - 1) * 8 + (pF - 1)) * kMaxN2 + t];     // nF x n
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(kMortarThreads) mortar_face_kernel(MortarArgs<
   else if (nb_t) qn[f] = face_flux<T>(nn, phin, f, sDn, tn, dnn, gn, -sgn, inv_wend_n, wsn[f]);
   __syncthreads();
   // C: first interpolation step X1[i][b] = sum_a I[i][a] X[a][b] for the four face fields
-  for (int t = tid; t < 2 * nF * n + 2 * nF * nn; t += kMortarThreads) {
+  for (int t = tid; t < 2 * nF * n + 2 * nF * nn; t += kFaceThreads) {
     int s = t, which, w;
     if (s < 2 * nF * n) { which = s / (nF * n); s -= which * nF * n; w = n; }
     else { s -= 2 * nF * n; which = 2 + s / (nF * nn); s -= (which - 2) * nF * nn; w = nn; }
@@ -156,7 +158,7 @@ __global__ void __launch_bounds__(kMortarThreads) mortar_face_kernel(MortarArgs<
   }
   __syncthreads();
   // D: second step and the differences on the finer grid
-  for (int t = tid; t < nF2; t += kMortarThreads) {
+  for (int t = tid; t < nF2; t += kFaceThreads) {
     const int i = t / nF, j = t - i * nF;
     T t_o = 0, q_o = 0, t_n = 0, q_n = 0;
     for (int b = 0; b < n; ++b) {
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__(kMortarThreads) mortar_face_kernel(MortarArgs<
   }
   __syncthreads();
   // E: restriction, first step Y1[a][j] = sum_i I[i][a] F[i][j]
-  for (int t = tid; t < 2 * n * nF; t += kMortarThreads) {
+  for (int t = tid; t < 2 * n * nF; t += kFaceThreads) {
     const int which = t / (n * nF), s = t - which * n * nF;
     const int aa = s / nF, j = s - aa * nF;
     const T* F = which == 0 ? rF : sF;
@@ -188,7 +190,7 @@ __global__ void __launch_bounds__(kMortarThreads) mortar_face_kernel(MortarArgs<
   __syncthreads();
   // F: second step; the lifting weight divided by the own omega s times the own metric row;
   // row and lifting rows go to the face's result slot
-  for (int t = tid; t < n2; t += kMortarThreads) {
+  for (int t = tid; t < n2; t += kFaceThreads) {
     const int aa = t / n, b = t - aa * n;
     T r = 0, sgm = 0;
     for (int j = 0; j < nF; ++j) {
@@ -261,7 +263,7 @@ __global__ void __launch_bounds__(kMortarThreads) mortar_gather_kernel(MortarArg
 template <typename T>
 void sipg_mortar(const MortarArgs<T>& a, hipStream_t st) {
   if (a.nel <= 0 || a.nface <= 0) return;
-  hipLaunchKernelGGL((mortar_face_kernel<T>), dim3(xcd_grid(a.nface * a.nrhs)), dim3(kMortarThreads), 0, st, a);
+  hipLaunchKernelGGL((mortar_face_kernel<T>), dim3(xcd_grid(a.nface * a.nrhs)), dim3(kFaceThreads), 0, st, a);
   hipLaunchKernelGGL((mortar_gather_kernel<T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(kMortarThreads), 0, st, a);
 }
 
