@@ -151,6 +151,10 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   }
   __syncthreads();
 
+  // a wavefront is one xi_3 layer when N^2 = 64: D[k][m] and D[m][k] are then uniform and
+  // come through the scalar cache instead of LDS
+  constexpr bool kLayer = N * N == 64 && EPB == 1;
+  const int ku = kLayer ? __builtin_amdgcn_readfirstlane(k) : k;
   // phase 1: reference derivatives and contravariant fluxes F_b = sum_c G_bc d_c u
   if (active) {
     T d0 = 0, d1 = 0, d2 = 0;
@@ -158,7 +162,7 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     for (int m = 0; m < N; ++m) {
       d0 += sDT[m * N + i] * su[le][(k * N + j) * P + m];
       d1 += sDT[m * N + j] * su[le][(k * N + m) * P + i];
-      d2 += sDT[m * N + k] * su[le][(m * N + j) * P + i];
+      d2 += (kLayer ? Dg[ku * N + m] : sDT[m * N + k]) * su[le][(m * N + j) * P + i];
     }
     sF[le][0][lnode] = gl[0] * d0 + gl[1] * d1 + gl[2] * d2;
     sF[le][1][lnode] = gl[1] * d0 + gl[3] * d1 + gl[4] * d2;
@@ -232,7 +236,7 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     for (int m = 0; m < N; ++m) {
       acc += sD[m * N + i] * sF[le][0][(k * N + j) * P + m];
       acc += sD[m * N + j] * sF[le][1][(k * N + m) * P + i];
-      acc += sD[m * N + k] * sF[le][2][(m * N + j) * P + i];
+      acc += (kLayer ? Dg[m * N + ku] : sD[m * N + k]) * sF[le][2][(m * N + j) * P + i];
     }
     if (WJ) acc += kappa * WJ[base + node] * uval;
     out[base + node] = mode == 0 ? gval - acc : acc;
