@@ -87,14 +87,23 @@ def _check(code, warn_ok=False):
     raise DgfasError(code, _lib.dgfas_last_error().decode())
 
 
-def _ptr(t):
+def _dev(t, n, name, dtype='float64'):
+    """Device pointer of a contiguous GPU tensor of `dtype` with at least n elements (None
+    passes through): the kernels take the pointer as it is, so a host tensor, another dtype
+    or a short vector is refused here rather than read out of bounds on the device."""
     if t is None:
         return None
-    if hasattr(t, 'data_ptr'):
-        if not t.is_contiguous():
-            raise ValueError('tensor must be contiguous')
-        return t.data_ptr()
-    raise TypeError('expected a torch tensor')
+    if not hasattr(t, 'data_ptr') or not hasattr(t, 'is_cuda'):
+        raise TypeError('%s: expected a torch tensor' % name)
+    if not t.is_cuda:
+        raise ValueError('%s: expected a device tensor' % name)
+    if str(t.dtype) != 'torch.' + dtype:
+        raise TypeError('%s: expected %s, got %s' % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError('%s: tensor must be contiguous' % name)
+    if t.numel() < n:
+        raise ValueError('%s: %d elements, at least %d needed' % (name, t.numel(), n))
+    return t.data_ptr()
 
 
 def default_options(**kw):
@@ -147,6 +156,14 @@ class Solver:
         nl = _I()
         _check(_lib.dgfas_levels(self._h, ctypes.byref(nl)))
         self.n_levels = nl.value
+        self.n_rhs = int(self.options.n_rhs)
+        self._ndof = {l: self.level_info(l)[1] for l in range(1, self.n_levels + 1)}
+
+    def _n(self, level):
+        """Elements of a vector argument on `level`: n_rhs * n_dof."""
+        if level not in self._ndof:
+            raise ValueError('level %d outside 1..%d' % (level, self.n_levels))
+        return self.n_rhs * self._ndof[level]
 
     def close(self):
         if getattr(self, '_h', None):
@@ -166,43 +183,51 @@ class Solver:
         return d.value, nd.value
 
     def rhs(self, f, b, uD=None, qN=None):
-        _check(_lib.dgfas_rhs(self._h, _ptr(f), _ptr(uD), _ptr(qN), _ptr(b)))
+        n = self._n(self.n_levels)
+        _check(_lib.dgfas_rhs(self._h, _dev(f, n, 'f'), _dev(uD, n, 'uD'), _dev(qN, n, 'qN'), _dev(b, n, 'b')))
 
     def apply(self, level, u, Au):
-        _check(_lib.dgfas_apply(self._h, level, _ptr(u), _ptr(Au)))
+        n = self._n(level)
+        _check(_lib.dgfas_apply(self._h, level, _dev(u, n, 'u'), _dev(Au, n, 'Au')))
 
     def residual(self, level, u, g, r):
-        _check(_lib.dgfas_residual(self._h, level, _ptr(u), _ptr(g), _ptr(r)))
+        n = self._n(level)
+        _check(_lib.dgfas_residual(self._h, level, _dev(u, n, 'u'), _dev(g, n, 'g'), _dev(r, n, 'r')))
 
     def schwarz(self, level, r, z):
-        _check(_lib.dgfas_schwarz(self._h, level, _ptr(r), _ptr(z)))
+        n = self._n(level)
+        _check(_lib.dgfas_schwarz(self._h, level, _dev(r, n, 'r'), _dev(z, n, 'z')))
 
     def smooth(self, level, u, g, n_steps):
-        _check(_lib.dgfas_smooth(self._h, level, _ptr(u), _ptr(g), n_steps))
+        n = self._n(level)
+        _check(_lib.dgfas_smooth(self._h, level, _dev(u, n, 'u'), _dev(g, n, 'g'), n_steps))
 
     def restrict(self, level, r_fine, r_coarse):
-        _check(_lib.dgfas_restrict(self._h, level, _ptr(r_fine), _ptr(r_coarse)))
+        nf, nc = self._n(level), self._n(level - 1)
+        _check(_lib.dgfas_restrict(self._h, level, _dev(r_fine, nf, 'r_fine'), _dev(r_coarse, nc, 'r_coarse')))
 
     def project(self, level, u_fine, u_coarse):
-        _check(_lib.dgfas_project(self._h, level, _ptr(u_fine), _ptr(u_coarse)))
+        nf, nc = self._n(level), self._n(level - 1)
+        _check(_lib.dgfas_project(self._h, level, _dev(u_fine, nf, 'u_fine'), _dev(u_coarse, nc, 'u_coarse')))
 
     def prolong_add(self, level, u_coarse, u_fine, ubar=None):
-        _check(_lib.dgfas_prolong_add(self._h, level, _ptr(u_coarse), _ptr(ubar), _ptr(u_fine)))
+        nf, nc = self._n(level), self._n(level - 1)
+        _check(_lib.dgfas_prolong_add(self._h, level, _dev(u_coarse, nc, 'u_coarse'), _dev(ubar, nc, 'ubar'),
+                                      _dev(u_fine, nf, 'u_fine')))
 
     def root_solve(self, u, g):
+        n = self._n(1)
         it = _I()
-        _check(_lib.dgfas_root_solve(self._h, _ptr(u), _ptr(g), ctypes.byref(it)))
+        _check(_lib.dgfas_root_solve(self._h, _dev(u, n, 'u'), _dev(g, n, 'g'), ctypes.byref(it)))
         return it.value
 
     def vcycle(self, u, f):
-        _check(_lib.dgfas_vcycle(self._h, _ptr(u), _ptr(f)))
+        n = self._n(self.n_levels)
+        _check(_lib.dgfas_vcycle(self._h, _dev(u, n, 'u'), _dev(f, n, 'f')))
 
     def solve(self, u, f, max_cycles=30, rtol=1e-10):
-        hist = np.zeros(max_cycles + 1)
-        nd = _I()
-        code = _check(_lib.dgfas_solve(self._h, _ptr(u), _ptr(f), max_cycles, rtol, hist.ctypes.data_as(c_dp),
-                                       ctypes.byref(nd)), warn_ok=True)
-        return hist[:nd.value + 1], code == DGFAS_OK
+        hist, code = solve_status(self, u, f, max_cycles, rtol)
+        return hist, code == DGFAS_OK
 
     def autotune(self, cache_path=None, reps=10):
         """Time per-degree against one-launch batches per level and stage (see dgfas_autotune);
@@ -215,7 +240,7 @@ class Solver:
     def norm(self, level, v):
         """Euclidean norm per right-hand side (numpy array of n_rhs values)."""
         out = np.zeros(self.options.n_rhs)
-        _check(_lib.dgfas_norm(self._h, level, _ptr(v), out.ctypes.data_as(c_dp)))
+        _check(_lib.dgfas_norm(self._h, level, _dev(v, self._n(level), 'v'), out.ctypes.data_as(c_dp)))
         return out
 
 
@@ -272,16 +297,23 @@ class Mlp:
         _check(_lib.dgfas_mlp_set_params(self._h, theta.ctypes.data))
 
     def forward(self, X, Y):
-        _check(_lib.dgfas_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(Y)))
+        rows = X.shape[0]
+        _check(_lib.dgfas_mlp_forward(self._h, _dev(X, rows * self.n_in, 'X', 'float32'), rows,
+                                      _dev(Y, rows * self.n_out, 'Y', 'float32')))
 
     def gradient(self, X, T, grad=None):
+        rows = X.shape[0]
         loss = ctypes.c_double()
-        _check(_lib.dgfas_mlp_gradient(self._h, _ptr(X), _ptr(T), X.shape[0], _ptr(grad), ctypes.byref(loss)))
+        _check(_lib.dgfas_mlp_gradient(self._h, _dev(X, rows * self.n_in, 'X', 'float32'),
+                                       _dev(T, rows * self.n_out, 'T', 'float32'), rows,
+                                       _dev(grad, self.n_params, 'grad', 'float32'), ctypes.byref(loss)))
         return loss.value
 
     def train(self, X, T, batch, steps, lr0=1e-3, lr_min=1e-5, total_steps=None):
+        rows = X.shape[0]
         losses = np.zeros(max(steps, 1))
-        _check(_lib.dgfas_mlp_train(self._h, _ptr(X), _ptr(T), X.shape[0], batch, steps, lr0, lr_min,
+        _check(_lib.dgfas_mlp_train(self._h, _dev(X, rows * self.n_in, 'X', 'float32'),
+                                    _dev(T, rows * self.n_out, 'T', 'float32'), rows, batch, steps, lr0, lr_min,
                                     total_steps or steps, losses.ctypes.data_as(c_dp)))
         return losses[:steps]
 
@@ -307,7 +339,10 @@ def learned_pairs(solver, r, centers, X, T):
     """Training pairs for the listed centre elements (numpy int array); returns PCG iterations."""
     c = np.ascontiguousarray(centers, dtype=np.int32)
     it = _I()
-    _check(_lib.dgfas_learned_pairs(solver._h, _ptr(r), c.ctypes.data, len(c), _ptr(X), _ptr(T), ctypes.byref(it)))
+    ns3 = T.shape[-1] if T.dim() == 2 else T.numel() // max(len(c), 1)
+    _check(_lib.dgfas_learned_pairs(solver._h, _dev(r, solver._n(solver.n_levels), 'r'), c.ctypes.data, len(c),
+                                    _dev(X, len(c) * (ns3 + 9), 'X', 'float32'), _dev(T, len(c) * ns3, 'T', 'float32'),
+                                    ctypes.byref(it)))
     return it.value
 
 
@@ -315,6 +350,7 @@ def solve_status(solver, u, f, max_cycles=30, rtol=1e-10):
     """Like Solver.solve but also returns the status code (0 ok, 1 not converged, 2 fallback)."""
     hist = np.zeros(max_cycles + 1)
     nd = _I()
-    code = _check(_lib.dgfas_solve(solver._h, _ptr(u), _ptr(f), max_cycles, rtol, hist.ctypes.data_as(c_dp),
-                                   ctypes.byref(nd)), warn_ok=True)
+    n = solver._n(solver.n_levels)
+    code = _check(_lib.dgfas_solve(solver._h, _dev(u, n, 'u'), _dev(f, n, 'f'), max_cycles, rtol,
+                                   hist.ctypes.data_as(c_dp), ctypes.byref(nd)), warn_ok=True)
     return hist[:nd.value + 1], code

@@ -80,3 +80,14 @@ def test_argument_errors_are_reported_without_gpu(lib):
     assert ei.value.code == lib.DGFAS_EINVAL
     with pytest.raises(lib.DgfasError):
         lib.schwarz_tables_1d(4, 5, 0, 0, 2.0)
+
+
+def test_binding_refuses_host_and_non_tensor_vectors(lib):
+    """Vector arguments go to the kernels as raw device pointers: a host tensor or a
+    non-tensor is refused in the binding before any call."""
+    torch = pytest.importorskip('torch')
+    with pytest.raises(ValueError):
+        lib._dev(torch.zeros(8, dtype=torch.float64), 8, 'u')
+    with pytest.raises(TypeError):
+        lib._dev(np.zeros(8), 8, 'u')
+    assert lib._dev(None, 8, 'u') is None
