@@ -118,17 +118,18 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     sDT[(tid % N) * N + tid / N] = dv;
   }
   if (active) su[le][lnode] = uval;
-  // phase 0: neighbour data of every face node: trace, normal derivative and metric row
-  T dn_nb[TPT], gn[TPT][3];
+  // phase 0: the neighbour data of every face node (normal node line and metric row) is
+  // loaded into registers here and used after the volume phase, which hides its latency
+  T lnv[TPT][N], gn[TPT][3];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     const int t = node + k * N3;
-    dn_nb[k] = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) lnv[k][m] = 0;
     gn[k][0] = gn[k][1] = gn[k][2] = 0;
     if (!active || t >= 6 * N2) continue;
     const int phi = t / N2, f = t - phi * N2, ax = phi >> 1;
     const int en = en_t[k];
-    T tr = 0;
     if (en >= 0) {
       const int phio = phi ^ 1;
       const int endo = (phio & 1) ? N - 1 : 0;
@@ -138,16 +139,9 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
       const int64_t gi = nbase + face_node<N>(phio, f, endo);
 #pragma unroll
       for (int c = 0; c < 3; ++c) gn[k][c] = G[sym_index(ax, c) * ndof + gi];
-      T dn = 0;
 #pragma unroll
-      for (int m = 0; m < N; ++m) {
-        const T v = line[m * st];
-        dn += Dg[endo * N + m] * v;
-        if (m == endo) tr = v;
-      }
-      dn_nb[k] = dn;
+      for (int m = 0; m < N; ++m) lnv[k][m] = line[m * st];
     }
-    sTr[le][phi][(f / N) * P + f % N] = tr;
   }
   __syncthreads();
 
@@ -167,6 +161,28 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     sF[le][0][lnode] = gl[0] * d0 + gl[1] * d1 + gl[2] * d2;
     sF[le][1][lnode] = gl[1] * d0 + gl[3] * d1 + gl[4] * d2;
     sF[le][2][lnode] = gl[2] * d0 + gl[4] * d1 + gl[5] * d2;
+  }
+  // the neighbour's trace and normal derivative at every face node
+  T dn_nb[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int t = node + k * N3;
+    dn_nb[k] = 0;
+    if (!active || t >= 6 * N2) continue;
+    const int phi = t / N2, f = t - phi * N2;
+    T tr = 0;
+    if (en_t[k] >= 0) {
+      const int endo = ((phi ^ 1) & 1) ? N - 1 : 0;
+      T dn = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        const T v = lnv[k][m];
+        dn += Dg[endo * N + m] * v;
+        if (m == endo) tr = v;
+      }
+      dn_nb[k] = dn;
+    }
+    sTr[le][phi][(f / N) * P + f % N] = tr;
   }
   __syncthreads();
 
