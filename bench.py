@@ -346,37 +346,27 @@ def main():
 
     t10 = {}
     if not args.no_t10:
-        hist, ok = lib.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
-        torch.cuda.synchronize()
-        t_a = time.perf_counter()
-        hist, ok = lib.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
-        torch.cuda.synchronize()
-        t10['fp64'] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1, 'converged': bool(ok),
-                       'final_rho': float(hist[-1])}
-        print('t10 fp64', t10['fp64'], file=sys.stderr, flush=True)
-        lib.close()
-        opts32 = B.default_options(precision=B.FP32, **cyc)
-        lib32 = B.Solver(np.full(E, p, np.int32), X, nbr, bc, opts32, stream=stream.cuda_stream)
-        hist, ok = lib32.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
-        torch.cuda.synchronize()
-        t_a = time.perf_counter()
-        hist, ok = lib32.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
-        torch.cuda.synchronize()
-        t10['fp32_smoother'] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1,
-                                'converged': bool(ok), 'final_rho': float(hist[-1])}
-        print('t10 fp32', t10['fp32_smoother'], file=sys.stderr, flush=True)
-        lib32.close()
-        optsb = B.default_options(precision=B.BF16, **cyc)
-        libb = B.Solver(np.full(E, p, np.int32), X, nbr, bc, optsb, stream=stream.cuda_stream)
-        hist, ok = libb.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
-        torch.cuda.synchronize()
-        t_a = time.perf_counter()
-        hist, ok = libb.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
-        torch.cuda.synchronize()
-        t10['bf16_matrix_core_smoother'] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1,
-                                            'converged': bool(ok), 'final_rho': float(hist[-1])}
-        print('t10 bf16', t10['bf16_matrix_core_smoother'], file=sys.stderr, flush=True)
-        libb.close()
+        def time_to_tol(solver, key):
+            hist, ok = solver.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+            torch.cuda.synchronize()
+            t_a = time.perf_counter()
+            hist, ok = solver.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+            torch.cuda.synchronize()
+            t10[key] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1, 'converged': bool(ok),
+                        'final_rho': float(hist[-1])}
+            print('t10', key, t10[key], file=sys.stderr, flush=True)
+            solver.close()
+
+        time_to_tol(lib, 'fp64')
+        # the other forms of the same cycle: FP32 / BF16 smoothing of the correction system, and
+        # a fixed 16-iteration root solve with every cycle replayed as one captured HIP graph
+        fixed = dict(cyc, root_rtol=0.0, root_max_iter=16, graph=1)
+        for key, kw in (('fp32_smoother', dict(cyc, precision=B.FP32)),
+                        ('bf16_matrix_core_smoother', dict(cyc, precision=B.BF16)),
+                        ('fp64_fixed_root16_whole_cycle_graph', fixed),
+                        ('fp32_smoother_fixed_root16_whole_cycle_graph', dict(fixed, precision=B.FP32))):
+            time_to_tol(B.Solver(np.full(E, p, np.int32), X, nbr, bc, B.default_options(**kw),
+                                 stream=stream.cuda_stream), key)
     else:
         lib.close()
 

@@ -82,7 +82,9 @@ typedef struct {
   int32_t smoother;         /* DGFAS_WAS (Alg. 5) or DGFAS_SCG (Alg. 6) on levels > 1 */
   int32_t ns1, ns2;         /* pre- and post-smoothing steps (Alg. 2) */
   int32_t root_max_iter;    /* SCG iteration cap of the root solve */
-  double root_rtol;         /* root SCG stops when ||r|| <= root_rtol * ||r_0|| */
+  double root_rtol;         /* root SCG stops when ||r|| <= root_rtol * ||r_0||; 0: exactly
+                               root_max_iter iterations with no convergence test (no host
+                               synchronisation: with graph = 1 the whole cycle is one graph) */
   int32_t precision;        /* DGFAS_FP64, or DGFAS_FP32: smoothing of the correction system
                                (eq. smoothers:system:correction) in FP32 on levels > 1 with the
                                FAS residual, tau-correction and root solve in FP64, or DGFAS_BF16:
@@ -98,8 +100,9 @@ typedef struct {
                                Levels with one degree always take one launch per stage */
   int32_t graph;            /* 1: dgfas_solve replays each V-cycle's smoothing and transfer legs
                                as two captured HIP graphs (the root solve between them runs
-                               eagerly); results are bitwise those of the eager cycle.  Not with
-                               the learned correction */
+                               eagerly), or the whole cycle as one graph when root_rtol = 0;
+                               results are bitwise those of the eager cycle.  Not with the
+                               learned correction */
   int32_t order;            /* element processing order of the sweep kernels: DGFAS_ORDER_NATURAL
                                (element index) or DGFAS_ORDER_MORTON (Morton order of the element
                                centroids, so that concurrently running workgroups of one XCD take
@@ -165,7 +168,8 @@ dgfas_status dgfas_prolong_add(dgfas_solver s, int32_t level, const double* u_co
                                const double* ubar_coarse, double* u_fine);
 
 /* Root solve on level 1: SCG (Alg. 6) from u until ||r|| <= root_rtol ||r_0|| or
- * root_max_iter iterations; iters (host, may be NULL) receives the count.  Synchronous. */
+ * root_max_iter iterations (root_rtol = 0: exactly root_max_iter, asynchronous); iters
+ * (host, may be NULL) receives the count.  Synchronous when root_rtol > 0. */
 dgfas_status dgfas_root_solve(dgfas_solver s, double* u, const double* g, int32_t* iters);
 
 /* One FAS V-cycle (Alg. 2, global p-coarsening) on the finest-level u for rhs f. */

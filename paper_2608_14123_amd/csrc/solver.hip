@@ -560,8 +560,13 @@ struct Solver {
     }
   }
 
+  // root_rtol = 0: exactly root_max_iter SCG iterations with no convergence test, so the root
+  // solve needs no host synchronisation and the whole cycle can be captured as one graph
+  bool fixed_root() const { return opt.root_rtol == 0.0; }
+
   int root_solve(double* u, const double* g, bool* breakdown) {
     Level& L = lv[0];
+    if (fixed_root()) return scg<double>(L, u, g, opt.root_max_iter, {}, breakdown);
     residual(L, u, g, L.r);
     std::vector<double> rmax = dots_sync(L, L.r, L.r);
     bool any = false;
@@ -591,20 +596,24 @@ struct Solver {
     T.g = const_cast<double*>(g_save);
   }
 
-  // The same cycle with both legs replayed from captured graphs (bitwise the same work).
+  // The same cycle with both legs replayed from captured graphs (bitwise the same work); with
+  // a fixed-iteration root solve the whole cycle is one graph.
   void vcycle_graphed(double* u_top, const double* f_top) {
     if (!gdown || gu != u_top || gf != f_top || graph_built_epoch != graph_epoch || graph_hint != rhint)
       build_graphs(u_top, f_top);
     rhint = false;
-    bool bd = false;
     HIPC(hipGraphLaunch(gdown, st));
-    root_solve(lv[0].u, lv[0].g, &bd);
-    HIPC(hipGraphLaunch(gup, st));
+    if (!fixed_root()) {
+      bool bd = false;
+      root_solve(lv[0].u, lv[0].g, &bd);
+      HIPC(hipGraphLaunch(gup, st));
+    }
   }
 
   // every work vector a leg may touch, allocated before capture
   void prepare_legs() {
     const bool fp32 = opt.precision != DGFAS_FP64;
+    if (fixed_root()) ensure_scg_vectors(lv[0], false);
     for (size_t l = 1; l < lv.size(); ++l) {
       Level& L = lv[l];
       if (fp32) ensure_mixed_vectors(L);
@@ -628,12 +637,22 @@ struct Solver {
     const bool hint = rhint;   // the captured down leg starts from r, as the replays will
     st = cap;
     hipGraphExec_t* dst[2] = {&gdown, &gup};
+    const bool whole = fixed_root();
     try {
-      for (int leg = 0; leg < 2; ++leg) {
+      for (int leg = 0; leg < (whole ? 1 : 2); ++leg) {
         HIPC(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         try {
-          if (leg == 0) leg_down();
-          else leg_up();
+          if (whole) {
+            leg_down();
+            rhint = false;
+            bool bd = false;
+            root_solve(lv[0].u, lv[0].g, &bd);
+            leg_up();
+          } else if (leg == 0) {
+            leg_down();
+          } else {
+            leg_up();
+          }
         } catch (...) {
           hipGraph_t g = nullptr;
           hipStreamEndCapture(cap, &g);
@@ -1180,6 +1199,7 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
     throw Error(DGFAS_EUNSUPPORTED, "overlap 2 needs one degree, p = 4 or 8");
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
+  if (!(o->root_rtol >= 0) || !std::isfinite(o->root_rtol)) throw Error(DGFAS_EINVAL, "root_rtol must be >= 0");
   if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32 && o->precision != DGFAS_BF16)
     throw Error(DGFAS_EINVAL, "unknown precision");
   if (o->n_rhs < 1 || o->n_rhs > 64) throw Error(DGFAS_EINVAL, "n_rhs must be 1..64");

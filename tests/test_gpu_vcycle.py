@@ -76,3 +76,32 @@ def test_curved_history(binding, p, ne, amp, cycles):
     torch.cuda.synchronize()
     assert np.abs(u.cpu().numpy() - uo.ravel()).max() <= 1e-9 * np.abs(uo).max()
     lib.close()
+
+
+def test_fixed_iteration_root_history_and_whole_cycle_graph(binding):
+    """root_rtol = 0: the root solve takes exactly root_max_iter SCG iterations, as the oracle
+    does with a zero threshold; the cycle then needs no host synchronisation, and with
+    graph = 1 dgfas_solve replays it as one captured graph, bitwise the eager cycle."""
+    case = Case('curved', 4, 3, amp=0.03)
+    print('vcycle fixed root', flush=True)
+    lv = case.oracle_levels()
+    top = lv[-1].mesh
+    f = W.uniform_nodal(top.n_dof(), 2)
+    bo = oop.rhs(top, f)
+    cycles = 8
+    uo, ho = osv.solve(lv, np.zeros_like(bo), bo, osv.Options('scg', 3, 2, root_rtol=0.0, root_maxit=6),
+                       max_cycles=cycles, rtol=0.0)
+    res = []
+    for graph in (0, 1):
+        lib = case.library(binding, smoother=binding.SCG, ns1=3, ns2=2, root_rtol=0.0, root_max_iter=6, graph=graph)
+        b = torch.empty(top.n_dof(), dtype=torch.float64, device='cuda')
+        lib.rhs(dev(f), b)
+        u = torch.zeros_like(b)
+        hg, _ = lib.solve(u, b, max_cycles=cycles, rtol=0.0)
+        histories_agree(list(hg), ho)
+        torch.cuda.synchronize()
+        res.append((np.array(hg), u.cpu().numpy()))
+        lib.close()
+    assert np.abs(res[0][1] - uo.ravel()).max() <= 1e-9 * np.abs(uo).max()
+    for x, y in zip(*res):
+        assert np.array_equal(x, y)
