@@ -751,8 +751,11 @@ template <int NMAX, typename T>
 __global__ void __launch_bounds__((SzShape<NMAX, 1>::THREADS))
 schwarz_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
   __shared__ __align__(16) char smem[sz_smem_upto<T, NMAX>()];
-  const int t = xcd_block(ntiles);
-  if (t < 0) return;
+  // tiles dealt round-robin over the XCDs (the hardware order): the work list runs from the
+  // largest degree to the smallest, and contiguous ranges per XCD would leave one XCD all
+  // the large tiles
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
   {
     const int k = find_bucket(bd, nb, kStageSolve, t);
     SchwarzArgs<T> x = a;
@@ -781,8 +784,11 @@ template <int NMAX, typename T>
 __global__ void __launch_bounds__(AddShape<NMAX>::THREADS)
 overlap_add_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
   __shared__ AddSmem sm;
-  const int t = xcd_block(ntiles);
-  if (t < 0) return;
+  // tiles dealt round-robin over the XCDs (the hardware order): the work list runs from the
+  // largest degree to the smallest, and contiguous ranges per XCD would leave one XCD all
+  // the large tiles
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
   {
     const int k = find_bucket(bd, nb, kStageAdd, t);
     SchwarzArgs<T> x = a;
