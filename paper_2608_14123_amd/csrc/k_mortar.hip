@@ -8,7 +8,7 @@
 // nu n.grad xi_c, written into the transposed volume contractions as in sipg_apply.
 //
 // Two launches: one workgroup per (face between degrees, right-hand side) computes the
-// face's row and lifting terms on the own face grid into a result slot, then one workgroup
+// face's row and lifting terms on both sides' face grids into two result slots, then one workgroup
 // per (element, right-hand side) adds its faces' terms in face order, every output node
 // written by one thread, so the result is deterministic.  Degrees are runtime values; the
 // face's D and interpolation tables are staged in LDS.
@@ -51,11 +51,14 @@ __device__ T face_flux(int n, int phi, int f, const T* D, const T* tr, const T* 
   return sgn * inv_wend * fl / wsf;
 }
 
-// Face results per (right-hand side, face task): the row term and the three lifting rows
-// on the own element's face grid
+// Face results per (right-hand side, face side): the row term and the three lifting rows on
+// that side's face grid; a face task writes slot 2k (its own side) and 2k + 1 (the other)
 constexpr int kFaceRes = 4 * kMaxN2;
 
-// One workgroup per (face between degrees, right-hand side): phases 0 to F of the face.
+// One workgroup per (face between degrees, right-hand side): phases 0 to D of the face once,
+// then the restriction to both sides' grids.  Seen from the other side the jump and flux
+// differences change sign, so its finer-grid row and lifting fields are the negatives of
+// this side's: both sides get what a task of their own would compute.
 template <typename T>
 __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T> a) {
   const int lbr = xcd_block(a.nface * a.nrhs);
@@ -64,7 +67,8 @@ __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T>
   const int ep = a.ftask[task], e = ep / 6, phi = ep - e * 6;
   const int tid = threadIdx.x;
   const T* __restrict__ u = a.u + (int64_t)rhs * a.ndof;
-  T* __restrict__ res = reinterpret_cast<T*>(a.fres) + ((int64_t)rhs * a.nface + task) * kFaceRes;
+  T* __restrict__ res = reinterpret_cast<T*>(a.fres) + ((int64_t)rhs * 2 * a.nface + 2 * task) * kFaceRes;
+  T* __restrict__ resn = res + kFaceRes;
   const int po = a.deg[e], n = po + 1, n2 = n * n;
   const int64_t base = a.off[e], fbase = a.offF[e];
   const T inv_wend_o = (T)(0.5 * po * (po + 1));
@@ -74,7 +78,7 @@ __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T>
   __shared__ T tn[kMaxN2], dnn[kMaxN2], qn[kMaxN2], wsn[kMaxN2], gn[3][kMaxN2];
   __shared__ T x1[4][kMaxN2];                 // half-interpolated own t, own q, nb t, nb q
   __shared__ T rF[kMaxN2], sF[kMaxN2];        // row term and lifting weight on the finer grid
-  __shared__ T y1[2][kMaxN2];                 // half-restricted row and lifting weight
+  __shared__ T y1[4][kMaxN2];                 // half-restricted row and lifting weight, both sides
 
   const int en = a.nbr[(int64_t)e * 6 + phi];
   const int pn = a.deg[en];
@@ -178,29 +182,52 @@ __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T>
     sF[t] = T(-0.5) * wF * jt;
   }
   __syncthreads();
-  // E: restriction, first step Y1[a][j] = sum_i I[i][a] F[i][j]
-  for (int t = tid; t < 2 * n * nF; t += kFaceThreads) {
-    const int which = t / (n * nF), s = t - which * n * nF;
-    const int aa = s / nF, j = s - aa * nF;
-    const T* F = which == 0 ? rF : sF;
-    T v = 0;
-    for (int i = 0; i < nF; ++i) v += sIo[i * n + aa] * F[i * nF + j];
-    y1[which][aa * nF + j] = v;
+  // E: restriction, first step Y1[a][j] = sum_i I[i][a] F[i][j], own side (I = Io, F) and
+  // other side (I = In, -F)
+  for (int t = tid; t < 2 * n * nF + 2 * nn * nF; t += kFaceThreads) {
+    if (t < 2 * n * nF) {
+      const int which = t / (n * nF), s = t - which * n * nF;
+      const int aa = s / nF, j = s - aa * nF;
+      const T* F = which == 0 ? rF : sF;
+      T v = 0;
+      for (int i = 0; i < nF; ++i) v += sIo[i * n + aa] * F[i * nF + j];
+      y1[which][aa * nF + j] = v;
+    } else {
+      const int s0 = t - 2 * n * nF, which = s0 / (nn * nF), s = s0 - which * nn * nF;
+      const int aa = s / nF, j = s - aa * nF;
+      const T* F = which == 0 ? rF : sF;
+      T v = 0;
+      for (int i = 0; i < nF; ++i) v += sIn[i * nn + aa] * (-F[i * nF + j]);
+      y1[2 + which][aa * nF + j] = v;
+    }
   }
   __syncthreads();
-  // F: second step; the lifting weight divided by the own omega s times the own metric row;
-  // row and lifting rows go to the face's result slot
-  for (int t = tid; t < n2; t += kFaceThreads) {
-    const int aa = t / n, b = t - aa * n;
-    T r = 0, sgm = 0;
-    for (int j = 0; j < nF; ++j) {
-      const T ij = sIo[j * n + b];
-      r += y1[0][aa * nF + j] * ij;
-      sgm += y1[1][aa * nF + j] * ij;
+  // F: second step; the lifting weight divided by the side's omega s times its metric row
+  // (the other side's outward normal is -n); row and lifting rows go to the result slots
+  for (int t = tid; t < n2 + nn2; t += kFaceThreads) {
+    if (t < n2) {
+      const int aa = t / n, b = t - aa * n;
+      T r = 0, sgm = 0;
+      for (int j = 0; j < nF; ++j) {
+        const T ij = sIo[j * n + b];
+        r += y1[0][aa * nF + j] * ij;
+        sgm += y1[1][aa * nF + j] * ij;
+      }
+      res[t] = r;
+      const T sc = sgm / wso[t] * sgn * inv_wend_o;
+      for (int c = 0; c < 3; ++c) res[(1 + c) * kMaxN2 + t] = sc * go[c][t];
+    } else {
+      const int tn2 = t - n2, aa = tn2 / nn, b = tn2 - aa * nn;
+      T r = 0, sgm = 0;
+      for (int j = 0; j < nF; ++j) {
+        const T ij = sIn[j * nn + b];
+        r += y1[2][aa * nF + j] * ij;
+        sgm += y1[3][aa * nF + j] * ij;
+      }
+      resn[tn2] = r;
+      const T sc = sgm / wsn[tn2] * (-sgn) * inv_wend_n;
+      for (int c = 0; c < 3; ++c) resn[(1 + c) * kMaxN2 + tn2] = sc * gn[c][tn2];
     }
-    res[t] = r;
-    const T sc = sgm / wso[t] * sgn * inv_wend_o;
-    for (int c = 0; c < 3; ++c) res[(1 + c) * kMaxN2 + t] = sc * go[c][t];
   }
 }
 
@@ -215,7 +242,7 @@ __global__ void __launch_bounds__(kMortarThreads) mortar_gather_kernel(MortarArg
   const int e = a.elist[li];
   const int tid = threadIdx.x;
   T* __restrict__ out = a.out + (int64_t)rhs * a.ndof;
-  const T* __restrict__ fres = reinterpret_cast<const T*>(a.fres) + (int64_t)rhs * a.nface * kFaceRes;
+  const T* __restrict__ fres = reinterpret_cast<const T*>(a.fres) + (int64_t)rhs * 2 * a.nface * kFaceRes;
   const int po = a.deg[e], n = po + 1, n2 = n * n, n3 = n2 * n;
   const int64_t base = a.off[e];
 

@@ -114,10 +114,10 @@ struct MortarArgs {
   const double* muf = nullptr;      // [E][6] mu_F nu
   const double* Dall = nullptr;     // differentiation matrices of degrees 1..8, degree p at (p-1) * 81
   const double* Iall = nullptr;     // interpolation degree q -> r at ((q-1) * 8 + (r-1)) * 81
-  int nface = 0;                    // faces between degrees (one task per own side)
-  const int* ftask = nullptr;       // [nface] e * 6 + phi
-  const int* fmap = nullptr;        // [nel][6] task of face phi of the list's element, or -1
-  void* fres = nullptr;             // [nrhs][nface][4][81] T: row and lifting terms per face
+  int nface = 0;                    // faces between degrees (one task per face, both sides)
+  const int* ftask = nullptr;       // [nface] e * 6 + phi of the face's lower-id side
+  const int* fmap = nullptr;        // [nel][6] result slot of face phi of the list's element, or -1
+  void* fres = nullptr;             // [nrhs][2 nface][4][81] T: row and lifting terms per face side
 };
 template <typename T>
 void sipg_mortar(const MortarArgs<T>& a, hipStream_t st);

@@ -111,10 +111,10 @@ struct Level {
   int nla = 0;                          // overlap-add tiles per right-hand side (uniform levels)
   double* zpart = nullptr;              // [2][nrhs][nla] fused z^T r, z^T (r - r0) partial sums
   int* mlist = nullptr;
-  int nmf = 0;                          // faces to another degree (own side)
-  int* mftask = nullptr;                // [nmf] e * 6 + phi
-  int* mfmap = nullptr;                 // [nm][6] face task of (list element, phi), or -1
-  double* mfres = nullptr;              // [nrhs][nmf][4][81] face results
+  int nmf = 0;                          // faces to another degree (one task per face)
+  int* mftask = nullptr;                // [nmf] e * 6 + phi of the lower-id side
+  int* mfmap = nullptr;                 // [nm][6] result slot of (list element, phi), or -1
+  double* mfres = nullptr;              // [nrhs][2 nmf][4][81] face results per side
   double* muf = nullptr;                // [E][6] mu_F nu
   // geometry
   double *X = nullptr, *G = nullptr, *WJ = nullptr, *ws = nullptr, *pen = nullptr;
@@ -898,13 +898,18 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     L.nm = (int)ml.size();
     if (L.nm) {
       L.mlist = s.own(upload(ml, st));
-      std::vector<int> ft, fm((size_t)L.nm * 6, -1);
+      // one task per face, listed from its lower-id side; slot 2k is that side's result,
+      // 2k + 1 the other side's
+      std::vector<int> ft, fm((size_t)L.nm * 6, -1), lidx(E, -1);
+      for (int li = 0; li < L.nm; ++li) lidx[ml[li]] = li;
       for (int li = 0; li < L.nm; ++li) {
         const int e = ml[li];
         for (int f = 0; f < 6; ++f) {
           const int en = s.h_nbr[e * 6 + f];
-          if (en >= 0 && deg[en] != deg[e]) {
-            fm[(size_t)li * 6 + f] = (int)ft.size();
+          if (en >= 0 && deg[en] != deg[e] && e < en) {
+            const int k = (int)ft.size();
+            fm[(size_t)li * 6 + f] = 2 * k;
+            fm[(size_t)lidx[en] * 6 + (f ^ 1)] = 2 * k + 1;
             ft.push_back(e * 6 + f);
           }
         }
@@ -912,7 +917,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       L.nmf = (int)ft.size();
       L.mftask = s.own(upload(ft, st));
       L.mfmap = s.own(upload(fm, st));
-      L.mfres = s.own(dalloc<double>((size_t)s.nrhs * L.nmf * 4 * 81));
+      L.mfres = s.own(dalloc<double>((size_t)s.nrhs * 2 * L.nmf * 4 * 81));
     }
   }
   // geometry per bucket
