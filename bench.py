@@ -22,7 +22,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes of one residual launch of the operator kernel at 32^3, p = 7 from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a 1 GiB copy (profiles/c2_curved_p7_hbm_traffic_pmc.md);
 # valid only for the kernel source it was measured on.
-OPERATOR_TRAFFIC = {'sha256_prefix': 'bae852c451b5e621', 'bytes': 1.695e9, 'ne': 32, 'p': 7}
+OPERATOR_TRAFFIC = {'sha256_prefix': '766af14cbdda7b53', 'bytes': 1.675e9, 'ne': 32, 'p': 7}
 
 
 def parse():
