@@ -89,3 +89,36 @@ def test_batched_scg_vcycles(binding, stretched):
     for k in range(R):
         assert np.abs(got[k] - sols[k]).max() <= 1e-9 * np.abs(sols[k]).max()
     lib.close()
+
+
+@pytest.mark.parametrize('precision', ['fp32', 'bf16'])
+def test_batched_rhs_match_single_solves(binding, stretched, precision):
+    """A batch of right-hand sides with the reduced-precision smoother and the whole cycle as
+    one graph (fixed-iteration root): each right-hand side's iterate is bitwise the one of its
+    own single solve, and the history is the worst of theirs."""
+    print('batch single', precision, flush=True)
+    prec = binding.FP32 if precision == 'fp32' else binding.BF16
+    n = stretched.oracle_levels()[-1].mesh.n_dof()
+    f = np.stack([W.uniform_nodal(n, 4100 + k) for k in range(R)])
+    kw = dict(smoother=binding.SCG, ns1=3, ns2=2, root_rtol=0.0, root_max_iter=6, graph=1, precision=prec)
+    cycles = 3
+    singles, hists = [], []
+    for k in range(R):
+        lib = stretched.library(binding, **kw)
+        b = torch.empty(n, dtype=torch.float64, device='cuda')
+        lib.rhs(dev(f[k]), b)
+        u = torch.zeros_like(b)
+        h, _ = lib.solve(u, b, max_cycles=cycles, rtol=0.0)
+        singles.append(host(u).copy())
+        hists.append(h)
+        lib.close()
+    lib = stretched.library(binding, n_rhs=R, **kw)
+    b = torch.empty(R * n, dtype=torch.float64, device='cuda')
+    lib.rhs(dev(f), b)
+    u = torch.zeros_like(b)
+    hg, _ = lib.solve(u, b, max_cycles=cycles, rtol=0.0)
+    got = host(u).reshape(R, n)
+    for k in range(R):
+        assert np.array_equal(got[k], singles[k]), k
+    assert np.array_equal(hg, np.max(np.array(hists), axis=0))
+    lib.close()
