@@ -91,3 +91,18 @@ def test_binding_refuses_host_and_non_tensor_vectors(lib):
     with pytest.raises(TypeError):
         lib._dev(np.zeros(8), 8, 'u')
     assert lib._dev(None, 8, 'u') is None
+
+
+@pytest.mark.parametrize('bad', [dict(root_rtol=-1.0), dict(root_rtol=float('nan')), dict(precision=7),
+                                 dict(n_rhs=0), dict(batch=5), dict(root_max_iter=0), dict(graph=2)])
+def test_bad_options_are_refused_before_any_device_work(lib, bad):
+    """Options are validated on the host before the solver touches the device, so the
+    refusal is seen without a GPU."""
+    from paper_2608_14123_amd import workloads as W
+    ne, p = 2, 2
+    nbr, bc = W.box_topology(ne, ne, ne)
+    X = W.element_coords(W.box_vertices(ne, ne, ne), lib.gll(p)[0], lambda x: x)
+    o = lib.default_options(**bad)
+    with pytest.raises(lib.DgfasError) as ei:
+        lib.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc, o)
+    assert ei.value.code == lib.DGFAS_EINVAL
