@@ -439,23 +439,38 @@ __device__ __forceinline__ void overlap_add_tile(SchwarzArgs<T> a, const int lbr
   const int tid = threadIdx.x;
   int(&sOff)[27] = sm.sOff;
   if (tid < 27) sOff[tid] = R.off[tid];
-  __syncthreads();
   const int le = tid / N3, node = tid - le * N3;
   const int li = lb * EPB + le;
-  double pz = 0, pz2 = 0;
-  if (le < EPB && li < a.nel) {
-    const int e = a.elist ? a.elist[li] : li;
-    const int64_t gi = elem_base<N>(a, e) + node;
-    const int l[3] = {node % N, (node / N) % N, node / (N * N)};
+  const bool act = le < EPB && li < a.nel;
+  // the loads that need no region table go out ahead of the barrier
+  int64_t gi = 0;
+  int e = 0, l[3] = {0, 0, 0}, od[3] = {0, 0, 0};
+  bool any = false;
+  T z0 = 0;
+  double rv = 0, r0v = 0;
+  if (act) {
+    e = a.elist ? a.elist[li] : li;
+    gi = elem_base<N>(a, e) + node;
+    l[0] = node % N;
+    l[1] = (node / N) % N;
+    l[2] = node / (N * N);
     // per direction the offset towards the one neighbour whose overlap can cover this node
-    int od[3];
-    bool any = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       od[d] = (l[d] < M) ? -1 : ((l[d] >= N - M) ? 1 : 0);
       any = any || od[d] != 0;
     }
-    T zv = 0;
+    if (any || a.dotz) z0 = a.z[gi];
+    if (a.dotz) {
+      const int64_t ri = (int64_t)rhs * a.ndof + gi;
+      rv = (double)a.dr[ri];
+      if (a.dr0) r0v = (double)a.dr0[ri];
+    }
+  }
+  __syncthreads();
+  double pz = 0, pz2 = 0;
+  if (act) {
+    T zv = z0;
     if (any) {
       const T* __restrict__ box = a.O + inbox_base<N, M>(a, e);
       // the up to 7 candidates (subsets of the non-zero directions): every load is issued
@@ -482,16 +497,12 @@ __device__ __forceinline__ void overlap_add_tile(SchwarzArgs<T> a, const int lbr
       T acc = 0;
 #pragma unroll
       for (int t = 0; t < 7; ++t) acc += ok[t] ? vals[t] : T(0);
-      zv = a.z[gi] + acc;
+      zv = z0 + acc;
       a.z[gi] = zv;
-    } else if (a.dotz) {
-      zv = a.z[gi];
     }
     if (a.dotz) {
-      const int64_t ri = (int64_t)rhs * a.ndof + gi;
-      const double rv = (double)a.dr[ri];
       pz = (double)zv * rv;
-      if (a.dr0) pz2 = (double)zv * (rv - (double)a.dr0[ri]);
+      if (a.dr0) pz2 = (double)zv * (rv - r0v);
     }
   }
   if (a.dotz) {
