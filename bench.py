@@ -92,7 +92,9 @@ def front_bench(args, torch, B):
     f = torch.from_numpy(f_host).cuda()
     uD = torch.from_numpy(uD_host).cuda()
     modes = [('per_degree', dict(batch=B.BATCH_PER_DEGREE)), ('one_launch', dict(batch=B.BATCH_ONE_LAUNCH)),
-             ('tuned_graph', dict(batch=B.BATCH_TUNED, graph=1))]
+             ('tuned_graph', dict(batch=B.BATCH_TUNED, graph=1)),
+             # a fixed 16-iteration root solve: every cycle is one captured graph
+             ('tuned_whole_cycle_graph_fixed_root16', dict(batch=B.BATCH_TUNED, graph=1, root_max_iter=16))]
     out_modes = {}
     tune = None
 
@@ -110,12 +112,15 @@ def front_bench(args, torch, B):
         for prec in ('fp64', 'fp32'):
             if prec == 'fp32' and name != 'tuned_graph':
                 continue
-            o = B.default_options(precision=B.FP64 if prec == 'fp64' else B.FP32, **cyc, **extra)
+            kw = dict(cyc, **extra)
+            if name.endswith('fixed_root16'):
+                kw['root_rtol'] = 0.0
+            o = B.default_options(precision=B.FP64 if prec == 'fp64' else B.FP32, **kw)
             lib = B.Solver(degs, flat, nbr, bc, o, stream=stream.cuda_stream)
             L = lib.n_levels
-            if name == 'tuned_graph' and tune is None:
+            if name.startswith('tuned') and tune is None:
                 tune = lib.autotune(None, reps=10)
-            elif name == 'tuned_graph':
+            elif name.startswith('tuned'):
                 lib.autotune(None, reps=10)
             b = torch.empty_like(f)
             lib.rhs(f, b, uD=uD)
