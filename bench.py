@@ -205,8 +205,8 @@ def stretched_bench(args, torch, B):
         return ev0.elapsed_time(ev1) / reps
 
     modes = {}
-    for prec in ('fp64', 'fp32'):
-        o = B.default_options(precision=B.FP64 if prec == 'fp64' else B.FP32, **cyc)
+    for prec in ('fp64', 'fp32', 'fp32_matrix_cores'):
+        o = B.default_options(precision={'fp64': B.FP64, 'fp32': B.FP32, 'fp32_matrix_cores': B.FP32_MFMA}[prec], **cyc)
         t0 = time.perf_counter()
         lib = B.Solver(np.full(E, p, np.int32), X, nbr, bc, o, stream=stream.cuda_stream)
         torch.cuda.synchronize()
@@ -368,6 +368,7 @@ def main():
         fixed = dict(cyc, root_rtol=0.0, root_max_iter=16, graph=1)
         for key, kw in (('fp32_smoother', dict(cyc, precision=B.FP32)),
                         ('bf16_matrix_core_smoother', dict(cyc, precision=B.BF16)),
+                        ('fp32_matrix_core_smoother', dict(cyc, precision=B.FP32_MFMA)),
                         ('fp64_fixed_root16_whole_cycle_graph', fixed),
                         ('fp32_smoother_fixed_root16_whole_cycle_graph', dict(fixed, precision=B.FP32))):
             time_to_tol(B.Solver(np.full(E, p, np.int32), X, nbr, bc, B.default_options(**kw),

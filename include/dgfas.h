@@ -50,7 +50,7 @@ enum { DGFAS_INTERIOR = 0, DGFAS_DIRICHLET = 1, DGFAS_NEUMANN = 2,
           where the subdomain has no overlap (own half of the interior face terms) */
        DGFAS_INTERIOR_NO_OVERLAP = 3 };
 enum { DGFAS_WAS = 0, DGFAS_SCG = 1 };
-enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1, DGFAS_BF16 = 2 };
+enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1, DGFAS_BF16 = 2, DGFAS_FP32_MFMA = 3 };
 enum { DGFAS_BATCH_PER_DEGREE = 0, DGFAS_BATCH_ONE_LAUNCH = 1, DGFAS_BATCH_TUNED = 2 };
 enum { DGFAS_ORDER_NATURAL = 0, DGFAS_ORDER_MORTON = 1 };
 
@@ -89,7 +89,8 @@ typedef struct {
                                (eq. smoothers:system:correction) in FP32 on levels > 1 with the
                                FAS residual, tau-correction and root solve in FP64, or DGFAS_BF16:
                                as DGFAS_FP32 with the subdomain solves' tensor contractions on
-                               BF16 matrix cores (operands rounded to BF16, FP32 accumulation) */
+                               BF16 matrix cores (operands rounded to BF16, FP32 accumulation),
+                               or DGFAS_FP32_MFMA: the same contractions on FP32 matrix cores */
   int32_t n_rhs;            /* right-hand sides solved together, 1..64: every vector argument is then
                                [n_rhs][n_dof] (each right-hand side contiguous) and every SCG scalar is
                                kept per right-hand side; the geometry is shared */

@@ -22,7 +22,7 @@ DGFAS_OK, DGFAS_ENOTCONV = 0, 1
 DGFAS_EINVAL, DGFAS_ENOMEM, DGFAS_EHIP, DGFAS_EUNSUPPORTED, DGFAS_EBREAKDOWN = -1, -2, -3, -4, -5
 INTERIOR, DIRICHLET, NEUMANN = 0, 1, 2
 WAS, SCG = 0, 1
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, FP32_MFMA = 0, 1, 2, 3
 BATCH_PER_DEGREE, BATCH_ONE_LAUNCH, BATCH_TUNED = 0, 1, 2
 ORDER_NATURAL, ORDER_MORTON = 0, 1
 

@@ -172,9 +172,9 @@ void schwarz_solve(int p, int m, const SchwarzArgs<T>& a, hipStream_t st);
 template <typename T>
 void schwarz_overlap_add(int p, int m, const SchwarzArgs<T>& a, hipStream_t st);
 int overlap_size(int p, int m);
-// FP32 subdomain solve with the contractions on BF16 matrix cores (overlap 1); false when
-// the arguments ask for something it does not do (masked, weighted-off or learned solves)
-bool schwarz_solve_mfma(int p, int m, const SchwarzArgs<float>& a, hipStream_t st);
+// FP32 subdomain solve with the contractions on BF16 (bf16) or FP32 matrix cores (overlap 1);
+// false when the arguments ask for something it does not do (masked, weighted-off or learned)
+bool schwarz_solve_mfma(int p, int m, const SchwarzArgs<float>& a, bool bf16, hipStream_t st);
 template <typename T>
 void schwarz_solve_batched(int pmax, const SchwarzArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l,
                            hipStream_t st);

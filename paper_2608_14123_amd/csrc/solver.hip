@@ -206,7 +206,7 @@ struct Solver {
   bool use_batch(const Level& L, int stage) const {
     if (L.uniform || L.bk.size() < 2) return false;
     if (stage != kStageOp && opt.overlap != 1) return false;   // batched Schwarz tiles take m = 1
-    if (stage == kStageSolve && opt.precision == DGFAS_BF16) return false;   // matrix-core tiles per degree
+    if (stage == kStageSolve && matrix_cores()) return false;   // matrix-core tiles per degree
     if (force_batch >= 0) return force_batch == 1;
     if (opt.batch == DGFAS_BATCH_ONE_LAUNCH) return true;
     if (opt.batch == DGFAS_BATCH_TUNED) return L.one_launch[stage] != 0;
@@ -307,7 +307,7 @@ struct Solver {
       SchwarzArgs<T> a = sz_args<T>(L, b, r, z, mode);
       if (stage == kStageSolve) {
         if constexpr (sizeof(T) == 4) {
-          if (opt.precision == DGFAS_BF16 && schwarz_solve_mfma(b.p, b.t->m, a, st)) continue;
+          if (matrix_cores() && schwarz_solve_mfma(b.p, b.t->m, a, opt.precision == DGFAS_BF16, st)) continue;
         }
         schwarz_solve<T>(b.p, b.t->m, a, st);
       } else {
@@ -470,7 +470,8 @@ struct Solver {
         SchwarzArgs<T> a = sz_args<T>(L, L.bk[0], r, z, 0);
         if (with_net) add_learned(L, a, r);
         bool done = false;
-        if constexpr (sizeof(T) == 4) done = opt.precision == DGFAS_BF16 && schwarz_solve_mfma(L.p, L.m, a, st);
+        if constexpr (sizeof(T) == 4)
+          done = matrix_cores() && schwarz_solve_mfma(L.p, L.m, a, opt.precision == DGFAS_BF16, st);
         if (!done) schwarz_solve<T>(L.p, L.m, a, st);
         a.dr = r;
         a.dr0 = i > 1 ? r0 : nullptr;
@@ -563,6 +564,8 @@ struct Solver {
   // root_rtol = 0: exactly root_max_iter SCG iterations with no convergence test, so the root
   // solve needs no host synchronisation and the whole cycle can be captured as one graph
   bool fixed_root() const { return opt.root_rtol == 0.0; }
+  // FD contractions of the FP32 smoother on matrix cores (BF16 or FP32 operands)
+  bool matrix_cores() const { return opt.precision == DGFAS_BF16 || opt.precision == DGFAS_FP32_MFMA; }
 
   int root_solve(double* u, const double* g, bool* breakdown) {
     Level& L = lv[0];
@@ -1129,7 +1132,8 @@ void Solver::autotune(const char* path, int reps, double* report) {
       fill((int64_t)nv, x, 0.5, st);
       fill((int64_t)nv, y, 0.25, st);
       for (int sg = 0; sg < 3; ++sg) {
-        const std::string key = arch + "|" + L.hist + "|" + (opt.precision == DGFAS_BF16 ? "bf16" : (opt.precision == DGFAS_FP32 ? "fp32" : "fp64")) + "|rhs" +
+        static const char* const kPrec[4] = {"fp64", "fp32", "bf16", "fp32mfma"};
+        const std::string key = arch + "|" + L.hist + "|" + kPrec[opt.precision] + "|rhs" +
                                 std::to_string(nrhs) + "|" + stage_name[sg];
         if (sg != kStageOp && opt.overlap != 1) continue;
         auto it = cache.find(key);
@@ -1205,7 +1209,8 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
   if (!(o->root_rtol >= 0) || !std::isfinite(o->root_rtol)) throw Error(DGFAS_EINVAL, "root_rtol must be >= 0");
-  if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32 && o->precision != DGFAS_BF16)
+  if (o->precision != DGFAS_FP64 && o->precision != DGFAS_FP32 && o->precision != DGFAS_BF16 &&
+      o->precision != DGFAS_FP32_MFMA)
     throw Error(DGFAS_EINVAL, "unknown precision");
   if (o->n_rhs < 1 || o->n_rhs > 64) throw Error(DGFAS_EINVAL, "n_rhs must be 1..64");
   if (o->batch < DGFAS_BATCH_PER_DEGREE || o->batch > DGFAS_BATCH_TUNED) throw Error(DGFAS_EINVAL, "unknown batch mode");

@@ -30,10 +30,12 @@ def host(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize('smoother,steps', [('was', 2), ('scg', 3)])
-def test_fp32_smoothing_update_error(binding, smoother, steps):
+@pytest.mark.parametrize('smoother,steps,mfma', [('was', 2, False), ('scg', 3, False), ('was', 2, True),
+                                                 ('scg', 3, True)])
+def test_fp32_smoothing_update_error(binding, smoother, steps, mfma):
+    """FP32 smoothing on the vector unit or with the FD contractions on FP32 matrix cores."""
     case = Case('curved_p7', 7, 3, amp=0.03, mu_star=5.0)
-    print('fp32 smooth', smoother, flush=True)
+    print('fp32 smooth', smoother, 'mfma' if mfma else 'valu', flush=True)
     lv = case.oracle_levels()
     top = lv[-1]
     n = top.mesh.n_dof()
@@ -42,7 +44,8 @@ def test_fp32_smoothing_update_error(binding, smoother, steps):
     g = rng.uniform(-1, 1, n)
     shape = (top.mesh.E, top.mesh.n, top.mesh.n, top.mesh.n)
     ref = osv.smooth(top, u.reshape(shape), g.reshape(shape), steps, osv.Options(smoother, steps, steps)).ravel()
-    lib = case.library(binding, precision=binding.FP32, smoother=binding.SCG if smoother == 'scg' else binding.WAS)
+    lib = case.library(binding, precision=binding.FP32_MFMA if mfma else binding.FP32,
+                       smoother=binding.SCG if smoother == 'scg' else binding.WAS)
     ud = dev(u)
     lib.smooth(lib.n_levels, ud, dev(g), steps)
     du_gpu, du_ref = host(ud) - u, ref - u
@@ -52,16 +55,18 @@ def test_fp32_smoothing_update_error(binding, smoother, steps):
     lib.close()
 
 
-def test_fp32_solve_reaches_fp64_solution(binding):
+@pytest.mark.parametrize('mfma', [False, True])
+def test_fp32_solve_reaches_fp64_solution(binding, mfma):
     case = Case('curved_p4', 4, 3, amp=0.03, mu_star=5.0)
-    print('fp32 solve', flush=True)
+    print('fp32 solve', 'mfma' if mfma else 'valu', flush=True)
     lv = case.oracle_levels()
     top = lv[-1].mesh
     f = W.uniform_nodal(top.n_dof(), 2)
     bo = oop.rhs(top, f)
     opts = osv.Options('scg', 3, 2, root_rtol=1e-1)
     uo, ho = osv.solve(lv, np.zeros_like(bo), bo, opts, max_cycles=30)
-    lib = case.library(binding, precision=binding.FP32, smoother=binding.SCG, ns1=3, ns2=2, root_rtol=1e-1)
+    lib = case.library(binding, precision=binding.FP32_MFMA if mfma else binding.FP32, smoother=binding.SCG,
+                       ns1=3, ns2=2, root_rtol=1e-1)
     b = torch.empty(top.n_dof(), dtype=torch.float64, device='cuda')
     lib.rhs(dev(f), b)
     u = torch.zeros_like(b)
