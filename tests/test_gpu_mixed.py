@@ -108,11 +108,11 @@ def front_problem(case, lib_side, binding=None):
     return f, uD
 
 
-@pytest.mark.parametrize('precision', ['fp64', 'fp32', 'bf16'])
+@pytest.mark.parametrize('precision', ['fp64', 'fp32', 'bf16', 'fp32mfma'])
 def test_mixed_vcycle_history_and_solution(binding, precision):
     """FAS-MG-SCG(3,2) on a mixed 2^3 mesh: FP64 follows the oracle's history cycle by cycle;
-    every precision (BF16: matrix-core subdomain solves per degree bucket) reaches the direct
-    solution of the mixed system."""
+    every precision (BF16 and FP32 matrix cores: subdomain solves per degree bucket) reaches
+    the direct solution of the mixed system."""
     print('mixed vcycle', precision, flush=True)
     case = MixedCase('mixed_vc_2^3', 2, [4, 3, 3, 2, 3, 2, 2, 2])
     lv = case.oracle_levels()
@@ -122,7 +122,7 @@ def test_mixed_vcycle_history_and_solution(binding, precision):
     opts = osv.Options('scg', 3, 2, root_rtol=1e-1)
     cycles = 6
     uo, ho = mx.solve(lv, np.zeros_like(bo), bo, opts, max_cycles=cycles, rtol=0.0)
-    prec = {'fp64': binding.FP64, 'fp32': binding.FP32, 'bf16': binding.BF16}[precision]
+    prec = {'fp64': binding.FP64, 'fp32': binding.FP32, 'bf16': binding.BF16, 'fp32mfma': binding.FP32_MFMA}[precision]
     lib = case.library(binding, smoother=binding.SCG, ns1=3, ns2=2, root_rtol=1e-1, precision=prec)
     f, uD = front_problem(case, True, binding)
     b = torch.empty(top.n_dof(), dtype=torch.float64, device='cuda')
