@@ -18,6 +18,8 @@ void pupdate(int64_t n, int nrhs, const T* z, T* p, T* x, const double* scal, in
 // x += alpha p
 template <typename T>
 void xupdate(int64_t n, int nrhs, T* x, const T* p, const double* scal, hipStream_t st);
+// y += (double)(x + alpha p)
+void xupdate_acc(int64_t n, int nrhs, const float* x, const float* p, const double* scal, double* y, hipStream_t st);
 // rout = rin - alpha q with sum rout^2 partials
 template <typename T>
 void cg_update(int64_t n, int nrhs, const T* rin, T* rout, const T* q, const double* scal, double* partial,

@@ -241,6 +241,21 @@ __global__ void xupdate_kernel(int64_t n, int nrhs, T* __restrict__ x, const T* 
   x[i] += (T)scal[(i / n) * 8 + 2] * p[i];
 }
 
+// y += (double)(x + alpha p): the last SCG update of an FP32 correction added straight to the
+// FP64 iterate (the correction itself is not needed afterwards)
+__global__ void xupdate_acc_kernel(int64_t n, int nrhs, const float* __restrict__ x, const float* __restrict__ p,
+                                   const double* __restrict__ scal, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const float xn = x[i] + (float)scal[(i / n) * 8 + 2] * p[i];
+  y[i] = y[i] + (double)xn;
+}
+
+void xupdate_acc(int64_t n, int nrhs, const float* x, const float* p, const double* scal, double* y, hipStream_t st) {
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL(xupdate_acc_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, nrhs, x, p, scal, y);
+}
+
 // rout = rin - alpha q (rout may be rin); partial[rhs*1024 + blk] = sum rout^2 (partial null: no sums)
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)

@@ -439,7 +439,7 @@ struct Solver {
 
   template <typename T>
   int scg(Level& L, T* x, const T* f, int n, const std::vector<double>& r_max, bool* breakdown,
-          bool zero_start = false) {
+          bool zero_start = false, double* xacc = nullptr) {
     ensure_scg_vectors(L, sizeof(T) == 4);
     const int nb = reduction_blocks(L.ndof);
     const int64_t nv = L.ndof * nrhs;
@@ -447,7 +447,7 @@ struct Solver {
     L.scg_vectors<T>(r, z, pv, q, r0);
     if (zero_start) {
       fill(nv, x, (T)0, st);
-      convert<T, T>(nv, f, r, 0, st);
+      if (f != r) convert<T, T>(nv, f, r, 0, st);   // the caller may have put f in r already
     } else if constexpr (sizeof(T) == 8) {
       if (r == L.r && r_max.empty()) first_residual(L, x, f);
       else residual_t(L, x, f, r);
@@ -530,7 +530,12 @@ struct Solver {
         it = i;
       }
     }
-    if (ran) xupdate<T>(L.ndof, nrhs, x, pv, scal, st);
+    if constexpr (sizeof(T) == 4) {
+      if (ran && xacc) xupdate_acc(L.ndof, nrhs, x, pv, scal, xacc, st);   // xacc += x + alpha p
+      else if (ran) xupdate<T>(L.ndof, nrhs, x, pv, scal, st);
+    } else {
+      if (ran) xupdate<T>(L.ndof, nrhs, x, pv, scal, st);
+    }
     if constexpr (sizeof(T) == 8) {
       if (ran && r_max.empty() && !msel && !mmask) L.rsm = r;
     }
@@ -541,10 +546,12 @@ struct Solver {
   // on A du = r in FP32 from du = 0, u += du (FP64).
   void scg_mixed(Level& L, double* u, const double* g, int n) {
     ensure_mixed_vectors(L);
+    ensure_scg_vectors(L, true);
     first_residual(L, u, g);
-    convert<double, float>(L.ndof * nrhs, L.r, L.r32, 0, st);
-    scg<float>(L, L.du32, L.r32, n, {}, nullptr, true);
-    convert<float, double>(L.ndof * nrhs, L.du32, u, 1, st);
+    // the FP32 residual goes straight into the SCG residual buffer, and the last update of the
+    // correction straight into u
+    convert<double, float>(L.ndof * nrhs, L.r, L.rc32, 0, st);
+    scg<float>(L, L.du32, L.rc32, n, {}, nullptr, true, u);
   }
 
   void smooth(Level& L, double* u, const double* g, int n) {
