@@ -253,7 +253,7 @@ def stretched_bench(args, torch, B):
 def main():
     args = parse()
     if args.gpus != 1:
-        print('bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "Sharding").',
+        print('bench.py runs on one GPU only: the library has no multi-GPU path.',
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -323,7 +323,8 @@ def main():
     print('residual %.3f ms, schwarz %.3f ms, sweep %.3f ms' % (ms_res, ms_sz, ms_sweep), file=sys.stderr,
           flush=True)
 
-    # algorithmic work ("Roofline accounting")
+    # algorithmic work: the operator's minimum bytes (u, g, r and the geometry as coordinates,
+    # 3 x 8 B) and the FD solve's exact flops, each over its measured launch time
     bytes_res = 48.0 * ndof                      # u, g, coordinates (3 x 8 B), r
     ach_res = bytes_res / (ms_res * 1e-3) / 1e9
     ns = p + 3

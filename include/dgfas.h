@@ -41,7 +41,7 @@ typedef enum {
   DGFAS_EINVAL = -1,       /* bad argument (null pointer, bad size, bad level) */
   DGFAS_ENOMEM = -2,       /* device allocation failed */
   DGFAS_EHIP = -3,         /* HIP runtime error (message in dgfas_last_error) */
-  DGFAS_EUNSUPPORTED = -4, /* valid input outside what this build implements */
+  DGFAS_EUNSUPPORTED = -4, /* valid input outside what the library implements */
   DGFAS_EBREAKDOWN = -5    /* non-finite value or p^T A p <= 0 inside SCG */
 } dgfas_status;
 

@@ -1,6 +1,6 @@
 """FP64 reference of the learned subdomain correction network (oracle; test infrastructure only).
 
-Not in the paper: the network is the learned addition of this build.  Three affine
+Not in the paper: the network is the learned addition to the method.  Three affine
 layers in -> h -> h -> out with ReLU after the first two; loss = mean squared error
 over all outputs.  Parameter layout (one flat array): W1[in][h] b1[h] W2[h][h] b2[h]
 W3[h][out] b3[out].  The gradient is pinned by central finite differences.
