@@ -9,10 +9,12 @@
 
 namespace dgfas {
 
+// one thread per output of the widest of the three contraction steps (the inputs are loaded
+// in a loop), so that a restriction does not idle most of a workgroup sized for its input
 template <int NI, int NO>
 struct TrShape {
-  static constexpr int NM = NI > NO ? NI : NO;
-  static constexpr int M3 = NM * NM * NM;
+  static constexpr int W1 = NI * NI * NO, W2 = NI * NO * NO, W3 = NO * NO * NO;
+  static constexpr int M3 = W1 > W2 ? (W1 > W3 ? W1 : W3) : (W2 > W3 ? W2 : W3);
   static constexpr int EPB = (M3 >= 256) ? 1 : (256 / M3);
   static constexpr int THREADS = ((EPB * M3 + 63) / 64) * 64;
 };
@@ -44,10 +46,12 @@ tensor3_kernel(XferArgs<T> a) {
   __shared__ T s1[EPB][NI * NI * NO];
   __shared__ T s2[EPB][NI * NO * NO];
   for (int t = tid; t < NO * NI; t += S::THREADS) sT[t] = a.Tm[t];
-  if (act && q < I3) {
-    T v = a.in[ib + q];
-    if (a.in2) v -= a.in2[ib + q];
-    s0[le][q] = v;
+  if (act) {
+    for (int t = q; t < I3; t += M3) {
+      T v = a.in[ib + t];
+      if (a.in2) v -= a.in2[ib + t];
+      s0[le][t] = v;
+    }
   }
   __syncthreads();
   if (act && q < NI * NI * NO) {   // [k][j][a]
