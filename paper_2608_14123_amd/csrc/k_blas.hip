@@ -9,12 +9,13 @@
 
 namespace dgfas {
 
-// one thread per output of the widest of the three contraction steps (the inputs are loaded
-// in a loop), so that a restriction does not idle most of a workgroup sized for its input
+// one thread per output of the wider of the first two contraction steps (the inputs and the
+// last step's outputs are taken in loops), so that neither a restriction nor a prolongation
+// idles most of a workgroup sized for its largest array
 template <int NI, int NO>
 struct TrShape {
   static constexpr int W1 = NI * NI * NO, W2 = NI * NO * NO, W3 = NO * NO * NO;
-  static constexpr int M3 = W1 > W2 ? (W1 > W3 ? W1 : W3) : (W2 > W3 ? W2 : W3);
+  static constexpr int M3 = W1 > W2 ? W1 : W2;
   static constexpr int EPB = (M3 >= 256) ? 1 : (256 / M3);
   static constexpr int THREADS = ((EPB * M3 + 63) / 64) * 64;
 };
@@ -68,11 +69,11 @@ tensor3_kernel(XferArgs<T> a) {
     s2[le][q] = s;
   }
   __syncthreads();
-  if (act && q < O3) {             // [c][b][a]
-    const int x = q % NO, y = (q / NO) % NO, c = q / (NO * NO);
+  for (int qq = q; act && qq < O3; qq += M3) {   // [c][b][a]
+    const int x = qq % NO, y = (qq / NO) % NO, c = qq / (NO * NO);
     T s = 0;
     for (int k = 0; k < NI; ++k) s += sT[c * NI + k] * s2[le][(k * NO + y) * NO + x];
-    const int64_t o = ob + q;
+    const int64_t o = ob + qq;
     a.out[o] = a.accumulate ? a.out[o] + s : s;
   }
 }
