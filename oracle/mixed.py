@@ -14,7 +14,13 @@ step here is a reading, stated where it is used:
   With equal degrees it is the conforming form (pinned).
 * Schwarz: a side toward a neighbour of another degree has no overlap ("i0": the 1D matrix
   keeps the interior face terms of the own element only); edge and vertex neighbours of
-  another degree are zero-filled and receive nothing.
+  another degree are zero-filled and receive nothing (Sec. 4.3.1 item 5 fills neighbours
+  without a counterpart with zeros).  Near a degree jump the tensor-product weights of the
+  subdomains that reach a node then no longer add up to one (two subdomains can disagree
+  about who covers a shared node), so the combined correction is normalised:
+  z = C^-1 sum_s R_s^T W_s A~_s^-1 R_s r with the diagonal C = sum_s R_s^T W_s R_s 1.
+  Every node is covered by its own element's subdomain with a positive weight, so C > 0;
+  where the tensor weights already add up to one (all of a uniform mesh) C = 1.
 * Levels: p_{l-1} = max(1, floor(p_l / 2)) per element; elements at degree 1 stay there.
 
 Elements are stored element-major with offsets; inside an element the layout is that of
@@ -241,21 +247,34 @@ class MixedSchwarz:
                             idx[s3, s2, s1] = mesh.off[nb] + (l3 * n + l2) * n + l1
             W = vs[2]['W'][:, None, None] * vs[1]['W'][None, :, None] * vs[0]['W'][None, None, :]
             self.sub.append(dict(idx=idx, v=vs, g=g, W=W))
+        # C = sum_s R_s^T W_s R_s 1, the weight sum at every node
+        C = np.zeros(mesh.n_dof())
+        for sd in self.sub:
+            valid = sd['idx'] >= 0
+            np.add.at(C, sd['idx'][valid], sd['W'][valid])
+        self.C = C
+
+    @staticmethod
+    def local_solve(sd, rs):
+        """Fast diagonalisation (S3 x S2 x S1) D^-1 (S3^T x S2^T x S1^T) rs of one subdomain."""
+        v, g = sd['v'], sd['g']
+        S1, S2, S3 = v[0]['S'], v[1]['S'], v[2]['S']
+        t = np.einsum('kc,jb,ia,kji->cba', S3, S2, S1, rs)
+        Dg = (g[0] + g[1] * v[0]['lam'][None, None, :] + g[2] * v[1]['lam'][None, :, None]
+              + g[3] * v[2]['lam'][:, None, None])
+        return np.einsum('kc,jb,ia,cba->kji', S3, S2, S1, t / Dg)
 
     def apply(self, r):
+        """z = C^-1 sum_s R_s^T W_s A~_s^-1 R_s r (eq. schwarz:correction, normalised weights)."""
         r = np.asarray(r, dtype=np.float64).ravel()
         z = np.zeros_like(r)
         for sd in self.sub:
-            idx, v, g = sd['idx'], sd['v'], sd['g']
+            idx = sd['idx']
             valid = idx >= 0
             rs = np.where(valid, r[np.where(valid, idx, 0)], 0.0)
-            S1, S2, S3 = v[0]['S'], v[1]['S'], v[2]['S']
-            t = np.einsum('kc,jb,ia,kji->cba', S3, S2, S1, rs)
-            Dg = (g[0] + g[1] * v[0]['lam'][None, None, :] + g[2] * v[1]['lam'][None, :, None]
-                  + g[3] * v[2]['lam'][:, None, None])
-            du = np.einsum('kc,jb,ia,cba->kji', S3, S2, S1, t / Dg)
+            du = self.local_solve(sd, rs)
             np.add.at(z, idx[valid], (sd['W'] * du)[valid])
-        return z
+        return z / self.C
 
 
 # ---------------------------------------------------------------------------- levels / cycle

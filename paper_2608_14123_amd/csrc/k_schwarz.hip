@@ -226,19 +226,22 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
     if (m1 >= 0 && m2 >= 0) {
       const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, l1 = m1 & 63, l2 = m2 & 63;
       const T w12 = sW[0][c1] * sW[1][c2];
-      int64_t db[3];
+      int64_t db[3], nbase[3];   // nbase: the column's node (l1, l2, 0) in the receiving element
       int ds[3];
 #pragma unroll
       for (int d3i = 0; d3i < 3; ++d3i) {
         const int d3 = d3i - 1;
         db[d3i] = -1;
         ds[d3i] = 0;
+        nbase[d3i] = 0;
         if (d1 == 0 && d2 == 0 && d3 == 0) {
           db[d3i] = elem_base<N>(a, e) + l2 * N + l1;
           ds[d3i] = N * N;
+          nbase[d3i] = db[d3i];
         } else {
           const int dest = sNb[d3i * 9 + (d2 + 1) * 3 + (d1 + 1)];
           if (dest >= 0) {
+            nbase[d3i] = elem_base<N>(a, dest) + l2 * N + l1;
             const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
             const int cc1 = d1 < 0 ? l1 - (N - M) : l1, cc2 = d2 < 0 ? l2 - (N - M) : l2;
             const int x1 = d1 ? M : N, x2 = d2 ? M : N;
@@ -254,9 +257,10 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
         const int d3i = m3 >> 6, l3 = m3 & 63;
         T t = tA[(s3 * NS + c2) * LS + c1];
         if (a.corr) t += (T)(a.cscale[e] * (double)a.corr[(int64_t)e * (NS * NS * NS) + (s3 * NS + c2) * NS + c1]);
-        const T v = a.unweighted ? t : w12 * sW[2][s3] * t;
+        T v = a.unweighted ? t : w12 * sW[2][s3] * t;
         const int64_t base = db[d3i];
         if (base < 0) continue;
+        if (a.cinv && !a.unweighted) v *= a.cinv[nbase[d3i] + l3 * (N * N)];   // normalised weight
         const int c3 = d3i == 0 ? l3 - (N - M) : l3;   // layer index inside the receiver's region
         const int64_t gi = base + (int64_t)c3 * ds[d3i];
         if (d1 == 0 && d2 == 0 && d3i == 1) {
@@ -377,16 +381,18 @@ __device__ __forceinline__ void schwarz_point_tile(SchwarzArgs<T> a, const int l
     if (m1 < 0 || m2 < 0 || m3 < 0) continue;
     T t = sm.tile[q];
     if (a.corr) t += (T)(a.cscale[e] * (double)a.corr[(int64_t)e * NT + q]);
-    const T val = a.unweighted ? t : sm.W[0][s1] * sm.W[1][s2] * sm.W[2][s3] * t;
+    T val = a.unweighted ? t : sm.W[0][s1] * sm.W[1][s2] * sm.W[2][s3] * t;
     const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, d3 = (m3 >> 6) - 1;
     const int l1 = m1 & 63, l2 = m2 & 63, l3 = m3 & 63;
     if (d1 == 0 && d2 == 0 && d3 == 0) {
       const int64_t gi = elem_base<N>(a, e) + (l3 * N + l2) * N + l1;
+      if (a.cinv && !a.unweighted) val *= a.cinv[gi];   // normalised weight
       if (a.mode == 0) a.z[gi] = val;
       else a.z[gi] += val;
     } else {
       const int dest = sm.nb[(d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1)];
       if (dest < 0) continue;
+      if (a.cinv && !a.unweighted) val *= a.cinv[elem_base<N>(a, dest) + (l3 * N + l2) * N + l1];
       const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);      // direction from dest back to e
       const int c1 = d1 < 0 ? l1 - (N - M) : l1, c2 = d2 < 0 ? l2 - (N - M) : l2, c3 = d3 < 0 ? l3 - (N - M) : l3;
       const int x1 = d1 ? M : N, x2 = d2 ? M : N;

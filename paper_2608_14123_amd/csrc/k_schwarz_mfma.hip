@@ -257,19 +257,22 @@ __global__ void __launch_bounds__(mf_threads<N + 2 * M>()) schwarz_mfma_kernel(S
     if (m1 < 0 || m2 < 0) continue;
     const int d1 = (m1 >> 6) - 1, d2 = (m2 >> 6) - 1, l1 = m1 & 63, l2 = m2 & 63;
     const float w12 = sW[0][c1] * sW[1][c2];
-    int64_t db[3];
+    int64_t db[3], nbase[3];   // nbase: the column's node (l1, l2, 0) in the receiving element
     int ds[3];
 #pragma unroll
     for (int d3i = 0; d3i < 3; ++d3i) {
       const int d3 = d3i - 1;
       db[d3i] = -1;
       ds[d3i] = 0;
+      nbase[d3i] = 0;
       if (d1 == 0 && d2 == 0 && d3 == 0) {
         db[d3i] = ebase + l2 * N + l1;
         ds[d3i] = N * N;
+        nbase[d3i] = db[d3i];
       } else {
         const int dest = sNb[d3i * 9 + (d2 + 1) * 3 + (d1 + 1)];
         if (dest >= 0) {
+          nbase[d3i] = (a.off ? a.off[dest] : (int64_t)dest * (N * N * N)) + l2 * N + l1;
           const int r = (1 - d3) * 9 + (1 - d2) * 3 + (1 - d1);
           const int cc1 = d1 < 0 ? l1 - (N - M) : l1, cc2 = d2 < 0 ? l2 - (N - M) : l2;
           const int x1 = d1 ? M : N, x2 = d2 ? M : N;
@@ -283,9 +286,10 @@ __global__ void __launch_bounds__(mf_threads<N + 2 * M>()) schwarz_mfma_kernel(S
       const int m3 = m3u[s3];
       if (m3 < 0) continue;
       const int d3i = m3 >> 6, l3 = m3 & 63;
-      const float v = w12 * sW[2][s3] * tile[(s3 * NS + c2) * LS + c1];
+      float v = w12 * sW[2][s3] * tile[(s3 * NS + c2) * LS + c1];
       const int64_t base = db[d3i];
       if (base < 0) continue;
+      if (a.cinv) v *= a.cinv[nbase[d3i] + l3 * (N * N)];   // normalised weight
       const int c3 = d3i == 0 ? l3 - (N - M) : l3;
       const int64_t gi = base + (int64_t)c3 * ds[d3i];
       if (d1 == 0 && d2 == 0 && d3i == 1) {

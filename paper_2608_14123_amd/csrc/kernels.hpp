@@ -145,6 +145,8 @@ struct SchwarzArgs {
   const T* lam = nullptr;     // [16][ns]
   const T* W = nullptr;       // [16][ns]
   const int* map1d = nullptr; // [16][ns]: (delta+1)*64 + loc, or -1 for padding
+  const T* cinv = nullptr;    // [ndof] 1 / (sum of the subdomain weights at the node) on levels
+                              // whose tensor weights do not add up to one (degree jumps); null: 1
   const uint8_t* sel = nullptr;  // [E] subdomains to solve (null: all)
   int unweighted = 0;            // 1: W = I (block-diagonal local solves)
   const float* corr = nullptr;   // [E][ns^3] learned correction added to the FD tile (or null)

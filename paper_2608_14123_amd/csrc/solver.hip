@@ -76,6 +76,8 @@ struct DegTab {
   double *S = nullptr, *ST = nullptr, *lam = nullptr, *W = nullptr;
   float *S32 = nullptr, *ST32 = nullptr, *lam32 = nullptr, *W32 = nullptr;
   int* map1d = nullptr;
+  std::vector<double> h_W;   // host copies of the weights and node maps [16][ns]
+  std::vector<int> h_map;
 };
 
 // The elements of one degree on a level (the whole level when it is uniform, elist = null),
@@ -125,6 +127,8 @@ struct Level {
   int8_t* var = nullptr;
   double *gco = nullptr, *O = nullptr;
   float *gco32 = nullptr, *O32 = nullptr;
+  double* cinv = nullptr;        // [ndof] 1 / weight sum per node where the tensor weights of the
+  float* cinv32 = nullptr;       // subdomains reaching it do not add up to one; null on uniform levels
   double* J9 = nullptr;          // [E][9] linear map Jacobian / det^(1/3) (network input)
   std::vector<int> h_nb27;       // host copy of the 26-neighbourhood
   // vectors
@@ -170,7 +174,7 @@ struct Solver {
   double* partial = nullptr;   // [2][nrhs][1024] first-stage sums
   double* scal = nullptr;      // [nrhs][8] SCG scalars
   double* partial2() { return partial + (size_t)1024 * nrhs; }
-  double* scratch = nullptr;
+  double* dotout = nullptr;    // [nrhs] results of dots_sync
   std::vector<void*> owned;
   // learned correction on the finest level (FP64 Schwarz applications)
   Mlp* mlp = nullptr;
@@ -396,9 +400,9 @@ struct Solver {
   std::vector<double> dots_sync(Level& L, const double* a, const double* b) {
     const int nb = reduction_blocks(L.ndof);
     dot_partials<double>(L.ndof, nrhs, a, b, nullptr, partial, nb, st);
-    finish(nb, nrhs, partial, nullptr, kOpStore, scal, scratch, st);
+    finish(nb, nrhs, partial, nullptr, kOpStore, scal, dotout, st);
     std::vector<double> h(nrhs);
-    HIPC(hipMemcpyAsync(h.data(), scratch, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(h.data(), dotout, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     return h;
   }
@@ -773,9 +777,9 @@ SchwarzArgs<T> Solver::sz_args(Level& L, const Bucket& b, const T* r, T* z, int 
   const DegTab& t = *b.t;
   a.map1d = t.map1d;
   if constexpr (sizeof(T) == 8) {
-    a.O = L.O; a.gco = L.gco; a.S = t.S; a.ST = t.ST; a.lam = t.lam; a.W = t.W;
+    a.O = L.O; a.gco = L.gco; a.S = t.S; a.ST = t.ST; a.lam = t.lam; a.W = t.W; a.cinv = L.cinv;
   } else {
-    a.O = L.O32; a.gco = L.gco32; a.S = t.S32; a.ST = t.ST32; a.lam = t.lam32; a.W = t.W32;
+    a.O = L.O32; a.gco = L.gco32; a.S = t.S32; a.ST = t.ST32; a.lam = t.lam32; a.W = t.W32; a.cinv = L.cinv32;
   }
   return a;
 }
@@ -821,6 +825,8 @@ DegTab& deg_tab(Solver& s, int p) {
   t.lam = s.own(upload(lam, st)); t.lam32 = s.own(upload(to_float(lam), st));
   t.W = s.own(upload(W, st)); t.W32 = s.own(upload(to_float(W), st));
   t.map1d = s.own(upload(map, st));
+  t.h_W = W;
+  t.h_map = map;
   return t;
 }
 
@@ -1021,6 +1027,41 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   L.var = s.own(upload(var, st));
   L.nb27 = s.own(upload(nb27, st));
   L.h_nb27 = nb27;
+  // Weight sum C = sum_s R_s^T W_s R_s 1 at every node.  Near a degree jump the subdomains that
+  // reach a node can disagree about who covers it (neighbours of another degree are zero filled),
+  // so the corrections are normalised by C there (C > 0: the own subdomain always covers a node)
+  if (!L.uniform && L.m > 0) {
+    std::vector<double> C((size_t)L.ndof, 0.0);
+    for (int e = 0; e < E; ++e) {
+      const DegTab& t = deg_tab(s, deg[e]);
+      const int n = t.n, NS = t.ns;
+      const int* mp[3];
+      const double* wp[3];
+      for (int d = 0; d < 3; ++d) {
+        mp[d] = &t.h_map[(size_t)var[e * 3 + d] * NS];
+        wp[d] = &t.h_W[(size_t)var[e * 3 + d] * NS];
+      }
+      for (int s3 = 0; s3 < NS; ++s3)
+        for (int s2 = 0; s2 < NS; ++s2)
+          for (int s1 = 0; s1 < NS; ++s1) {
+            const int m1 = mp[0][s1], m2 = mp[1][s2], m3 = mp[2][s3];
+            if (m1 < 0 || m2 < 0 || m3 < 0) continue;
+            const int nb = nb27[(size_t)e * 27 + (m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6)];
+            if (nb < 0 || deg[nb] != deg[e]) continue;
+            C[off[nb] + ((m3 & 63) * n + (m2 & 63)) * n + (m1 & 63)] += wp[0][s1] * wp[1][s2] * wp[2][s3];
+          }
+    }
+    bool all_one = true;
+    for (double& c : C) {
+      if (!(c > 0)) throw Error(DGFAS_EINVAL, "node without a covering subdomain");
+      all_one = all_one && c == 1.0;
+      c = 1.0 / c;
+    }
+    if (!all_one) {
+      L.cinv = s.own(upload(C, st));
+      L.cinv32 = s.own(upload(to_float(C), st));
+    }
+  }
   const size_t nin = (size_t)L.nin * s.nrhs;
   const bool fp32 = s.opt.precision != DGFAS_FP64;
   L.O = s.own(dalloc<double>(nin));
@@ -1281,7 +1322,7 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   if (o->order == DGFAS_ORDER_MORTON) s->rank = morton_rank(m);
   s->partial = s->own(dalloc<double>((size_t)2048 * s->nrhs));
   s->scal = s->own(dalloc<double>((size_t)8 * s->nrhs));
-  s->scratch = s->own(dalloc<double>((size_t)8 * s->nrhs));
+  s->dotout = s->own(dalloc<double>((size_t)8 * s->nrhs));
   // face tables of the mixed-degree kernel: D of degrees 1..8 (stride 81) and the
   // interpolation from degree q to degree r at ((q - 1) 8 + r - 1) 81
   {

@@ -73,3 +73,66 @@ def test_mixed_vcycle_converges_to_the_direct_solution():
     uex = np.linalg.solve(top.assemble(), b)
     assert np.abs(u - uex).max() <= 1e-9 * np.abs(uex).max()
     assert np.abs(u - uD).max() < 0.05            # the discrete solution approximates the front
+
+
+def _pou_mesh(name):
+    if name == 'centre_jump':        # degree 4 in the centre of degree-3 elements: face jumps, and
+        degs = np.full(27, 3)        # edge/vertex neighbours of the face neighbours on the other degree
+        degs[13] = 4
+    elif name == 'random_1to5':      # jumps across faces, edges and vertices in every combination
+        degs = np.random.default_rng(3).integers(1, 6, 27)
+    else:
+        degs = np.full(27, 3)
+    mm, *_ = mixed_mesh(3, degs, lambda Y: W.sine_bump_map(Y, 0.03))
+    return mm, degs
+
+
+@pytest.mark.parametrize('name', ['centre_jump', 'random_1to5', 'uniform'])
+def test_mixed_schwarz_weights_are_a_partition_of_unity(name, monkeypatch):
+    """With every local solve replaced by the identity, the combined correction of Sec. 4.3.1 is
+    C^-1 sum_s R_s^T W_s R_s r, which must return r itself at every node: the weighted gather
+    and scatter of the apply path form a partition of unity.  Without the normalisation the
+    weight sums at degree jumps are 3/4 or 5/4, and on a uniform mesh they are 1 exactly.
+    A subdomain reaches only elements of its own degree (zero fill, Sec. 4.3.1 item 5)."""
+    mm, degs = _pou_mesh(name)
+    sz = mx.MixedSchwarz(mm, 1)
+    monkeypatch.setattr(mx.MixedSchwarz, 'local_solve', staticmethod(lambda sd, rs: rs))
+    r = np.random.default_rng(1).standard_normal(mm.n_dof())
+    assert np.abs(sz.apply(r) - r).max() <= 1e-14 * np.abs(r).max()
+    defect = np.abs(sz.C - 1.0).max()
+    if name == 'uniform':
+        assert defect == 0.0
+    else:
+        assert 0.2 < defect < 0.3
+    owner = np.repeat(np.arange(mm.E), (degs + 1) ** 3)
+    for e, sd in enumerate(sz.sub):
+        idx = sd['idx'][sd['idx'] >= 0]
+        assert np.all(degs[owner[idx]] == degs[e])
+
+
+def test_mixed_discretisation_converges_at_the_rate_of_its_lower_degree():
+    """Manufactured solution u = sin(pi x) sin(pi y) sin(pi z) under the curved map, degree 2 on
+    x < 1/2 and 3 beyond (the layout refines self-similarly, so the face between the degrees
+    stays a plane).  The L2 error from 2^3 to 4^3 elements falls at about p_min + 1 = 3, the rate
+    of the uniform degree-2 discretisation on the same meshes (3.19), with GLL quadrature and
+    the mixed-face integration of the finer side; a dropped or mis-signed face term breaks the
+    consistency and the rate."""
+    errs = []
+    for ne in (2, 4):
+        ex = np.arange(ne ** 3) % ne
+        degs = 2 + (ex >= ne // 2).astype(np.int64)
+        nbr, bc = W.box_topology(ne, ne, ne)
+        X = W.element_coords_mixed(W.box_vertices(ne, ne, ne), degs, lambda p: gll(p)[0],
+                                   lambda Y: W.sine_bump_map(Y, 0.03))
+        levels = mx.build_mixed_levels(degs, X, nbr, bc, m=1)
+        top = levels[-1].mesh
+        uex = np.concatenate([W.sine_solution(x[None])[0].ravel() for x in X])
+        b = top.rhs(3 * np.pi ** 2 * uex)
+        u, hist = mx.solve(levels, np.zeros_like(b), b, sv.Options('scg', 3, 2, root_rtol=1e-8), max_cycles=20,
+                           rtol=1e-8)
+        assert hist[-1] <= 1e-8
+        e2 = sum(float(np.sum(top.el[e].w3 * top.el[e].detJ[0] * (top.block(u, e) - top.block(uex, e)) ** 2))
+                 for e in range(top.E))
+        errs.append(np.sqrt(e2))
+    rate = np.log2(errs[0] / errs[1])
+    assert 2.8 < rate < 3.6, (errs, rate)
