@@ -78,3 +78,70 @@ def fas_vcycle_dense(H, u_top, f_top, ns1, ns2):
         u[l] = u[l] + I @ (u[l - 1] - ubar[l - 1])
         u[l] = was(l, u[l], g[l], ns2)
     return u[-1]
+
+
+def _was_dense(H, l, v, rhs, k):
+    for _ in range(k):
+        v = v + H.B[l] @ (rhs - H.A[l] @ v)
+    return v
+
+
+def _sub(H, l):
+    """The hierarchy of levels 1..l (root first) as a new DenseHierarchy view."""
+    S = DenseHierarchy.__new__(DenseHierarchy)
+    S.A, S.B, S.T = H.A[:l], H.B[:l], H.T[:l]
+    return S
+
+
+def level_rhs_dense(H, f_top):
+    fs = [None] * len(H.A)
+    fs[-1] = f_top
+    for l in range(len(H.A) - 1, 0, -1):
+        fs[l - 1] = H.T[l][1] @ fs[l]
+    return fs
+
+
+def fmg_dense(H, f_top, ns1, ns2):
+    """Alg. 4 from a zero start with WAS smoothing and exact root solves, in explicit matrices."""
+    L = len(H.A)
+    fs = level_rhs_dense(H, f_top)
+    u = np.zeros(H.A[0].shape[0])
+    for l in range(1, L):
+        u = fas_vcycle_dense(_sub(H, l), u, fs[l - 1], ns1, ns2)
+        u = H.T[l][0] @ u
+    return u
+
+
+def cmg_dense(H, f_top, ns0):
+    """Alg. 3 from a zero start with WAS smoothing and an exact root solve, in explicit matrices."""
+    L = len(H.A)
+    fs = level_rhs_dense(H, f_top)
+    u = np.linalg.solve(H.A[0], fs[0])
+    for l in range(1, L - 1):
+        u = _was_dense(H, l, H.T[l][0] @ u, fs[l], ns0)
+    return H.T[L - 1][0] @ u
+
+
+def crossover_cycles_dense(H, u, f_top, ns1, ns2, nsc, n):
+    """n FAS V-cycles where every cycle after the first starts with nsc - ns2 top-level
+    pre-smoothing steps (explicit matrices, WAS, exact root solve)."""
+    L = len(H.A)
+    for k in range(n):
+        pre = ns1 if k == 0 else nsc - ns2
+        v = [None] * L
+        g = [None] * L
+        ub = [None] * L
+        v[-1], g[-1] = u.copy(), f_top
+        for l in range(L - 1, 0, -1):
+            I, R, P = H.T[l]
+            v[l] = _was_dense(H, l, v[l], g[l], pre if l == L - 1 else ns1)
+            r = g[l] - H.A[l] @ v[l]
+            ub[l - 1] = P @ v[l]
+            v[l - 1] = ub[l - 1].copy()
+            g[l - 1] = H.A[l - 1] @ v[l - 1] + R @ r
+        v[0] = np.linalg.solve(H.A[0], g[0])
+        for l in range(1, L):
+            I, R, P = H.T[l]
+            v[l] = _was_dense(H, l, v[l] + I @ (v[l - 1] - ub[l - 1]), g[l], ns2)
+        u = v[-1]
+    return u

@@ -61,8 +61,9 @@ def quintic(t):
     return 10 * t ** 3 - 15 * t ** 4 + 6 * t ** 5
 
 
-def variant_1d(p, m, left, right, mu_star):
+def variant_1d(p, m, left, right, mu_star, weighting='quintic'):
     """1D subdomain data of a face-condition variant (left, right) in {'i','d','n'}.
+    weighting 'plain' gives W = 1 (plain additive Schwarz, no partition of unity).
 
     Returns dict with 'nodes' [(delta, local index)], diagonal mass 'M', stiffness 'L',
     eigenvectors 'S' (S^T M S = I), eigenvalues 'lam' (S^T L S = diag lam) and weights 'W'.
@@ -108,6 +109,8 @@ def variant_1d(p, m, left, right, mu_star):
             if d is not None:
                 wr = quintic((d + a) / (2 * a))
         W[s] = wl * wr
+    if weighting == 'plain':
+        W = np.ones(len(nodes))
     return dict(nodes=nodes, M=M, L=L, S=S, lam=lam, W=W)
 
 
@@ -140,8 +143,8 @@ def neighbour_27(mesh, e, delta):
 class Schwarz:
     """Precomputed subdomain data of one mesh level with overlap m."""
 
-    def __init__(self, mesh, m):
-        self.mesh, self.m = mesh, m
+    def __init__(self, mesh, m, weighting='quintic'):
+        self.mesh, self.m, self.weighting = mesh, m, weighting
         self.g = surrogate_coefficients(mesh)
         self.variants = {}
         self.groups = {}
@@ -166,7 +169,7 @@ class Schwarz:
 
     def _variant(self, lr):
         if lr not in self.variants:
-            self.variants[lr] = variant_1d(self.mesh.p, self.m, lr[0], lr[1], self.mesh.mu_star)
+            self.variants[lr] = variant_1d(self.mesh.p, self.m, lr[0], lr[1], self.mesh.mu_star, self.weighting)
         return self.variants[lr]
 
     def fd_solve(self, grp, rs, sel=None):

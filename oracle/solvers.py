@@ -9,6 +9,24 @@
          frozen elements): the projected coarse solution u_bar = P u_l is
          stored and reused in the prolongation u_l += I (u_{l-1} - u_bar).
 * CS   - Alg. 1, the linear correction scheme, for the FAS == CS check.
+* CMG  - Alg. 3, cascadic start-up: root solve, then on every level up to L-1 the
+         interpolated coarser solution smoothed with n_s0 steps (Sec. 3.3, FAS-CMG).
+* FMG  - Alg. 4, full multigrid start-up: a V-cycle on levels 1..l, then interpolation
+         to level l+1, for l = 1..L-1 (Sec. 3.3, FAS-FMG).
+* Crossover smoothing (Sec. 6.1 method names): between two consecutive cycles the top
+  level gets n_sc smoothing steps in place of the n_s2 post- plus n_s1 pre-smoothing steps.
+
+Readings (the paper leaves these open):
+* Level right-hand sides of the start-ups: f_{l-1} = R f_l, the fine load vector tested with
+  the coarse basis (Alg. 3 and 4 take f on every level; with global coarsening no coarse
+  element is a leaf).
+* Start values on coarser levels: the projection P of the next finer level's start value
+  (zero when the top level starts from zero).
+* Alg. 3 ends its loop at level L-1; the top level then receives u_L = I u_{L-1}, which the
+  first V-cycle smooths.
+* Crossover: cycle k > 1 begins with n_sc - n_s2 top-level pre-smoothing steps, so the steps
+  between the residual checks of two cycles add up to n_sc (the total of the cost model,
+  eq. mg-method:cost:total); the coarser levels keep n_s1.
 """
 import numpy as np
 
@@ -19,9 +37,9 @@ from . import transfer as tr
 
 
 class Level:
-    def __init__(self, mesh, m):
+    def __init__(self, mesh, m, weighting='quintic'):
         self.mesh = mesh
-        self.schwarz = Schwarz(mesh, m)
+        self.schwarz = Schwarz(mesh, m, weighting)
         self.p = mesh.p
 
     def A(self, u):
@@ -31,8 +49,10 @@ class Level:
         return self.schwarz.apply(r)
 
 
-def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0):
-    """Level list (root first) for global p-coarsening of a uniform-degree mesh."""
+def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0, weighting='quintic', delta=None):
+    """Level list (root first) for global p-coarsening of a uniform-degree mesh.  With `delta`
+    the overlap of every level follows from its degree (Sec. 4.3.1 item 3), else it is m."""
+    from .schwarz import overlap_layers
     chain = tr.degree_chain(p)
     levels = [None] * len(chain)
     Xl = np.asarray(X, dtype=np.float64)
@@ -40,7 +60,8 @@ def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0):
         pl = chain[li]
         if li < len(chain) - 1:
             Xl = tr.coarse_coords(pl, chain[li + 1], Xl)
-        levels[li] = Level(Mesh(pl, Xl, nbr, bc, nu=nu, kappa=kappa, mu_star=mu_star), m)
+        ml = min(overlap_layers(pl, delta), pl) if delta is not None else m
+        levels[li] = Level(Mesh(pl, Xl, nbr, bc, nu=nu, kappa=kappa, mu_star=mu_star), ml, weighting)
     return levels
 
 
@@ -86,13 +107,20 @@ def scg(level, u, f, n_i, r_max=0.0, first_dir='z', precond=None, stats=None):
 
 
 class Options:
-    """Cycle parameters: smoother 'was'|'scg', ns1, ns2; root 'scg' (to root_rtol) or 'direct'."""
+    """Cycle parameters: smoother 'was'|'scg', ns1, ns2; root 'scg' (to root_rtol) or 'direct';
+    start None | 'cmg' | 'fmg' with n_s0 CMG steps per level (default ns1 + ns2); crossover
+    steps nsc on the top level between cycles (default ns1 + ns2, i.e. none)."""
 
     def __init__(self, smoother='was', ns1=2, ns2=2, root_rtol=1e-12, root_maxit=500, first_dir='z',
-                 root='scg'):
+                 root='scg', start=None, ns0=None, nsc=None):
         self.smoother, self.ns1, self.ns2 = smoother, ns1, ns2
         self.root_rtol, self.root_maxit, self.first_dir = root_rtol, root_maxit, first_dir
         self.root = root
+        self.start = start
+        self.ns0 = ns1 + ns2 if ns0 is None else ns0
+        self.nsc = ns1 + ns2 if nsc is None else nsc
+        if self.nsc < ns2:
+            raise ValueError('crossover needs nsc >= ns2')
 
 
 def smooth(level, u, g, n, opts):
@@ -111,8 +139,9 @@ def root_solve(level, u, g, opts, stats=None):
     return scg(level, u, g, opts.root_maxit, opts.root_rtol * r0, opts.first_dir, stats=stats)
 
 
-def fas_vcycle(levels, u_top, f_top, opts):
-    """Alg. 2 with global p-coarsening; returns the new top-level solution."""
+def fas_vcycle(levels, u_top, f_top, opts, ns1_top=None):
+    """Alg. 2 with global p-coarsening; returns the new top-level solution.  ns1_top replaces
+    ns1 on the top level (crossover smoothing)."""
     L = len(levels)
     u = [None] * L
     g = [None] * L
@@ -120,7 +149,8 @@ def fas_vcycle(levels, u_top, f_top, opts):
     u[L - 1], g[L - 1] = u_top, f_top
     for l in range(L - 1, 0, -1):
         lv, lc = levels[l], levels[l - 1]
-        u[l] = smooth(lv, u[l], g[l], opts.ns1, opts)
+        n1 = ns1_top if (l == L - 1 and ns1_top is not None) else opts.ns1
+        u[l] = smooth(lv, u[l], g[l], n1, opts)
         r = g[l] - lv.A(u[l])
         ubar[l - 1] = tr.project(lc.p, lv.p, u[l])
         u[l - 1] = ubar[l - 1].copy()
@@ -152,14 +182,61 @@ def cs_vcycle(levels, u_top, f_top, opts):
     return u[L - 1]
 
 
+def level_rhs(levels, f_top):
+    """f_l on every level (root first), f_{l-1} = R f_l."""
+    fs = [None] * len(levels)
+    fs[-1] = f_top
+    for l in range(len(levels) - 1, 0, -1):
+        fs[l - 1] = tr.restrict(levels[l - 1].p, levels[l].p, fs[l])
+    return fs
+
+
+def _start_values(levels, u_top):
+    us = [None] * len(levels)
+    us[-1] = u_top
+    for l in range(len(levels) - 1, 0, -1):
+        us[l - 1] = tr.project(levels[l - 1].p, levels[l].p, us[l])
+    return us
+
+
+def cmg_start(levels, u_top, f_top, opts):
+    """Alg. 3 (FAS-CMG start-up); returns the top-level start value I u_{L-1}."""
+    L = len(levels)
+    fs, us = level_rhs(levels, f_top), _start_values(levels, u_top)
+    u = root_solve(levels[0], us[0], fs[0], opts)
+    for l in range(1, L - 1):
+        u = tr.prolong(levels[l - 1].p, levels[l].p, u)
+        u = smooth(levels[l], u, fs[l], opts.ns0, opts)
+    return tr.prolong(levels[L - 2].p, levels[L - 1].p, u) if L > 1 else u
+
+
+def fmg_start(levels, u_top, f_top, opts):
+    """Alg. 4 (FAS-FMG start-up): for l = 1..L-1 a V-cycle on levels 1..l, then u_{l+1} = I u_l."""
+    L = len(levels)
+    fs, us = level_rhs(levels, f_top), _start_values(levels, u_top)
+    u = us[0]
+    for l in range(1, L):
+        u = fas_vcycle(levels[:l], u, fs[l - 1], opts)
+        u = tr.prolong(levels[l - 1].p, levels[l].p, u)
+    return u if L > 1 else fas_vcycle(levels, u, fs[0], opts)
+
+
 def solve(levels, u0, f, opts, max_cycles=30, rtol=1e-10, cycle=fas_vcycle):
-    """Repeat V-cycles until ||r||/||r0|| <= rtol; returns (u, history of relative residuals)."""
+    """Optional start-up (opts.start), then V-cycles until ||r||/||r0|| <= rtol, with
+    r0 = f - A u0; returns (u, history of relative residuals after each cycle)."""
     top = levels[-1]
     u = u0.copy()
     r0 = norm(f - top.A(u))
+    if opts.start == 'cmg':
+        u = cmg_start(levels, u, f, opts)
+    elif opts.start == 'fmg':
+        u = fmg_start(levels, u, f, opts)
     hist = [1.0]
-    for _ in range(max_cycles):
-        u = cycle(levels, u, f, opts)
+    for k in range(max_cycles):
+        if cycle is fas_vcycle:
+            u = cycle(levels, u, f, opts, ns1_top=None if k == 0 else opts.nsc - opts.ns2)
+        else:
+            u = cycle(levels, u, f, opts)
         hist.append(norm(f - top.A(u)) / r0)
         if hist[-1] <= rtol:
             break
