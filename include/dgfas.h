@@ -155,6 +155,16 @@ dgfas_status dgfas_residual(dgfas_solver s, int32_t level, const double* u, cons
  * (eq. schwarz:correction) with fast-diagonalisation subdomain solves. */
 dgfas_status dgfas_schwarz(dgfas_solver s, int32_t level, const double* r, double* z);
 
+/* The same z = B r as dgfas_schwarz, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The call allocates
+ * nothing: its overlap inbox is a static device array of 8 Mi doubles (64 MiB), one per device,
+ * which every call on that device shares and which keeps the last call's contents; the call clears
+ * what it needs with a fill kernel first.  Calls that overlap on one device race on it.
+ * Levels whose inbox (n_rhs times the overlap slots of every element) exceeds the array are
+ * refused with DGFAS_EINVAL; with the learned correction attached, the finest level is refused
+ * with DGFAS_EUNSUPPORTED (its network may allocate). */
+dgfas_status dgfas_schwarz_noalloc(dgfas_solver s, int32_t level, const double* r, double* z);
+
 /* n_steps smoothing steps of the configured smoother on A_l u = g, in place
  * (Alg. 5 WAS, or Alg. 6 SCG with r_max = 0). */
 dgfas_status dgfas_smooth(dgfas_solver s, int32_t level, double* u, const double* g, int32_t n_steps);

@@ -62,6 +62,7 @@ _sig = {
     'dgfas_apply': (_I, [_V, _I, _V, _V]),
     'dgfas_residual': (_I, [_V, _I, _V, _V, _V]),
     'dgfas_schwarz': (_I, [_V, _I, _V, _V]),
+    'dgfas_schwarz_noalloc': (_I, [_V, _I, _V, _V]),
     'dgfas_smooth': (_I, [_V, _I, _V, _V, _I]),
     'dgfas_restrict': (_I, [_V, _I, _V, _V]),
     'dgfas_project': (_I, [_V, _I, _V, _V]),
@@ -197,6 +198,11 @@ class Solver:
     def schwarz(self, level, r, z):
         n = self._n(level)
         _check(_lib.dgfas_schwarz(self._h, level, _dev(r, n, 'r'), _dev(z, n, 'z')))
+
+    def schwarz_noalloc(self, level, r, z):
+        """z = B r with the overlap inbox in the library's static device array (no allocation)."""
+        n = self._n(level)
+        _check(_lib.dgfas_schwarz_noalloc(self._h, level, _dev(r, n, 'r'), _dev(z, n, 'z')))
 
     def smooth(self, level, u, g, n_steps):
         n = self._n(level)

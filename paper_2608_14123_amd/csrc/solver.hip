@@ -6,6 +6,7 @@
 #include <cmath>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <cstdio>
 #include <cstring>
@@ -38,6 +39,32 @@ struct Error : std::runtime_error {
       throw Error(DGFAS_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));                    \
   } while (0)
 
+
+// Overlap inbox of dgfas_schwarz_noalloc.  Every device holds its own copy of the array; its
+// address on each device is resolved once (hipGetSymbolAddress, with that device current) at
+// the first solver creation there, and host code uses only the resolved address.
+constexpr size_t kNoAllocDoubles = (size_t)8 << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// resolve the array's address on the current device (called at set-up)
+void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw Error(DGFAS_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw Error(DGFAS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = static_cast<double*>(ptr);
+}
+
+double* scratch_address(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+}
 
 template <typename T>
 T* dalloc(size_t n) {
@@ -171,6 +198,8 @@ struct Solver {
   bool rhint = false;
   bool graph_hint = false;
   int nrhs = 1;            // right-hand sides per batch; vectors are [nrhs][ndof]
+  int dev = 0;             // device the solver was created on
+  double* inbox64 = nullptr;   // when set: FP64 overlap inbox of the Schwarz calls instead of L.O
   double* partial = nullptr;   // [2][nrhs][1024] first-stage sums
   double* scal = nullptr;      // [nrhs][8] SCG scalars
   double* partial2() { return partial + (size_t)1024 * nrhs; }
@@ -777,7 +806,7 @@ SchwarzArgs<T> Solver::sz_args(Level& L, const Bucket& b, const T* r, T* z, int 
   const DegTab& t = *b.t;
   a.map1d = t.map1d;
   if constexpr (sizeof(T) == 8) {
-    a.O = L.O; a.gco = L.gco; a.S = t.S; a.ST = t.ST; a.lam = t.lam; a.W = t.W; a.cinv = L.cinv;
+    a.O = inbox64 ? inbox64 : L.O; a.gco = L.gco; a.S = t.S; a.ST = t.ST; a.lam = t.lam; a.W = t.W; a.cinv = L.cinv;
   } else {
     a.O = L.O32; a.gco = L.gco32; a.S = t.S32; a.ST = t.ST32; a.lam = t.lam32; a.W = t.W32; a.cinv = L.cinv32;
   }
@@ -1307,6 +1336,8 @@ std::vector<int64_t> morton_rank(const dgfas_mesh_desc* m) {
 Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   validate(m, o);
   std::unique_ptr<Solver> s(new Solver());
+  HIPC(hipGetDevice(&s->dev));
+  resolve_scratch(s->dev);
   s->opt = *o;
   s->st = (hipStream_t)stream;
   s->E = m->n_elem;
@@ -1555,6 +1586,33 @@ dgfas_status dgfas_schwarz(dgfas_solver sv, int32_t level, const double* r, doub
   Solver* s = S_(sv);
   need(r, "r"); need(z, "z");
   s->schwarz(s->level(level), r, z, 0);
+  HIPC(hipGetLastError());
+  API_END
+}
+
+dgfas_status dgfas_schwarz_noalloc(dgfas_solver sv, int32_t level, const double* r, double* z) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(r, "r"); need(z, "z");
+  Level& L = s->level(level);
+  const size_t need_d = (size_t)L.nin * s->nrhs;
+  if (need_d > kNoAllocDoubles)
+    throw Error(DGFAS_EINVAL, "level " + std::to_string(level) + " needs an overlap inbox of " +
+                                  std::to_string(need_d) + " doubles, more than the " +
+                                  std::to_string(kNoAllocDoubles) + " of the static scratch array");
+  if (s->learned && &L == &s->lv.back())
+    throw Error(DGFAS_EUNSUPPORTED, "the learned correction's network may allocate; detach it first");
+  double* box = scratch_address(s->dev);
+  if (!box) throw Error(DGFAS_EHIP, "scratch array not resolved on this device");
+  struct Reset {   // the override never outlives the call, also when it throws
+    Solver* s;
+    ~Reset() { s->inbox64 = nullptr; }
+  } reset{s};
+  // regions that no subdomain writes (absent neighbours, another degree) must read zero, and the
+  // array holds whatever the last call on this device left in it
+  if (need_d) fill((int64_t)need_d, box, 0.0, s->st);
+  s->inbox64 = box;
+  s->schwarz(L, r, z, 0);
   HIPC(hipGetLastError());
   API_END
 }
