@@ -85,9 +85,12 @@ def _legendre_rows(p):
 class O1:
     """Uniform-degree mesh of degree p with global p-coarsening p_{l-1} = max(1, p_l // 2).
 
-    X: (E, 3, n, n, n) coordinates at the oracle's GLL nodes; nbr, bc: (E, 6)."""
+    X: (E, 3, n, n, n) coordinates at the oracle's GLL nodes; nbr, bc: (E, 6).  The overlap is m
+    on every level (capped at the degree), or with `delta` the number of the neighbour's GLL
+    nodes with (1 + xi)/2 <= delta at each level's degree (Sec. 4.3.1 item 3)."""
 
-    def __init__(self, p, X, nbr, bc, m=1, kappa=0.0, nu=1.0, mu_star=2.0):
+    def __init__(self, p, X, nbr, bc, m=1, kappa=0.0, nu=1.0, mu_star=2.0, delta=None):
+        from .schwarz import overlap_layers
         self.L = lib()
         self.chain = degree_chain(p)
         self.E = int(np.asarray(X).shape[0])
@@ -101,7 +104,7 @@ class O1:
             x, w = gll(pl)
             Dm = np.ascontiguousarray(diff_matrix(pl))
             v0, v1 = _legendre_rows(pl)
-            ml = min(m, pl)
+            ml = min(overlap_layers(pl, delta) if delta is not None else m, pl)
             nv = np.zeros(9, dtype=np.int32)
             mp = -np.ones((9, NSMAX), dtype=np.int32)
             S = np.zeros((9, NSMAX * NSMAX))
