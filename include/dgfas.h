@@ -53,6 +53,8 @@ enum { DGFAS_WAS = 0, DGFAS_SCG = 1 };
 enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1, DGFAS_BF16 = 2, DGFAS_FP32_MFMA = 3 };
 enum { DGFAS_BATCH_PER_DEGREE = 0, DGFAS_BATCH_ONE_LAUNCH = 1, DGFAS_BATCH_TUNED = 2 };
 enum { DGFAS_ORDER_NATURAL = 0, DGFAS_ORDER_MORTON = 1 };
+enum { DGFAS_START_NONE = 0, DGFAS_START_CMG = 1, DGFAS_START_FMG = 2 };
+enum { DGFAS_WEIGHT_QUINTIC = 0, DGFAS_WEIGHT_PLAIN = 1 };
 
 typedef struct dgfas_solver_s* dgfas_solver;
 
@@ -78,7 +80,11 @@ typedef struct {
   double kappa;             /* >= 0 */
   double nu;                /* > 0 */
   double mu_star;           /* penalty scale of eq. helmholtz:dgm, > 0 */
-  int32_t overlap;          /* Schwarz overlap m in node layers, 0..p (Sec. 4.3.1 item 3) */
+  int32_t overlap;          /* Schwarz overlap m in node layers (Sec. 4.3.1 item 3), or < 0: m per
+                               degree from delta (the neighbour's GLL nodes with (1 + xi)/2 <= delta,
+                               its face node included).  Kernels exist for m in {0, 1} at every
+                               degree, m = 2 at p = 4 and 8, and m = 3 at p = 8; other pairs on any
+                               level give DGFAS_EUNSUPPORTED */
   int32_t smoother;         /* DGFAS_WAS (Alg. 5) or DGFAS_SCG (Alg. 6) on levels > 1 */
   int32_t ns1, ns2;         /* pre- and post-smoothing steps (Alg. 2) */
   int32_t root_max_iter;    /* SCG iteration cap of the root solve */
@@ -110,7 +116,18 @@ typedef struct {
                                a compact 3D block and share their neighbours' data in L2).
                                Operator and Schwarz results are bitwise the same; dot products
                                fused into the kernels sum their partials in another order */
-  int32_t reserved[3];
+  int32_t start;            /* start-up of dgfas_solve (Sec. 3.3): DGFAS_START_NONE, DGFAS_START_CMG
+                               (Alg. 3, cascadic) or DGFAS_START_FMG (Alg. 4, full multigrid); the
+                               coarser levels' right-hand sides are f_{l-1} = R f_l */
+  int32_t ns0;              /* CMG smoothing steps per level; <= 0: ns1 + ns2 */
+  int32_t nsc;              /* crossover smoothing (Sec. 6.1 method names): top-level steps between
+                               the residual checks of two consecutive cycles, i.e. every cycle after
+                               the first starts with nsc - ns2 pre-smoothing steps on the finest
+                               level; <= 0: ns1 + ns2 (no crossover); must be >= ns2 */
+  int32_t weighting;        /* DGFAS_WEIGHT_QUINTIC (the partition of unity of Sec. 4.3.1) or
+                               DGFAS_WEIGHT_PLAIN (W = I: plain additive Schwarz) */
+  double delta;             /* overlap width in the standard element when overlap < 0, 0 <= delta < 1 */
+  int32_t reserved[2];
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);
@@ -138,6 +155,9 @@ void dgfas_destroy(dgfas_solver s);
  * level when degrees differ; n_dof is the sum of (p_e+1)^3 over the elements). */
 dgfas_status dgfas_levels(dgfas_solver s, int32_t* n_levels);
 dgfas_status dgfas_level_info(dgfas_solver s, int32_t level, int32_t* degree, int64_t* n_dof);
+/* Schwarz overlap m (node layers) of a level's largest degree, as set by overlap or delta; the
+ * subdomain tile of that degree has ns = degree + 1 + 2m nodes per direction. */
+dgfas_status dgfas_level_overlap(dgfas_solver s, int32_t level, int32_t* m);
 
 /* Right-hand side of eq. helmholtz:system on the finest level from nodal values
  * (device): f [n_dof], uD [n_dof] (values at Dirichlet face nodes are used; may be
@@ -183,10 +203,16 @@ dgfas_status dgfas_prolong_add(dgfas_solver s, int32_t level, const double* u_co
  * (host, may be NULL) receives the count.  Synchronous when root_rtol > 0. */
 dgfas_status dgfas_root_solve(dgfas_solver s, double* u, const double* g, int32_t* iters);
 
+/* The configured start-up alone (DGFAS_START_CMG: Alg. 3, DGFAS_START_FMG: Alg. 4) from the
+ * finest-level start value u (projected to the coarser levels); u receives the interpolated
+ * start value I u_{L-1}.  DGFAS_START_NONE leaves u unchanged.  Synchronous (root solves). */
+dgfas_status dgfas_startup(dgfas_solver s, double* u, const double* f);
+
 /* One FAS V-cycle (Alg. 2, global p-coarsening) on the finest-level u for rhs f. */
 dgfas_status dgfas_vcycle(dgfas_solver s, double* u, const double* f);
 
-/* FAS V-cycles until ||f - A u|| <= rtol ||f - A u_0|| for every right-hand side, or max_cycles.
+/* The configured start-up (start), then FAS V-cycles with crossover smoothing (nsc) until
+ * ||f - A u|| <= rtol ||f - A u_0|| for every right-hand side, or max_cycles.
  * hist (host, may be NULL) receives max_cycles+1 relative residuals, the largest over the
  * right-hand sides (entry 0 = 1);
  * n_done (host, may be NULL) the number of cycles run.  Synchronises once per cycle.

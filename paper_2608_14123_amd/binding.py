@@ -25,6 +25,8 @@ WAS, SCG = 0, 1
 FP64, FP32, BF16, FP32_MFMA = 0, 1, 2, 3
 BATCH_PER_DEGREE, BATCH_ONE_LAUNCH, BATCH_TUNED = 0, 1, 2
 ORDER_NATURAL, ORDER_MORTON = 0, 1
+START_NONE, START_CMG, START_FMG = 0, 1, 2
+WEIGHT_QUINTIC, WEIGHT_PLAIN = 0, 1
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -39,7 +41,9 @@ class Options(ctypes.Structure):
                 ('overlap', ctypes.c_int32), ('smoother', ctypes.c_int32), ('ns1', ctypes.c_int32),
                 ('ns2', ctypes.c_int32), ('root_max_iter', ctypes.c_int32), ('root_rtol', ctypes.c_double),
                 ('precision', ctypes.c_int32), ('n_rhs', ctypes.c_int32), ('batch', ctypes.c_int32),
-                ('graph', ctypes.c_int32), ('order', ctypes.c_int32), ('reserved', ctypes.c_int32 * 3)]
+                ('graph', ctypes.c_int32), ('order', ctypes.c_int32), ('start', ctypes.c_int32),
+                ('ns0', ctypes.c_int32), ('nsc', ctypes.c_int32), ('weighting', ctypes.c_int32),
+                ('delta', ctypes.c_double), ('reserved', ctypes.c_int32 * 2)]
 
 
 class DgfasError(RuntimeError):
@@ -58,6 +62,7 @@ _sig = {
     'dgfas_destroy': (None, [_V]),
     'dgfas_levels': (_I, [_V, ctypes.POINTER(_I)]),
     'dgfas_level_info': (_I, [_V, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64)]),
+    'dgfas_level_overlap': (_I, [_V, _I, ctypes.POINTER(_I)]),
     'dgfas_rhs': (_I, [_V, _V, _V, _V, _V]),
     'dgfas_apply': (_I, [_V, _I, _V, _V]),
     'dgfas_residual': (_I, [_V, _I, _V, _V, _V]),
@@ -69,6 +74,7 @@ _sig = {
     'dgfas_prolong_add': (_I, [_V, _I, _V, _V, _V]),
     'dgfas_root_solve': (_I, [_V, _V, _V, ctypes.POINTER(_I)]),
     'dgfas_vcycle': (_I, [_V, _V, _V]),
+    'dgfas_startup': (_I, [_V, _V, _V]),
     'dgfas_solve': (_I, [_V, _V, _V, _I, ctypes.c_double, c_dp, ctypes.POINTER(_I)]),
     'dgfas_norm': (_I, [_V, _I, _V, c_dp]),
     'dgfas_autotune': (_I, [_V, ctypes.c_char_p, _I, c_dp]),
@@ -183,6 +189,11 @@ class Solver:
         _check(_lib.dgfas_level_info(self._h, level, ctypes.byref(d), ctypes.byref(nd)))
         return d.value, nd.value
 
+    def level_overlap(self, level):
+        m = _I()
+        _check(_lib.dgfas_level_overlap(self._h, level, ctypes.byref(m)))
+        return m.value
+
     def rhs(self, f, b, uD=None, qN=None):
         n = self._n(self.n_levels)
         _check(_lib.dgfas_rhs(self._h, _dev(f, n, 'f'), _dev(uD, n, 'uD'), _dev(qN, n, 'qN'), _dev(b, n, 'b')))
@@ -226,6 +237,11 @@ class Solver:
         it = _I()
         _check(_lib.dgfas_root_solve(self._h, _dev(u, n, 'u'), _dev(g, n, 'g'), ctypes.byref(it)))
         return it.value
+
+    def startup(self, u, f):
+        """The configured CMG / FMG start-up: u (finest level) receives the start value."""
+        n = self._n(self.n_levels)
+        _check(_lib.dgfas_startup(self._h, _dev(u, n, 'u'), _dev(f, n, 'f')))
 
     def vcycle(self, u, f):
         n = self._n(self.n_levels)
@@ -345,7 +361,9 @@ def learned_pairs(solver, r, centers, X, T):
     """Training pairs for the listed centre elements (numpy int array); returns PCG iterations."""
     c = np.ascontiguousarray(centers, dtype=np.int32)
     it = _I()
-    ns3 = T.shape[-1] if T.dim() == 2 else T.numel() // max(len(c), 1)
+    # the library writes n (ns^3 + 9) values to X and n ns^3 to T, ns from its finest level
+    L = solver.n_levels
+    ns3 = (solver.level_info(L)[0] + 1 + 2 * solver.level_overlap(L)) ** 3
     _check(_lib.dgfas_learned_pairs(solver._h, _dev(r, solver._n(solver.n_levels), 'r'), c.ctypes.data, len(c),
                                     _dev(X, len(c) * (ns3 + 9), 'X', 'float32'), _dev(T, len(c) * ns3, 'T', 'float32'),
                                     ctypes.byref(it)))

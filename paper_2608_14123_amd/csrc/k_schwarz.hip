@@ -739,6 +739,7 @@ void launch_overlap(const SchwarzArgs<T>& a, hipStream_t st) {
     case 8 * 16 + 0: F<9, 0, T>(a, st); break;                                  \
     case 8 * 16 + 1: F<9, 1, T>(a, st); break;                                  \
     case 8 * 16 + 2: F<9, 2, T>(a, st); break;                                  \
+    case 8 * 16 + 3: F<9, 3, T>(a, st); break;                                  \
     default: break;                                                             \
   }
 

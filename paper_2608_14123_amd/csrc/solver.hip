@@ -134,6 +134,7 @@ struct Level {
   int tiles[3] = {0, 0, 0};             // work-list length per stage
   int one_launch[3] = {0, 0, 0};        // tuned choice per stage
   std::string hist;                     // degree histogram "p:count,..." (autotuner key)
+  bool all_m1 = true;                   // every degree bucket has overlap 1 (batched Schwarz tiles)
   int nm = 0;                           // elements with a face to another degree
   int nlb = 0;                          // operator tiles per right-hand side (uniform levels)
   double* kpart = nullptr;              // [nrhs][nlb] fused p^T A p partial sums (uniform levels)
@@ -197,6 +198,8 @@ struct Solver {
   // once the cycle's pre-smoothing on the finest level has run)
   bool rhint = false;
   bool graph_hint = false;
+  int ns1_top = -1;        // finest-level pre-smoothing steps of the next cycle (crossover); -1: ns1
+  int graph_ns1 = -1;      // ns1_top the captured graphs were built with
   int nrhs = 1;            // right-hand sides per batch; vectors are [nrhs][ndof]
   int dev = 0;             // device the solver was created on
   double* inbox64 = nullptr;   // when set: FP64 overlap inbox of the Schwarz calls instead of L.O
@@ -238,7 +241,7 @@ struct Solver {
   // one launch over all buckets for this level and stage?
   bool use_batch(const Level& L, int stage) const {
     if (L.uniform || L.bk.size() < 2) return false;
-    if (stage != kStageOp && opt.overlap != 1) return false;   // batched Schwarz tiles take m = 1
+    if (stage != kStageOp && !L.all_m1) return false;   // batched Schwarz tiles take m = 1
     if (stage == kStageSolve && matrix_cores()) return false;   // matrix-core tiles per degree
     if (force_batch >= 0) return force_batch == 1;
     if (opt.batch == DGFAS_BATCH_ONE_LAUNCH) return true;
@@ -631,10 +634,10 @@ struct Solver {
     T.u = u_top;
     T.g = const_cast<double*>(f_top);
     bool bd = false;
-    leg_down();
+    leg_down(Lc - 1);
     rhint = false;
     root_solve(lv[0].u, lv[0].g, &bd);
-    leg_up();
+    leg_up(Lc - 1);
     T.u = u_save;
     T.g = const_cast<double*>(g_save);
   }
@@ -642,7 +645,8 @@ struct Solver {
   // The same cycle with both legs replayed from captured graphs (bitwise the same work); with
   // a fixed-iteration root solve the whole cycle is one graph.
   void vcycle_graphed(double* u_top, const double* f_top) {
-    if (!gdown || gu != u_top || gf != f_top || graph_built_epoch != graph_epoch || graph_hint != rhint)
+    if (!gdown || gu != u_top || gf != f_top || graph_built_epoch != graph_epoch || graph_hint != rhint ||
+        graph_ns1 != ns1_top)
       build_graphs(u_top, f_top);
     rhint = false;
     HIPC(hipGraphLaunch(gdown, st));
@@ -686,15 +690,15 @@ struct Solver {
         HIPC(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         try {
           if (whole) {
-            leg_down();
+            leg_down(Lc - 1);
             rhint = false;
             bool bd = false;
             root_solve(lv[0].u, lv[0].g, &bd);
-            leg_up();
+            leg_up(Lc - 1);
           } else if (leg == 0) {
-            leg_down();
+            leg_down(Lc - 1);
           } else {
-            leg_up();
+            leg_up(Lc - 1);
           }
         } catch (...) {
           hipGraph_t g = nullptr;
@@ -722,14 +726,63 @@ struct Solver {
     gf = f_top;
     graph_built_epoch = graph_epoch;
     graph_hint = hint;
+    graph_ns1 = ns1_top;
   }
 
-  void leg_down() {
+  // V-cycle on levels 1..top + 1 with lv[top] as the top level (its own u and g); top = 0 is
+  // the root solve alone
+  void vcycle_sub(int top) {
+    bool bd = false;
+    if (top > 0) leg_down(top);
+    rhint = false;
+    root_solve(lv[0].u, lv[0].g, &bd);
+    if (top > 0) leg_up(top);
+  }
+
+  // Start-up (Sec. 3.3): the coarser levels' right-hand sides f_{l-1} = R f_l go to their g and
+  // the start values u_{l-1} = P u_l to their u; then Alg. 4 (FMG: a V-cycle on levels 1..l, then
+  // u_{l+1} = I u_l) or Alg. 3 (CMG: root solve, then u_l = I u_{l-1} smoothed with ns0 steps up
+  // to level L - 1); the top level receives I u_{L-1}
+  void startup(double* u_top, const double* f_top) {
     const int Lc = (int)lv.size();
+    if (opt.start == DGFAS_START_NONE) return;
+    rhint = false;
+    if (Lc == 1) {
+      bool bd = false;
+      root_solve(u_top, f_top, &bd);
+      return;
+    }
     for (int l = Lc - 1; l >= 1; --l) {
       Level& F = lv[l];
       Level& C = lv[l - 1];
-      smooth(F, F.u, F.g, opt.ns1);
+      transfer(F, C, 1, l == Lc - 1 ? f_top : F.g, nullptr, C.g, 0);
+      transfer(F, C, 0, l == Lc - 1 ? u_top : F.u, nullptr, C.u, 0);
+    }
+    if (opt.start == DGFAS_START_FMG) {
+      for (int l = 0; l <= Lc - 2; ++l) {
+        vcycle_sub(l);
+        transfer(lv[l + 1], lv[l], 2, lv[l].u, nullptr, l + 1 == Lc - 1 ? u_top : lv[l + 1].u, 0);
+      }
+    } else {
+      const int ns0 = opt.ns0 > 0 ? opt.ns0 : opt.ns1 + opt.ns2;
+      bool bd = false;
+      root_solve(lv[0].u, lv[0].g, &bd);
+      for (int l = 1; l <= Lc - 2; ++l) {
+        transfer(lv[l], lv[l - 1], 2, lv[l - 1].u, nullptr, lv[l].u, 0);
+        smooth(lv[l], lv[l].u, lv[l].g, ns0);
+      }
+      transfer(lv[Lc - 1], lv[Lc - 2], 2, lv[Lc - 2].u, nullptr, u_top, 0);
+    }
+  }
+
+  // down leg of a V-cycle whose top level is lv[top]; the finest level takes ns1_top
+  // pre-smoothing steps when set (crossover smoothing)
+  void leg_down(int top) {
+    const int Lc = (int)lv.size();
+    for (int l = top; l >= 1; --l) {
+      Level& F = lv[l];
+      Level& C = lv[l - 1];
+      smooth(F, F.u, F.g, (l == Lc - 1 && ns1_top >= 0) ? ns1_top : opt.ns1);
       rhint = false;
       // r = g - A u: an FP64 SCG smoother leaves it as its recurrence residual (the same
       // vector up to rounding), any other smoother has it computed here
@@ -746,9 +799,8 @@ struct Solver {
     }
   }
 
-  void leg_up() {
-    const int Lc = (int)lv.size();
-    for (int l = 1; l < Lc; ++l) {
+  void leg_up(int top) {
+    for (int l = 1; l <= top; ++l) {
       Level& F = lv[l];
       Level& C = lv[l - 1];
       transfer(F, C, 2, C.u, C.ubar, F.u, 1);                                  // u += I (u_c - ubar)
@@ -815,6 +867,21 @@ SchwarzArgs<T> Solver::sz_args(Level& L, const Bucket& b, const T* r, T* z, int 
 
 const int kFace[3][2] = {{0, 1}, {2, 3}, {4, 5}};
 
+// Overlap layers at degree p: the option itself, or from delta (Sec. 4.3.1 item 3): the number
+// of the neighbour's GLL nodes with (1 + xi)/2 <= delta, its face node included
+int overlap_of(const dgfas_options& o, int p) {
+  if (o.overlap >= 0) return std::min(o.overlap, p);
+  const Gll& g = gll_table(p);
+  int m = 0;
+  for (int i = 0; i <= p; ++i)
+    if (0.5 * (1.0 + g.x[i]) <= o.delta + 1e-14) ++m;
+  return std::min(m, p);
+}
+// (degree, overlap) pairs with Schwarz kernels
+bool overlap_supported(int p, int m) {
+  return m == 0 || m == 1 || (m == 2 && (p == 4 || p == 8)) || (m == 3 && p == 8);
+}
+
 // tables of degree p (built once per solver)
 DegTab& deg_tab(Solver& s, int p) {
   auto it = s.tabs.find(p);
@@ -823,7 +890,7 @@ DegTab& deg_tab(Solver& s, int p) {
   DegTab& t = s.tabs[p];
   const Gll& gl = gll_table(p);
   t.p = p; t.n = p + 1;
-  t.m = std::min(s.opt.overlap, p);
+  t.m = overlap_of(s.opt, p);
   t.ns = t.n + 2 * t.m;
   t.inv_wend = 1.0 / gl.w[0];
   t.D = s.own(upload(gl.D, st));
@@ -838,6 +905,7 @@ DegTab& deg_tab(Solver& s, int p) {
     for (int right = 0; right < kSides; ++right) {
       const int v = left * kSides + right;
       Variant1D vt = make_variant_1d(p, t.m, left, right, s.opt.mu_star);
+      if (s.opt.weighting == DGFAS_WEIGHT_PLAIN) std::fill(vt.W.begin(), vt.W.end(), 1.0);   // W = I
       for (int i = 0; i < vt.ns; ++i) {
         for (int a = 0; a < vt.ns; ++a) S[v * NS * NS + i * NS + a] = vt.S[i * vt.ns + a];
         lam[v * NS + i] = vt.lam[i];
@@ -868,7 +936,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   L.p = *std::max_element(deg.begin(), deg.end());
   L.uniform = *std::min_element(deg.begin(), deg.end()) == L.p;
   L.n = L.p + 1; L.N2 = L.n * L.n; L.N3 = L.N2 * L.n;
-  L.m = std::min(s.opt.overlap, L.p);
+  L.m = overlap_of(s.opt, L.p);
   L.ns = L.n + 2 * L.m;
   L.inv_wend = 1.0 / gll_table(L.p).w[0];
   // element-major layout with offsets
@@ -879,7 +947,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     off[e] = nd; offF[e] = nf; offO[e] = no;
     nd += (int64_t)n * n * n;
     nf += 6 * (int64_t)n * n;
-    no += overlap_size(deg[e], std::min(s.opt.overlap, deg[e]));
+    no += overlap_size(deg[e], overlap_of(s.opt, deg[e]));
   }
   L.ndof = nd; L.nfs = nf; L.nin = no;
   L.h_off = off;
@@ -900,6 +968,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       std::stable_sort(b.h_elist.begin(), b.h_elist.end(), [&](int x, int y) { return s.rank[x] < s.rank[y]; });
     if (!L.uniform || !s.rank.empty()) b.elist = s.own(upload(b.h_elist, st));
     b.t = &deg_tab(s, p);
+    L.all_m1 = L.all_m1 && b.t->m == 1;
     L.bk.push_back(std::move(b));
   }
   // degree histogram and the one-launch work lists (largest degree first)
@@ -1059,7 +1128,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   // Weight sum C = sum_s R_s^T W_s R_s 1 at every node.  Near a degree jump the subdomains that
   // reach a node can disagree about who covers it (neighbours of another degree are zero filled),
   // so the corrections are normalised by C there (C > 0: the own subdomain always covers a node)
-  if (!L.uniform && L.m > 0) {
+  if (!L.uniform && L.m > 0 && s.opt.weighting == DGFAS_WEIGHT_QUINTIC) {
     std::vector<double> C((size_t)L.ndof, 0.0);
     for (int e = 0; e < E; ++e) {
       const DegTab& t = deg_tab(s, deg[e]);
@@ -1212,7 +1281,7 @@ void Solver::autotune(const char* path, int reps, double* report) {
         static const char* const kPrec[4] = {"fp64", "fp32", "bf16", "fp32mfma"};
         const std::string key = arch + "|" + L.hist + "|" + kPrec[opt.precision] + "|rhs" +
                                 std::to_string(nrhs) + "|" + stage_name[sg];
-        if (sg != kStageOp && opt.overlap != 1) continue;
+        if (sg != kStageOp && !L.all_m1) continue;
         auto it = cache.find(key);
         if (it != cache.end()) {
           L.one_launch[sg] = it->second;
@@ -1263,12 +1332,8 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (!m || !o) throw Error(DGFAS_EINVAL, "null mesh or options");
   if (m->n_elem <= 0 || !m->degree || !m->coords || !m->face_nbr || !m->face_bc)
     throw Error(DGFAS_EINVAL, "mesh arrays missing or n_elem <= 0");
-  const int p = m->degree[0];
-  bool uniform = true;
-  for (int e = 0; e < m->n_elem; ++e) {
+  for (int e = 0; e < m->n_elem; ++e)
     if (m->degree[e] < 1 || m->degree[e] > 8) throw Error(DGFAS_EUNSUPPORTED, "degree must be 1..8");
-    uniform = uniform && m->degree[e] == p;
-  }
   for (int e = 0; e < m->n_elem; ++e)
     for (int f = 0; f < 6; ++f) {
       const int en = m->face_nbr[e * 6 + f];
@@ -1279,10 +1344,25 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
         throw Error(DGFAS_EINVAL, "boundary face without a Dirichlet/Neumann code");
     }
   if (!(o->nu > 0) || !(o->kappa >= 0) || !(o->mu_star > 0)) throw Error(DGFAS_EINVAL, "bad coefficients");
-  if (o->overlap < 0 || o->overlap > 1 + (p >= 4 ? 1 : 0))
-    throw Error(DGFAS_EUNSUPPORTED, "overlap must be 0 or 1 (2 for p = 4, 8)");
-  if (o->overlap == 2 && (!uniform || (p != 4 && p != 8)))
-    throw Error(DGFAS_EUNSUPPORTED, "overlap 2 needs one degree, p = 4 or 8");
+  if (o->overlap < 0 && !(o->delta >= 0.0 && o->delta < 1.0)) throw Error(DGFAS_EINVAL, "delta must be in [0, 1)");
+  // every degree on every level (p -> max(1, p / 2) per element) needs a kernel for its overlap
+  {
+    bool seen[9] = {false};
+    for (int e = 0; e < m->n_elem; ++e)
+      for (int q = m->degree[e];; q = std::max(1, q / 2)) {
+        seen[q] = true;
+        if (q == 1) break;
+      }
+    for (int q = 1; q <= 8; ++q)
+      if (seen[q] && !overlap_supported(q, overlap_of(*o, q)))
+        throw Error(DGFAS_EUNSUPPORTED, "no Schwarz kernel for degree " + std::to_string(q) + " with overlap " +
+                                            std::to_string(overlap_of(*o, q)));
+  }
+  if (o->weighting != DGFAS_WEIGHT_QUINTIC && o->weighting != DGFAS_WEIGHT_PLAIN)
+    throw Error(DGFAS_EINVAL, "unknown weighting");
+  if (o->start != DGFAS_START_NONE && o->start != DGFAS_START_CMG && o->start != DGFAS_START_FMG)
+    throw Error(DGFAS_EINVAL, "unknown start-up");
+  if (o->nsc > 0 && o->nsc < o->ns2) throw Error(DGFAS_EINVAL, "nsc must be >= ns2 (or <= 0 for none)");
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
   if (!(o->root_rtol >= 0) || !std::isfinite(o->root_rtol)) throw Error(DGFAS_EINVAL, "root_rtol must be >= 0");
@@ -1489,6 +1569,9 @@ void dgfas_default_options(dgfas_options* o) {
   o->root_rtol = 1e-12;
   o->precision = DGFAS_FP64;
   o->n_rhs = 1;
+  o->start = DGFAS_START_NONE;
+  o->weighting = DGFAS_WEIGHT_QUINTIC;
+  o->delta = 0.08;
 }
 
 dgfas_status dgfas_gll(int32_t p, double* x, double* w) {
@@ -1541,6 +1624,13 @@ dgfas_status dgfas_level_info(dgfas_solver s, int32_t level, int32_t* degree, in
   Level& L = S_(s)->level(level);
   if (degree) *degree = L.p;
   if (n_dof) *n_dof = L.ndof;
+  API_END
+}
+
+dgfas_status dgfas_level_overlap(dgfas_solver s, int32_t level, int32_t* m) {
+  API_BEGIN
+  need(m, "m");
+  *m = S_(s)->level(level).m;
   API_END
 }
 
@@ -1675,6 +1765,15 @@ dgfas_status dgfas_root_solve(dgfas_solver sv, double* u, const double* g, int32
   API_END
 }
 
+dgfas_status dgfas_startup(dgfas_solver sv, double* u, const double* f) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(u, "u"); need(f, "f");
+  s->startup(u, f);
+  HIPC(hipStreamSynchronize(s->st));
+  API_END
+}
+
 dgfas_status dgfas_vcycle(dgfas_solver sv, double* u, const double* f) {
   API_BEGIN
   Solver* s = S_(sv);
@@ -1690,14 +1789,25 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
   Solver* s = S_(sv);
   need(u, "u"); need(f, "f");
   if (max_cycles < 0) throw Error(DGFAS_EINVAL, "negative max_cycles");
-  struct HintReset {   // no residual hint survives the call, also when a cycle throws
+  struct HintReset {   // no residual hint or crossover count survives the call, also when it throws
     Solver* s;
-    ~HintReset() { s->rhint = false; }
+    ~HintReset() {
+      s->rhint = false;
+      s->ns1_top = -1;
+    }
   } hint_reset{s};
   Level& T = s->lv.back();
   s->residual(T, u, f, T.r);
   std::vector<double> r0 = s->dots_sync(T, T.r, T.r);
   for (double& v : r0) v = std::sqrt(v);
+  if (s->opt.start != DGFAS_START_NONE) {
+    s->startup(u, f);
+    s->residual(T, u, f, T.r);   // the cycles below take T.r as f - A u of the start value
+  }
+  // crossover: every cycle after the first starts with nsc - ns2 finest-level pre-smoothing steps
+  const int nsc = s->opt.nsc > 0 ? s->opt.nsc : s->opt.ns1 + s->opt.ns2;
+  const int pre_later = nsc - s->opt.ns2;
+  const bool crossover = pre_later != s->opt.ns1;
   if (hist) hist[0] = 1.0;
   int k = 0;
   auto worst = [&](const std::vector<double>& rr) {
@@ -1726,7 +1836,9 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
     if (s->learned)
       HIPC(hipMemcpyAsync(usave, u, T.ndof * s->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s->st));
     s->rhint = true;   // T.r holds f - A u of this u (computed before the loop or below)
-    if (s->opt.graph && !attached) s->vcycle_graphed(u, f);
+    s->ns1_top = (crossover && k > 0) ? pre_later : -1;
+    // the first cycle of a crossover solve runs eagerly, so that the graphs keep the later cycles' shape
+    if (s->opt.graph && !attached && !(crossover && k == 0)) s->vcycle_graphed(u, f);
     else s->vcycle(u, f);
     s->rhint = false;
     s->residual(T, u, f, T.r);

@@ -14,9 +14,10 @@ from paper_2608_14123_amd import workloads as W
 
 class Case:
     def __init__(self, name, p, ne, amp=0.0, bc_code=1, kappa=0.0, mu_star=2.0, periodic=False, lengths=(1, 1, 1),
-                 perturb=None, m=1):
+                 perturb=None, m=1, weighting='quintic', delta=None):
         self.name, self.p, self.ne, self.amp = name, p, ne, amp
         self.kappa, self.mu_star, self.m = kappa, mu_star, m
+        self.weighting, self.delta = weighting, delta
         self.nbr, self.bc = W.box_topology(ne, ne, ne, periodic=(periodic,) * 3, bc_code=bc_code)
         V = W.box_vertices(ne, ne, ne, lengths=lengths)
         if perturb is not None:
@@ -30,11 +31,17 @@ class Case:
 
     def oracle_levels(self):
         X = self.coords(oracle_gll(self.p)[0])
-        return osv.build_levels(self.p, X, self.nbr, self.bc, m=self.m, kappa=self.kappa, mu_star=self.mu_star)
+        return osv.build_levels(self.p, X, self.nbr, self.bc, m=self.m, kappa=self.kappa, mu_star=self.mu_star,
+                                weighting=self.weighting, delta=self.delta)
 
     def library(self, binding, **opt):
         X = self.coords(binding.gll(self.p)[0])
-        o = binding.default_options(kappa=self.kappa, mu_star=self.mu_star, overlap=self.m, **opt)
+        extra = dict(weighting=binding.WEIGHT_PLAIN if self.weighting == 'plain' else binding.WEIGHT_QUINTIC)
+        if self.delta is not None:
+            extra.update(overlap=-1, delta=self.delta)
+        else:
+            extra.update(overlap=self.m)
+        o = binding.default_options(kappa=self.kappa, mu_star=self.mu_star, **extra, **opt)
         return binding.Solver(np.full(self.E, self.p, dtype=np.int32), X, self.nbr, self.bc, o)
 
     def __repr__(self):

@@ -106,3 +106,31 @@ def test_bad_options_are_refused_before_any_device_work(lib, bad):
     with pytest.raises(lib.DgfasError) as ei:
         lib.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc, o)
     assert ei.value.code == lib.DGFAS_EINVAL
+
+
+@pytest.mark.parametrize('bad', [dict(start=3), dict(weighting=2), dict(ns2=3, nsc=2),
+                                 dict(overlap=-1, delta=1.0), dict(overlap=-1, delta=-0.1)])
+def test_bad_start_crossover_weighting_and_delta_are_refused(lib, bad):
+    from paper_2608_14123_amd import workloads as W
+    ne, p = 2, 4
+    nbr, bc = W.box_topology(ne, ne, ne)
+    X = W.element_coords(W.box_vertices(ne, ne, ne), lib.gll(p)[0])
+    with pytest.raises(lib.DgfasError) as ei:
+        lib.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc, lib.default_options(**bad))
+    assert ei.value.code == lib.DGFAS_EINVAL
+
+
+@pytest.mark.parametrize('p,kw', [(8, dict(overlap=-1, delta=0.5)), (7, dict(overlap=2)), (5, dict(overlap=3))])
+def test_overlap_without_a_kernel_is_unsupported(lib, p, kw):
+    """delta = 0.5 at p = 8 covers the neighbour's GLL nodes up to its centre: m = 5, for which no
+    Schwarz kernel exists; m = 2 exists only at p = 4 and 8, m = 3 only at p = 8."""
+    from oracle.schwarz import overlap_layers
+    from paper_2608_14123_amd import workloads as W
+    if 'delta' in kw:
+        assert overlap_layers(p, kw['delta']) == 5
+    ne = 2
+    nbr, bc = W.box_topology(ne, ne, ne)
+    X = W.element_coords(W.box_vertices(ne, ne, ne), lib.gll(p)[0])
+    with pytest.raises(lib.DgfasError) as ei:
+        lib.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc, lib.default_options(**kw))
+    assert ei.value.code == lib.DGFAS_EUNSUPPORTED
