@@ -1,10 +1,13 @@
-"""Benchmark: FAS V-cycles with Schwarz-preconditioned CG smoothing on the curved 32^3, p = 7 workload.
+"""Benchmark: the Schwarz sweep and FAS V-cycles on the curved 32^3, p = 7 workload.
 
 One step = one FAS-MG-SCG(3,2) V-cycle (Alg. 2 with Alg. 6 smoothing, p-levels
 7 -> 3 -> 1, SCG root solve) over the 16.8M-DOF curvilinear mesh (sine-bump
 map, mu_star = 5), FP64, inputs resident in HBM.  Prints one JSON line.
-`value` is the whole-job sweep throughput: fine-level DOF times fine-level
-Schwarz sweeps per cycle (ns1 + ns2), divided by the cycle time.
+`value` is the FP64 WAS sweep throughput on the finest level (residual r = g - A u,
+Schwarz application and update u += B r; Alg. 5), median of per-call event timings:
+DOF / sweep time.  Beside it: the same sweep in FP32 and BF16, the Schwarz application and
+one SCG iteration, the time to 1e-10 of the plain, reduced-precision, graph and FMG
+forms with their HBM-roofline time, and the C/OpenMP oracle on the host's cores.
 """
 import argparse
 import json
@@ -39,7 +42,7 @@ def parse():
     ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched'],
                     help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8); '
                          'stretched: 48^3, p = 8, aspect 1:100, 16 right-hand sides')
-    ap.add_argument('--cycles', type=int, default=8, help='stretched workload: V-cycles per solve')
+    ap.add_argument('--cycles', type=int, default=30, help='stretched workload: largest V-cycle count of a solve')
     return ap.parse_args()
 
 
@@ -50,32 +53,80 @@ def build_workload(ne, p, xi):
     return X, nbr, bc
 
 
-def cpu_baseline(ne, p, budget_s=20.0):
-    """Oracle FP64 Schwarz sweep (r = g - A u; u += B r) on an 8^3-element block of the same mesh."""
-    from oracle import solvers as osv
+def host_info():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = 'unknown'
+    try:
+        with open('/proc/cpuinfo') as fh:
+            for line in fh:
+                if line.startswith('model name'):
+                    model = line.split(':', 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count()
+    return {'cpu_model': model, 'nproc': os.cpu_count(), 'allowed_cpus': allowed}
+
+
+def cpu_baseline(ne, p, n10_c2, reps=5):
+    """The C/OpenMP FP64 oracle (O1) on this host's cores: medians of `reps` timed runs after a
+    warm-up of one WAS sweep (residual, Schwarz, update), one Schwarz application and one
+    operator application on the full curved 32^3, p = 7 mesh, one FAS-MG-SCG(3,2) cycle (whose
+    time times the GPU's cycle count estimates the oracle's t10 there), and the full solve of
+    the 4^3, p = 4 unit-cube case."""
+    info = host_info()          # before the OpenMP runtime binds this thread to one CPU
+    os.environ.setdefault('OMP_PROC_BIND', 'close')
+    from oracle import o1
     from oracle.gll import gll as ogll
-    from oracle.mesh import Mesh
     from paper_2608_14123_amd import workloads as W
-    sub = 8
-    V, nbr_full, bc_full, mp = W.curved_cube(ne)
-    Vs = V[:sub + 1, :sub + 1, :sub + 1]
-    nbr, bc = W.box_topology(sub, sub, sub)
-    X = W.element_coords(Vs, ogll(p)[0], mp)
-    lv = osv.Level(Mesh(p, X, nbr, bc, mu_star=5.0), 1)
-    nd = lv.mesh.n_dof()
-    g = W.uniform_nodal(lv.mesh.X[:, 0].shape, 2)
-    u = np.zeros_like(g)
+
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    V, nbr, bc, mp = W.curved_cube(ne)
+    X = W.element_coords(V, ogll(p)[0], mp)
     t0 = time.perf_counter()
-    reps = 0
-    while True:
-        u = osv.was(lv, u, g, 1)
-        reps += 1
-        if time.perf_counter() - t0 > budget_s or reps >= 50:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    return {'value': nd / dt / 1e9, 'unit': 'GDOF/s', 'cores': 1, 'kind': 'oracle',
-            'sample': '%d WAS sweeps (residual + Schwarz + update) on the %d^3-element corner block '
-                      '(%d DOF) of the same mesh, numpy FP64 single thread' % (reps, sub, nd)}
+    fast = o1.O1(p, X, nbr, bc, m=1, mu_star=5.0)
+    setup = time.perf_counter() - t0
+    L = fast.n_levels
+    nd = fast.ndof[L]
+    g = fast.rhs(W.uniform_nodal(nd, 2))
+    u = W.uniform_nodal(nd, 4)
+    s_sweep = med(lambda: fast.smooth(L, u, g, 1, 'was'))
+    s_sz = med(lambda: fast.schwarz(L, g))
+    s_op = med(lambda: fast.apply(L, u))
+    t0 = time.perf_counter()
+    fast.solve(g, smoother='scg', ns1=3, ns2=2, root_rtol=0.1, max_cycles=1, rtol=0.0)
+    s_cycle = time.perf_counter() - t0
+    fast.close()
+    # C1: 4^3 unit cubes, p = 4, f = 3 pi^2 sin sin sin, FAS-MG-WAS(2,2) to 1e-10
+    Vc, nbrc, bcc = W.cartesian_unit_cube(4)
+    Xc = W.element_coords(Vc, ogll(4)[0])
+    c1 = o1.O1(4, Xc, nbrc, bcc)
+    bc1 = c1.rhs((3 * np.pi ** 2 * W.sine_solution(Xc)).ravel())
+    t0 = time.perf_counter()
+    _, h1, _ = c1.solve(bc1, smoother='was', ns1=2, ns2=2, max_cycles=30, rtol=1e-10)
+    t10_c1 = time.perf_counter() - t0
+    c1.close()
+    out = {'value': round(nd / s_sweep / 1e9, 4), 'unit': 'GDOF/s', 'cores': o1.threads(), 'kind': 'oracle',
+           'sample': 'O1 (C/OpenMP, FP64) on the full %d^3, p = %d curved mesh (%d DOF): median of %d WAS sweeps '
+                     '(residual + Schwarz + update) after one warm-up; set-up %.1f s' % (ne, p, nd, reps, setup),
+           'schwarz_gdofs': round(nd / s_sz / 1e9, 4), 'operator_gdofs': round(nd / s_op / 1e9, 4),
+           'c2_cycle_s': round(s_cycle, 3),
+           'c2_t10_estimate_s': round(s_cycle * n10_c2, 2),
+           'c2_t10_estimate_basis': 'one FAS-MG-SCG(3,2) cycle timed, times the %d cycles to 1e-10' % n10_c2,
+           'c1_t10_s': round(t10_c1, 4), 'c1_n10': len(h1) - 1, 'omp_proc_bind': os.environ.get('OMP_PROC_BIND')}
+    out.update(info)
+    return out
 
 
 def front_bench(args, torch, B):
@@ -179,9 +230,10 @@ def front_bench(args, torch, B):
 def stretched_bench(args, torch, B):
     """The anisotropic stress workload: 48^3 elements on [0,1]^2 x [0,100] (aspect 1:100),
     interior vertices perturbed by U[-0.2, 0.2] h_min (seed 4), p = 8 (80,621,568 DOF), 16
-    right-hand sides (nodal U[-1,1], seeds 4000..4015) in one batch, FAS-MG-SCG(12,4).
-    Reports the Schwarz application and one SCG iteration over all 16 right-hand sides, and
-    the first cycles' history and time, FP64 and FP32 smoothers.  Prints one JSON line."""
+    right-hand sides (nodal U[-1,1], seeds 4000..4015) in one batch, FAS-MG-SCG(12,4) with the
+    overlap of delta = 0.24.  Reports the Schwarz application and one SCG iteration over all 16
+    right-hand sides, and the time to 1e-10 (every right-hand side) with FP64 and FP32
+    smoothers.  Prints one JSON line."""
     from paper_2608_14123_amd import workloads as W
     ne, p, R = 48, 8, 16
     E = ne ** 3
@@ -192,7 +244,8 @@ def stretched_bench(args, torch, B):
     f = torch.empty(R * ndof, dtype=torch.float64, device='cuda')
     for k in range(R):
         f[k * ndof:(k + 1) * ndof].copy_(torch.from_numpy(W.uniform_nodal(ndof, 4000 + k)))
-    cyc = dict(smoother=B.SCG, ns1=12, ns2=4, mu_star=5.0, root_rtol=0.1, n_rhs=R)
+    # the paper's overlap for its aspect-ratio tests, delta = 0.24: m = 3 at p = 8, 2 at p = 4
+    cyc = dict(smoother=B.SCG, ns1=12, ns2=4, mu_star=5.0, root_rtol=0.1, n_rhs=R, overlap=-1, delta=0.24)
 
     def timed(fn, reps):
         fn()
@@ -230,8 +283,9 @@ def stretched_bench(args, torch, B):
         t0 = time.perf_counter()
         hist, ok = lib.solve(u, b, max_cycles=args.cycles, rtol=1e-10)
         torch.cuda.synchronize()
-        rec['cycles'] = len(hist) - 1
-        rec['s_per_cycle'] = round((time.perf_counter() - t0) / max(1, len(hist) - 1), 4)
+        rec['t10_s'] = round(time.perf_counter() - t0, 3)
+        rec['n10'] = len(hist) - 1
+        rec['s_per_cycle'] = round(rec['t10_s'] / max(1, len(hist) - 1), 4)
         rec['converged_1e-10'] = bool(ok)
         rec['hist'] = ['%.3e' % h for h in hist]
         print(prec, rec, file=sys.stderr, flush=True)
@@ -244,7 +298,8 @@ def stretched_bench(args, torch, B):
         'warmup': 1, 'ms_per_step': round(modes['fp64']['s_per_cycle'] * 1e3, 2), 'higher_is_better': True,
         'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64', 'data': 'synthetic',
         'config': {'workload': 'stretched_perturbed_48^3_p8_aspect100_16rhs', 'n_dof_per_rhs': ndof, 'n_rhs': R,
-                   'cycle': 'FAS-MG-SCG(12,4), p-levels 8->4->2->1, root SCG to 1e-1', 'mu_star': 5.0},
+                   'cycle': 'FAS-MG-SCG(12,4), p-levels 8->4->2->1, root SCG to 1e-1', 'mu_star': 5.0,
+                   'overlap': 'delta 0.24: m = 3 at p = 8, 2 at p = 4, 1 below'},
         'modes': modes,
     }
     print(json.dumps(out))
@@ -274,12 +329,17 @@ def main():
     f_host = W.uniform_nodal(ndof, 2)
     stream = torch.cuda.current_stream()
     cyc = dict(smoother=B.SCG, ns1=3, ns2=2, mu_star=5.0, root_rtol=0.1)
-    opts = B.default_options(**cyc)
+    degs = np.full(E, p, np.int32)
+
+    def solver(**kw):
+        return B.Solver(degs, X, nbr, bc, B.default_options(**dict(cyc, **kw)), stream=stream.cuda_stream)
+
     t_setup = time.perf_counter()
-    lib = B.Solver(np.full(E, p, np.int32), X, nbr, bc, opts, stream=stream.cuda_stream)
+    lib = solver()
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     L = lib.n_levels
+    level_dofs = [lib.level_info(l)[1] for l in range(1, L + 1)]
     levels_str = '->'.join(str(lib.level_info(l)[0]) for l in range(L, 0, -1))
     f = torch.from_numpy(f_host).cuda()
     b = torch.empty_like(f)
@@ -287,6 +347,7 @@ def main():
     u = torch.zeros_like(b)
     print('setup %.2fs, %d levels, %d DOF' % (t_setup, L, ndof), file=sys.stderr, flush=True)
 
+    # timed steps: FAS-MG-SCG(3,2) V-cycles
     for _ in range(args.warmup):
         lib.vcycle(u, b)
     torch.cuda.synchronize()
@@ -297,39 +358,67 @@ def main():
         lib.vcycle(u, b)
     torch.cuda.synchronize()
     ms_cycle = (time.perf_counter() - t0) * 1e3 / args.steps
-    sweeps = opts.ns1 + opts.ns2
-    value = ndof * sweeps / (ms_cycle * 1e-3) / 1e9
     print('V-cycle %.3f ms' % ms_cycle, file=sys.stderr, flush=True)
 
-    # isolated kernels on the cycle's stream, timed by events on that stream
     g = torch.from_numpy(W.uniform_nodal(ndof, 3)).cuda()
     r = torch.empty_like(g)
     uu = torch.from_numpy(W.uniform_nodal(ndof, 4)).cuda()
 
-    def timed(fn):
+    def med_ms(fn, reps=None):
+        """median of per-call event timings on the library's stream, after one warm-up call"""
+        reps = reps or args.reps
         fn()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(args.reps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record(stream)
             fn()
-        ev1.record(stream)
-        ev1.synchronize()
-        return ev0.elapsed_time(ev1) / args.reps
+            e1.record(stream)
+        evs[-1][1].synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
 
-    ms_res = timed(lambda: lib.residual(L, uu, g, r))
-    ms_sz = timed(lambda: lib.schwarz(L, g, r))
-    ms_sweep = timed(lambda: lib.smooth(L, uu, g, 1))   # residual + one SCG iteration
-    sweep_gdofs = ndof / (ms_sweep * 1e-3) / 1e9
-    print('residual %.3f ms, schwarz %.3f ms, sweep %.3f ms' % (ms_res, ms_sz, ms_sweep), file=sys.stderr,
-          flush=True)
+    def mean_ms(fn, reps=None):
+        """mean over back-to-back calls between two events (the launch duration of one kernel)"""
+        reps = reps or args.reps
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # kernels and sweeps of the FP64 SCG solver on the finest level
+    ms_res = mean_ms(lambda: lib.residual(L, uu, g, r))          # one operator launch
+    ms_sz = med_ms(lambda: lib.schwarz(L, g, r))                # FD solve + overlap add
+    ms_scg1 = med_ms(lambda: lib.smooth(L, uu, g, 1))
+    ms_scg3 = med_ms(lambda: lib.smooth(L, uu, g, 3))
+    ms_scg_it = (ms_scg3 - ms_scg1) / 2                          # one SCG iteration
+    lib_sweeps = {}
+    # WAS sweeps (r = g - A u; u += B r) in each precision: FP64 one call of one step; the
+    # reduced-precision forms time one inner correction sweep as smooth(2) - smooth(1)
+    for key, kw in (('fp64', {}), ('fp32', dict(precision=B.FP32)), ('bf16', dict(precision=B.BF16)),
+                    ('fp32_matrix_cores', dict(precision=B.FP32_MFMA))):
+        w = solver(smoother=B.WAS, **kw)
+        t1 = med_ms(lambda: w.smooth(L, uu, g, 1))
+        if key == 'fp64':
+            ms = t1
+        else:
+            ms = med_ms(lambda: w.smooth(L, uu, g, 2)) - t1
+        w.close()
+        bal = 72.0 if key == 'fp64' else 36.0
+        gd = ndof / (ms * 1e-3) / 1e9
+        lib_sweeps[key] = {'ms': round(ms, 4), 'gdofs': round(gd, 3), 'algorithmic_bytes_per_dof': bal,
+                           'roofline_gdofs': round(HBM_PEAK_GBS / bal, 1), 'frac': round(gd / (HBM_PEAK_GBS / bal), 4)}
+        print('WAS sweep', key, lib_sweeps[key], file=sys.stderr, flush=True)
+    value = lib_sweeps['fp64']['gdofs']
 
     # algorithmic work: the operator's minimum bytes (u, g, r and the geometry as coordinates,
     # 3 x 8 B) and the FD solve's exact flops, each over its measured launch time
-    bytes_res = 48.0 * ndof                      # u, g, coordinates (3 x 8 B), r
+    bytes_res = 48.0 * ndof
     ach_res = bytes_res / (ms_res * 1e-3) / 1e9
     ns = p + 3
     n_int = ne - 2
-    # exact FD flops: 4 (n1+n2+n3) n1 n2 n3 + n1 n2 n3 per subdomain, summed over boundary classes
     sizes = [ns] * n_int + [ns - 1] * 2
     flops_fd = 0.0
     for a in sizes:
@@ -344,36 +433,55 @@ def main():
                and p == OPERATOR_TRAFFIC['p'] else None)
     roof_res = {'kernel': 'sipg_apply_kernel<8,double> (residual)', 'bound': 'hbm', 'achieved': round(ach_res, 1),
                 'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': round(ach_res / HBM_PEAK_GBS, 4),
-                'traffic': traffic, 'traffic_unit': 'bytes per launch', 'algorithmic_bytes': bytes_res}
+                'traffic': traffic, 'traffic_unit': 'bytes per launch', 'algorithmic_bytes': bytes_res,
+                'launch_ms': round(ms_res, 4)}
     roof_fd = {'kernel': 'schwarz_solve_kernel<8,1,double> + overlap add', 'bound': 'alu',
                'achieved': round(ach_fd, 2), 'peak': FP64_PEAK_TFLOPS, 'unit': 'TFLOP/s',
-               'frac': round(ach_fd / FP64_PEAK_TFLOPS, 4), 'traffic': None}
-    dominant, other = (roof_res, roof_fd) if 5 * ms_res >= 4 * ms_sz else (roof_fd, roof_res)
+               'frac': round(ach_fd / FP64_PEAK_TFLOPS, 4), 'traffic': None, 'median_ms': round(ms_sz, 4)}
+    dominant, other = (roof_res, roof_fd) if ms_res >= ms_sz else (roof_fd, roof_res)
+
+    def t10_roof_s(n10, ns1, ns2, nsc, lowp):
+        """Algorithmic time of the n10 cycles at the HBM roof: per cycle the finest level's
+        smoothing iterations (each an operator and a Schwarz application: 72 B/DOF in FP64,
+        36 B/DOF in FP32) plus two FP64 residuals (48 B/DOF), scaled by the coarser levels'
+        share of the DOF; start-ups are not counted."""
+        pre = ns1 if (nsc is None or n10 <= 1) else (ns1 + (n10 - 1) * (nsc - ns2)) / n10
+        per_dof = (pre + ns2) * (36.0 if lowp else 72.0) + 2 * 48.0
+        return n10 * per_dof * sum(level_dofs) / (HBM_PEAK_GBS * 1e9)
 
     t10 = {}
     if not args.no_t10:
-        def time_to_tol(solver, key):
-            hist, ok = solver.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+        def time_to_tol(solver_, key, ns=(3, 2), nsc=None, lowp=False):
+            hist, ok = solver_.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
             torch.cuda.synchronize()
             t_a = time.perf_counter()
-            hist, ok = solver.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
+            hist, ok = solver_.solve(u.zero_(), b, max_cycles=30, rtol=1e-10)
             torch.cuda.synchronize()
-            t10[key] = {'t10_s': round(time.perf_counter() - t_a, 4), 'n10': len(hist) - 1, 'converged': bool(ok),
-                        'final_rho': float(hist[-1])}
+            ts = time.perf_counter() - t_a
+            n10 = len(hist) - 1
+            roof = t10_roof_s(n10, ns[0], ns[1], nsc, lowp)
+            t10[key] = {'t10_s': round(ts, 4), 'n10': n10, 'converged': bool(ok), 'final_rho': float(hist[-1]),
+                        't10_roof_s': round(roof, 5), 't10_over_roof': round(ts / roof, 2)}
             print('t10', key, t10[key], file=sys.stderr, flush=True)
-            solver.close()
+            solver_.close()
 
         time_to_tol(lib, 'fp64')
-        # the other forms of the same cycle: FP32 / BF16 smoothing of the correction system, and
-        # a fixed 16-iteration root solve with every cycle replayed as one captured HIP graph
-        fixed = dict(cyc, root_rtol=0.0, root_max_iter=16, graph=1)
-        for key, kw in (('fp32_smoother', dict(cyc, precision=B.FP32)),
-                        ('bf16_matrix_core_smoother', dict(cyc, precision=B.BF16)),
-                        ('fp32_matrix_core_smoother', dict(cyc, precision=B.FP32_MFMA)),
-                        ('fp64_fixed_root16_whole_cycle_graph', fixed),
-                        ('fp32_smoother_fixed_root16_whole_cycle_graph', dict(fixed, precision=B.FP32))):
-            time_to_tol(B.Solver(np.full(E, p, np.int32), X, nbr, bc, B.default_options(**kw),
-                                 stream=stream.cuda_stream), key)
+        # the other forms of the same cycle: FP32 / BF16 smoothing of the correction system, a
+        # fixed 16-iteration root solve with every cycle one captured HIP graph, and the paper's
+        # start-ups: FAS-FMG-SCG(3,2) and FAS-FMG-SCG(3,2,3) with crossover smoothing (the
+        # paper's best p = 8 method on its Cartesian meshes)
+        fixed = dict(root_rtol=0.0, root_max_iter=16, graph=1)
+        fmg = dict(start=B.START_FMG)
+        for key, kw, nsc, lowp in (
+                ('fp32_smoother', dict(precision=B.FP32), None, True),
+                ('bf16_matrix_core_smoother', dict(precision=B.BF16), None, True),
+                ('fp32_matrix_core_smoother', dict(precision=B.FP32_MFMA), None, True),
+                ('fp64_fixed_root16_whole_cycle_graph', fixed, None, False),
+                ('fp32_smoother_fixed_root16_whole_cycle_graph', dict(fixed, precision=B.FP32), None, True),
+                ('fp64_fmg', fmg, None, False),
+                ('fp32_smoother_fmg_fixed_root16_graph', dict(fmg, precision=B.FP32, **fixed), None, True),
+                ('fp64_fmg_crossover3', dict(fmg, nsc=3), 3, False)):
+            time_to_tol(solver(**kw), key, nsc=nsc, lowp=lowp)
     else:
         lib.close()
 
@@ -390,19 +498,24 @@ def main():
         'ms_per_step': round(ms_cycle, 4), 'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None,
         'dtype': 'f64', 'data': 'synthetic',
         'config': {'workload': 'curved_cube_%d^3_p%d_sine_bump_0.1' % (ne, p), 'n_dof': ndof,
-                   'cycle': 'FAS-MG-SCG(3,2), p-levels %s, root SCG to 1e-1' % levels_str, 'overlap': 1,
-                   'mu_star': 5.0,
-                   'rhs': 'U[-1,1] seed 2'},
+                   'value': 'FP64 WAS sweep (residual + Schwarz + update) on the finest level, median of %d'
+                            % args.reps,
+                   'step': 'one FAS-MG-SCG(3,2) V-cycle, p-levels %s, root SCG to 1e-1' % levels_str,
+                   'overlap': 1, 'mu_star': 5.0, 'rhs': 'U[-1,1] seed 2'},
         'roofline': dominant,
         'roofline_other': other,
-        'sweep_gdofs_isolated': round(sweep_gdofs, 3),
-        'kernel_ms': {'residual': round(ms_res, 4), 'schwarz': round(ms_sz, 4),
-                      'residual_plus_scg_iteration': round(ms_sweep, 4)},
+        'was_sweep': lib_sweeps,
+        'kernel_ms': {'operator_launch': round(ms_res, 4), 'schwarz_application': round(ms_sz, 4),
+                      'scg_iteration': round(ms_scg_it, 4)},
+        'schwarz_gdofs': round(ndof / (ms_sz * 1e-3) / 1e9, 3),
+        'scg_iteration_gdofs': round(ndof / (ms_scg_it * 1e-3) / 1e9, 3),
+        'cycle_gdofs_5_sweeps': round(ndof * 5 / (ms_cycle * 1e-3) / 1e9, 3),
         't10': t10,
         'setup_s': round(t_setup, 3),
     }
     if not args.no_cpu:
-        out['cpu_baseline'] = cpu_baseline(ne, p)
+        n10 = t10.get('fp64', {}).get('n10', 22)
+        out['cpu_baseline'] = cpu_baseline(ne, p, n10)
     print(json.dumps(out))
 
 
