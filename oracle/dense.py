@@ -48,7 +48,9 @@ class DenseHierarchy:
     def __init__(self, levels):
         self.A = [op.assemble(lv.mesh) for lv in levels]
         self.B = [schwarz_matrix(lv) for lv in levels]
-        self.T = [None] + [transfer_matrices(levels[l].mesh.E, levels[l - 1].p, levels[l].p)
+        from .hmg import dense_transfers
+        self.T = [None] + [dense_transfers(levels[l].down) if getattr(levels[l], 'down', None) is not None
+                           else transfer_matrices(levels[l].mesh.E, levels[l - 1].p, levels[l].p)
                            for l in range(1, len(levels))]
 
 

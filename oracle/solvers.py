@@ -69,6 +69,23 @@ def norm(v):
     return float(np.sqrt(np.sum(np.asarray(v) ** 2)))
 
 
+# transfers between level lv and the next coarser level lc: p-coarsening (Sec. 3.2, per element)
+# or, when lv carries an h-coarsening in `down` (oracle.hmg), the parent/children transfers
+def t_project(lc, lv, u, kind='interp'):
+    ht = getattr(lv, 'down', None)
+    return ht.project(u) if ht is not None else tr.project(lc.p, lv.p, u, kind)
+
+
+def t_restrict(lc, lv, r):
+    ht = getattr(lv, 'down', None)
+    return ht.restrict(r) if ht is not None else tr.restrict(lc.p, lv.p, r)
+
+
+def t_prolong(lc, lv, uc):
+    ht = getattr(lv, 'down', None)
+    return ht.prolong(uc) if ht is not None else tr.prolong(lc.p, lv.p, uc)
+
+
 def was(level, u, f, n_i):
     """Alg. 5 (weighted additive Schwarz)."""
     for _ in range(n_i):
@@ -112,8 +129,9 @@ class Options:
     steps nsc on the top level between cycles (default ns1 + ns2, i.e. none)."""
 
     def __init__(self, smoother='was', ns1=2, ns2=2, root_rtol=1e-12, root_maxit=500, first_dir='z',
-                 root='scg', start=None, ns0=None, nsc=None):
+                 root='scg', start=None, ns0=None, nsc=None, projection='interp'):
         self.smoother, self.ns1, self.ns2 = smoother, ns1, ns2
+        self.projection = projection
         self.root_rtol, self.root_maxit, self.first_dir = root_rtol, root_maxit, first_dir
         self.root = root
         self.start = start
@@ -152,13 +170,13 @@ def fas_vcycle(levels, u_top, f_top, opts, ns1_top=None):
         n1 = ns1_top if (l == L - 1 and ns1_top is not None) else opts.ns1
         u[l] = smooth(lv, u[l], g[l], n1, opts)
         r = g[l] - lv.A(u[l])
-        ubar[l - 1] = tr.project(lc.p, lv.p, u[l])
+        ubar[l - 1] = t_project(lc, lv, u[l], opts.projection)
         u[l - 1] = ubar[l - 1].copy()
-        g[l - 1] = lc.A(u[l - 1]) + tr.restrict(lc.p, lv.p, r)
+        g[l - 1] = lc.A(u[l - 1]) + t_restrict(lc, lv, r)
     u[0] = root_solve(levels[0], u[0], g[0], opts)
     for l in range(1, L):
         lv, lc = levels[l], levels[l - 1]
-        u[l] = u[l] + tr.prolong(lc.p, lv.p, u[l - 1] - ubar[l - 1])
+        u[l] = u[l] + t_prolong(lc, lv, u[l - 1] - ubar[l - 1])
         u[l] = smooth(lv, u[l], g[l], opts.ns2, opts)
     return u[L - 1]
 
@@ -187,7 +205,7 @@ def level_rhs(levels, f_top):
     fs = [None] * len(levels)
     fs[-1] = f_top
     for l in range(len(levels) - 1, 0, -1):
-        fs[l - 1] = tr.restrict(levels[l - 1].p, levels[l].p, fs[l])
+        fs[l - 1] = t_restrict(levels[l - 1], levels[l], fs[l])
     return fs
 
 
@@ -195,7 +213,7 @@ def _start_values(levels, u_top):
     us = [None] * len(levels)
     us[-1] = u_top
     for l in range(len(levels) - 1, 0, -1):
-        us[l - 1] = tr.project(levels[l - 1].p, levels[l].p, us[l])
+        us[l - 1] = t_project(levels[l - 1], levels[l], us[l])
     return us
 
 
@@ -205,9 +223,9 @@ def cmg_start(levels, u_top, f_top, opts):
     fs, us = level_rhs(levels, f_top), _start_values(levels, u_top)
     u = root_solve(levels[0], us[0], fs[0], opts)
     for l in range(1, L - 1):
-        u = tr.prolong(levels[l - 1].p, levels[l].p, u)
+        u = t_prolong(levels[l - 1], levels[l], u)
         u = smooth(levels[l], u, fs[l], opts.ns0, opts)
-    return tr.prolong(levels[L - 2].p, levels[L - 1].p, u) if L > 1 else u
+    return t_prolong(levels[L - 2], levels[L - 1], u) if L > 1 else u
 
 
 def fmg_start(levels, u_top, f_top, opts):
@@ -217,7 +235,7 @@ def fmg_start(levels, u_top, f_top, opts):
     u = us[0]
     for l in range(1, L):
         u = fas_vcycle(levels[:l], u, fs[l - 1], opts)
-        u = tr.prolong(levels[l - 1].p, levels[l].p, u)
+        u = t_prolong(levels[l - 1], levels[l], u)
     return u if L > 1 else fas_vcycle(levels, u, fs[0], opts)
 
 

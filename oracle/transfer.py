@@ -33,9 +33,21 @@ def restrict(pc, pf, rf):
     return tensor3(interp_1d(pc, pf).T, rf)
 
 
-def project(pc, pf, uf):
-    """P: fine solution -> coarse by evaluation at the coarse GLL nodes."""
-    return tensor3(interp_1d(pf, pc), uf)
+def l2_project_1d(p_from, p_to):
+    """Reference-element L2 projection of a degree-p_from nodal polynomial onto degree p_to < p_from
+    (Sec. 3.2 names L2 projection beside embedded interpolation): P = (I^T W I)^-1 I^T W with
+    I = interp_1d(p_to, p_from) and W the p_from GLL weights.  The p_from GLL rule integrates
+    every product involved exactly (degree <= p_to + p_from <= 2 p_from - 1)."""
+    I = interp_1d(p_to, p_from)
+    _, w = gll(p_from)
+    return np.linalg.solve(I.T @ (w[:, None] * I), I.T * w[None, :])
+
+
+def project(pc, pf, uf, kind='interp'):
+    """P: fine solution -> coarse, by evaluation at the coarse GLL nodes (embedded interpolation)
+    or by the L2 projection of l2_project_1d (kind 'l2')."""
+    T = interp_1d(pf, pc) if kind == 'interp' else l2_project_1d(pf, pc)
+    return tensor3(T, uf)
 
 
 def coarse_coords(pc, pf, X):

@@ -134,3 +134,21 @@ def test_p_convergence_exponential():
     e = [_solve_error(p, 2, 0.0) for p in (2, 3, 4, 5, 6)]
     assert all(e[i + 1] < 0.5 * e[i] for i in range(len(e) - 1)), e
     assert e[-1] < 1e-4
+
+
+@pytest.mark.parametrize('pf', [2, 3, 4, 7, 8])
+def test_l2_projection_is_the_orthogonal_projection(pf):
+    """The 1D L2 projection onto degree pc = pf // 2 reproduces coarse polynomials (P I = Id) and
+    leaves a residual orthogonal to every coarse polynomial, checked with Gauss-Legendre
+    quadrature of pf + 2 points (exact for the products, independent of the GLL rule)."""
+    from oracle.transfer import l2_project_1d, interp_1d
+    from oracle.gll import lagrange_eval
+    pc = max(1, pf // 2)
+    P = l2_project_1d(pf, pc)
+    assert np.abs(P @ interp_1d(pc, pf) - np.eye(pc + 1)).max() < 1e-13
+    xf, _ = gll(pf)
+    xc, _ = gll(pc)
+    xq, wq = np.polynomial.legendre.leggauss(pf + 2)
+    uf = np.random.default_rng(pf).standard_normal(pf + 1)
+    res = lagrange_eval(xf, xq) @ uf - lagrange_eval(xc, xq) @ (P @ uf)
+    assert np.abs(lagrange_eval(xc, xq).T @ (wq * res)).max() < 1e-13
