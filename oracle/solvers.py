@@ -95,7 +95,8 @@ def was(level, u, f, n_i):
 
 
 def scg(level, u, f, n_i, r_max=0.0, first_dir='z', precond=None, stats=None):
-    """Alg. 6 (Schwarz-preconditioned inexact CG); exits when ||r|| <= r_max."""
+    """Alg. 6 (Schwarz-preconditioned inexact CG); exits when ||r|| <= r_max, or when p^T A p <= 0
+    makes the step length undefined (breakdown), with the last iterate."""
     B = level.B if precond is None else precond
     r = f - level.A(u)
     p = r.copy() if first_dir == 'r' else None
@@ -111,7 +112,10 @@ def scg(level, u, f, n_i, r_max=0.0, first_dir='z', precond=None, stats=None):
             p = z.copy()
         q = level.A(p)
         gamma = np.sum(z * r)
-        alpha = gamma / np.sum(p * q)
+        pq = np.sum(p * q)
+        if not pq > 0:          # alpha = gamma / p^T A p is undefined: stop with the last iterate
+            break
+        alpha = gamma / pq
         r0 = r
         r = r - alpha * q
         u = u + alpha * p
