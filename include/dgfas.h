@@ -55,6 +55,7 @@ enum { DGFAS_BATCH_PER_DEGREE = 0, DGFAS_BATCH_ONE_LAUNCH = 1, DGFAS_BATCH_TUNED
 enum { DGFAS_ORDER_NATURAL = 0, DGFAS_ORDER_MORTON = 1 };
 enum { DGFAS_START_NONE = 0, DGFAS_START_CMG = 1, DGFAS_START_FMG = 2 };
 enum { DGFAS_WEIGHT_QUINTIC = 0, DGFAS_WEIGHT_PLAIN = 1 };
+enum { DGFAS_PROJECT_INTERP = 0, DGFAS_PROJECT_L2 = 1 };
 
 typedef struct dgfas_solver_s* dgfas_solver;
 
@@ -73,6 +74,9 @@ typedef struct {
                                must keep det J > 0 */
   const int32_t* face_nbr;  /* [n_elem][6] neighbour element, or -1 on the boundary */
   const int8_t* face_bc;    /* [n_elem][6] DGFAS_DIRICHLET / DGFAS_NEUMANN on boundary faces */
+  int32_t box[3];           /* h-coarsening only (options.h_levels > 0): the mesh is a box of
+                               nx x ny x nz elements numbered e = ex + nx (ey + ny ez), its face
+                               neighbours those of the box or its periodic wraps; else ignored */
 } dgfas_mesh_desc;
 
 /* Solver options.  Defaults come from dgfas_default_options. */
@@ -127,7 +131,17 @@ typedef struct {
   int32_t weighting;        /* DGFAS_WEIGHT_QUINTIC (the partition of unity of Sec. 4.3.1) or
                                DGFAS_WEIGHT_PLAIN (W = I: plain additive Schwarz) */
   double delta;             /* overlap width in the standard element when overlap < 0, 0 <= delta < 1 */
-  int32_t reserved[2];
+  int32_t projection;       /* FAS solution projection P (Sec. 3.2): DGFAS_PROJECT_INTERP (embedded
+                               interpolation: evaluation at the coarse GLL nodes) or DGFAS_PROJECT_L2
+                               (reference-element L2 projection (I^T W I)^-1 I^T W per direction) */
+  int32_t h_levels;         /* h-coarsening (Sec. 3.1): the finest box mesh is coarsened h_levels
+                               times into parents of 2 x 2 x 2 children at the same degree, with the
+                               transfers of Sec. 3.2 (I embedded, R = I^T, P the children's fields at
+                               the parent's nodes averaged where they meet); needs one degree and
+                               mesh.box.  0: none */
+  int32_t h_only;           /* with h_levels > 0: 1 makes the coarsest h-level the root (pure h-MG,
+                               root SCG at the fine degree); 0 p-coarsens it down to p = 1 */
+  int32_t reserved[1];
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);
@@ -158,6 +172,20 @@ dgfas_status dgfas_level_info(dgfas_solver s, int32_t level, int32_t* degree, in
 /* Schwarz overlap m (node layers) of a level's largest degree, as set by overlap or delta; the
  * subdomain tile of that degree has ns = degree + 1 + 2m nodes per direction. */
 dgfas_status dgfas_level_overlap(dgfas_solver s, int32_t level, int32_t* m);
+
+/* Workspace: the per-call scratch of the configured cycle (the work vectors of every level,
+ * the overlap inboxes, reduction partials and SCG scalars; no state is kept in it between
+ * calls).  After dgfas_create it is one library-owned device block of workspace_size bytes.
+ * dgfas_set_workspace hands in a caller-owned device buffer instead (for example a torch
+ * tensor): at least that many bytes, 256-byte aligned, kept alive by the caller until the
+ * solver is destroyed or another workspace is set; the library then frees its block, so the
+ * configured cycle runs in caller-owned memory only (the geometry and tables stay the
+ * library's).  dptr = NULL returns to a library-owned block.  The call synchronises the stream
+ * first, clears what must start at zero, and drops captured graphs.  Work that the configured
+ * cycle does not do (dgfas_root_solve on a level without SCG vectors, the learned correction)
+ * may still allocate its buffers on first use. */
+dgfas_status dgfas_workspace_size(dgfas_solver s, size_t* bytes);
+dgfas_status dgfas_set_workspace(dgfas_solver s, void* dptr, size_t bytes);
 
 /* Right-hand side of eq. helmholtz:system on the finest level from nodal values
  * (device): f [n_dof], uD [n_dof] (values at Dirichlet face nodes are used; may be

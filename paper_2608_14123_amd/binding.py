@@ -27,13 +27,14 @@ BATCH_PER_DEGREE, BATCH_ONE_LAUNCH, BATCH_TUNED = 0, 1, 2
 ORDER_NATURAL, ORDER_MORTON = 0, 1
 START_NONE, START_CMG, START_FMG = 0, 1, 2
 WEIGHT_QUINTIC, WEIGHT_PLAIN = 0, 1
+PROJECT_INTERP, PROJECT_L2 = 0, 1
 
 c_dp = ctypes.POINTER(ctypes.c_double)
 
 
 class MeshDesc(ctypes.Structure):
     _fields_ = [('n_elem', ctypes.c_int32), ('degree', ctypes.c_void_p), ('coords', ctypes.c_void_p),
-                ('face_nbr', ctypes.c_void_p), ('face_bc', ctypes.c_void_p)]
+                ('face_nbr', ctypes.c_void_p), ('face_bc', ctypes.c_void_p), ('box', ctypes.c_int32 * 3)]
 
 
 class Options(ctypes.Structure):
@@ -43,7 +44,8 @@ class Options(ctypes.Structure):
                 ('precision', ctypes.c_int32), ('n_rhs', ctypes.c_int32), ('batch', ctypes.c_int32),
                 ('graph', ctypes.c_int32), ('order', ctypes.c_int32), ('start', ctypes.c_int32),
                 ('ns0', ctypes.c_int32), ('nsc', ctypes.c_int32), ('weighting', ctypes.c_int32),
-                ('delta', ctypes.c_double), ('reserved', ctypes.c_int32 * 2)]
+                ('delta', ctypes.c_double), ('projection', ctypes.c_int32), ('h_levels', ctypes.c_int32),
+                ('h_only', ctypes.c_int32), ('reserved', ctypes.c_int32 * 1)]
 
 
 class DgfasError(RuntimeError):
@@ -63,6 +65,8 @@ _sig = {
     'dgfas_levels': (_I, [_V, ctypes.POINTER(_I)]),
     'dgfas_level_info': (_I, [_V, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64)]),
     'dgfas_level_overlap': (_I, [_V, _I, ctypes.POINTER(_I)]),
+    'dgfas_workspace_size': (_I, [_V, ctypes.POINTER(ctypes.c_size_t)]),
+    'dgfas_set_workspace': (_I, [_V, _V, ctypes.c_size_t]),
     'dgfas_rhs': (_I, [_V, _V, _V, _V, _V]),
     'dgfas_apply': (_I, [_V, _I, _V, _V]),
     'dgfas_residual': (_I, [_V, _I, _V, _V, _V]),
@@ -143,7 +147,7 @@ def schwarz_tables_1d(p, m, left, right, mu_star):
 class Solver:
     """One level hierarchy on the current device (see dgfas_create)."""
 
-    def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None):
+    def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None, box=None):
         degree = np.ascontiguousarray(degree, dtype=np.int32)
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         face_nbr = np.ascontiguousarray(face_nbr, dtype=np.int32)
@@ -154,7 +158,8 @@ class Solver:
         if coords.size != int(3 * np.sum((degree.astype(np.int64) + 1) ** 3)):
             raise ValueError('coords must hold 3 (p_e+1)^3 values per element')
         self._keep = (degree, coords, face_nbr, face_bc)
-        desc = MeshDesc(E, degree.ctypes.data, coords.ctypes.data, face_nbr.ctypes.data, face_bc.ctypes.data)
+        desc = MeshDesc(E, degree.ctypes.data, coords.ctypes.data, face_nbr.ctypes.data, face_bc.ctypes.data,
+                        (ctypes.c_int32 * 3)(*(box or (0, 0, 0))))
         self.options = options if options is not None else default_options()
         h = _V()
         st = None if stream is None else _V(stream)
@@ -188,6 +193,21 @@ class Solver:
         nd = ctypes.c_int64()
         _check(_lib.dgfas_level_info(self._h, level, ctypes.byref(d), ctypes.byref(nd)))
         return d.value, nd.value
+
+    def workspace_size(self):
+        n = ctypes.c_size_t()
+        _check(_lib.dgfas_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def set_workspace(self, buf):
+        """Use a caller-owned device tensor (uint8, at least workspace_size() bytes) as the
+        workspace, or None for a library-owned block; the tensor is kept alive here."""
+        if buf is None:
+            _check(_lib.dgfas_set_workspace(self._h, None, 0))
+        else:
+            _check(_lib.dgfas_set_workspace(self._h, _dev(buf, self.workspace_size(), 'workspace', 'uint8'),
+                                            buf.numel()))
+        self._ws = buf
 
     def level_overlap(self, level):
         m = _I()

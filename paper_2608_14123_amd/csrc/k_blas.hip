@@ -107,6 +107,82 @@ bool tensor3(int n_in, int n_out, const XferArgs<T>& a, hipStream_t st) {
 template bool tensor3<double>(int, int, const XferArgs<double>&, hipStream_t);
 template bool tensor3<float>(int, int, const XferArgs<float>&, hipStream_t);
 
+// One workgroup per (parent, component, right-hand side), one thread per node: kinds 0 and 1
+// gather the eight children (each contracted with its bits' 1D matrices through LDS, summed in
+// child order), kind 2 contracts the parent's block once per child and adds it there.
+template <int N, typename T>
+__global__ void __launch_bounds__((N * N * N + 63) / 64 * 64) htransfer_kernel(HXferArgs<T> a) {
+  constexpr int N2 = N * N, N3 = N * N * N;
+  const int nsub = a.nrhs * a.ncomp;
+  const int parent = blockIdx.x / nsub, sub = blockIdx.x - parent * nsub;
+  if (parent >= a.ncoarse) return;
+  const int rhs = sub / a.ncomp, comp = sub - rhs * a.ncomp;
+  const int q = threadIdx.x;
+  const bool act = q < N3;
+  const int x = q % N, y = (q / N) % N, z = q / N2;
+  __shared__ T sM[6][N2];
+  __shared__ T s0[N3], s1[N3], s2[N3];
+  for (int t = q; t < 6 * N2; t += blockDim.x) sM[t / N2][t % N2] = a.M[t];
+  const int64_t cb = (int64_t)rhs * a.stride_c + ((int64_t)parent * a.ncomp + comp) * N3;
+  // out_node = sum_k Mz[z][k] sum_j My[y][j] sum_i Mx[x][i] s0[k][j][i]
+  auto contract = [&](const T* Mx, const T* My, const T* Mz) -> T {
+    __syncthreads();
+    if (act) {
+      T v = 0;
+      for (int i = 0; i < N; ++i) v += Mx[x * N + i] * s0[(z * N + y) * N + i];
+      s1[q] = v;
+    }
+    __syncthreads();
+    if (act) {
+      T v = 0;
+      for (int j = 0; j < N; ++j) v += My[y * N + j] * s1[(z * N + j) * N + x];
+      s2[q] = v;
+    }
+    __syncthreads();
+    T v = 0;
+    if (act)
+      for (int k = 0; k < N; ++k) v += Mz[z * N + k] * s2[(k * N + y) * N + x];
+    return v;
+  };
+  if (a.kind <= 1) {
+    const int m0 = a.kind == 0 ? 0 : 2;
+    T acc = 0;
+    for (int c = 0; c < 8; ++c) {
+      const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
+      const int child = a.children[(int64_t)parent * 8 + c];
+      __syncthreads();   // the previous child's contraction has read s0
+      if (act) s0[q] = a.in[(int64_t)rhs * a.stride_f + ((int64_t)child * a.ncomp + comp) * N3 + q];
+      acc += contract(sM[m0 + bx], sM[m0 + by], sM[m0 + bz]);
+    }
+    if (act) a.out[cb + q] = a.accumulate ? a.out[cb + q] + acc : acc;
+  } else {
+    if (act) s0[q] = a.in[cb + q] - (a.in2 ? a.in2[cb + q] : T(0));
+    for (int c = 0; c < 8; ++c) {
+      const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
+      const int child = a.children[(int64_t)parent * 8 + c];
+      const T v = contract(sM[4 + bx], sM[4 + by], sM[4 + bz]);
+      if (act) {
+        T& o = a.out[(int64_t)rhs * a.stride_f + ((int64_t)child * a.ncomp + comp) * N3 + q];
+        o = a.accumulate ? o + v : v;   // every child node belongs to one parent: written once
+      }
+    }
+  }
+}
+
+template <typename T>
+bool htransfer(int p, const HXferArgs<T>& a, hipStream_t st) {
+  if (a.ncoarse <= 0) return true;
+  const dim3 g((unsigned)((int64_t)a.ncoarse * a.nrhs * a.ncomp));
+  switch (p) {
+#define HTC(P) \
+  case P: hipLaunchKernelGGL((htransfer_kernel<P + 1, T>), g, dim3(((P + 1) * (P + 1) * (P + 1) + 63) / 64 * 64), 0, st, a); return true;
+    HTC(1) HTC(2) HTC(3) HTC(4) HTC(5) HTC(6) HTC(7) HTC(8)
+#undef HTC
+    default: return false;
+  }
+}
+template bool htransfer<double>(int, const HXferArgs<double>&, hipStream_t);
+
 // ---------------------------------------------------------------------------
 constexpr int kRedThreads = 256;
 

@@ -203,6 +203,28 @@ struct XferArgs {
 template <typename T>
 bool tensor3(int n_in, int n_out, const XferArgs<T>& a, hipStream_t st);
 
+// Transfers across one h-coarsening (Sec. 3.2) on uniform levels of degree N - 1: a parent and
+// its eight children c = bx + 2 by + 4 bz, child b covering xi in [-1, 0] (b = 0) or [0, 1] of
+// the parent in each direction.  kind 0: out = P in (children -> parent, the children's fields at
+// the parent's nodes, averaged where shared); 1: out (=|+=) R in, R = I^T; 2: out (=|+=) I (in - in2)
+// (parent -> children).  Element e's block of component c and right-hand side k starts at
+// k stride + (e ncomp + c) N^3.
+template <typename T>
+struct HXferArgs {
+  int kind = 0;
+  int ncoarse = 0;                   // parents
+  const int* children = nullptr;     // [ncoarse][8] fine element ids
+  int ncomp = 1, nrhs = 1;
+  int64_t stride_f = 0, stride_c = 0;
+  const T* M = nullptr;              // [6][N][N]: P_0, P_1, R_0 = I_0^T, R_1 = I_1^T, I_0, I_1
+  const T* in = nullptr;
+  const T* in2 = nullptr;            // subtracted from in when non-null (kind 2)
+  T* out = nullptr;
+  int accumulate = 0;                // add to out
+};
+template <typename T>
+bool htransfer(int p, const HXferArgs<T>& a, hipStream_t st);
+
 int reduction_blocks(int64_t n);
 
 }  // namespace dgfas

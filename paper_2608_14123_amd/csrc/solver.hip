@@ -121,6 +121,16 @@ struct Bucket {
 struct Level {
   int p = 0, n = 0, N2 = 0, N3 = 0, E = 0, m = 0, ns = 0;   // p: largest degree on the level
   bool uniform = true;
+  // topology of this level (a level below an h-coarsening has an eighth of the elements)
+  int* nbr = nullptr;
+  int8_t* bc = nullptr;
+  std::vector<int> h_nbr;
+  std::vector<int8_t> h_bc;
+  int box[3] = {0, 0, 0};
+  // the next coarser level is this one h-coarsened (Sec. 3.1): parents of 2 x 2 x 2 children
+  bool hdown = false;
+  int* hchild = nullptr;                // [E of the coarser level][8] children of every parent
+  double* hM = nullptr;                 // [6][n][n] P_0, P_1, I_0^T, I_1^T, I_0, I_1
   int64_t ndof = 0, nfs = 0, nin = 0;   // nodes, face-node slots and inbox slots per right-hand side
   double inv_wend = 0;
   std::vector<int> h_deg;
@@ -225,11 +235,47 @@ struct Solver {
     if (p) owned.push_back(p);
     return p;
   }
+  // Workspace: the per-call scratch of the configured cycle (work vectors of every level,
+  // overlap inboxes, reduction partials, SCG scalars).  Slots are registered during set-up and
+  // laid out in one block, 256-byte aligned; the block is the library's own until
+  // dgfas_set_workspace hands in a caller's buffer.  The slots carry no state between calls.
+  struct WsSlot {
+    void** p;
+    size_t bytes;
+    int zero;          // 0: none, 8 / 4: cleared as doubles / floats when assigned
+  };
+  std::vector<WsSlot> ws;
+  void* ws_block = nullptr;   // library-owned block, null while a caller's buffer is in use
+  size_t ws_bytes = 0;
+  template <typename T>
+  void reserve(T*& slot, size_t n, bool zero = false) {
+    slot = nullptr;
+    if (n) ws.push_back({reinterpret_cast<void**>(&slot), n * sizeof(T), zero ? (int)sizeof(T) : 0});
+  }
+  static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+  size_t ws_layout() const {
+    size_t off = 0;
+    for (const WsSlot& w : ws) off = align256(off) + w.bytes;
+    return align256(off);
+  }
+  void ws_assign(char* base) {
+    size_t off = 0;
+    for (const WsSlot& w : ws) {
+      off = align256(off);
+      *w.p = base + off;
+      if (w.zero == 8) fill((int64_t)(w.bytes / 8), static_cast<double*>(*w.p), 0.0, st);
+      if (w.zero == 4) fill((int64_t)(w.bytes / 4), static_cast<float*>(*w.p), 0.0f, st);
+      off += w.bytes;
+    }
+    for (Level& L : lv) L.rsm = nullptr;
+    ++graph_epoch;   // captured graphs hold the old addresses
+  }
   ~Solver() {
     if (st) hipStreamSynchronize(st);
     drop_graphs();
     if (cap) hipStreamDestroy(cap);
     for (void* p : owned) hipFree(p);
+    if (ws_block) hipFree(ws_block);
   }
   void drop_graphs() {
     if (gdown) hipGraphExecDestroy(gdown);
@@ -281,7 +327,7 @@ struct Solver {
     if (L.nm) {
       MortarArgs<T> m;
       m.nel = L.nm; m.elist = L.mlist; m.nrhs = nrhs; m.ndof = L.ndof; m.u = u; m.out = out; m.mode = mode;
-      m.deg = L.deg; m.off = L.off; m.offF = L.offF; m.nbr = nbr; m.ws = L.ws; m.muf = L.muf;
+      m.deg = L.deg; m.off = L.off; m.offF = L.offF; m.nbr = L.nbr; m.ws = L.ws; m.muf = L.muf;
       m.Dall = Dall; m.Iall = Iall;
       m.nface = L.nmf; m.ftask = L.mftask; m.fmap = L.mfmap; m.fres = L.mfres;
       if constexpr (sizeof(T) == 8) m.G = L.G;
@@ -360,6 +406,14 @@ struct Solver {
   // kind 0: out = P in (projection), 1: out (+)= R in (restriction), 2: out += I (in - in2)
   // (prolongation), per element from the fine level's buckets
   void transfer(Level& F, Level& C, int kind, const double* in, const double* in2, double* out, int acc) {
+    if (F.hdown) {
+      HXferArgs<double> a;
+      a.kind = kind; a.ncoarse = C.E; a.children = F.hchild; a.nrhs = nrhs;
+      a.stride_f = F.ndof; a.stride_c = C.ndof; a.M = F.hM;
+      a.in = in; a.in2 = in2; a.out = out; a.accumulate = acc;
+      if (!htransfer<double>(F.p, a, st)) throw Error(DGFAS_EUNSUPPORTED, "no h-transfer kernel for this degree");
+      return;
+    }
     for (const Bucket& b : F.bk) {
       XferArgs<double> a;
       a.Tm = kind == 0 ? b.Pm : (kind == 1 ? b.Rm : b.Im);
@@ -826,8 +880,8 @@ OpArgs<T> Solver::op_args(Level& L, const Bucket& b, int mode, const T* u, const
   a.g = g;
   a.out = out;
   a.mode = mode;
-  a.nbr = nbr;
-  a.bc = bc;
+  a.nbr = L.nbr;
+  a.bc = L.bc;
   a.kappa = (T)opt.kappa;
   a.inv_wend = (T)b.t->inv_wend;
   if constexpr (sizeof(T) == 8) {
@@ -930,8 +984,7 @@ DegTab& deg_tab(Solver& s, int p) {
 // Level set-up from per-element degrees and device coordinates (element e at 3 off[e]).
 void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double* dX) {
   hipStream_t st = s.st;
-  const int E = s.E;
-  L.E = E;
+  const int E = L.E;   // set by the caller with the level's topology
   L.h_deg = deg;
   L.p = *std::max_element(deg.begin(), deg.end());
   L.uniform = *std::min_element(deg.begin(), deg.end()) == L.p;
@@ -964,9 +1017,9 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       if (deg[e] == p) b.h_elist.push_back(e);
     if (b.h_elist.empty()) continue;
     b.p = p; b.n = p + 1; b.nel = (int)b.h_elist.size();
-    if (!s.rank.empty())
+    if (!s.rank.empty() && L.E == s.E)
       std::stable_sort(b.h_elist.begin(), b.h_elist.end(), [&](int x, int y) { return s.rank[x] < s.rank[y]; });
-    if (!L.uniform || !s.rank.empty()) b.elist = s.own(upload(b.h_elist, st));
+    if (!L.uniform || (!s.rank.empty() && L.E == s.E)) b.elist = s.own(upload(b.h_elist, st));
     b.t = &deg_tab(s, p);
     L.all_m1 = L.all_m1 && b.t->m == 1;
     L.bk.push_back(std::move(b));
@@ -1004,7 +1057,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     for (int e = 0; e < E; ++e) {
       bool any = false;
       for (int f = 0; f < 6; ++f) {
-        const int en = s.h_nbr[e * 6 + f];
+        const int en = L.h_nbr[e * 6 + f];
         any = any || (en >= 0 && deg[en] != deg[e]);
       }
       if (any) ml.push_back(e);
@@ -1019,7 +1072,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       for (int li = 0; li < L.nm; ++li) {
         const int e = ml[li];
         for (int f = 0; f < 6; ++f) {
-          const int en = s.h_nbr[e * 6 + f];
+          const int en = L.h_nbr[e * 6 + f];
           if (en >= 0 && deg[en] != deg[e] && e < en) {
             const int k = (int)ft.size();
             fm[(size_t)li * 6 + f] = 2 * k;
@@ -1031,7 +1084,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       L.nmf = (int)ft.size();
       L.mftask = s.own(upload(ft, st));
       L.mfmap = s.own(upload(fm, st));
-      L.mfres = s.own(dalloc<double>((size_t)s.nrhs * 2 * L.nmf * 4 * 81));
+      s.reserve(L.mfres, (size_t)s.nrhs * 2 * L.nmf * 4 * 81);
     }
   }
   // geometry per bucket
@@ -1052,7 +1105,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     geometry(b.p, g, b.t->D, b.t->w1, b.t->x1, s.opt.nu, st);
     HIPC(hipGetLastError());
   }
-  penalty(E, L.p, L.deg, L.offF, s.opt.mu_star, s.opt.nu, s.nbr, s.bc, L.vol, L.area, L.ws, L.pen, L.muf, st);
+  penalty(E, L.p, L.deg, L.offF, s.opt.mu_star, s.opt.nu, L.nbr, L.bc, L.vol, L.area, L.ws, L.pen, L.muf, st);
   HIPC(hipGetLastError());
   int hbad = 0;
   HIPC(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1106,9 +1159,9 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       int code[2];
       for (int sd = 0; sd < 2; ++sd) {
         const int f = kFace[d][sd];
-        const int en = s.h_nbr[e * 6 + f];
+        const int en = L.h_nbr[e * 6 + f];
         if (en >= 0) code[sd] = deg[en] == deg[e] ? kInterior : kInteriorNoOverlap;
-        else code[sd] = s.h_bc[e * 6 + f] == DGFAS_NEUMANN ? kNeumann : kDirichlet;
+        else code[sd] = L.h_bc[e * 6 + f] == DGFAS_NEUMANN ? kNeumann : kDirichlet;
       }
       var[e * 3 + d] = (int8_t)(code[0] * kSides + code[1]);
     }
@@ -1118,7 +1171,7 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
           int cur = e;
           const int dd[3] = {d1, d2, d3};
           for (int d = 0; d < 3 && cur >= 0; ++d)
-            if (dd[d]) cur = s.h_nbr[cur * 6 + kFace[d][dd[d] > 0]];
+            if (dd[d]) cur = L.h_nbr[cur * 6 + kFace[d][dd[d] > 0]];
           nb27[e * 27 + (d3 + 1) * 9 + (d2 + 1) * 3 + (d1 + 1)] = cur;
         }
   }
@@ -1160,44 +1213,41 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       L.cinv32 = s.own(upload(to_float(C), st));
     }
   }
+  // Per-call scratch of the configured cycle: reserved in the workspace, which is laid out
+  // once every level is built.  Inbox regions of absent neighbours (and of neighbours of
+  // another degree) are never written and must read as zero.
   const size_t nin = (size_t)L.nin * s.nrhs;
   const bool fp32 = s.opt.precision != DGFAS_FP64;
-  L.O = s.own(dalloc<double>(nin));
-  if (fp32) L.O32 = s.own(dalloc<float>(nin));
-  // inbox regions of absent neighbours (and of neighbours of another degree) are never
-  // written and must read as zero
-  if (nin) {
-    HIPC(hipMemsetAsync(L.O, 0, nin * sizeof(double), st));
-    if (fp32) HIPC(hipMemsetAsync(L.O32, 0, nin * sizeof(float), st));
-  }
+  s.reserve(L.O, nin, true);
+  if (fp32) s.reserve(L.O32, nin, true);
   if (L.uniform) {
     L.nlb = stage_tiles(kStageOp, L.p, E, 1);
-    L.kpart = s.own(dalloc<double>((size_t)L.nlb * s.nrhs));
+    s.reserve(L.kpart, (size_t)L.nlb * s.nrhs);
     if (L.m > 0) {
       L.nla = stage_tiles(kStageAdd, L.p, E, 1);
-      L.zpart = s.own(dalloc<double>((size_t)2 * L.nla * s.nrhs));
+      s.reserve(L.zpart, (size_t)2 * L.nla * s.nrhs);
     }
   }
   // work vectors
   const size_t nv = (size_t)L.ndof * s.nrhs;
-  L.r = s.own(dalloc<double>(nv));
+  s.reserve(L.r, nv);
   const bool scg_here = s.opt.smoother == DGFAS_SCG || &L == &s.lv[0];
   const bool dbl_scg = scg_here && !(fp32 && &L != &s.lv[0]);
-  if (dbl_scg || !fp32) L.z = s.own(dalloc<double>(nv));
+  if (dbl_scg || !fp32) s.reserve(L.z, nv);
   if (dbl_scg) {
-    L.pv = s.own(dalloc<double>(nv));
-    L.q = s.own(dalloc<double>(nv));
-    L.r0 = s.own(dalloc<double>(nv));
+    s.reserve(L.pv, nv);
+    s.reserve(L.q, nv);
+    s.reserve(L.r0, nv);
   }
   if (fp32 && &L != &s.lv[0]) {
-    L.r32 = s.own(dalloc<float>(nv));
-    L.du32 = s.own(dalloc<float>(nv));
-    L.rc32 = s.own(dalloc<float>(nv));
+    s.reserve(L.r32, nv);
+    s.reserve(L.du32, nv);
+    s.reserve(L.rc32, nv);
     if (s.opt.smoother == DGFAS_SCG) {
-      L.z32 = s.own(dalloc<float>(nv));
-      L.p32 = s.own(dalloc<float>(nv));
-      L.q32 = s.own(dalloc<float>(nv));
-      L.r0_32 = s.own(dalloc<float>(nv));
+      s.reserve(L.z32, nv);
+      s.reserve(L.p32, nv);
+      s.reserve(L.q32, nv);
+      s.reserve(L.r0_32, nv);
     }
   }
   HIPC(hipStreamSynchronize(st));
@@ -1360,9 +1410,37 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   }
   if (o->weighting != DGFAS_WEIGHT_QUINTIC && o->weighting != DGFAS_WEIGHT_PLAIN)
     throw Error(DGFAS_EINVAL, "unknown weighting");
+  if (o->projection != DGFAS_PROJECT_INTERP && o->projection != DGFAS_PROJECT_L2)
+    throw Error(DGFAS_EINVAL, "unknown projection");
   if (o->start != DGFAS_START_NONE && o->start != DGFAS_START_CMG && o->start != DGFAS_START_FMG)
     throw Error(DGFAS_EINVAL, "unknown start-up");
   if (o->nsc > 0 && o->nsc < o->ns2) throw Error(DGFAS_EINVAL, "nsc must be >= ns2 (or <= 0 for none)");
+  if (o->h_levels < 0 || o->h_levels > 8) throw Error(DGFAS_EINVAL, "h_levels must be 0..8");
+  if (o->h_only != 0 && o->h_only != 1) throw Error(DGFAS_EINVAL, "h_only must be 0 or 1");
+  if (o->h_levels > 0) {
+    // h-coarsening needs one degree and a box numbering e = ex + nx (ey + ny ez) whose dimensions
+    // halve h_levels times; the face neighbours must be those of the box (or its periodic wraps)
+    const int nx = m->box[0], ny = m->box[1], nz = m->box[2];
+    if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz != m->n_elem)
+      throw Error(DGFAS_EINVAL, "h-coarsening needs box dimensions with nx ny nz = n_elem");
+    const int div = 1 << o->h_levels;
+    if (nx % div || ny % div || nz % div)
+      throw Error(DGFAS_EINVAL, "box dimensions must be divisible by 2^h_levels");
+    for (int e = 0; e < m->n_elem; ++e) {
+      if (m->degree[e] != m->degree[0]) throw Error(DGFAS_EUNSUPPORTED, "h-coarsening needs one degree");
+      const int c[3] = {e % nx, (e / nx) % ny, e / (nx * ny)}, dim[3] = {nx, ny, nz};
+      for (int f = 0; f < 6; ++f) {
+        const int ax = f >> 1, dir = (f & 1) ? 1 : -1;
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[ax] = (cc[ax] + dir + dim[ax]) % dim[ax];
+        const int en = m->face_nbr[e * 6 + f], box_nb = cc[0] + nx * (cc[1] + ny * cc[2]);
+        const bool edge = (dir < 0 && c[ax] == 0) || (dir > 0 && c[ax] == dim[ax] - 1);
+        if (en >= 0 ? en != box_nb : !edge)
+          throw Error(DGFAS_EINVAL, "face neighbours do not follow the box numbering");
+      }
+    }
+    if (o->order == DGFAS_ORDER_MORTON) throw Error(DGFAS_EUNSUPPORTED, "Morton order with h-coarsening");
+  }
   if (o->smoother != DGFAS_WAS && o->smoother != DGFAS_SCG) throw Error(DGFAS_EINVAL, "unknown smoother");
   if (o->ns1 < 0 || o->ns2 < 0 || o->root_max_iter < 1) throw Error(DGFAS_EINVAL, "bad step counts");
   if (!(o->root_rtol >= 0) || !std::isfinite(o->root_rtol)) throw Error(DGFAS_EINVAL, "root_rtol must be >= 0");
@@ -1431,9 +1509,9 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   s->bc = s->own(upload(s->h_bc, s->st));
   s->nrhs = o->n_rhs;
   if (o->order == DGFAS_ORDER_MORTON) s->rank = morton_rank(m);
-  s->partial = s->own(dalloc<double>((size_t)2048 * s->nrhs));
-  s->scal = s->own(dalloc<double>((size_t)8 * s->nrhs));
-  s->dotout = s->own(dalloc<double>((size_t)8 * s->nrhs));
+  s->reserve(s->partial, (size_t)2048 * s->nrhs);
+  s->reserve(s->scal, (size_t)8 * s->nrhs);
+  s->reserve(s->dotout, (size_t)8 * s->nrhs);
   // face tables of the mixed-degree kernel: D of degrees 1..8 (stride 81) and the
   // interpolation from degree q to degree r at ((q - 1) 8 + r - 1) 81
   {
@@ -1449,65 +1527,139 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
     s->Dall = s->own(upload(Dall, s->st));
     s->Iall = s->own(upload(Iall, s->st));
   }
-  // per-element degree chain p_{l-1} = max(1, floor(p_l / 2)); levels from the largest degree
-  std::vector<std::vector<int>> degs{std::vector<int>(m->degree, m->degree + E)};
-  while (*std::max_element(degs.back().begin(), degs.back().end()) > 1) {
-    std::vector<int> c(E);
-    for (int e = 0; e < E; ++e) c[e] = std::max(1, degs.back()[e] / 2);
-    degs.push_back(c);
+  // Level specs, finest first: h_levels h-coarsenings at the fine degree (Sec. 3.1: 2 x 2 x 2
+  // children per parent), then, unless h_only, the per-element degree chain
+  // p_{l-1} = max(1, floor(p_l / 2)) on the coarsest h-mesh
+  struct Spec {
+    int E;
+    std::vector<int> deg, nbr;
+    std::vector<int8_t> bc;
+    int box[3];
+    bool hdown;
+    std::vector<int> children;   // [E of the next coarser spec][8] when hdown
+  };
+  std::vector<Spec> sp;
+  sp.push_back({E, std::vector<int>(m->degree, m->degree + E), s->h_nbr, s->h_bc, {m->box[0], m->box[1], m->box[2]},
+                false, {}});
+  for (int h = 0; h < o->h_levels; ++h) {
+    Spec& F = sp.back();
+    const int nx = F.box[0], ny = F.box[1], NX = nx / 2, NY = F.box[1] / 2, NZ = F.box[2] / 2;
+    const int Ec = NX * NY * NZ;
+    Spec C{Ec, std::vector<int>(Ec, F.deg[0]), std::vector<int>((size_t)Ec * 6, -1),
+           std::vector<int8_t>((size_t)Ec * 6, DGFAS_INTERIOR), {NX, NY, NZ}, false, {}};
+    F.children.resize((size_t)Ec * 8);
+    for (int P = 0; P < Ec; ++P) {
+      const int Px = P % NX, Py = (P / NX) % NY, Pz = P / (NX * NY);
+      for (int c = 0; c < 8; ++c)
+        F.children[(size_t)P * 8 + c] = (2 * Px + (c & 1)) + nx * ((2 * Py + ((c >> 1) & 1)) + ny * (2 * Pz + (c >> 2)));
+      // a parent face takes its neighbour and boundary code from a child on that face
+      for (int f = 0; f < 6; ++f) {
+        const int ch = F.children[(size_t)P * 8 + ((f & 1) << (f >> 1))];
+        const int en = F.nbr[(size_t)ch * 6 + f];
+        if (en >= 0) {
+          const int ex = en % nx, ey = (en / nx) % ny, ez = en / (nx * ny);
+          C.nbr[(size_t)P * 6 + f] = ex / 2 + NX * (ey / 2 + NY * (ez / 2));
+        } else {
+          C.bc[(size_t)P * 6 + f] = F.bc[(size_t)ch * 6 + f];
+        }
+      }
+    }
+    F.hdown = true;
+    sp.push_back(std::move(C));
   }
-  std::reverse(degs.begin(), degs.end());
-  const int Lc = (int)degs.size();
+  if (!o->h_only) {
+    while (*std::max_element(sp.back().deg.begin(), sp.back().deg.end()) > 1) {
+      Spec C = sp.back();
+      C.hdown = false;
+      C.children.clear();
+      for (int& d : C.deg) d = std::max(1, d / 2);
+      sp.push_back(std::move(C));
+    }
+  }
+  std::reverse(sp.begin(), sp.end());   // root first
+  const int Lc = (int)sp.size();
   s->lv.resize(Lc);
-  size_t nX = 0;
-  for (int e = 0; e < E; ++e) nX += (size_t)3 * (degs[Lc - 1][e] + 1) * (degs[Lc - 1][e] + 1) * (degs[Lc - 1][e] + 1);
-  double* X = s->own(dalloc<double>(nX));
-  HIPC(hipMemcpyAsync(X, m->coords, nX * sizeof(double), hipMemcpyHostToDevice, s->st));
+  for (int li = 0; li < Lc; ++li) {
+    Level& L = s->lv[li];
+    L.E = sp[li].E;
+    L.h_nbr = sp[li].nbr;
+    L.h_bc = sp[li].bc;
+    for (int d = 0; d < 3; ++d) L.box[d] = sp[li].box[d];
+    L.nbr = s->own(upload(L.h_nbr, s->st));
+    L.bc = s->own(upload(L.h_bc, s->st));
+    L.hdown = sp[li].hdown;
+    if (L.hdown) {
+      L.hchild = s->own(upload(sp[li].children, s->st));
+      L.hM = s->own(upload(h_child_matrices(sp[li].deg[0]), s->st));
+    }
+  }
+  auto ncoords = [](const std::vector<int>& dg) {
+    size_t n = 0;
+    for (int d : dg) n += (size_t)3 * (d + 1) * (d + 1) * (d + 1);
+    return n;
+  };
+  double* X = s->own(dalloc<double>(ncoords(sp[Lc - 1].deg)));
+  HIPC(hipMemcpyAsync(X, m->coords, ncoords(sp[Lc - 1].deg) * sizeof(double), hipMemcpyHostToDevice, s->st));
   for (int li = Lc - 1; li >= 0; --li) {
     Level& L = s->lv[li];
+    const std::vector<int>& dgl = sp[li].deg;
     if (li < Lc - 1) {
-      // coarse geometry: fine coordinates evaluated at the coarse GLL nodes, per element
+      // coarse geometry: the fine map evaluated at the coarse GLL nodes, per element (p) or per
+      // parent from its children (h, averaged where the children meet)
       Level& F = s->lv[li + 1];
-      size_t nXc = 0;
-      for (int e = 0; e < E; ++e) nXc += (size_t)3 * (degs[li][e] + 1) * (degs[li][e] + 1) * (degs[li][e] + 1);
-      double* Xc = s->own(dalloc<double>(nXc));
-      std::vector<int64_t> offc(E);
-      int64_t o = 0;
-      for (int e = 0; e < E; ++e) { offc[e] = o; o += (int64_t)(degs[li][e] + 1) * (degs[li][e] + 1) * (degs[li][e] + 1); }
-      int64_t* d_offc = F.uniform ? nullptr : s->own(upload(offc, s->st));
-      const bool cu = *std::min_element(degs[li].begin(), degs[li].end()) ==
-                      *std::max_element(degs[li].begin(), degs[li].end());
-      for (Bucket& b : F.bk) {
-        const int pf = b.p, pc = std::max(1, pf / 2);
-        std::vector<double> P = interp_matrix(pf, pc), I = interp_matrix(pc, pf);
-        std::vector<double> R((size_t)(pc + 1) * (pf + 1));
-        for (int a = 0; a <= pc; ++a)
-          for (int c = 0; c <= pf; ++c) R[a * (pf + 1) + c] = I[c * (pc + 1) + a];
-        b.pc = pc;
-        b.Pm = s->own(upload(P, s->st));
-        b.Im = s->own(upload(I, s->st));
-        b.Rm = s->own(upload(R, s->st));
-        XferArgs<double> a;
-        a.Tm = b.Pm; a.in = X; a.out = Xc;
-        if (F.uniform) {
-          a.nel = 3 * E;
-        } else {
-          a.nel = b.nel; a.elist = b.elist; a.ncomp = 3; a.off_in = F.off; a.off_out = cu ? nullptr : d_offc;
-        }
-        if (!tensor3<double>(pf + 1, pc + 1, a, s->st))
-          throw Error(DGFAS_EUNSUPPORTED, "no transfer kernel for this degree pair");
+      double* Xc = s->own(dalloc<double>(ncoords(dgl)));
+      if (F.hdown) {
+        HXferArgs<double> a;
+        a.kind = 0; a.ncoarse = L.E; a.children = F.hchild; a.ncomp = 3; a.M = F.hM; a.in = X; a.out = Xc;
+        if (!htransfer<double>(F.p, a, s->st)) throw Error(DGFAS_EUNSUPPORTED, "no h-transfer kernel for this degree");
         HIPC(hipGetLastError());
+      } else {
+        const int Ep = L.E;
+        std::vector<int64_t> offc(Ep);
+        int64_t oc = 0;
+        for (int e = 0; e < Ep; ++e) { offc[e] = oc; oc += (int64_t)(dgl[e] + 1) * (dgl[e] + 1) * (dgl[e] + 1); }
+        int64_t* d_offc = F.uniform ? nullptr : s->own(upload(offc, s->st));
+        const bool cu = *std::min_element(dgl.begin(), dgl.end()) == *std::max_element(dgl.begin(), dgl.end());
+        for (Bucket& b : F.bk) {
+          const int pf = b.p, pc = std::max(1, pf / 2);
+          // the geometry of the coarse level is the fine map evaluated at the coarse nodes; the
+          // solution projection is that evaluation or the L2 projection (Sec. 3.2)
+          std::vector<double> Pg = interp_matrix(pf, pc), I = interp_matrix(pc, pf);
+          std::vector<double> P = s->opt.projection == DGFAS_PROJECT_L2 && pc < pf ? l2_projection_matrix(pf, pc) : Pg;
+          std::vector<double> R((size_t)(pc + 1) * (pf + 1));
+          for (int a = 0; a <= pc; ++a)
+            for (int c = 0; c <= pf; ++c) R[a * (pf + 1) + c] = I[c * (pc + 1) + a];
+          b.pc = pc;
+          b.Pm = s->own(upload(P, s->st));
+          b.Im = s->own(upload(I, s->st));
+          b.Rm = s->own(upload(R, s->st));
+          double* Pgeo = s->own(upload(Pg, s->st));
+          XferArgs<double> a;
+          a.Tm = Pgeo; a.in = X; a.out = Xc;
+          if (F.uniform) {
+            a.nel = 3 * Ep;
+          } else {
+            a.nel = b.nel; a.elist = b.elist; a.ncomp = 3; a.off_in = F.off; a.off_out = cu ? nullptr : d_offc;
+          }
+          if (!tensor3<double>(pf + 1, pc + 1, a, s->st))
+            throw Error(DGFAS_EUNSUPPORTED, "no transfer kernel for this degree pair");
+          HIPC(hipGetLastError());
+        }
       }
       X = Xc;
     }
-    build_level(*s, L, degs[li], X);
+    build_level(*s, L, dgl, X);
     L.X = X;
     if (li < Lc - 1) {
-      L.u = s->own(dalloc<double>((size_t)L.ndof * s->nrhs));
-      L.g = s->own(dalloc<double>((size_t)L.ndof * s->nrhs));
-      L.ubar = s->own(dalloc<double>((size_t)L.ndof * s->nrhs));
+      s->reserve(L.u, (size_t)L.ndof * s->nrhs);
+      s->reserve(L.g, (size_t)L.ndof * s->nrhs);
+      s->reserve(L.ubar, (size_t)L.ndof * s->nrhs);
     }
   }
+  // the workspace: one library-owned block until the caller hands in its own buffer
+  s->ws_bytes = s->ws_layout();
+  s->ws_block = dalloc<char>(s->ws_bytes);
+  s->ws_assign(static_cast<char*>(s->ws_block));
   HIPC(hipStreamSynchronize(s->st));
   return s.release();
 }
@@ -1627,6 +1779,38 @@ dgfas_status dgfas_level_info(dgfas_solver s, int32_t level, int32_t* degree, in
   API_END
 }
 
+dgfas_status dgfas_workspace_size(dgfas_solver sv, size_t* bytes) {
+  API_BEGIN
+  need(bytes, "bytes");
+  *bytes = S_(sv)->ws_bytes;
+  API_END
+}
+
+dgfas_status dgfas_set_workspace(dgfas_solver sv, void* dptr, size_t bytes) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  if (dptr) {
+    if (bytes < s->ws_bytes)
+      throw Error(DGFAS_EINVAL, "workspace of " + std::to_string(bytes) + " bytes, " +
+                                    std::to_string(s->ws_bytes) + " needed");
+    if (reinterpret_cast<uintptr_t>(dptr) % 256) throw Error(DGFAS_EINVAL, "workspace must be 256-byte aligned");
+  }
+  HIPC(hipStreamSynchronize(s->st));   // work still queued may use the current buffers
+  s->drop_graphs();
+  void* old = s->ws_block;
+  if (dptr) {
+    s->ws_assign(static_cast<char*>(dptr));
+    s->ws_block = nullptr;
+  } else {
+    void* blk = dalloc<char>(s->ws_bytes);
+    s->ws_assign(static_cast<char*>(blk));
+    s->ws_block = blk;
+  }
+  HIPC(hipStreamSynchronize(s->st));
+  if (old && old != s->ws_block) HIPC(hipFree(old));
+  API_END
+}
+
 dgfas_status dgfas_level_overlap(dgfas_solver s, int32_t level, int32_t* m) {
   API_BEGIN
   need(m, "m");
@@ -1645,7 +1829,7 @@ dgfas_status dgfas_rhs(dgfas_solver sv, const double* f, const double* uD, const
       RhsArgs a;
       a.nel = bk.nel; a.elist = bk.elist; a.off = T.off; a.offF = T.offF; a.ndof = T.ndof;
       a.f = f + o; a.uD = uD ? uD + o : nullptr; a.qN = qN ? qN + o : nullptr; a.b = b + o;
-      a.G = T.G; a.WJ = T.WJ; a.pen = T.pen; a.ws = T.ws; a.nbr = s->nbr; a.bc = s->bc;
+      a.G = T.G; a.WJ = T.WJ; a.pen = T.pen; a.ws = T.ws; a.nbr = T.nbr; a.bc = T.bc;
       rhs(bk.p, a, bk.t->D, bk.t->inv_wend, s->st);
     }
   }

@@ -3,6 +3,7 @@
 // cyclic Jacobi rotations.
 #include "tables.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -157,6 +158,81 @@ std::vector<double> interp_matrix(int p_from, int p_to) {
     for (int j = 0; j < nf; ++j) T[i * nf + j] = (lam[j] / (y - gf.x[j])) / den;
   }
   return T;
+}
+
+// L[i*n + j] = l_j(y_i) for the degree-p GLL Lagrange basis (barycentric form)
+static std::vector<double> lagrange_at(int p, const std::vector<double>& y) {
+  const Gll& g = gll_table(p);
+  const int n = p + 1;
+  const std::vector<double> lam = bary_weights(g.x);
+  std::vector<double> L(y.size() * n, 0.0);
+  for (size_t i = 0; i < y.size(); ++i) {
+    int hit = -1;
+    for (int j = 0; j < n; ++j)
+      if (y[i] == g.x[j]) hit = j;
+    if (hit >= 0) { L[i * n + hit] = 1.0; continue; }
+    double den = 0.0;
+    for (int j = 0; j < n; ++j) den += lam[j] / (y[i] - g.x[j]);
+    for (int j = 0; j < n; ++j) L[i * n + j] = (lam[j] / (y[i] - g.x[j])) / den;
+  }
+  return L;
+}
+
+std::vector<double> h_child_matrices(int p) {
+  const Gll& g = gll_table(p);
+  const int n = p + 1, n2 = n * n;
+  std::vector<double> out(6 * n2, 0.0);
+  for (int b = 0; b < 2; ++b) {
+    std::vector<double> yi(n), yp(n);
+    for (int i = 0; i < n; ++i) {
+      yi[i] = (g.x[i] + (2 * b - 1)) / 2.0;
+      yp[i] = std::min(1.0, std::max(-1.0, 2.0 * g.x[i] - (2 * b - 1)));
+    }
+    const std::vector<double> I = lagrange_at(p, yi), P = lagrange_at(p, yp);
+    for (int i = 0; i < n; ++i) {
+      const bool mid = std::fabs(g.x[i]) < 1e-14, inside = b == 0 ? g.x[i] < 0 : g.x[i] > 0;
+      const double w = mid ? 0.5 : (inside ? 1.0 : 0.0);
+      for (int j = 0; j < n; ++j) {
+        out[b * n2 + i * n + j] = w * P[i * n + j];          // P_b
+        out[(2 + b) * n2 + j * n + i] = I[i * n + j];        // I_b^T
+        out[(4 + b) * n2 + i * n + j] = I[i * n + j];        // I_b
+      }
+    }
+  }
+  return out;
+}
+
+std::vector<double> l2_projection_matrix(int p_from, int p_to) {
+  const int nf = p_from + 1, nc = p_to + 1;
+  const std::vector<double> I = interp_matrix(p_to, p_from);   // nf x nc
+  const std::vector<double>& w = gll_table(p_from).w;
+  // normal equations M P = B with M = I^T W I (nc x nc, SPD) and B = I^T W (nc x nf)
+  std::vector<double> M(nc * nc, 0.0), B(nc * nf, 0.0);
+  for (int a = 0; a < nc; ++a) {
+    for (int b = 0; b < nc; ++b)
+      for (int q = 0; q < nf; ++q) M[a * nc + b] += I[q * nc + a] * w[q] * I[q * nc + b];
+    for (int q = 0; q < nf; ++q) B[a * nf + q] = I[q * nc + a] * w[q];
+  }
+  // Gaussian elimination with partial pivoting on [M | B]
+  for (int c = 0; c < nc; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < nc; ++r)
+      if (std::fabs(M[r * nc + c]) > std::fabs(M[piv * nc + c])) piv = r;
+    if (piv != c) {
+      for (int k = 0; k < nc; ++k) std::swap(M[c * nc + k], M[piv * nc + k]);
+      for (int k = 0; k < nf; ++k) std::swap(B[c * nf + k], B[piv * nf + k]);
+    }
+    for (int r = 0; r < nc; ++r) {
+      if (r == c) continue;
+      const double f = M[r * nc + c] / M[c * nc + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < nc; ++k) M[r * nc + k] -= f * M[c * nc + k];
+      for (int k = 0; k < nf; ++k) B[r * nf + k] -= f * B[c * nf + k];
+    }
+  }
+  for (int r = 0; r < nc; ++r)
+    for (int k = 0; k < nf; ++k) B[r * nf + k] /= M[r * nc + r];
+  return B;
 }
 
 Variant1D make_variant_1d(int p, int m, int left, int right, double mu_star) {

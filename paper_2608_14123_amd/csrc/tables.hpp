@@ -20,6 +20,18 @@ const Gll& gll_table(int p);
 // polynomial at the GLL nodes of degree p_to.
 std::vector<double> interp_matrix(int p_from, int p_to);
 
+// h-coarsening matrices of degree p (Sec. 3.2), each (p+1) x (p+1) row-major, in the order
+// P_0, P_1, I_0^T, I_1^T, I_0, I_1 for the children b = 0 (xi in [-1, 0] of the parent) and 1:
+// I_b[i][j] = l_j((x_i + 2b - 1) / 2) (the parent's basis at the child's nodes) and
+// P_b[i][j] = w_b(i) l_j(2 x_i - (2b - 1)) (the child's basis at the parent's nodes, weighted
+// 1 in the child's half, 1/2 at the shared midpoint, 0 elsewhere).
+std::vector<double> h_child_matrices(int p);
+
+// Reference-element L2 projection of a degree-p_from nodal polynomial onto degree p_to < p_from
+// (Sec. 3.2): P = (I^T W I)^-1 I^T W with I = interp_matrix(p_to, p_from) and W the p_from GLL
+// weights, which integrate every product involved exactly.  Row-major p_to+1 x p_from+1.
+std::vector<double> l2_projection_matrix(int p_from, int p_to);
+
 // Face condition of one side of a 1D subdomain; kInteriorNoOverlap is an interior face
 // whose subdomain stops at the face (neighbour of another degree): the 1D matrix keeps
 // the own element's half of the interior face terms and no node of the neighbour.

@@ -154,3 +154,32 @@ def test_delta_overlap_history_on_the_stretched_mesh(binding):
     histories_agree(list(hg), ho)
     assert rel(host(u), uo) <= 1e-9
     lib.close()
+
+
+def test_l2_projection_transfers_and_history(binding):
+    """projection = L2 (Sec. 3.2): dgfas_project on every level against the oracle's
+    reference-element L2 projection, and the FAS-MG-WAS(2,2) history with it."""
+    from oracle import transfer as otr
+    case = Case('curved', 4, 3, amp=0.03)
+    lv = case.oracle_levels()
+    lib = case.library(binding, projection=binding.PROJECT_L2)
+    rng = np.random.default_rng(9)
+    for l in range(2, lib.n_levels + 1):
+        pf, pc = lv[l - 1].p, lv[l - 2].p
+        uf = rng.uniform(-1, 1, lv[l - 1].mesh.n_dof())
+        out = torch.empty(lv[l - 2].mesh.n_dof(), dtype=torch.float64, device='cuda')
+        lib.project(l, dev(uf), out)
+        ref = otr.project(pc, pf, uf.reshape((case.E,) + (pf + 1,) * 3), 'l2')
+        assert rel(host(out), ref) <= 1e-13, l
+    top = lv[-1].mesh
+    f = W.uniform_nodal(top.n_dof(), 2)
+    bo = oop.rhs(top, f.reshape((top.E,) + (5,) * 3))
+    uo, ho = osv.solve(lv, np.zeros_like(bo), bo, osv.Options('was', 2, 2, projection='l2'), max_cycles=30)
+    b = torch.empty(bo.size, dtype=torch.float64, device='cuda')
+    lib.rhs(dev(f), b)
+    u = torch.zeros_like(b)
+    hg, ok = lib.solve(u, b, max_cycles=30, rtol=1e-10)
+    assert ok
+    histories_agree(list(hg), ho)
+    assert rel(host(u), uo) <= 1e-9
+    lib.close()
