@@ -42,7 +42,7 @@ def parse():
     ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched'],
                     help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8); '
                          'stretched: 48^3, p = 8, aspect 1:100, 16 right-hand sides')
-    ap.add_argument('--cycles', type=int, default=30, help='stretched workload: largest V-cycle count of a solve')
+    ap.add_argument('--cycles', type=int, default=40, help='stretched workload: largest V-cycle count of a solve')
     return ap.parse_args()
 
 
@@ -258,8 +258,9 @@ def stretched_bench(args, torch, B):
         return ev0.elapsed_time(ev1) / reps
 
     modes = {}
-    for prec in ('fp64', 'fp32', 'fp32_matrix_cores'):
-        o = B.default_options(precision={'fp64': B.FP64, 'fp32': B.FP32, 'fp32_matrix_cores': B.FP32_MFMA}[prec], **cyc)
+    # (the matrix-core FD tile takes overlap 1 only; at m = 3 the FP32 solves run on the vector unit)
+    for prec in ('fp64', 'fp32'):
+        o = B.default_options(precision={'fp64': B.FP64, 'fp32': B.FP32}[prec], **cyc)
         t0 = time.perf_counter()
         lib = B.Solver(np.full(E, p, np.int32), X, nbr, bc, o, stream=stream.cuda_stream)
         torch.cuda.synchronize()
@@ -332,7 +333,8 @@ def main():
     degs = np.full(E, p, np.int32)
 
     def solver(**kw):
-        return B.Solver(degs, X, nbr, bc, B.default_options(**dict(cyc, **kw)), stream=stream.cuda_stream)
+        return B.Solver(degs, X, nbr, bc, B.default_options(**dict(cyc, **kw)), stream=stream.cuda_stream,
+                        box=(ne, ne, ne))
 
     t_setup = time.perf_counter()
     lib = solver()
@@ -480,7 +482,10 @@ def main():
                 ('fp32_smoother_fixed_root16_whole_cycle_graph', dict(fixed, precision=B.FP32), None, True),
                 ('fp64_fmg', fmg, None, False),
                 ('fp32_smoother_fmg_fixed_root16_graph', dict(fmg, precision=B.FP32, **fixed), None, True),
-                ('fp64_fmg_crossover3', dict(fmg, nsc=3), 3, False)):
+                ('fp64_fmg_crossover3', dict(fmg, nsc=3), 3, False),
+                # h-coarsening (Sec. 3.1): 32^3 -> 16^3 -> 8^3 -> 4^3 elements at p = 7, then the p-levels
+                ('fp64_h3_then_p', dict(h_levels=3), None, False),
+                ('fp64_h3_then_p_fmg', dict(h_levels=3, **fmg), None, False)):
             time_to_tol(solver(**kw), key, nsc=nsc, lowp=lowp)
     else:
         lib.close()
