@@ -130,6 +130,7 @@ def build_hlevels(p, X, nbr, bc, box, h_levels, m=1, nu=1.0, kappa=0.0, mu_star=
     from .solvers import Level, build_levels
     X = np.asarray(X, dtype=np.float64)
     nbr, bc = np.asarray(nbr), np.asarray(bc)
+    nu = np.asarray(nu, dtype=np.float64)
     fine = []
     cur_box = tuple(box)
     for _ in range(h_levels):
@@ -138,6 +139,10 @@ def build_hlevels(p, X, nbr, bc, box, h_levels, m=1, nu=1.0, kappa=0.0, mu_star=
         lv.down = ht
         fine.append(lv)
         X = np.stack([ht.project(X[:, a]) for a in range(3)], axis=1)
+        if nu.ndim == 4:                     # a nodal coefficient follows the geometry
+            nu = ht.project(nu)
+        elif nu.ndim == 1:
+            raise ValueError('h-coarsening takes a scalar or nodal nu')
         nbr, bc = ht.coarsen_topology(nbr, bc)
         cur_box = ht.cbox
     if p_coarsen:

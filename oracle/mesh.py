@@ -70,6 +70,10 @@ class Mesh:
 
     X: (E, 3, n, n, n) nodal coordinates; nbr: (E, 6) neighbour ids (-1 = boundary);
     bc: (E, 6) boundary codes on boundary faces (1 Dirichlet, 2 Neumann).
+    nu: the diffusivity (eq. helmholtz:pde), a positive scalar, one value per element or one
+    value per node (E, n, n, n).  nu_n holds it per node, nu_e the element averages
+    int_e nu dx / int_e dx taken with the GLL quadrature (the averaged coefficient of the
+    Schwarz surrogate, Sec. 4.3.1).
     """
 
     def __init__(self, p, X, nbr, bc, nu=1.0, kappa=0.0, mu_star=2.0):
@@ -78,12 +82,26 @@ class Mesh:
         self.E = self.X.shape[0]
         self.nbr = np.asarray(nbr, dtype=np.int64)
         self.bc = np.asarray(bc, dtype=np.int64)
-        self.nu, self.kappa, self.mu_star = float(nu), float(kappa), float(mu_star)
+        n = self.n
+        nu = np.asarray(nu, dtype=np.float64)
+        if nu.ndim == 1:
+            nu = nu[:, None, None, None]
+        self.nu_n = np.broadcast_to(nu, (self.E, n, n, n)).copy()
+        # the blade case's nu = 1 + cos cos cos vanishes at isolated points (Sec. 6.2.5): nodal
+        # values may be zero, element averages may not
+        if not np.all(self.nu_n >= 0):
+            raise ValueError('nu must be non-negative')
+        self.nu = float(nu) if nu.ndim == 0 else None
+        self.kappa, self.mu_star = float(kappa), float(mu_star)
         self.x1d, self.w1d = gll(p)
         self.D = diff_matrix(p)
         w = self.w1d
         self.w3 = w[:, None, None] * w[None, :, None] * w[None, None, :]
         self._volume_metric()
+        wj = self.w3 * self.detJ
+        self.nu_e = np.sum(wj * self.nu_n, axis=(1, 2, 3)) / np.sum(wj, axis=(1, 2, 3))
+        if not np.all(self.nu_e > 0):
+            raise ValueError('the element averages of nu must be positive')
         self._face_geometry()
         self._penalty()
 

@@ -12,6 +12,9 @@ with [u] = n^- u^- + n^+ u^+ and {w} = (w^- + w^+)/2 (Sec. 2.2).  Each
 element assembles its own rows; on an interior face it uses its own outward
 normal n and the jump j = u_own - u_nbr.  The term -{nu grad v}.[u] for the
 test functions of one element is its transposed face gradient ("lifting").
+nu is given per node: at a face node the average is (nu^- d_n u^- + nu^+ d_n u^+)/2 with
+each side's own nodal value, the penalty takes max(nu^-, nu^+) there, and the lifting of an
+element's test functions its own value.
 """
 import numpy as np
 
@@ -39,12 +42,13 @@ def _add_lifting(mesh, lift, sigma, phi):
 def apply(mesh, u):
     """A u for the SIPG operator (eq. helmholtz:system). u: (E, n, n, n)."""
     u = np.asarray(u, dtype=np.float64).reshape(mesh.E, mesh.n, mesh.n, mesh.n)
-    nu, kappa = mesh.nu, mesh.kappa
+    kappa = mesh.kappa
+    nu_v = mesh.nu_n
     grad = mesh.grad(u)
     # volume term: sum_b D_b^T [ w J nu grad(xi_b) . grad u ] + kappa w J u
     out = kappa * mesh.w3 * mesh.detJ * u
     for b in range(3):
-        flux_b = nu * mesh.w3 * mesh.detJ * np.einsum('ekjia,eakji->ekji', mesh.dxi[..., b, :], grad)
+        flux_b = nu_v * mesh.w3 * mesh.detJ * np.einsum('ekjia,eakji->ekji', mesh.dxi[..., b, :], grad)
         out = out + dT_ref(mesh.D, flux_b, b)
     lift = [np.zeros_like(u) for _ in range(3)]
     for phi in range(6):
@@ -54,6 +58,7 @@ def apply(mesh, u):
         nb = mesh.nbr[:, phi]
         row = np.zeros_like(uf)
         sigma = np.zeros_like(uf)
+        nu_o = face_view(mesh.nu_n, phi)
         inter = nb >= 0
         if np.any(inter):
             en = nb[inter]
@@ -63,14 +68,16 @@ def apply(mesh, u):
             jmp = uf[inter] - u_nb
             mu = mesh.mu[inter, phi][:, None, None]
             wsi = ws[inter]
-            row[inter] = mu * nu * wsi * jmp - 0.5 * wsi * nu * (dn_own[inter] + dn_nb)
-            sigma[inter] = -0.5 * nu * wsi * jmp
+            nu_i, nu_n = nu_o[inter], face_view(mesh.nu_n[en], OPPOSITE[phi])
+            row[inter] = mu * np.maximum(nu_i, nu_n) * wsi * jmp - 0.5 * wsi * (nu_i * dn_own[inter] + nu_n * dn_nb)
+            sigma[inter] = -0.5 * nu_i * wsi * jmp
         dir_ = (nb < 0) & (mesh.bc[:, phi] == 1)
         if np.any(dir_):
             mu = mesh.mu[dir_, phi][:, None, None]
             wsd = ws[dir_]
-            row[dir_] = 2.0 * mu * nu * wsd * uf[dir_] - wsd * nu * dn_own[dir_]
-            sigma[dir_] = -nu * wsd * uf[dir_]
+            nu_d = nu_o[dir_]
+            row[dir_] = 2.0 * mu * nu_d * wsd * uf[dir_] - wsd * nu_d * dn_own[dir_]
+            sigma[dir_] = -nu_d * wsd * uf[dir_]
         # Neumann faces contribute nothing to the operator
         fv = face_view(out, phi)
         fv += row
@@ -94,8 +101,9 @@ def rhs(mesh, f, uD=None, qN=None):
         if uD is not None and np.any(dir_):
             ud = face_view(np.asarray(uD, dtype=np.float64).reshape(b.shape), phi)
             mu = mesh.mu[dir_, phi][:, None, None]
-            row[dir_] = 2.0 * mu * mesh.nu * ws[dir_] * ud[dir_]
-            sigma[dir_] = -mesh.nu * ws[dir_] * ud[dir_]
+            nu_d = face_view(mesh.nu_n, phi)[dir_]
+            row[dir_] = 2.0 * mu * nu_d * ws[dir_] * ud[dir_]
+            sigma[dir_] = -nu_d * ws[dir_] * ud[dir_]
         neu = (nb < 0) & (mesh.bc[:, phi] == 2)
         if qN is not None and np.any(neu):
             qn = face_view(np.asarray(qN, dtype=np.float64).reshape(b.shape), phi)

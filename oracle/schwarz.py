@@ -47,12 +47,14 @@ def surrogate_dx(mesh):
 
 
 def surrogate_coefficients(mesh, dx=None):
-    """g0 = kappa dx1 dx2 dx3 / 8, g_i = nu dx_j dx_k / (2 dx_i) (eq. schwarz:tpo)."""
+    """g0 = kappa dx1 dx2 dx3 / 8, g_i = nu dx_j dx_k / (2 dx_i) (eq. schwarz:tpo), with the
+    element's averaged nu (its own value: nu is constant per element)."""
     dx = surrogate_dx(mesh) if dx is None else dx
+    nu = mesh.nu_e
     g0 = mesh.kappa * np.prod(dx, axis=1) / 8.0
-    g1 = mesh.nu * dx[:, 1] * dx[:, 2] / (2.0 * dx[:, 0])
-    g2 = mesh.nu * dx[:, 2] * dx[:, 0] / (2.0 * dx[:, 1])
-    g3 = mesh.nu * dx[:, 0] * dx[:, 1] / (2.0 * dx[:, 2])
+    g1 = nu * dx[:, 1] * dx[:, 2] / (2.0 * dx[:, 0])
+    g2 = nu * dx[:, 2] * dx[:, 0] / (2.0 * dx[:, 1])
+    g3 = nu * dx[:, 0] * dx[:, 1] / (2.0 * dx[:, 2])
     return np.stack([g0, g1, g2, g3], axis=1)
 
 

@@ -51,17 +51,23 @@ class Level:
 
 def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0, weighting='quintic', delta=None):
     """Level list (root first) for global p-coarsening of a uniform-degree mesh.  With `delta`
-    the overlap of every level follows from its degree (Sec. 4.3.1 item 3), else it is m."""
+    the overlap of every level follows from its degree (Sec. 4.3.1 item 3), else it is m.
+    A nodal nu (E, n, n, n) at the fine degree is, like the geometry, evaluated at the nodes of
+    each coarser level (reading: every level rediscretises the same coefficient field)."""
     from .schwarz import overlap_layers
     chain = tr.degree_chain(p)
     levels = [None] * len(chain)
     Xl = np.asarray(X, dtype=np.float64)
+    nul = np.asarray(nu, dtype=np.float64)
+    nodal = nul.ndim == 4
     for li in range(len(chain) - 1, -1, -1):
         pl = chain[li]
         if li < len(chain) - 1:
             Xl = tr.coarse_coords(pl, chain[li + 1], Xl)
+            if nodal:
+                nul = tr.coarse_coords(pl, chain[li + 1], nul[:, None])[:, 0]
         ml = min(overlap_layers(pl, delta), pl) if delta is not None else m
-        levels[li] = Level(Mesh(pl, Xl, nbr, bc, nu=nu, kappa=kappa, mu_star=mu_star), ml, weighting)
+        levels[li] = Level(Mesh(pl, Xl, nbr, bc, nu=nul, kappa=kappa, mu_star=mu_star), ml, weighting)
     return levels
 
 

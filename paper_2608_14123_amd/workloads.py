@@ -122,6 +122,23 @@ def sine_solution(X, k=np.pi):
 
 # --- named workloads -----------------------------------------------------------------
 
+def cosine_diffusivity(X, k=2 * np.pi):
+    """nu = 1 + cos(k x) cos(k y) cos(k z) at coordinates X (E, 3, ...): the variable
+    diffusivity of the paper's blade case (Sec. 6.2.5), between 0 and 2."""
+    return 1.0 + np.cos(k * X[:, 0]) * np.cos(k * X[:, 1]) * np.cos(k * X[:, 2])
+
+
+def cosine_diffusivity_source(X, k=2 * np.pi, kappa=1.0):
+    """f = kappa u - div(nu grad u) for u = sine_solution(X, k) and nu = cosine_diffusivity(X, k):
+    with s_a = sin(k x_a), c_a = cos(k x_a), grad nu . grad u = -3 k^2 (s c)_1 (s c)_2 (s c)_3
+    and nu lap u = -3 k^2 nu u."""
+    s = [np.sin(k * X[:, a]) for a in range(3)]
+    c = [np.cos(k * X[:, a]) for a in range(3)]
+    u = s[0] * s[1] * s[2]
+    nu = 1.0 + c[0] * c[1] * c[2]
+    return kappa * u + 3.0 * k * k * nu * u + 3.0 * k * k * (s[0] * c[0]) * (s[1] * c[1]) * (s[2] * c[2])
+
+
 def cartesian_unit_cube(ne):
     """ne^3 uniform cubes on [0,1]^3 with Dirichlet boundary."""
     nbr, bc = box_topology(ne, ne, ne)
