@@ -2,6 +2,7 @@
 // backward and Adam training on the GPU, and their C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -39,14 +40,14 @@ T* mal(size_t n) {
 
 Mlp::~Mlp() {
   if (st) hipStreamSynchronize(st);
-  void* ps[] = {w, wb, g, m, v, Xb, H1b, H2b, dYb, G2b, G1b, H1, H2, dY, G2, G1, part};
+  void* ps[] = {w, wb, w3p, g, m, v, Xb, H1b, H2b, dYb, G2b, G1b, H1, H2, G2, G1, part, kws};
   for (void* p : ps)
     if (p) hipFree(p);
 }
 
 void Mlp::reserve(int rows) {
   if (rows <= cap) return;
-  void* ps[] = {Xb, H1b, H2b, dYb, G2b, G1b, H1, H2, dY, G2, G1};
+  void* ps[] = {Xb, H1b, H2b, dYb, G2b, G1b, H1, H2, G2, G1, kws};
   MHIP(hipStreamSynchronize(st));
   for (void* p : ps)
     if (p) hipFree(p);
@@ -54,44 +55,54 @@ void Mlp::reserve(int rows) {
   Xb = mal<uint16_t>((size_t)rows * in);
   H1b = mal<uint16_t>((size_t)rows * h);
   H2b = mal<uint16_t>((size_t)rows * h);
-  dYb = mal<uint16_t>((size_t)rows * out);
+  dYb = mal<uint16_t>((size_t)rows * outp);
+  MHIP(hipMemsetAsync(dYb, 0, (size_t)rows * outp * sizeof(uint16_t), st));   // padding columns stay zero
   G2b = mal<uint16_t>((size_t)rows * h);
   G1b = mal<uint16_t>((size_t)rows * h);
   H1 = mal<float>((size_t)rows * h);
   H2 = mal<float>((size_t)rows * h);
-  dY = mal<float>((size_t)rows * out);
   G2 = mal<float>((size_t)rows * h);
   G1 = mal<float>((size_t)rows * h);
+  // up to 16 K-slices of the largest weight gradient (at most 2^24 floats: a slice count the
+  // cap cannot hold falls back to fewer slices)
+  const int64_t mn = std::max<int64_t>((int64_t)(in + 1) * h,
+                                       std::max<int64_t>((int64_t)(h + 1) * h, (int64_t)(h + 1) * out));
+  kws_cap = std::min<int64_t>(16 * mn, (int64_t)1 << 24);
+  kws = mal<float>((size_t)kws_cap);
 }
 
-void Mlp::refresh_bf16() { cast_bf16(n_params, w, wb, st); }
+void Mlp::refresh_w3p() { pad_rows(h, out, outp, wb + off_w3, w3p, st); }
+
+void Mlp::refresh_bf16() {
+  cast_bf16(n_params, w, wb, st);
+  refresh_w3p();
+}
 
 void Mlp::forward(const float* X, int rows, float* Y) {
   reserve(rows);
   cast_bf16((int64_t)rows * in, X, Xb, st);
-  gemm_bf16(rows, h, in, Xb, in, 1, wb + off_w1, h, 1, H1, H1b, w + off_b1, 1, 0, st);
+  gemm_bf16(rows, h, in, Xb, in, 1, wb + off_w1, h, 1, H1, H1b, w + off_b1, 1, 0, st, kws, kws_cap);
   gemm_bf16(rows, h, h, H1b, h, 1, wb + off_w2, h, 1, H2, H2b, w + off_b2, 1, 0, st);
-  gemm_bf16(rows, out, h, H2b, h, 1, wb + off_w3, out, 1, Y, nullptr, w + off_b3, 0, 0, st);
+  gemm_bf16(rows, out, h, H2b, h, 1, w3p, outp, 1, Y, nullptr, w + off_b3, 0, 0, st);
 }
 
 double Mlp::backward(const float* X, const float* T, int rows, float* Y) {
   forward(X, rows, Y);
   const int64_t ny = (int64_t)rows * out;
-  const int nb = 256;
-  mse_grad(ny, Y, T, 1.0f / (float)ny, dY, dYb, part, nb, st);
+  const int nb = kLossBlocks;
+  mse_grad(ny, out, outp, Y, T, 1.0f / (float)ny, dYb, part, nb, st);
+  // every weight gradient is a GEMM over the rows whose A operand gets a row of ones: its last
+  // output row is the bias gradient, which follows the weights in the parameter array
   // layer 3
-  gemm_bf16(h, out, rows, H2b, 1, h, dYb, out, 1, g + off_w3, nullptr, nullptr, 0, 0, st);
-  colsum(rows, out, dY, g + off_b3, st);
-  gemm_bf16(rows, h, out, dYb, out, 1, wb + off_w3, 1, out, G2, nullptr, nullptr, 0, 0, st);
+  gemm_bf16(h + 1, out, rows, H2b, 1, h, dYb, outp, 1, g + off_w3, nullptr, nullptr, 0, 0, st, kws, kws_cap, 1);
+  gemm_bf16(rows, h, out, dYb, outp, 1, w3p, 1, outp, G2, nullptr, nullptr, 0, 0, st, kws, kws_cap);
   relu_back((int64_t)rows * h, G2, H2, G2b, st);
   // layer 2
-  gemm_bf16(h, h, rows, H1b, 1, h, G2b, h, 1, g + off_w2, nullptr, nullptr, 0, 0, st);
-  colsum(rows, h, G2, g + off_b2, st);
+  gemm_bf16(h + 1, h, rows, H1b, 1, h, G2b, h, 1, g + off_w2, nullptr, nullptr, 0, 0, st, kws, kws_cap, 1);
   gemm_bf16(rows, h, h, G2b, h, 1, wb + off_w2, 1, h, G1, nullptr, nullptr, 0, 0, st);
   relu_back((int64_t)rows * h, G1, H1, G1b, st);
   // layer 1
-  gemm_bf16(in, h, rows, Xb, 1, in, G1b, h, 1, g + off_w1, nullptr, nullptr, 0, 0, st);
-  colsum(rows, h, G1, g + off_b1, st);
+  gemm_bf16(in + 1, h, rows, Xb, 1, in, G1b, h, 1, g + off_w1, nullptr, nullptr, 0, 0, st, kws, kws_cap, 1);
   std::vector<double> hp(nb);
   MHIP(hipMemcpyAsync(hp.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st));
   MHIP(hipStreamSynchronize(st));
@@ -152,7 +163,9 @@ dgfas_status dgfas_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uin
   m->n_params = o;
   m->w = mal<float>(o); m->wb = mal<uint16_t>(o); m->g = mal<float>(o);
   m->m = mal<float>(o); m->v = mal<float>(o);
-  m->part = mal<double>(256);
+  m->outp = (n_out + 7) / 8 * 8;
+  m->w3p = mal<uint16_t>((size_t)n_hidden * m->outp);
+  m->part = mal<double>(kLossBlocks);
   // He-normal weights (seeded), zero biases
   std::vector<float> hw(o, 0.f);
   std::mt19937_64 rng(seed);
@@ -257,6 +270,7 @@ dgfas_status dgfas_mlp_train(dgfas_mlp p, const float* X, const float* T, int64_
       const float b1 = 0.9f, b2 = 0.999f;
       const float c1 = 1.f - std::pow(b1, (float)m->step), c2 = 1.f - std::pow(b2, (float)m->step);
       adam(m->n_params, m->w, m->g, m->m, m->v, m->wb, lr, b1, b2, 1e-8f, c1, c2, m->st);
+      m->refresh_w3p();
     }
     MHIP(hipStreamSynchronize(m->st));
   } catch (...) {

@@ -55,6 +55,8 @@ CASES = [
     Case('curved_p8_2^3', 8, 2, amp=0.03),
     Case('curved_p2_5^3', 2, 5, amp=0.02),
     Case('neumann_kappa_p5_3^3', 5, 3, amp=0.03, bc_code=2, kappa=0.7),
+    Case('neumann_kappa_p7_3^3', 7, 3, amp=0.03, bc_code=2, kappa=0.7),
+    Case('periodic_p7_4^3', 7, 4, periodic=True, kappa=0.5),
     Case('stretched_p8_3^3', 8, 3, lengths=(1.0, 1.0, 100.0), perturb=(0.2, 4), mu_star=5.0),
 ]
 

@@ -24,7 +24,19 @@ def bf16_round(a):
     return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize('n_in,h,n_out,rows', [(37, 64, 29, 50), (1340, 256, 1331, 96)])
+def blocks(n_in, h, n_out):
+    """(name, slice) of the parameter blocks W1 b1 W2 b2 W3 b3."""
+    out, o = [], 0
+    for name, n in (('W1', n_in * h), ('b1', h), ('W2', h * h), ('b2', h), ('W3', h * n_out), ('b3', n_out)):
+        out.append((name, slice(o, o + n)))
+        o += n
+    return out
+
+
+# rows >= 512 take the split-K weight gradients (K = rows cut into slices, the last one ragged)
+# and several chunks of the bias column sums
+@pytest.mark.parametrize('n_in,h,n_out,rows', [(37, 64, 29, 50), (1340, 256, 1331, 96), (64, 64, 40, 1500),
+                                               (1340, 256, 1331, 1100)])
 def test_forward_and_gradient(binding, n_in, h, n_out, rows):
     print('mlp', n_in, h, n_out, rows, flush=True)
     net = binding.Mlp(n_in, h, n_out, seed=5)
@@ -48,6 +60,10 @@ def test_forward_and_gradient(binding, n_in, h, n_out, rows):
     print('forward rel err %.2e, loss rel err %.2e, gradient rel err %.2e' % (ferr, abs(loss - lo) / lo, gerr))
     # BF16 rounding of the hidden activations and of the back-propagated signals bounds the error
     assert ferr < 2e-2 and abs(loss - lo) / lo < 2e-2 and gerr < 5e-2
+    g = grad.cpu().numpy()
+    for name, sl in blocks(n_in, h, n_out):
+        berr = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
+        assert berr < 5e-2, (name, berr)
     net.close()
 
 
