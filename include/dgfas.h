@@ -77,6 +77,14 @@ typedef struct {
   int32_t box[3];           /* h-coarsening only (options.h_levels > 0): the mesh is a box of
                                nx x ny x nz elements numbered e = ex + nx (ey + ny ez), its face
                                neighbours those of the box or its periodic wraps; else ignored */
+  const double* nu_nodal;   /* spatially varying diffusivity nu(x) of eq. helmholtz:pde at the GLL
+                               nodes, laid out like a solution vector, or NULL: options.nu
+                               everywhere.  One degree only.  Values >= 0 with positive element
+                               averages.  The bilinear form (eq. helmholtz:dgm) weights the volume
+                               term and each side's normal flux with its own nodal values and the
+                               interior penalty with max(nu-, nu+); the Schwarz surrogate takes the
+                               element average (Sec. 4.3.1); coarser levels evaluate the field at
+                               their own nodes, as they do the geometry */
 } dgfas_mesh_desc;
 
 /* Solver options.  Defaults come from dgfas_default_options. */

@@ -34,7 +34,8 @@ c_dp = ctypes.POINTER(ctypes.c_double)
 
 class MeshDesc(ctypes.Structure):
     _fields_ = [('n_elem', ctypes.c_int32), ('degree', ctypes.c_void_p), ('coords', ctypes.c_void_p),
-                ('face_nbr', ctypes.c_void_p), ('face_bc', ctypes.c_void_p), ('box', ctypes.c_int32 * 3)]
+                ('face_nbr', ctypes.c_void_p), ('face_bc', ctypes.c_void_p), ('box', ctypes.c_int32 * 3),
+                ('nu_nodal', ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -147,7 +148,7 @@ def schwarz_tables_1d(p, m, left, right, mu_star):
 class Solver:
     """One level hierarchy on the current device (see dgfas_create)."""
 
-    def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None, box=None):
+    def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None, box=None, nu=None):
         degree = np.ascontiguousarray(degree, dtype=np.int32)
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         face_nbr = np.ascontiguousarray(face_nbr, dtype=np.int32)
@@ -157,9 +158,13 @@ class Solver:
             raise ValueError('face tables must be (n_elem, 6)')
         if coords.size != int(3 * np.sum((degree.astype(np.int64) + 1) ** 3)):
             raise ValueError('coords must hold 3 (p_e+1)^3 values per element')
-        self._keep = (degree, coords, face_nbr, face_bc)
+        if nu is not None:
+            nu = np.ascontiguousarray(nu, dtype=np.float64)
+            if nu.size * 3 != coords.size:
+                raise ValueError('nu must hold (p_e+1)^3 values per element')
+        self._keep = (degree, coords, face_nbr, face_bc, nu)
         desc = MeshDesc(E, degree.ctypes.data, coords.ctypes.data, face_nbr.ctypes.data, face_bc.ctypes.data,
-                        (ctypes.c_int32 * 3)(*(box or (0, 0, 0))))
+                        (ctypes.c_int32 * 3)(*(box or (0, 0, 0))), None if nu is None else nu.ctypes.data)
         self.options = options if options is not None else default_options()
         h = _V()
         st = None if stream is None else _V(stream)

@@ -407,6 +407,7 @@ geometry_kernel(GeoArgs g, const double* __restrict__ Dg, const double* __restri
   const int64_t fbase = g.offF ? g.offF[e] : (int64_t)e * 6 * N2;
   __shared__ double sX[EPB][3][N3];
   __shared__ double sWJ[EPB][N3];
+  __shared__ double sWJnu[EPB][N3];
   __shared__ double sws[EPB][6][N2];
   if (active)
     for (int a = 0; a < 3; ++a) sX[le][a][node] = X[3 * base + (int64_t)a * N3 + node];
@@ -437,9 +438,10 @@ geometry_kernel(GeoArgs g, const double* __restrict__ Dg, const double* __restri
     const double det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
     if (!(det > 0)) atomicOr(g.bad, 1);
     const double wq = w1[i] * w1[j] * w1[k];
-    // grad xi_b = C[:, b] / det  ->  G_bc = w nu (C[:,b] . C[:,c]) / det
+    // grad xi_b = C[:, b] / det  ->  G_bc = w nu (C[:,b] . C[:,c]) / det, nu at the node
     const int64_t ndof = g.ndof, gi = base + node;
-    const double sc = wq * nu / det;
+    const double nuq = g.nun ? g.nun[gi] : nu;
+    const double sc = wq * nuq / det;
     double Gb[6];
     Gb[0] = sc * (C[0][0] * C[0][0] + C[1][0] * C[1][0] + C[2][0] * C[2][0]);
     Gb[1] = sc * (C[0][0] * C[0][1] + C[1][0] * C[1][1] + C[2][0] * C[2][1]);
@@ -450,6 +452,7 @@ geometry_kernel(GeoArgs g, const double* __restrict__ Dg, const double* __restri
     for (int c = 0; c < 6; ++c) G[c * ndof + gi] = Gb[c];
     WJ[gi] = wq * det;
     sWJ[le][node] = wq * det;
+    sWJnu[le][node] = wq * det * nuq;
     // face nodes: omega * s with N = dx/dxi_t1 x dx/dxi_t2 (tangential columns of J)
     const int idx[3] = {i, j, k};
     for (int ax = 0; ax < 3; ++ax) {
@@ -476,9 +479,13 @@ geometry_kernel(GeoArgs g, const double* __restrict__ Dg, const double* __restri
       area[(int64_t)e * 6 + task] = a;
       for (int f = 0; f < N2; ++f) ws[fbase + task * N2 + f] = sws[le][task][f];
     } else if (task == 6) {
-      double v = 0;
-      for (int t = 0; t < N3; ++t) v += sWJ[le][t];
+      double v = 0, vn = 0;
+      for (int t = 0; t < N3; ++t) {
+        v += sWJ[le][t];
+        vn += sWJnu[le][t];
+      }
       vol[e] = v;
+      if (g.nuavg) g.nuavg[e] = vn / v;
     } else {
       // coefficient of L_1(xi_b) L_0 L_0 in the Legendre expansion of coordinate a
       const int q = task - 7, a = q / 3, b = q % 3;
@@ -524,12 +531,22 @@ void geometry(int p, const GeoArgs& g, const double* D, const double* w, const d
   }
 }
 
-// Penalty factor per element-face node: interior mu_F nu omega s with
+// node of face phi at face-node index f (layout of face_node) and normal index t, degree n - 1
+__device__ __forceinline__ int face_node_n(int n, int phi, int f, int t) {
+  const int a = f / n, b = f % n, ax = phi >> 1;
+  if (ax == 0) return (a * n + b) * n + t;
+  if (ax == 1) return (a * n + t) * n + b;
+  return (t * n + a) * n + b;
+}
+
+// Penalty factor per element-face node: interior mu_F max(nu-, nu+) omega s with
 // mu_F = mu_star avg(p(p+1)/(2 h_perp)) over the two sides (each with its own degree),
-// Dirichlet 2 mu nu omega s, Neumann 0; h_perp = vol / area (eq. helmholtz:dgm).
+// Dirichlet 2 mu nu omega s, Neumann 0; h_perp = vol / area (eq. helmholtz:dgm).  With a nodal
+// nu (one degree), nu- and nu+ are the two sides' values at the face node.
 // muf[e][phi] = mu_F nu (Dirichlet: 2 mu nu) for the face integration on mixed-degree faces.
 __global__ void penalty_kernel(int E, int p, const int* __restrict__ deg, const int64_t* __restrict__ offF,
-                               double mu_star, double nu, const int* __restrict__ nbr,
+                               double mu_star, double nu, const double* __restrict__ nun,
+                               const int* __restrict__ nbr,
                                const int8_t* __restrict__ bc, const double* __restrict__ vol,
                                const double* __restrict__ area, const double* __restrict__ ws,
                                double* __restrict__ pen, double* __restrict__ muf) {
@@ -544,21 +561,31 @@ __global__ void penalty_kernel(int E, int p, const int* __restrict__ deg, const 
   if (en >= 0) {
     const int pn = deg ? deg[en] : p;
     const double oth = pn * (pn + 1) / (2.0 * (vol[en] / area[(int64_t)en * 6 + (phi ^ 1)]));
-    fac = mu_star * 0.5 * (own + oth) * nu;
+    fac = mu_star * 0.5 * (own + oth);
   } else if (bc[t] == 1) {
-    fac = 2.0 * mu_star * own * nu;
+    fac = 2.0 * mu_star * own;
   }
-  if (muf) muf[t] = fac;
+  if (muf) muf[t] = fac * nu;
   const int64_t fb = (offF ? offF[e] : (int64_t)e * 6 * N2) + (int64_t)phi * N2;
-  for (int f = 0; f < N2; ++f) pen[fb + f] = fac * ws[fb + f];
+  if (!nun) {
+    for (int f = 0; f < N2; ++f) pen[fb + f] = fac * nu * ws[fb + f];
+    return;
+  }
+  const int n = pe + 1, N3 = N2 * n;
+  const int end = (phi & 1) ? n - 1 : 0, endo = end ? 0 : n - 1;
+  for (int f = 0; f < N2; ++f) {
+    double nf = nun[(int64_t)e * N3 + face_node_n(n, phi, f, end)];
+    if (en >= 0) nf = fmax(nf, nun[(int64_t)en * N3 + face_node_n(n, phi ^ 1, f, endo)]);
+    pen[fb + f] = fac * nf * ws[fb + f];
+  }
 }
 
-void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const int* nbr,
-             const int8_t* bc, const double* vol, const double* area, const double* ws, double* pen, double* muf,
-             hipStream_t st) {
+void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const double* nun,
+             const int* nbr, const int8_t* bc, const double* vol, const double* area, const double* ws, double* pen,
+             double* muf, hipStream_t st) {
   const int64_t n = (int64_t)E * 6;
   hipLaunchKernelGGL(penalty_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, E, p, deg, offF, mu_star,
-                     nu, nbr, bc, vol, area, ws, pen, muf);
+                     nu, nun, nbr, bc, vol, area, ws, pen, muf);
 }
 
 }  // namespace dgfas

@@ -71,6 +71,8 @@ struct GeoArgs {
   const double* X = nullptr;        // coordinates, element e at 3 off[e]: [3][(p+1)^3]
   double *G = nullptr, *WJ = nullptr, *ws = nullptr, *vol = nullptr, *area = nullptr, *lin = nullptr;
   int* bad = nullptr;               // set when det J <= 0 somewhere
+  const double* nun = nullptr;      // nodal diffusivity (null: the scalar nu everywhere)
+  double* nuavg = nullptr;          // [E] element average of nu (int nu dx / int dx), or null
 };
 void geometry(int p, const GeoArgs& g, const double* D, const double* w, const double* x, double nu,
               hipStream_t st);
@@ -89,7 +91,9 @@ struct RhsArgs {
 };
 void rhs(int p, const RhsArgs& r, const double* D, double inv_wend, hipStream_t st);
 
-void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const int* nbr,
+// nun: nodal diffusivity (uniform degree, offsets e (p+1)^3) or null for the scalar nu
+void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const double* nun,
+             const int* nbr,
              const int8_t* bc, const double* vol, const double* area, const double* ws, double* pen, double* muf,
              hipStream_t st);
 

@@ -159,6 +159,8 @@ struct Level {
   // geometry
   double *X = nullptr, *G = nullptr, *WJ = nullptr, *ws = nullptr, *pen = nullptr;
   double *vol = nullptr, *area = nullptr, *lin = nullptr;
+  double* nun = nullptr;         // nodal diffusivity of the level, or null (the scalar nu)
+  double* nuavg = nullptr;       // [E] element averages of nun
   float *G32 = nullptr, *WJ32 = nullptr, *pen32 = nullptr;
   // Schwarz
   int* nb27 = nullptr;
@@ -982,7 +984,7 @@ DegTab& deg_tab(Solver& s, int p) {
 }
 
 // Level set-up from per-element degrees and device coordinates (element e at 3 off[e]).
-void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double* dX) {
+void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double* dX, double* dNu) {
   hipStream_t st = s.st;
   const int E = L.E;   // set by the caller with the level's topology
   L.h_deg = deg;
@@ -1096,16 +1098,20 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   L.vol = s.own(dalloc<double>(E));
   L.area = s.own(dalloc<double>((size_t)E * 6));
   L.lin = s.own(dalloc<double>((size_t)E * 9));
+  L.nun = dNu;
+  if (dNu) L.nuavg = s.own(dalloc<double>(E));
   int* bad = s.own(dalloc<int>(1));
   HIPC(hipMemsetAsync(bad, 0, sizeof(int), st));
   for (const Bucket& b : L.bk) {
     GeoArgs g;
     g.nel = b.nel; g.elist = b.elist; g.off = L.off; g.offF = L.offF; g.ndof = L.ndof; g.X = dX;
     g.G = L.G; g.WJ = L.WJ; g.ws = L.ws; g.vol = L.vol; g.area = L.area; g.lin = L.lin; g.bad = bad;
+    g.nun = L.nun; g.nuavg = L.nuavg;
     geometry(b.p, g, b.t->D, b.t->w1, b.t->x1, s.opt.nu, st);
     HIPC(hipGetLastError());
   }
-  penalty(E, L.p, L.deg, L.offF, s.opt.mu_star, s.opt.nu, L.nbr, L.bc, L.vol, L.area, L.ws, L.pen, L.muf, st);
+  penalty(E, L.p, L.deg, L.offF, s.opt.mu_star, s.opt.nu, L.nun, L.nbr, L.bc, L.vol, L.area, L.ws, L.pen, L.muf,
+          st);
   HIPC(hipGetLastError());
   int hbad = 0;
   HIPC(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1121,6 +1127,11 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
 
   // surrogate cuboid (Sec. 4.3.1 steps 1-3): Delta x_b = 2|a_b| (vol / prod)^(1/3)
   std::vector<double> vol = download(L.vol, E, st), lin = download(L.lin, (size_t)E * 9, st);
+  // the surrogate's nu: the element average of a nodal field (Sec. 4.3.1), else the scalar
+  std::vector<double> nue = L.nuavg ? download(L.nuavg, E, st) : std::vector<double>(E, s.opt.nu);
+  for (int e = 0; e < E; ++e)
+    if (!(nue[e] > 0))
+      throw Error(DGFAS_EINVAL, "the element average of nu must be positive (degree " + std::to_string(L.p) + ")");
   std::vector<double> gco((size_t)E * 4);
   for (int e = 0; e < E; ++e) {
     double ell[3];
@@ -1132,9 +1143,9 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     const double sc = std::cbrt(vol[e] / (ell[0] * ell[1] * ell[2]));
     const double dx[3] = {ell[0] * sc, ell[1] * sc, ell[2] * sc};
     gco[e * 4 + 0] = s.opt.kappa * dx[0] * dx[1] * dx[2] / 8.0;
-    gco[e * 4 + 1] = s.opt.nu * dx[1] * dx[2] / (2.0 * dx[0]);
-    gco[e * 4 + 2] = s.opt.nu * dx[2] * dx[0] / (2.0 * dx[1]);
-    gco[e * 4 + 3] = s.opt.nu * dx[0] * dx[1] / (2.0 * dx[2]);
+    gco[e * 4 + 1] = nue[e] * dx[1] * dx[2] / (2.0 * dx[0]);
+    gco[e * 4 + 2] = nue[e] * dx[2] * dx[0] / (2.0 * dx[1]);
+    gco[e * 4 + 3] = nue[e] * dx[0] * dx[1] / (2.0 * dx[2]);
   }
   L.gco = s.own(upload(gco, st));
   {
@@ -1394,6 +1405,15 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
         throw Error(DGFAS_EINVAL, "boundary face without a Dirichlet/Neumann code");
     }
   if (!(o->nu > 0) || !(o->kappa >= 0) || !(o->mu_star > 0)) throw Error(DGFAS_EINVAL, "bad coefficients");
+  if (m->nu_nodal) {
+    const int p = m->degree[0];
+    for (int e = 1; e < m->n_elem; ++e)
+      if (m->degree[e] != p) throw Error(DGFAS_EUNSUPPORTED, "a nodal nu needs one degree on the mesh");
+    const int64_t n = (int64_t)m->n_elem * (p + 1) * (p + 1) * (p + 1);
+    for (int64_t q = 0; q < n; ++q)
+      if (!(m->nu_nodal[q] >= 0) || !std::isfinite(m->nu_nodal[q]))
+        throw Error(DGFAS_EINVAL, "nodal nu must be finite and >= 0");
+  }
   if (o->overlap < 0 && !(o->delta >= 0.0 && o->delta < 1.0)) throw Error(DGFAS_EINVAL, "delta must be in [0, 1)");
   // every degree on every level (p -> max(1, p / 2) per element) needs a kernel for its overlap
   {
@@ -1600,6 +1620,13 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   };
   double* X = s->own(dalloc<double>(ncoords(sp[Lc - 1].deg)));
   HIPC(hipMemcpyAsync(X, m->coords, ncoords(sp[Lc - 1].deg) * sizeof(double), hipMemcpyHostToDevice, s->st));
+  // a nodal diffusivity follows the geometry from level to level (one component)
+  double* NU = nullptr;
+  if (m->nu_nodal) {
+    NU = s->own(dalloc<double>(ncoords(sp[Lc - 1].deg) / 3));
+    HIPC(hipMemcpyAsync(NU, m->nu_nodal, ncoords(sp[Lc - 1].deg) / 3 * sizeof(double), hipMemcpyHostToDevice,
+                        s->st));
+  }
   for (int li = Lc - 1; li >= 0; --li) {
     Level& L = s->lv[li];
     const std::vector<int>& dgl = sp[li].deg;
@@ -1608,11 +1635,17 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
       // parent from its children (h, averaged where the children meet)
       Level& F = s->lv[li + 1];
       double* Xc = s->own(dalloc<double>(ncoords(dgl)));
+      double* NUc = NU ? s->own(dalloc<double>(ncoords(dgl) / 3)) : nullptr;
       if (F.hdown) {
         HXferArgs<double> a;
         a.kind = 0; a.ncoarse = L.E; a.children = F.hchild; a.ncomp = 3; a.M = F.hM; a.in = X; a.out = Xc;
         if (!htransfer<double>(F.p, a, s->st)) throw Error(DGFAS_EUNSUPPORTED, "no h-transfer kernel for this degree");
         HIPC(hipGetLastError());
+        if (NU) {
+          a.ncomp = 1; a.in = NU; a.out = NUc;
+          htransfer<double>(F.p, a, s->st);
+          HIPC(hipGetLastError());
+        }
       } else {
         const int Ep = L.E;
         std::vector<int64_t> offc(Ep);
@@ -1644,11 +1677,18 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
           if (!tensor3<double>(pf + 1, pc + 1, a, s->st))
             throw Error(DGFAS_EUNSUPPORTED, "no transfer kernel for this degree pair");
           HIPC(hipGetLastError());
+          if (NU) {   // one degree: the whole level is one block of E elements
+            XferArgs<double> an;
+            an.Tm = Pgeo; an.in = NU; an.out = NUc; an.nel = Ep;
+            tensor3<double>(pf + 1, pc + 1, an, s->st);
+            HIPC(hipGetLastError());
+          }
         }
       }
       X = Xc;
+      NU = NUc;
     }
-    build_level(*s, L, dgl, X);
+    build_level(*s, L, dgl, X, NU);
     L.X = X;
     if (li < Lc - 1) {
       s->reserve(L.u, (size_t)L.ndof * s->nrhs);

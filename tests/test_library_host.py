@@ -134,3 +134,26 @@ def test_overlap_without_a_kernel_is_unsupported(lib, p, kw):
     with pytest.raises(lib.DgfasError) as ei:
         lib.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc, lib.default_options(**kw))
     assert ei.value.code == lib.DGFAS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize('case', ['negative', 'nan', 'mixed_degrees'])
+def test_bad_nodal_nu_is_refused(lib, case):
+    """A nodal diffusivity must be finite and >= 0 and needs one degree on the mesh; both are
+    checked on the host before any device work."""
+    from paper_2608_14123_amd import workloads as W
+    ne, p = 2, 3
+    nbr, bc = W.box_topology(ne, ne, ne)
+    deg = np.full(ne ** 3, p, np.int32)
+    if case == 'mixed_degrees':
+        deg[0] = 2
+    xs = {q: lib.gll(q)[0] for q in set(deg.tolist())}
+    X = np.concatenate([x.ravel() for x in W.element_coords_mixed(W.box_vertices(ne, ne, ne), deg,
+                                                                  lambda q: xs[q])])
+    nu = np.ones(X.size // 3)
+    if case == 'negative':
+        nu[5] = -0.1
+    elif case == 'nan':
+        nu[7] = np.nan
+    with pytest.raises(lib.DgfasError) as ei:
+        lib.Solver(deg, X, nbr, bc, lib.default_options(), nu=nu)
+    assert ei.value.code == (lib.DGFAS_EUNSUPPORTED if case == 'mixed_degrees' else lib.DGFAS_EINVAL)
