@@ -85,6 +85,17 @@ typedef struct {
                                interior penalty with max(nu-, nu+); the Schwarz surrogate takes the
                                element average (Sec. 4.3.1); coarser levels evaluate the field at
                                their own nodes, as they do the geometry */
+  const int32_t* refine_count;  /* local refinement (options.local_steps > 0, Sec. 3.1): elements of
+                               the base mesh, then of each refined level in turn, marked for regular
+                               refinement; refine_count[k] entries of refine_list per step k */
+  const int32_t* refine_list;   /* element ids of the level being refined.  A marked element must be
+                               active, and so must every element of its 3 x 3 x 3 block inside the
+                               domain (the block's other elements are refined irregularly: their
+                               children are frozen).  The refined level lists, parent by parent in
+                               id order, the 8 children c = bx + 2 by + 4 bz of every regularly or
+                               irregularly refined parent (b = 1: the upper half of the parent's
+                               reference interval along that axis); a child's geometry is its
+                               parent's map at the child's nodes */
 } dgfas_mesh_desc;
 
 /* Solver options.  Defaults come from dgfas_default_options. */
@@ -149,7 +160,11 @@ typedef struct {
                                mesh.box.  0: none */
   int32_t h_only;           /* with h_levels > 0: 1 makes the coarsest h-level the root (pure h-MG,
                                root SCG at the fine degree); 0 p-coarsens it down to p = 1 */
-  int32_t reserved[1];
+  int32_t local_steps;      /* local h-refinement (Sec. 3.1, 3.3): levels above the given base mesh
+                               built from mesh.refine_count / refine_list, with twig, leaf and
+                               frozen elements; the base is p-coarsened down to p = 1 below it.
+                               One degree, FP64, one right-hand side, no h_levels, start-up, graph,
+                               nodal nu or learned correction.  0: none */
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);
@@ -201,7 +216,29 @@ dgfas_status dgfas_set_workspace(dgfas_solver s, void* dptr, size_t bytes);
  * b [n_dof] is written. */
 dgfas_status dgfas_rhs(dgfas_solver s, const double* f, const double* uD, const double* qN, double* b);
 
-/* Au = A_l u (eq. helmholtz:system on level l). */
+/* Local refinement (options.local_steps > 0).  Every level keeps its own solution; the leaves
+ * of every level carry the original right-hand side and the twigs the FAS one (eq.
+ * helmholtz:fas).  dgfas_solve then runs Alg. 2 with the frozen update and measures the
+ * composite residual: the 2-norm of f^l - A u over the leaf rows of every level (eq.
+ * helmholtz:fas:converged:leaves), relative to its value at the start; the top level's u and f
+ * are the call's, the other levels start from zero in every call.
+ *
+ * Element classes of a level into cls (host, [n_elem] of that level): 0 twig, 1 leaf, 2 frozen. */
+dgfas_status dgfas_level_classes(dgfas_solver s, int32_t level, int8_t* cls);
+/* Nodal coordinates of a level (host, per element [3][(p+1)^3]), e.g. to evaluate f there. */
+dgfas_status dgfas_level_coords(dgfas_solver s, int32_t level, double* coords);
+/* b = the discrete right-hand side of eq. helmholtz:system on level l (device vectors of that
+ * level; uD, qN may be NULL), over all its elements. */
+dgfas_status dgfas_level_rhs(dgfas_solver s, int32_t level, const double* f, const double* uD, const double* qN,
+                             double* b);
+/* The leaf rows of b (device, n_dof of the level) become the right-hand side of a level below
+ * the top; the rest of that level's right-hand side is set by the cycle. */
+dgfas_status dgfas_set_level_rhs(dgfas_solver s, int32_t level, const double* b);
+/* u = the current solution of a level below the top (device, n_dof of the level). */
+dgfas_status dgfas_level_solution(dgfas_solver s, int32_t level, double* u);
+
+/* Au = A_l u (eq. helmholtz:system on level l).  On a locally refined level only the rows of
+ * active elements are written. */
 dgfas_status dgfas_apply(dgfas_solver s, int32_t level, const double* u, double* Au);
 
 /* r = g - A_l u (Alg. 2 residual computation). */

@@ -35,7 +35,7 @@ c_dp = ctypes.POINTER(ctypes.c_double)
 class MeshDesc(ctypes.Structure):
     _fields_ = [('n_elem', ctypes.c_int32), ('degree', ctypes.c_void_p), ('coords', ctypes.c_void_p),
                 ('face_nbr', ctypes.c_void_p), ('face_bc', ctypes.c_void_p), ('box', ctypes.c_int32 * 3),
-                ('nu_nodal', ctypes.c_void_p)]
+                ('nu_nodal', ctypes.c_void_p), ('refine_count', ctypes.c_void_p), ('refine_list', ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ('graph', ctypes.c_int32), ('order', ctypes.c_int32), ('start', ctypes.c_int32),
                 ('ns0', ctypes.c_int32), ('nsc', ctypes.c_int32), ('weighting', ctypes.c_int32),
                 ('delta', ctypes.c_double), ('projection', ctypes.c_int32), ('h_levels', ctypes.c_int32),
-                ('h_only', ctypes.c_int32), ('reserved', ctypes.c_int32 * 1)]
+                ('h_only', ctypes.c_int32), ('local_steps', ctypes.c_int32)]
 
 
 class DgfasError(RuntimeError):
@@ -69,6 +69,11 @@ _sig = {
     'dgfas_workspace_size': (_I, [_V, ctypes.POINTER(ctypes.c_size_t)]),
     'dgfas_set_workspace': (_I, [_V, _V, ctypes.c_size_t]),
     'dgfas_rhs': (_I, [_V, _V, _V, _V, _V]),
+    'dgfas_level_classes': (_I, [_V, _I, _V]),
+    'dgfas_level_coords': (_I, [_V, _I, c_dp]),
+    'dgfas_level_rhs': (_I, [_V, _I, _V, _V, _V, _V]),
+    'dgfas_set_level_rhs': (_I, [_V, _I, _V]),
+    'dgfas_level_solution': (_I, [_V, _I, _V]),
     'dgfas_apply': (_I, [_V, _I, _V, _V]),
     'dgfas_residual': (_I, [_V, _I, _V, _V, _V]),
     'dgfas_schwarz': (_I, [_V, _I, _V, _V]),
@@ -148,7 +153,10 @@ def schwarz_tables_1d(p, m, left, right, mu_star):
 class Solver:
     """One level hierarchy on the current device (see dgfas_create)."""
 
-    def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None, box=None, nu=None):
+    def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None, box=None, nu=None,
+                 refine=None):
+        """refine: with options.local_steps > 0, one list of element ids per refinement step
+        (ids of the level being refined; see dgfas_mesh_desc.refine_list)."""
         degree = np.ascontiguousarray(degree, dtype=np.int32)
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         face_nbr = np.ascontiguousarray(face_nbr, dtype=np.int32)
@@ -162,9 +170,15 @@ class Solver:
             nu = np.ascontiguousarray(nu, dtype=np.float64)
             if nu.size * 3 != coords.size:
                 raise ValueError('nu must hold (p_e+1)^3 values per element')
-        self._keep = (degree, coords, face_nbr, face_bc, nu)
+        rc = rl = None
+        if refine is not None:
+            rc = np.ascontiguousarray([len(r) for r in refine], dtype=np.int32)
+            rl = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.int32) for r in refine])
+                                      if len(refine) else np.zeros(0), dtype=np.int32)
+        self._keep = (degree, coords, face_nbr, face_bc, nu, rc, rl)
         desc = MeshDesc(E, degree.ctypes.data, coords.ctypes.data, face_nbr.ctypes.data, face_bc.ctypes.data,
-                        (ctypes.c_int32 * 3)(*(box or (0, 0, 0))), None if nu is None else nu.ctypes.data)
+                        (ctypes.c_int32 * 3)(*(box or (0, 0, 0))), None if nu is None else nu.ctypes.data,
+                        None if rc is None else rc.ctypes.data, None if rl is None or rl.size == 0 else rl.ctypes.data)
         self.options = options if options is not None else default_options()
         h = _V()
         st = None if stream is None else _V(stream)
@@ -271,6 +285,40 @@ class Solver:
     def vcycle(self, u, f):
         n = self._n(self.n_levels)
         _check(_lib.dgfas_vcycle(self._h, _dev(u, n, 'u'), _dev(f, n, 'f')))
+
+    def level_classes(self, level):
+        """Element classes of a level: 0 twig, 1 leaf, 2 frozen (numpy int8)."""
+        E = self.level_elements(level)
+        out = np.zeros(E, dtype=np.int8)
+        _check(_lib.dgfas_level_classes(self._h, level, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def level_elements(self, level):
+        deg = _I()
+        nd = ctypes.c_int64()
+        _check(_lib.dgfas_level_info(self._h, level, ctypes.byref(deg), ctypes.byref(nd)))
+        return int(nd.value // (deg.value + 1) ** 3)
+
+    def level_coords(self, level):
+        """Nodal coordinates of a level, (n_elem, 3, n, n, n) numpy."""
+        deg = _I()
+        nd = ctypes.c_int64()
+        _check(_lib.dgfas_level_info(self._h, level, ctypes.byref(deg), ctypes.byref(nd)))
+        n = deg.value + 1
+        out = np.zeros((nd.value // n ** 3, 3, n, n, n))
+        _check(_lib.dgfas_level_coords(self._h, level, out.ctypes.data_as(c_dp)))
+        return out
+
+    def level_rhs(self, level, f, b, uD=None, qN=None):
+        n = self._n(level)
+        _check(_lib.dgfas_level_rhs(self._h, level, _dev(f, n, 'f'), _dev(uD, n, 'uD'), _dev(qN, n, 'qN'),
+                                    _dev(b, n, 'b')))
+
+    def set_level_rhs(self, level, b):
+        _check(_lib.dgfas_set_level_rhs(self._h, level, _dev(b, self._n(level), 'b')))
+
+    def level_solution(self, level, u):
+        _check(_lib.dgfas_level_solution(self._h, level, _dev(u, self._n(level), 'u')))
 
     def solve(self, u, f, max_cycles=30, rtol=1e-10):
         hist, code = solve_status(self, u, f, max_cycles, rtol)

@@ -114,8 +114,9 @@ template <int N, typename T>
 __global__ void __launch_bounds__((N * N * N + 63) / 64 * 64) htransfer_kernel(HXferArgs<T> a) {
   constexpr int N2 = N * N, N3 = N * N * N;
   const int nsub = a.nrhs * a.ncomp;
-  const int parent = blockIdx.x / nsub, sub = blockIdx.x - parent * nsub;
-  if (parent >= a.ncoarse) return;
+  const int pidx = blockIdx.x / nsub, sub = blockIdx.x - pidx * nsub;
+  if (pidx >= a.ncoarse) return;
+  const int parent = a.parents ? a.parents[pidx] : pidx;
   const int rhs = sub / a.ncomp, comp = sub - rhs * a.ncomp;
   const int q = threadIdx.x;
   const bool act = q < N3;
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__((N * N * N + 63) / 64 * 64) htransfer_kernel(H
     T acc = 0;
     for (int c = 0; c < 8; ++c) {
       const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
-      const int child = a.children[(int64_t)parent * 8 + c];
+      const int child = a.children[(int64_t)pidx * 8 + c];
       __syncthreads();   // the previous child's contraction has read s0
       if (act) s0[q] = a.in[(int64_t)rhs * a.stride_f + ((int64_t)child * a.ncomp + comp) * N3 + q];
       acc += contract(sM[m0 + bx], sM[m0 + by], sM[m0 + bz]);
@@ -159,7 +160,7 @@ __global__ void __launch_bounds__((N * N * N + 63) / 64 * 64) htransfer_kernel(H
     if (act) s0[q] = a.in[cb + q] - (a.in2 ? a.in2[cb + q] : T(0));
     for (int c = 0; c < 8; ++c) {
       const int bx = c & 1, by = (c >> 1) & 1, bz = c >> 2;
-      const int child = a.children[(int64_t)parent * 8 + c];
+      const int child = a.children[(int64_t)pidx * 8 + c];
       const T v = contract(sM[4 + bx], sM[4 + by], sM[4 + bz]);
       if (act) {
         T& o = a.out[(int64_t)rhs * a.stride_f + ((int64_t)child * a.ncomp + comp) * N3 + q];
@@ -182,6 +183,39 @@ bool htransfer(int p, const HXferArgs<T>& a, hipStream_t st) {
   }
 }
 template bool htransfer<double>(int, const HXferArgs<double>&, hipStream_t);
+
+__global__ void __launch_bounds__(256) copy_rows_kernel(const int* __restrict__ list, int n, int n3,
+                                                        const double* __restrict__ src, double* __restrict__ dst) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const int64_t o = (int64_t)list[i] * n3;
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) dst[o + q] = src[o + q];
+}
+
+void copy_rows(const int* list, int n, int n3, const double* src, double* dst, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(copy_rows_kernel, dim3(n), dim3(256), 0, st, list, n, n3, src, dst);
+}
+
+__global__ void __launch_bounds__(256) rows_sumsq_kernel(const int* __restrict__ list, int n, int n3,
+                                                         const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const int64_t o = (int64_t)list[i] * n3;
+  double s = 0;
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) s += v[o + q] * v[o + q];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = sh[0];
+}
+
+void rows_sumsq(const int* list, int n, int n3, const double* v, double* out, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(rows_sumsq_kernel, dim3(n), dim3(256), 0, st, list, n, n3, v, out);
+}
 
 // ---------------------------------------------------------------------------
 constexpr int kRedThreads = 256;

@@ -216,8 +216,9 @@ bool tensor3(int n_in, int n_out, const XferArgs<T>& a, hipStream_t st);
 template <typename T>
 struct HXferArgs {
   int kind = 0;
-  int ncoarse = 0;                   // parents
-  const int* children = nullptr;     // [ncoarse][8] fine element ids
+  int ncoarse = 0;                   // parents of this launch
+  const int* parents = nullptr;      // [ncoarse] parent element ids (null: 0..ncoarse-1)
+  const int* children = nullptr;     // [ncoarse][8] fine element ids, row i for parents[i]
   int ncomp = 1, nrhs = 1;
   int64_t stride_f = 0, stride_c = 0;
   const T* M = nullptr;              // [6][N][N]: P_0, P_1, R_0 = I_0^T, R_1 = I_1^T, I_0, I_1
@@ -226,6 +227,10 @@ struct HXferArgs {
   T* out = nullptr;
   int accumulate = 0;                // add to out
 };
+// dst rows of the listed elements = src rows (n3 values per element, uniform layout)
+void copy_rows(const int* list, int n, int n3, const double* src, double* dst, hipStream_t st);
+// out[i] = sum of squares of v over element list[i] (n3 values per element, uniform layout)
+void rows_sumsq(const int* list, int n, int n3, const double* v, double* out, hipStream_t st);
 template <typename T>
 bool htransfer(int p, const HXferArgs<T>& a, hipStream_t st);
 

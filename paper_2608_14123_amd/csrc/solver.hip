@@ -118,6 +118,10 @@ struct Bucket {
   double *Pm = nullptr, *Im = nullptr, *Rm = nullptr;
 };
 
+// element classes of local refinement (Sec. 3.1)
+const int8_t kTwig = 0, kLeaf = 1, kFrozen = 2;
+const int8_t kLevelEdge = 3;   // host only: a frozen element's face toward the unrefined region
+
 struct Level {
   int p = 0, n = 0, N2 = 0, N3 = 0, E = 0, m = 0, ns = 0;   // p: largest degree on the level
   bool uniform = true;
@@ -131,6 +135,19 @@ struct Level {
   bool hdown = false;
   int* hchild = nullptr;                // [E of the coarser level][8] children of every parent
   double* hM = nullptr;                 // [6][n][n] P_0, P_1, I_0^T, I_1^T, I_0, I_1
+  // local refinement (Sec. 3.1): element classes; the sweep kernels run over the active
+  // elements, frozen ones are data.  The transfer lists to the level below sit on the finer
+  // level: twig parents with their active children, irregular (leaf) parents with their frozen
+  // children.
+  bool lr = false;
+  std::vector<int8_t> h_cls;            // kTwig / kLeaf / kFrozen per element
+  int nact = 0, nleaf = 0, ntwig = 0;
+  int *act_list = nullptr, *leaf_list = nullptr, *twig_list = nullptr;
+  int* sdeg = nullptr;                  // degree per element for the Schwarz kernels, frozen -1
+  bool lr_down = false;                 // built from the level below by local refinement
+  int ntw = 0, nir = 0;
+  int *tw_par = nullptr, *tw_ch = nullptr, *ir_par = nullptr, *ir_ch = nullptr;
+  double* sq = nullptr;                 // [nleaf] composite-residual partials
   int64_t ndof = 0, nfs = 0, nin = 0;   // nodes, face-node slots and inbox slots per right-hand side
   double inv_wend = 0;
   std::vector<int> h_deg;
@@ -848,6 +865,16 @@ struct Solver {
         rF = F.r;
       }
       F.rsm = nullptr;
+      if (F.lr_down) {
+        // local refinement (Alg. 2, eq. helmholtz:fas:rhs): only the twigs take the projected
+        // solution and the FAS right-hand side A u + R r; leaves keep theirs
+        lr_transfer(F, C, 0, false, F.u, nullptr, C.ubar, 0);                     // ubar^t = P u^a
+        copy_rows(C.twig_list, C.ntwig, C.N3, C.ubar, C.u, st);
+        apply(C, C.u, C.r);                                                      // A u (active rows)
+        lr_transfer(F, C, 1, false, rF, nullptr, C.r, 1);                        //   + R r at twigs
+        copy_rows(C.twig_list, C.ntwig, C.N3, C.r, C.g, st);
+        continue;
+      }
       transfer(F, C, 0, F.u, nullptr, C.ubar, 0);                              // ubar = P u
       HIPC(hipMemcpyAsync(C.u, C.ubar, C.ndof * nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       apply(C, C.ubar, C.g);                                                     // g = A ubar
@@ -855,11 +882,48 @@ struct Solver {
     }
   }
 
+  // transfers of a locally refined level F and the level C below it: kind 0 projection and
+  // 1 restriction from the active children into the twig parents, kind 2 prolongation from the
+  // twig parents (irregular = false) or the irregular leaf parents (true) to their children
+  void lr_transfer(Level& F, Level& C, int kind, bool irregular, const double* in, const double* in2, double* out,
+                   int acc) {
+    HXferArgs<double> a;
+    a.kind = kind;
+    a.ncoarse = irregular ? F.nir : F.ntw;
+    a.parents = irregular ? F.ir_par : F.tw_par;
+    a.children = irregular ? F.ir_ch : F.tw_ch;
+    a.nrhs = 1; a.stride_f = F.ndof; a.stride_c = C.ndof; a.M = F.hM;
+    a.in = in; a.in2 = in2; a.out = out; a.accumulate = acc;
+    if (!htransfer<double>(F.p, a, st)) throw Error(DGFAS_EUNSUPPORTED, "no h-transfer kernel for this degree");
+  }
+
+  // composite residual (eq. helmholtz:fas:converged:leaves): sum over the levels of the squared
+  // leaf rows of g - A u, with the top level's u and g given
+  double composite_norm2(const double* u_top, const double* g_top) {
+    double s2 = 0.0;
+    const int Lc = (int)lv.size();
+    for (int l = 0; l < Lc; ++l) {
+      Level& L = lv[l];
+      if (!L.nleaf) continue;
+      const bool top = l == Lc - 1;
+      residual(L, top ? u_top : L.u, top ? g_top : L.g, L.r);
+      rows_sumsq(L.leaf_list, L.nleaf, L.N3, L.r, L.sq, st);
+      std::vector<double> h = download(L.sq, L.nleaf, st);
+      for (double v : h) s2 += v;
+    }
+    return s2;
+  }
+
   void leg_up(int top) {
     for (int l = 1; l <= top; ++l) {
       Level& F = lv[l];
       Level& C = lv[l - 1];
-      transfer(F, C, 2, C.u, C.ubar, F.u, 1);                                  // u += I (u_c - ubar)
+      if (F.lr_down) {
+        lr_transfer(F, C, 2, true, C.u, nullptr, F.u, 0);                      // u^f = I u^l_{l-1}
+        lr_transfer(F, C, 2, false, C.u, C.ubar, F.u, 1);                      // u^a += I (u^t - ubar^t)
+      } else {
+        transfer(F, C, 2, C.u, C.ubar, F.u, 1);                                // u += I (u_c - ubar)
+      }
       smooth(F, F.u, F.g, opt.ns2);
     }
   }
@@ -876,6 +940,7 @@ OpArgs<T> Solver::op_args(Level& L, const Bucket& b, int mode, const T* u, const
   a.off = L.off;
   a.offF = L.offF;
   a.deg = L.deg;
+  if (L.lr) { a.nel = L.nact; a.elist = L.act_list; }
   a.ndof = L.ndof;
   a.nrhs = nrhs;
   a.u = u;
@@ -902,7 +967,8 @@ SchwarzArgs<T> Solver::sz_args(Level& L, const Bucket& b, const T* r, T* z, int 
   a.elist = b.elist;
   a.off = L.off;
   a.offO = L.offO;
-  a.deg = L.deg;
+  a.deg = L.lr ? L.sdeg : L.deg;
+  if (L.lr) { a.nel = L.nact; a.elist = L.act_list; }
   a.ndof = L.ndof;
   a.nin = L.nin;
   a.nrhs = nrhs;
@@ -1025,6 +1091,25 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     b.t = &deg_tab(s, p);
     L.all_m1 = L.all_m1 && b.t->m == 1;
     L.bk.push_back(std::move(b));
+  }
+  // local refinement: the sweep kernels take the active elements (frozen ones keep their
+  // values, their rows are never written); the Schwarz kernels see a frozen element as one of
+  // another degree (no overlap into it, zero fill, no scatter)
+  if (L.lr) {
+    std::vector<int> act, leaf, twig, sd(E);
+    for (int e = 0; e < E; ++e) {
+      const int8_t c = L.h_cls[e];
+      if (c != kFrozen) act.push_back(e);
+      if (c == kLeaf) leaf.push_back(e);
+      if (c == kTwig) twig.push_back(e);
+      sd[e] = c == kFrozen ? -1 : deg[e];
+    }
+    L.nact = (int)act.size(); L.nleaf = (int)leaf.size(); L.ntwig = (int)twig.size();
+    L.act_list = s.own(upload(act, st));
+    if (L.nleaf) L.leaf_list = s.own(upload(leaf, st));
+    if (L.ntwig) L.twig_list = s.own(upload(twig, st));
+    L.sdeg = s.own(upload(sd, st));
+    if (L.nleaf) L.sq = s.own(dalloc<double>(L.nleaf));
   }
   // degree histogram and the one-launch work lists (largest degree first)
   for (const Bucket& b : L.bk) L.hist += std::to_string(b.p) + ":" + std::to_string(b.nel) + ",";
@@ -1171,7 +1256,8 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       for (int sd = 0; sd < 2; ++sd) {
         const int f = kFace[d][sd];
         const int en = L.h_nbr[e * 6 + f];
-        if (en >= 0) code[sd] = deg[en] == deg[e] ? kInterior : kInteriorNoOverlap;
+        const bool frozen_nb = L.lr && en >= 0 && L.h_cls[en] == kFrozen;
+        if (en >= 0) code[sd] = deg[en] == deg[e] && !frozen_nb ? kInterior : kInteriorNoOverlap;
         else code[sd] = L.h_bc[e * 6 + f] == DGFAS_NEUMANN ? kNeumann : kDirichlet;
       }
       var[e * 3 + d] = (int8_t)(code[0] * kSides + code[1]);
@@ -1192,9 +1278,12 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   // Weight sum C = sum_s R_s^T W_s R_s 1 at every node.  Near a degree jump the subdomains that
   // reach a node can disagree about who covers it (neighbours of another degree are zero filled),
   // so the corrections are normalised by C there (C > 0: the own subdomain always covers a node)
-  if (!L.uniform && L.m > 0 && s.opt.weighting == DGFAS_WEIGHT_QUINTIC) {
+  // (a frozen neighbour is treated as one of another degree; frozen nodes get no correction)
+  auto frozen = [&](int e) { return L.lr && L.h_cls[e] == kFrozen; };
+  if ((!L.uniform || L.lr) && L.m > 0 && s.opt.weighting == DGFAS_WEIGHT_QUINTIC) {
     std::vector<double> C((size_t)L.ndof, 0.0);
     for (int e = 0; e < E; ++e) {
+      if (frozen(e)) continue;
       const DegTab& t = deg_tab(s, deg[e]);
       const int n = t.n, NS = t.ns;
       const int* mp[3];
@@ -1209,15 +1298,20 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
             const int m1 = mp[0][s1], m2 = mp[1][s2], m3 = mp[2][s3];
             if (m1 < 0 || m2 < 0 || m3 < 0) continue;
             const int nb = nb27[(size_t)e * 27 + (m3 >> 6) * 9 + (m2 >> 6) * 3 + (m1 >> 6)];
-            if (nb < 0 || deg[nb] != deg[e]) continue;
+            if (nb < 0 || deg[nb] != deg[e] || frozen(nb)) continue;
             C[off[nb] + ((m3 & 63) * n + (m2 & 63)) * n + (m1 & 63)] += wp[0][s1] * wp[1][s2] * wp[2][s3];
           }
     }
     bool all_one = true;
-    for (double& c : C) {
-      if (!(c > 0)) throw Error(DGFAS_EINVAL, "node without a covering subdomain");
-      all_one = all_one && c == 1.0;
-      c = 1.0 / c;
+    for (int e = 0; e < E; ++e) {
+      const int64_t n3 = (int64_t)(deg[e] + 1) * (deg[e] + 1) * (deg[e] + 1);
+      for (int64_t q = off[e]; q < off[e] + n3; ++q) {
+        double& c = C[q];
+        if (frozen(e)) { c = 1.0; continue; }
+        if (!(c > 0)) throw Error(DGFAS_EINVAL, "node without a covering subdomain");
+        all_one = all_one && c == 1.0;
+        c = 1.0 / c;
+      }
     }
     if (!all_one) {
       L.cinv = s.own(upload(C, st));
@@ -1232,23 +1326,25 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   s.reserve(L.O, nin, true);
   if (fp32) s.reserve(L.O32, nin, true);
   if (L.uniform) {
-    L.nlb = stage_tiles(kStageOp, L.p, E, 1);
+    const int nsweep = L.lr ? L.nact : E;   // elements the sweep kernels take
+    L.nlb = stage_tiles(kStageOp, L.p, nsweep, 1);
     s.reserve(L.kpart, (size_t)L.nlb * s.nrhs);
     if (L.m > 0) {
-      L.nla = stage_tiles(kStageAdd, L.p, E, 1);
+      L.nla = stage_tiles(kStageAdd, L.p, nsweep, 1);
       s.reserve(L.zpart, (size_t)2 * L.nla * s.nrhs);
     }
   }
   // work vectors
+  // (on a locally refined level the kernels never write frozen rows, which must read as zero)
   const size_t nv = (size_t)L.ndof * s.nrhs;
-  s.reserve(L.r, nv);
+  s.reserve(L.r, nv, L.lr);
   const bool scg_here = s.opt.smoother == DGFAS_SCG || &L == &s.lv[0];
   const bool dbl_scg = scg_here && !(fp32 && &L != &s.lv[0]);
-  if (dbl_scg || !fp32) s.reserve(L.z, nv);
+  if (dbl_scg || !fp32) s.reserve(L.z, nv, L.lr);
   if (dbl_scg) {
-    s.reserve(L.pv, nv);
-    s.reserve(L.q, nv);
-    s.reserve(L.r0, nv);
+    s.reserve(L.pv, nv, L.lr);
+    s.reserve(L.q, nv, L.lr);
+    s.reserve(L.r0, nv, L.lr);
   }
   if (fp32 && &L != &s.lv[0]) {
     s.reserve(L.r32, nv);
@@ -1436,6 +1532,16 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
     throw Error(DGFAS_EINVAL, "unknown start-up");
   if (o->nsc > 0 && o->nsc < o->ns2) throw Error(DGFAS_EINVAL, "nsc must be >= ns2 (or <= 0 for none)");
   if (o->h_levels < 0 || o->h_levels > 8) throw Error(DGFAS_EINVAL, "h_levels must be 0..8");
+  if (o->local_steps < 0 || o->local_steps > 8) throw Error(DGFAS_EINVAL, "local_steps must be 0..8");
+  if (o->local_steps > 0) {
+    if (!m->refine_count || !m->refine_list) throw Error(DGFAS_EINVAL, "local refinement needs refine_count and refine_list");
+    for (int e = 1; e < m->n_elem; ++e)
+      if (m->degree[e] != m->degree[0]) throw Error(DGFAS_EUNSUPPORTED, "local refinement needs one degree");
+    if (o->h_levels > 0 || o->n_rhs != 1 || o->precision != DGFAS_FP64 || o->start != DGFAS_START_NONE ||
+        o->graph != 0 || m->nu_nodal || o->nsc > 0 || o->order != DGFAS_ORDER_NATURAL)
+      throw Error(DGFAS_EUNSUPPORTED, "local refinement runs FP64, one right-hand side, plain V-cycles, natural "
+                                      "order, constant nu and no h_levels");
+  }
   if (o->h_only != 0 && o->h_only != 1) throw Error(DGFAS_EINVAL, "h_only must be 0 or 1");
   if (o->h_levels > 0) {
     // h-coarsening needs one degree and a box numbering e = ex + nx (ey + ny ez) whose dimensions
@@ -1511,6 +1617,135 @@ std::vector<int64_t> morton_rank(const dgfas_mesh_desc* m) {
   return rank;
 }
 
+// Local refinement (Sec. 3.1): `steps` levels above the finest spec (the base).  On each level
+// the listed active elements are refined regularly (8 active children) and the other elements
+// of their 3 x 3 x 3 blocks irregularly (8 frozen children); a marked element's in-domain block
+// must be active.  Children follow their parents in id order, child c = bx + 2 by + 4 bz, with
+// the parent's map evaluated at the child's nodes.  A child face lies inside its parent (a
+// sibling), on a parent face toward a refined neighbour (that neighbour's child across the
+// face), on the domain boundary (the parent's code) or toward an unrefined element
+// (kLevelEdge: frozen children only).
+template <class SpecT>
+void add_local_specs(std::vector<SpecT>& sp, const dgfas_mesh_desc* m, int steps) {
+  SpecT& B = sp.back();
+  const int p = B.deg[0], n = p + 1, n3 = n * n * n;
+  B.X.assign(m->coords, m->coords + (size_t)B.E * 3 * n3);
+  B.cls.assign(B.E, kLeaf);
+  const std::vector<double> Mh = h_child_matrices(p);   // [6][n][n]: P0, P1, I0^T, I1^T, I0, I1
+  const double* Ib[2] = {&Mh[(size_t)4 * n * n], &Mh[(size_t)5 * n * n]};
+  int64_t pos = 0;
+  for (int k = 0; k < steps; ++k) {
+    SpecT& P = sp.back();
+    const int E = P.E;
+    auto walk = [&](int e, const int dd[3], bool& edge) {
+      int cur = e;
+      edge = false;
+      for (int d = 0; d < 3 && cur >= 0; ++d)
+        if (dd[d]) {
+          const int f = 2 * d + (dd[d] > 0);
+          const int nx = P.nbr[(size_t)cur * 6 + f];
+          if (nx < 0 && P.bc[(size_t)cur * 6 + f] == kLevelEdge) edge = true;
+          cur = nx;
+        }
+      return cur;
+    };
+    std::vector<int8_t> kind(E, -1);   // kTwig: regular, kFrozen: irregular
+    const int cnt = m->refine_count[k];
+    if (cnt < 0) throw Error(DGFAS_EINVAL, "negative refine_count");
+    for (int q = 0; q < cnt; ++q) {
+      const int e = m->refine_list[pos + q];
+      if (e < 0 || e >= E) throw Error(DGFAS_EINVAL, "refine_list entry out of range");
+      if (P.cls[e] == kFrozen) throw Error(DGFAS_EINVAL, "a frozen element cannot be refined");
+      if (kind[e] == kTwig) throw Error(DGFAS_EINVAL, "an element is listed twice for refinement");
+      kind[e] = kTwig;
+    }
+    for (int q = 0; q < cnt; ++q) {
+      const int e = m->refine_list[pos + q];
+      for (int d3 = -1; d3 <= 1; ++d3)
+        for (int d2 = -1; d2 <= 1; ++d2)
+          for (int d1 = -1; d1 <= 1; ++d1) {
+            const int dd[3] = {d1, d2, d3};
+            bool edge = false;
+            const int x = walk(e, dd, edge);
+            if (edge || (x >= 0 && P.cls[x] == kFrozen))
+              throw Error(DGFAS_EINVAL, "a refined element needs an active 3 x 3 x 3 block inside the domain");
+            if (x >= 0 && kind[x] != kTwig) kind[x] = kFrozen;
+          }
+    }
+    pos += cnt;
+    SpecT C;
+    C.E = 0;
+    C.hdown = false;
+    C.box[0] = C.box[1] = C.box[2] = 0;
+    std::vector<int> first(E, -1);
+    for (int e = 0; e < E; ++e)
+      if (kind[e] >= 0) {
+        first[e] = C.E;
+        C.E += 8;
+        (kind[e] == kTwig ? C.tw : C.ir).push_back(e);
+      }
+    if (C.E == 0) throw Error(DGFAS_EINVAL, "a refinement step refines no element");
+    C.deg.assign(C.E, p);
+    C.nbr.assign((size_t)C.E * 6, -1);
+    C.bc.assign((size_t)C.E * 6, DGFAS_INTERIOR);
+    C.cls.assign(C.E, kLeaf);
+    C.X.assign((size_t)C.E * 3 * n3, 0.0);
+    std::vector<double> t1(n3), t2(n3);
+    for (int e = 0; e < E; ++e) {
+      if (kind[e] < 0) continue;
+      if (kind[e] == kTwig) P.cls[e] = kTwig;
+      for (int c = 0; c < 8; ++c) {
+        const int ch = first[e] + c;
+        const int b[3] = {c & 1, (c >> 1) & 1, c >> 2};
+        C.cls[ch] = kind[e] == kTwig ? kLeaf : kFrozen;
+        (kind[e] == kTwig ? C.twc : C.irc).push_back(ch);
+        for (int a = 0; a < 3; ++a) {   // X_child = (I_bz x I_by x I_bx) X_parent
+          const double* xp = &P.X[((size_t)e * 3 + a) * n3];
+          for (int kk = 0; kk < n; ++kk)
+            for (int j = 0; j < n; ++j)
+              for (int i = 0; i < n; ++i) {
+                double v = 0;
+                for (int q = 0; q < n; ++q) v += Ib[b[0]][i * n + q] * xp[(kk * n + j) * n + q];
+                t1[(kk * n + j) * n + i] = v;
+              }
+          for (int kk = 0; kk < n; ++kk)
+            for (int j = 0; j < n; ++j)
+              for (int i = 0; i < n; ++i) {
+                double v = 0;
+                for (int q = 0; q < n; ++q) v += Ib[b[1]][j * n + q] * t1[(kk * n + q) * n + i];
+                t2[(kk * n + j) * n + i] = v;
+              }
+          double* xc = &C.X[((size_t)ch * 3 + a) * n3];
+          for (int kk = 0; kk < n; ++kk)
+            for (int j = 0; j < n; ++j)
+              for (int i = 0; i < n; ++i) {
+                double v = 0;
+                for (int q = 0; q < n; ++q) v += Ib[b[2]][kk * n + q] * t2[(q * n + j) * n + i];
+                xc[(kk * n + j) * n + i] = v;
+              }
+        }
+        for (int f = 0; f < 6; ++f) {
+          const int ax = f >> 1, sd = f & 1;
+          if (b[ax] != sd) {   // the sibling across the parent's mid-plane
+            C.nbr[(size_t)ch * 6 + f] = first[e] + (c ^ (1 << ax));
+            continue;
+          }
+          const int en = P.nbr[(size_t)e * 6 + f];
+          if (en < 0) {
+            C.bc[(size_t)ch * 6 + f] = P.bc[(size_t)e * 6 + f];
+          } else if (kind[en] >= 0) {
+            C.nbr[(size_t)ch * 6 + f] = first[en] + (c ^ (1 << ax));
+          } else {
+            if (kind[e] == kTwig) throw Error(DGFAS_EINVAL, "an active child without its neighbour");
+            C.bc[(size_t)ch * 6 + f] = kLevelEdge;
+          }
+        }
+      }
+    }
+    sp.push_back(std::move(C));
+  }
+}
+
 Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   validate(m, o);
   std::unique_ptr<Solver> s(new Solver());
@@ -1557,6 +1792,10 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
     int box[3];
     bool hdown;
     std::vector<int> children;   // [E of the next coarser spec][8] when hdown
+    // local refinement: classes, host coordinates, and the transfer lists to the spec below
+    std::vector<int8_t> cls;
+    std::vector<double> X;
+    std::vector<int> tw, twc, ir, irc;
   };
   std::vector<Spec> sp;
   sp.push_back({E, std::vector<int>(m->degree, m->degree + E), s->h_nbr, s->h_bc, {m->box[0], m->box[1], m->box[2]},
@@ -1597,6 +1836,7 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
     }
   }
   std::reverse(sp.begin(), sp.end());   // root first
+  if (o->local_steps > 0) add_local_specs(sp, m, o->local_steps);
   const int Lc = (int)sp.size();
   s->lv.resize(Lc);
   for (int li = 0; li < Lc; ++li) {
@@ -1604,6 +1844,18 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
     L.E = sp[li].E;
     L.h_nbr = sp[li].nbr;
     L.h_bc = sp[li].bc;
+    for (int8_t& c : L.h_bc)   // a frozen element's face toward the unrefined region: no face term
+      if (c == kLevelEdge) c = DGFAS_NEUMANN;
+    L.lr = !sp[li].cls.empty();
+    L.h_cls = sp[li].cls;
+    if (!sp[li].tw.empty() || !sp[li].ir.empty()) {
+      L.lr_down = true;
+      L.ntw = (int)sp[li].tw.size();
+      L.nir = (int)sp[li].ir.size();
+      if (L.ntw) { L.tw_par = s->own(upload(sp[li].tw, s->st)); L.tw_ch = s->own(upload(sp[li].twc, s->st)); }
+      if (L.nir) { L.ir_par = s->own(upload(sp[li].ir, s->st)); L.ir_ch = s->own(upload(sp[li].irc, s->st)); }
+      L.hM = s->own(upload(h_child_matrices(sp[li].deg[0]), s->st));
+    }
     for (int d = 0; d < 3; ++d) L.box[d] = sp[li].box[d];
     L.nbr = s->own(upload(L.h_nbr, s->st));
     L.bc = s->own(upload(L.h_bc, s->st));
@@ -1618,8 +1870,10 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
     for (int d : dg) n += (size_t)3 * (d + 1) * (d + 1) * (d + 1);
     return n;
   };
+  // the finest level's coordinates: the mesh's, or those of the top locally refined level
   double* X = s->own(dalloc<double>(ncoords(sp[Lc - 1].deg)));
-  HIPC(hipMemcpyAsync(X, m->coords, ncoords(sp[Lc - 1].deg) * sizeof(double), hipMemcpyHostToDevice, s->st));
+  HIPC(hipMemcpyAsync(X, sp[Lc - 1].X.empty() ? m->coords : sp[Lc - 1].X.data(),
+                      ncoords(sp[Lc - 1].deg) * sizeof(double), hipMemcpyHostToDevice, s->st));
   // a nodal diffusivity follows the geometry from level to level (one component)
   double* NU = nullptr;
   if (m->nu_nodal) {
@@ -1630,7 +1884,11 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   for (int li = Lc - 1; li >= 0; --li) {
     Level& L = s->lv[li];
     const std::vector<int>& dgl = sp[li].deg;
-    if (li < Lc - 1) {
+    if (li < Lc - 1 && !sp[li].X.empty()) {
+      // a locally refined level or its base: coordinates built on the host
+      X = s->own(dalloc<double>(ncoords(dgl)));
+      HIPC(hipMemcpyAsync(X, sp[li].X.data(), ncoords(dgl) * sizeof(double), hipMemcpyHostToDevice, s->st));
+    } else if (li < Lc - 1) {
       // coarse geometry: the fine map evaluated at the coarse GLL nodes, per element (p) or per
       // parent from its children (h, averaged where the children meet)
       Level& F = s->lv[li + 1];
@@ -1691,9 +1949,9 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
     build_level(*s, L, dgl, X, NU);
     L.X = X;
     if (li < Lc - 1) {
-      s->reserve(L.u, (size_t)L.ndof * s->nrhs);
-      s->reserve(L.g, (size_t)L.ndof * s->nrhs);
-      s->reserve(L.ubar, (size_t)L.ndof * s->nrhs);
+      s->reserve(L.u, (size_t)L.ndof * s->nrhs, L.lr);
+      s->reserve(L.g, (size_t)L.ndof * s->nrhs, L.lr);
+      s->reserve(L.ubar, (size_t)L.ndof * s->nrhs, L.lr);
     }
   }
   // the workspace: one library-owned block until the caller hands in its own buffer
@@ -1858,11 +2116,9 @@ dgfas_status dgfas_level_overlap(dgfas_solver s, int32_t level, int32_t* m) {
   API_END
 }
 
-dgfas_status dgfas_rhs(dgfas_solver sv, const double* f, const double* uD, const double* qN, double* b) {
-  API_BEGIN
-  Solver* s = S_(sv);
-  need(f, "f"); need(b, "b");
-  Level& T = s->lv.back();
+namespace dgfas {
+namespace {
+void level_rhs(Solver* s, Level& T, const double* f, const double* uD, const double* qN, double* b) {
   for (int k = 0; k < s->nrhs; ++k) {
     const int64_t o = (int64_t)k * T.ndof;
     for (const Bucket& bk : T.bk) {
@@ -1874,6 +2130,65 @@ dgfas_status dgfas_rhs(dgfas_solver sv, const double* f, const double* uD, const
     }
   }
   HIPC(hipGetLastError());
+}
+}  // namespace
+}  // namespace dgfas
+
+dgfas_status dgfas_rhs(dgfas_solver sv, const double* f, const double* uD, const double* qN, double* b) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(f, "f"); need(b, "b");
+  level_rhs(s, s->lv.back(), f, uD, qN, b);
+  API_END
+}
+
+dgfas_status dgfas_level_rhs(dgfas_solver sv, int32_t level, const double* f, const double* uD, const double* qN,
+                             double* b) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(f, "f"); need(b, "b");
+  level_rhs(s, s->level(level), f, uD, qN, b);
+  API_END
+}
+
+dgfas_status dgfas_level_classes(dgfas_solver sv, int32_t level, int8_t* cls) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(cls, "cls");
+  Level& L = s->level(level);
+  for (int e = 0; e < L.E; ++e) cls[e] = L.lr ? L.h_cls[e] : kTwig + (level == (int)s->lv.size() ? kLeaf : 0);
+  API_END
+}
+
+dgfas_status dgfas_level_coords(dgfas_solver sv, int32_t level, double* coords) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(coords, "coords");
+  Level& L = s->level(level);
+  HIPC(hipMemcpyAsync(coords, L.X, (size_t)3 * L.ndof * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPC(hipStreamSynchronize(s->st));
+  API_END
+}
+
+dgfas_status dgfas_set_level_rhs(dgfas_solver sv, int32_t level, const double* b) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(b, "b");
+  if (level == (int)s->lv.size()) throw Error(DGFAS_EINVAL, "the top level's right-hand side is the solve's f");
+  Level& L = s->level(level);
+  if (!L.lr || !L.nleaf) throw Error(DGFAS_EINVAL, "the level has no leaves");
+  copy_rows(L.leaf_list, L.nleaf, L.N3, b, L.g, s->st);
+  HIPC(hipGetLastError());
+  API_END
+}
+
+dgfas_status dgfas_level_solution(dgfas_solver sv, int32_t level, double* u) {
+  API_BEGIN
+  Solver* s = S_(sv);
+  need(u, "u");
+  if (level == (int)s->lv.size()) throw Error(DGFAS_EINVAL, "the top level's solution is the solve's u");
+  Level& L = s->level(level);
+  HIPC(hipMemcpyAsync(u, L.u, (size_t)L.ndof * sizeof(double), hipMemcpyDeviceToDevice, s->st));
   API_END
 }
 
@@ -2021,6 +2336,27 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
     }
   } hint_reset{s};
   Level& T = s->lv.back();
+  if (s->opt.local_steps > 0) {
+    // local refinement: the lower levels start from zero, and the history is that of the
+    // composite residual over the leaves of every level
+    for (size_t l = 0; l + 1 < s->lv.size(); ++l) fill(s->lv[l].ndof, s->lv[l].u, 0.0, s->st);
+    s->rhint = false;
+    const double r0 = std::sqrt(s->composite_norm2(u, f));
+    if (hist) hist[0] = 1.0;
+    int k = 0;
+    bool conv = r0 == 0.0;
+    while (!conv && k < max_cycles) {
+      s->vcycle(u, f);
+      const double rk = std::sqrt(s->composite_norm2(u, f)) / r0;
+      ++k;
+      if (hist) hist[k] = rk;
+      if (!std::isfinite(rk)) throw Error(DGFAS_EBREAKDOWN, "non-finite residual");
+      conv = rk <= rtol;
+    }
+    if (n_done) *n_done = k;
+    if (!conv) { g_err = "tolerance not reached"; return DGFAS_ENOTCONV; }
+    return DGFAS_OK;
+  }
   s->residual(T, u, f, T.r);
   std::vector<double> r0 = s->dots_sync(T, T.r, T.r);
   for (double& v : r0) v = std::sqrt(v);
@@ -2090,8 +2426,6 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
   API_END
 }
 
-#if 0
-#endif
 
 dgfas_status dgfas_norm(dgfas_solver sv, int32_t level, const double* v, double* out) {
   API_BEGIN
@@ -2107,6 +2441,7 @@ dgfas_status dgfas_set_learned(dgfas_solver sv, dgfas_mlp m, int32_t enabled) {
   Solver* s = S_(sv);
   Level& T = s->lv.back();
   if (!enabled) { s->learned = false; return DGFAS_OK; }
+  if (s->opt.local_steps > 0) throw Error(DGFAS_EUNSUPPORTED, "no learned correction with local refinement");
   if (!m) throw Error(DGFAS_EINVAL, "null network");
   if (!T.uniform) throw Error(DGFAS_EUNSUPPORTED, "learned correction needs one degree on the finest level");
   Mlp* net = dgfas_mlp_impl(m);
