@@ -40,10 +40,11 @@ def parse():
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle cpu_baseline leg')
     ap.add_argument('--no-t10', action='store_true', help='skip the time-to-tolerance solves')
     ap.add_argument('--calib-copy', action='store_true', help='also run a plain copy kernel (PMC calibration)')
-    ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched', 'mlp'],
+    ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched', 'mlp', 'local'],
                     help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8); '
                          'stretched: 48^3, p = 8, aspect 1:100, 16 right-hand sides; mlp: the learned '
-                         'correction network at its p = 8 size')
+                         'correction network at its p = 8 size; local: local refinement, 16^3 p = 7 with two '
+                         'nested zones')
     ap.add_argument('--cycles', type=int, default=40, help='stretched workload: largest V-cycle count of a solve')
     return ap.parse_args()
 
@@ -229,6 +230,99 @@ def front_bench(args, torch, B):
     print(json.dumps(out))
 
 
+def local_bench(args, torch, B):
+    """Local refinement (Sec. 3.1, 3.3): the curved 16^3, p = 7 cube with two nested zones refined
+    around its centre (radii 0.3 and 0.15 of the unit cube), a Gaussian source there, solved to a
+    composite residual of 1e-10: FAS-MG-SCG(3,2) on the headline's sine-bump map (amplitude 0.1,
+    mu_star = 5; WAS(2,2) diverges there, as without refinement), and FAS-MG-WAS(2,2) on a milder
+    map (amplitude 0.03, mu_star = 2).  Reports the active DOF per level, n10, t10, the V-cycle time
+    and the finest level's operator over its active elements."""
+    from paper_2608_14123_amd import workloads as W
+    ne, p = 16, 7
+    zones = [((0.5, 0.5, 0.5), 0.3), ((0.5, 0.5, 0.5), 0.15)]
+    refine = W.local_refine_lists(ne, zones)
+    xi = B.gll(p)[0]
+    V, nbr, bc, mp = W.curved_cube(ne)
+    stream = torch.cuda.current_stream()
+    modes = {}
+    structure = None
+    for name, amp, mu, kw in (('bump0.1_scg32', 0.1, 5.0, dict(smoother=B.SCG, ns1=3, ns2=2)),
+                              ('bump0.03_was22', 0.03, 2.0, dict(smoother=B.WAS, ns1=2, ns2=2))):
+        X = W.element_coords(V, xi, lambda Y: mp(Y, amp))
+        t0 = time.perf_counter()
+        lib = B.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc,
+                       B.default_options(local_steps=len(refine), mu_star=mu, root_rtol=0.1, **kw),
+                       stream=stream.cuda_stream, refine=refine)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        L = lib.n_levels
+        n3 = (p + 1) ** 3
+        bl = []
+        levels = []
+        for l in range(1, L + 1):
+            cls = lib.level_classes(l)
+            Xl = lib.level_coords(l)
+            t = torch.empty(Xl.size // 3, dtype=torch.float64, device='cuda')
+            lib.level_rhs(l, torch.from_numpy(W.gaussian_source(Xl).ravel()).cuda(), t, uD=torch.zeros_like(t))
+            bl.append(t)
+            if l < L and (cls == 1).any():
+                lib.set_level_rhs(l, t)
+            levels.append({'elements': int(len(cls)), 'twig': int((cls == 0).sum()), 'leaf': int((cls == 1).sum()),
+                           'frozen': int((cls == 2).sum()), 'active_dof': int((cls != 2).sum()) * n3})
+        structure = levels
+        u = torch.zeros_like(bl[-1])
+        lib.solve(u, bl[-1], max_cycles=args.warmup, rtol=0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lib.solve(u.zero_(), bl[-1], max_cycles=args.steps, rtol=0.0)
+        torch.cuda.synchronize()
+        ms_cycle = (time.perf_counter() - t0) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        try:
+            hist, ok = lib.solve(u.zero_(), bl[-1], max_cycles=40, rtol=1e-10)
+        except B.DgfasError as ex:          # a diverging cycle is recorded, not fatal
+            hist, ok = [float('nan')], False
+            print(name, 'solve failed:', ex, file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t10 = time.perf_counter() - t0
+        # the finest level's operator over its active elements
+        g = torch.from_numpy(W.uniform_nodal(bl[-1].numel(), 3)).cuda()
+        r = torch.zeros_like(g)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        lib.residual(L, u, g, r)
+        ev0.record(stream)
+        for _ in range(args.reps):
+            lib.residual(L, u, g, r)
+        ev1.record(stream)
+        ev1.synchronize()
+        op_ms = ev0.elapsed_time(ev1) / args.reps
+        modes[name] = {'setup_s': round(setup_s, 3), 'ms_per_cycle': round(ms_cycle, 3), 'n10': len(hist) - 1,
+                       't10_s': round(t10, 4), 'converged': bool(ok), 'hist': ['%.3e' % h for h in hist],
+                       'finest_operator_ms': round(op_ms, 4)}
+        print(name, modes[name], file=sys.stderr, flush=True)
+        lib.close()
+    active = sum(lv['active_dof'] for lv in structure)
+    fin = structure[-1]['active_dof']
+    best = modes['bump0.1_scg32']
+    sweeps = 5
+    ach = 48.0 * fin / (best['finest_operator_ms'] * 1e-3) / 1e9
+    out = {
+        'metric': 'GDOF/s per Schwarz sweep; time-to-1e-10 residual, plain FP64 vs mixed/learned',
+        'value': round(active * sweeps / (best['ms_per_cycle'] * 1e-3) / 1e9, 3), 'unit': 'GDOF/s', 'n_gpus': 1,
+        'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': best['ms_per_cycle'], 'higher_is_better': True,
+        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64', 'data': 'synthetic',
+        'config': {'workload': 'local_refinement_curved_16^3_p7_zones_0.3_0.15', 'active_dof': active,
+                   'uniform_equivalent_dof': (4 * ne) ** 3 * (p + 1) ** 3, 'levels': structure,
+                   'value': 'active DOF of all levels x 5 sweeps over the FAS-MG-SCG(3,2) cycle time',
+                   'rhs': 'exp(-50 |x - c|^2), u_D = 0', 'mu_star': 5.0, 'root': 'SCG to 1e-1'},
+        'roofline': {'kernel': 'sipg_apply_kernel<8,double> over the finest level\'s active elements', 'bound': 'hbm',
+                     'achieved': round(ach, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+                     'frac': round(ach / HBM_PEAK_GBS, 4), 'traffic': None},
+        'modes': modes,
+    }
+    print(json.dumps(out))
+
+
 def mlp_bench(args, torch, B):
     """The learned correction's network at the size of the p = 8, m = 1 subdomain tile: 1340 -> 256
     -> 256 -> 1331, batch 4096 (BF16 weights, FP32 accumulation on the matrix cores).  Times the
@@ -372,6 +466,8 @@ def main():
     if args.workload == 'stretched':
         stretched_bench(args, torch, B)
         return
+    if args.workload == 'local':
+        return local_bench(args, torch, B)
     if args.workload == 'mlp':
         mlp_bench(args, torch, B)
         return

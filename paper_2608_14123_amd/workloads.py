@@ -139,6 +139,54 @@ def cosine_diffusivity_source(X, k=2 * np.pi, kappa=1.0):
     return kappa * u + 3.0 * k * k * nu * u + 3.0 * k * k * (s[0] * c[0]) * (s[1] * c[1]) * (s[2] * c[2])
 
 
+def local_refine_lists(ne, zones):
+    """Element ids to refine per local step on an ne^3 box mesh of the unit cube: on the grid of
+    step k (ne 2^k cells per axis) the active cells whose centre lies within zone k's radius of
+    its centre and whose in-domain 3 x 3 x 3 block is all active.  Cells are numbered as the
+    library numbers the levels it builds: the base e = ex + ne (ey + ne ez), a refined level
+    parent by parent in id order with children c = bx + 2 by + 4 bz; the block of a refined
+    cell is refined irregularly (frozen children).  zones: [(centre, radius), ...] in the
+    unmapped unit cube."""
+    offs = [(a, b, c) for c in (-1, 0, 1) for b in (-1, 0, 1) for a in (-1, 0, 1) if (a, b, c) != (0, 0, 0)]
+    e = np.arange(ne ** 3)
+    cells = np.stack([e % ne, (e // ne) % ne, e // (ne * ne)], axis=1)
+    frozen = np.zeros(len(cells), dtype=bool)
+    n = ne
+    out = []
+    for centre, radius in zones:
+        index = {tuple(c): i for i, c in enumerate(cells)}
+        mid = (cells + 0.5) / n
+        want = (np.linalg.norm(mid - np.asarray(centre), axis=1) < radius) & ~frozen
+        marked = np.zeros(len(cells), dtype=bool)
+        for i in np.nonzero(want)[0]:
+            ok = True
+            for o in offs:
+                nb = cells[i] + o
+                if np.all((nb >= 0) & (nb < n)):
+                    j = index.get(tuple(nb), -1)
+                    ok = ok and j >= 0 and not frozen[j]
+            marked[i] = ok
+        irregular = np.zeros(len(cells), dtype=bool)
+        for i in np.nonzero(marked)[0]:
+            for o in offs:
+                j = index.get(tuple(cells[i] + o), -1)
+                if j >= 0 and not marked[j]:
+                    irregular[j] = True
+        out.append(np.nonzero(marked)[0].astype(np.int32))
+        parents = np.nonzero(marked | irregular)[0]
+        kids = np.array([[c & 1, (c >> 1) & 1, c >> 2] for c in range(8)])
+        cells = (2 * cells[parents][:, None, :] + kids[None]).reshape(-1, 3)
+        frozen = np.repeat(irregular[parents], 8)
+        n *= 2
+    return out
+
+
+def gaussian_source(X, centre=(0.5, 0.5, 0.5), a=50.0):
+    """f = exp(-a |x - centre|^2) at coordinates X (E, 3, ...): a localised source."""
+    d2 = sum((X[:, k] - centre[k]) ** 2 for k in range(3))
+    return np.exp(-a * d2)
+
+
 def cartesian_unit_cube(ne):
     """ne^3 uniform cubes on [0,1]^3 with Dirichlet boundary."""
     nbr, bc = box_topology(ne, ne, ne)

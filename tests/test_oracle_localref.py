@@ -89,3 +89,14 @@ def test_two_nested_zones_converge():
     rates = np.array(h[1:]) / np.array(h[:-1])
     # measured 0.18, 0.31, 0.23, 0.27, 0.25, 0.26, 0.25
     assert rates.max() < 0.35 and h[-1] < 1e-4, h
+
+
+def test_refine_list_generator_numbers_levels_like_the_builder():
+    """workloads.local_refine_lists (the benchmark's input) marks and numbers the cells of each
+    step as the oracle's builder does on a Cartesian box."""
+    ne, p = 4, 2
+    zones = [((0.5, 0.5, 0.5), 0.3), ((0.5, 0.5, 0.5), 0.2)]
+    X, nbr, bc = base_mesh(p, ne)
+    data = lr.build_local_mesh(p, (ne,) * 3, X, nbr, bc, [near(c, r) for c, r in zones])
+    lists = W.local_refine_lists(ne, zones)
+    assert [list(x) for x in lists] == [list(np.nonzero(d['cls'] == lr.TWIG)[0]) for d in data[:-1]]
