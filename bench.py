@@ -235,7 +235,7 @@ def local_bench(args, torch, B):
     around its centre (radii 0.3 and 0.15 of the unit cube), a Gaussian source there, solved to a
     composite residual of 1e-10: FAS-MG-SCG(3,2) on the headline's sine-bump map (amplitude 0.1,
     mu_star = 5; WAS(2,2) diverges there, as without refinement), and FAS-MG-WAS(2,2) on a milder
-    map (amplitude 0.03, mu_star = 2).  Reports the active DOF per level, n10, t10, the V-cycle time
+    map (amplitude 0.03, mu_star = 2), each without and with the FMG start-up.  Reports the active DOF per level, n10, t10, the V-cycle time
     and the finest level's operator over its active elements."""
     from paper_2608_14123_amd import workloads as W
     ne, p = 16, 7
@@ -247,7 +247,10 @@ def local_bench(args, torch, B):
     modes = {}
     structure = None
     for name, amp, mu, kw in (('bump0.1_scg32', 0.1, 5.0, dict(smoother=B.SCG, ns1=3, ns2=2)),
-                              ('bump0.03_was22', 0.03, 2.0, dict(smoother=B.WAS, ns1=2, ns2=2))):
+                              ('bump0.1_scg32_fmg', 0.1, 5.0, dict(smoother=B.SCG, ns1=3, ns2=2, start=B.START_FMG)),
+                              ('bump0.03_was22', 0.03, 2.0, dict(smoother=B.WAS, ns1=2, ns2=2)),
+                              ('bump0.03_was22_fmg', 0.03, 2.0, dict(smoother=B.WAS, ns1=2, ns2=2,
+                                                                   start=B.START_FMG))):
         X = W.element_coords(V, xi, lambda Y: mp(Y, amp))
         t0 = time.perf_counter()
         lib = B.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc,
@@ -265,7 +268,7 @@ def local_bench(args, torch, B):
             t = torch.empty(Xl.size // 3, dtype=torch.float64, device='cuda')
             lib.level_rhs(l, torch.from_numpy(W.gaussian_source(Xl).ravel()).cuda(), t, uD=torch.zeros_like(t))
             bl.append(t)
-            if l < L and (cls == 1).any():
+            if l < L:
                 lib.set_level_rhs(l, t)
             levels.append({'elements': int(len(cls)), 'twig': int((cls == 0).sum()), 'leaf': int((cls == 1).sum()),
                            'frozen': int((cls == 2).sum()), 'active_dof': int((cls != 2).sum()) * n3})

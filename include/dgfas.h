@@ -163,8 +163,8 @@ typedef struct {
   int32_t local_steps;      /* local h-refinement (Sec. 3.1, 3.3): levels above the given base mesh
                                built from mesh.refine_count / refine_list, with twig, leaf and
                                frozen elements; the base is p-coarsened down to p = 1 below it.
-                               One degree, FP64, one right-hand side, no h_levels, start-up, graph,
-                               nodal nu or learned correction.  0: none */
+                               One degree, FP64, one right-hand side, no h_levels, CMG start-up,
+                               crossover, graph, nodal nu or learned correction.  0: none */
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);
@@ -231,8 +231,10 @@ dgfas_status dgfas_level_coords(dgfas_solver s, int32_t level, double* coords);
  * level; uD, qN may be NULL), over all its elements. */
 dgfas_status dgfas_level_rhs(dgfas_solver s, int32_t level, const double* f, const double* uD, const double* qN,
                              double* b);
-/* The leaf rows of b (device, n_dof of the level) become the right-hand side of a level below
- * the top; the rest of that level's right-hand side is set by the cycle. */
+/* b (device, n_dof of the level): the discrete right-hand side of a level below the top, copied
+ * into library memory.  Its leaf rows enter every cycle (the twig rows are set by the cycle);
+ * with the FMG start-up (options.start, Alg. 4) each level's active rows serve the stage whose
+ * top it is, its twigs acting as leaves there, so every level below the top needs one. */
 dgfas_status dgfas_set_level_rhs(dgfas_solver s, int32_t level, const double* b);
 /* u = the current solution of a level below the top (device, n_dof of the level). */
 dgfas_status dgfas_level_solution(dgfas_solver s, int32_t level, double* u);

@@ -37,6 +37,11 @@ Readings:
 * Convergence is measured on the composite problem, eq. helmholtz:fas:converged:leaves: the
   2-norm of f^l - A u over the leaf rows of every level, relative to its value for the initial
   state.
+* FMG start-up (Alg. 4): stage l runs a V-cycle on levels 1..l in which level l is the top, so
+  its twigs act as leaves with that level's own discrete right-hand side on all its active
+  elements; then u_{l+1} = I u_l, i.e. the active children take the interpolation of their twig
+  parents and the frozen children that of their leaf parents.  Levels below the base are global
+  p-levels and take their own discrete right-hand side as well.
 """
 import numpy as np
 
@@ -346,6 +351,28 @@ def fas_vcycle(levels, us, gs, opts):
     return us
 
 
+def _interpolate_up(lc, lv, uc, uf):
+    """u_l = I u_{l-1} (Alg. 4): active children of twigs and frozen children of leaves."""
+    if lv.down is None:
+        return tr.prolong(lc.p, lv.p, uc)
+    out = lv.down.prolong(uc, uf, TWIG)
+    return lv.down.prolong(uc, out, FROZEN)
+
+
+def fmg_start(levels, b_full, opts):
+    """Alg. 4 on the locally refined levels; b_full: every level's discrete right-hand side on
+    all its elements (root first).  Returns the start values of every level."""
+    L = len(levels)
+    us = [np.zeros((lv.mesh.E, lv.mesh.n, lv.mesh.n, lv.mesh.n)) for lv in levels]
+    gs = level_rhs(levels, b_full)
+    for top in range(L - 1):
+        act = levels[top].active[:, None, None, None]
+        sub_g = gs[:top] + [np.where(act, np.asarray(b_full[top]).reshape(us[top].shape), 0.0)]
+        us[:top + 1] = fas_vcycle(levels[:top + 1], us[:top + 1], sub_g, opts)
+        us[top + 1] = _interpolate_up(levels[top], levels[top + 1], us[top], us[top + 1])
+    return us
+
+
 def composite_residual(levels, us, gs):
     """2-norm of the leaf rows of g_l - A u_l over all levels (g_l = b_l on leaves)."""
     s = 0.0
@@ -356,10 +383,15 @@ def composite_residual(levels, us, gs):
 
 
 def solve(levels, b, opts, max_cycles=30, rtol=1e-10):
-    """V-cycles from u = 0 until the composite residual falls by rtol; returns (us, history)."""
+    """V-cycles from u = 0 (after the FMG start-up when opts.start == 'fmg') until the composite
+    residual falls by rtol relative to that of u = 0; returns (us, history).  b: every level's
+    discrete right-hand side (the leaf rows enter the cycle, the FMG start-up takes all active
+    rows)."""
     us = [np.zeros((lv.mesh.E, lv.mesh.n, lv.mesh.n, lv.mesh.n)) for lv in levels]
     gs = level_rhs(levels, b)
     r0 = composite_residual(levels, us, gs)
+    if opts.start == 'fmg':
+        us = fmg_start(levels, b, opts)
     hist = [1.0]
     for _ in range(max_cycles):
         us = fas_vcycle(levels, us, gs, opts)

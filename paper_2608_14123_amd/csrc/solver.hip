@@ -148,6 +148,8 @@ struct Level {
   int ntw = 0, nir = 0;
   int *tw_par = nullptr, *tw_ch = nullptr, *ir_par = nullptr, *ir_ch = nullptr;
   double* sq = nullptr;                 // [nleaf] composite-residual partials
+  double* bfull = nullptr;              // the level's discrete right-hand side (levels below the
+                                        // top; library memory, kept between calls)
   int64_t ndof = 0, nfs = 0, nin = 0;   // nodes, face-node slots and inbox slots per right-hand side
   double inv_wend = 0;
   std::vector<int> h_deg;
@@ -897,6 +899,28 @@ struct Solver {
     if (!htransfer<double>(F.p, a, st)) throw Error(DGFAS_EUNSUPPORTED, "no h-transfer kernel for this degree");
   }
 
+  // FMG start-up on locally refined levels (Alg. 4): stage `top` is a V-cycle on levels
+  // 1..top + 1 whose top level takes its own discrete right-hand side on every active element
+  // (its twigs act as leaves), then u_{top+2} = I u_{top+1}: active children from their twig
+  // parents, frozen children from their leaf parents
+  void startup_lr(double* u_top) {
+    const int Lc = (int)lv.size();
+    for (int top = 0; top <= Lc - 2; ++top) {
+      Level& T = lv[top];
+      if (T.lr) copy_rows(T.act_list, T.nact, T.N3, T.bfull, T.g, st);
+      else HIPC(hipMemcpyAsync(T.g, T.bfull, T.ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+      vcycle_sub(top);
+      Level& F = lv[top + 1];
+      double* uf = top + 1 == Lc - 1 ? u_top : F.u;
+      if (F.lr_down) {
+        lr_transfer(F, T, 2, false, T.u, nullptr, uf, 0);
+        lr_transfer(F, T, 2, true, T.u, nullptr, uf, 0);
+      } else {
+        transfer(F, T, 2, T.u, nullptr, uf, 0);
+      }
+    }
+  }
+
   // composite residual (eq. helmholtz:fas:converged:leaves): sum over the levels of the squared
   // leaf rows of g - A u, with the top level's u and g given
   double composite_norm2(const double* u_top, const double* g_top) {
@@ -1537,7 +1561,7 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
     if (!m->refine_count || !m->refine_list) throw Error(DGFAS_EINVAL, "local refinement needs refine_count and refine_list");
     for (int e = 1; e < m->n_elem; ++e)
       if (m->degree[e] != m->degree[0]) throw Error(DGFAS_EUNSUPPORTED, "local refinement needs one degree");
-    if (o->h_levels > 0 || o->n_rhs != 1 || o->precision != DGFAS_FP64 || o->start != DGFAS_START_NONE ||
+    if (o->h_levels > 0 || o->n_rhs != 1 || o->precision != DGFAS_FP64 || o->start == DGFAS_START_CMG ||
         o->graph != 0 || m->nu_nodal || o->nsc > 0 || o->order != DGFAS_ORDER_NATURAL)
       throw Error(DGFAS_EUNSUPPORTED, "local refinement runs FP64, one right-hand side, plain V-cycles, natural "
                                       "order, constant nu and no h_levels");
@@ -2175,10 +2199,10 @@ dgfas_status dgfas_set_level_rhs(dgfas_solver sv, int32_t level, const double* b
   Solver* s = S_(sv);
   need(b, "b");
   if (level == (int)s->lv.size()) throw Error(DGFAS_EINVAL, "the top level's right-hand side is the solve's f");
+  if (s->opt.local_steps <= 0) throw Error(DGFAS_EINVAL, "per-level right-hand sides need local refinement");
   Level& L = s->level(level);
-  if (!L.lr || !L.nleaf) throw Error(DGFAS_EINVAL, "the level has no leaves");
-  copy_rows(L.leaf_list, L.nleaf, L.N3, b, L.g, s->st);
-  HIPC(hipGetLastError());
+  if (!L.bfull) L.bfull = s->own(dalloc<double>(L.ndof));
+  HIPC(hipMemcpyAsync(L.bfull, b, (size_t)L.ndof * sizeof(double), hipMemcpyDeviceToDevice, s->st));
   API_END
 }
 
@@ -2339,9 +2363,21 @@ dgfas_status dgfas_solve(dgfas_solver sv, double* u, const double* f, int32_t ma
   if (s->opt.local_steps > 0) {
     // local refinement: the lower levels start from zero, and the history is that of the
     // composite residual over the leaves of every level
-    for (size_t l = 0; l + 1 < s->lv.size(); ++l) fill(s->lv[l].ndof, s->lv[l].u, 0.0, s->st);
+    for (size_t l = 0; l + 1 < s->lv.size(); ++l) {
+      Level& L = s->lv[l];
+      fill(L.ndof, L.u, 0.0, s->st);
+      if (L.lr && L.nleaf) {
+        if (!L.bfull) throw Error(DGFAS_EINVAL, "a level with leaves has no right-hand side (dgfas_set_level_rhs)");
+        copy_rows(L.leaf_list, L.nleaf, L.N3, L.bfull, L.g, s->st);
+      }
+    }
     s->rhint = false;
     const double r0 = std::sqrt(s->composite_norm2(u, f));
+    if (s->opt.start == DGFAS_START_FMG) {
+      for (size_t l = 0; l + 1 < s->lv.size(); ++l)
+        if (!s->lv[l].bfull) throw Error(DGFAS_EINVAL, "the FMG start-up needs every level's right-hand side");
+      s->startup_lr(u);
+    }
     if (hist) hist[0] = 1.0;
     int k = 0;
     bool conv = r0 == 0.0;

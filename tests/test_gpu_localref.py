@@ -108,14 +108,14 @@ def test_operator_and_schwarz_every_level(pair):
         assert rel(host(out), ref) < 1e-11, (case.name, l)
 
 
-@pytest.mark.parametrize('smoother', ['was', 'scg'])
-def test_histories_and_solutions_match_oracle(pair, binding, smoother):
+@pytest.mark.parametrize('smoother,start', [('was', None), ('scg', None), ('was', 'fmg')])
+def test_histories_and_solutions_match_oracle(pair, binding, smoother, start):
     case, lib0, levels, refine = pair
     ns = (2, 2) if smoother == 'was' else (3, 2)
     b = [op.rhs(lv.mesh, source(lv.mesh.X), uD=np.zeros((lv.mesh.E,) + (lv.mesh.n,) * 3)) for lv in levels]
-    us, ho = lr.solve(levels, b, osv.Options(smoother, *ns), max_cycles=8, rtol=1e-13)
+    us, ho = lr.solve(levels, b, osv.Options(smoother, *ns, start=start), max_cycles=8, rtol=1e-13)
     lib = case.library(binding, refine, smoother=binding.SCG if smoother == 'scg' else binding.WAS, ns1=ns[0],
-                       ns2=ns[1])
+                       ns2=ns[1], start=binding.START_FMG if start == 'fmg' else binding.START_NONE)
     L = lib.n_levels
     bl = []
     for l in range(1, L + 1):
@@ -124,7 +124,7 @@ def test_histories_and_solutions_match_oracle(pair, binding, smoother):
         lib.level_rhs(l, dev(source(Xl)), t, uD=torch.zeros_like(t))
         assert rel(host(t), b[l - 1]) < 1e-12
         bl.append(t)
-        if l < L and (levels[l - 1].cls == lr.LEAF).any():
+        if l < L:
             lib.set_level_rhs(l, t)
     u = torch.zeros_like(bl[-1])
     hist, _ = lib.solve(u, bl[-1], max_cycles=len(ho) - 1, rtol=1e-13)

@@ -100,3 +100,17 @@ def test_refine_list_generator_numbers_levels_like_the_builder():
     data = lr.build_local_mesh(p, (ne,) * 3, X, nbr, bc, [near(c, r) for c, r in zones])
     lists = W.local_refine_lists(ne, zones)
     assert [list(x) for x in lists] == [list(np.nonzero(d['cls'] == lr.TWIG)[0]) for d in data[:-1]]
+
+
+def test_fmg_start_cuts_the_first_cycle():
+    """FAS-FMG (Alg. 4) on the two-zone mesh with a smooth source: the start-up leaves a first
+    cycle residual far below the plain first cycle's, and the cycles still converge."""
+    p, ne = 3, 4
+    X, nbr, bc = base_mesh(p, ne, lambda Y: W.sine_bump_map(Y, 0.05))
+    c = (0.5, 0.5, 0.5)
+    levels = lr.build_local_levels(p, (ne,) * 3, X, nbr, bc, [near(c, 0.3), near(c, 0.2)], p_coarsen=True)
+    b = level_b(levels, lambda Y: np.exp(-20 * np.sum((Y - 0.5) ** 2, axis=1)))
+    _, h0 = lr.solve(levels, b, sv.Options('was', 2, 2), max_cycles=3, rtol=1e-12)
+    _, h1 = lr.solve(levels, b, sv.Options('was', 2, 2, start='fmg'), max_cycles=3, rtol=1e-12)
+    # measured first cycles 0.18 plain, 0.0026 with FMG
+    assert h1[1] < 0.05 * h0[1] and h1[-1] < h1[1], (h0, h1)
