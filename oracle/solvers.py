@@ -100,11 +100,24 @@ def was(level, u, f, n_i):
     return u
 
 
-def scg(level, u, f, n_i, r_max=0.0, first_dir='z', precond=None, stats=None):
+def project_range(v):
+    """v minus its mean: the component orthogonal to the constants, which span the null space
+    of A when kappa = 0 and no face is Dirichlet (the range of the symmetric A)."""
+    return v - np.mean(v)
+
+
+def scg(level, u, f, n_i, r_max=0.0, first_dir='z', precond=None, stats=None, project=None):
     """Alg. 6 (Schwarz-preconditioned inexact CG); exits when ||r|| <= r_max, or when p^T A p <= 0
-    makes the step length undefined (breakdown), with the last iterate."""
+    makes the step length undefined (breakdown), with the last iterate.  With `project` the
+    residual and every preconditioned residual are projected (remark on IPCG for semidefinite
+    systems, Sec. 4.3.2)."""
     B = level.B if precond is None else precond
+    if project is not None:
+        B0 = B
+        B = lambda v: project(B0(v))
     r = f - level.A(u)
+    if project is not None:
+        r = project(r)
     p = r.copy() if first_dir == 'r' else None
     gamma = None
     r0 = None
@@ -136,11 +149,15 @@ def scg(level, u, f, n_i, r_max=0.0, first_dir='z', precond=None, stats=None):
 class Options:
     """Cycle parameters: smoother 'was'|'scg', ns1, ns2; root 'scg' (to root_rtol) or 'direct';
     start None | 'cmg' | 'fmg' with n_s0 CMG steps per level (default ns1 + ns2); crossover
-    steps nsc on the top level between cycles (default ns1 + ns2, i.e. none)."""
+    steps nsc on the top level between cycles (default ns1 + ns2, i.e. none); null_space: the
+    operator is semidefinite (kappa = 0, no Dirichlet face) and the root SCG projects its
+    residuals onto the range of A (remark on IPCG, Sec. 4.3.2; the right-hand side must have
+    zero mean)."""
 
     def __init__(self, smoother='was', ns1=2, ns2=2, root_rtol=1e-12, root_maxit=500, first_dir='z',
-                 root='scg', start=None, ns0=None, nsc=None, projection='interp'):
+                 root='scg', start=None, ns0=None, nsc=None, projection='interp', null_space=False):
         self.smoother, self.ns1, self.ns2 = smoother, ns1, ns2
+        self.null_space = null_space
         self.projection = projection
         self.root_rtol, self.root_maxit, self.first_dir = root_rtol, root_maxit, first_dir
         self.root = root
@@ -163,8 +180,10 @@ def root_solve(level, u, g, opts, stats=None):
     if opts.root == 'direct':
         A = op.assemble(level.mesh)
         return np.linalg.solve(A, g.ravel()).reshape(u.shape)
-    r0 = norm(g - level.A(u))
-    return scg(level, u, g, opts.root_maxit, opts.root_rtol * r0, opts.first_dir, stats=stats)
+    pr = project_range if opts.null_space else None
+    r = g - level.A(u)
+    r0 = norm(r if pr is None else pr(r))
+    return scg(level, u, g, opts.root_maxit, opts.root_rtol * r0, opts.first_dir, stats=stats, project=pr)
 
 
 def fas_vcycle(levels, u_top, f_top, opts, ns1_top=None):
