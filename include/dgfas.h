@@ -165,6 +165,12 @@ typedef struct {
                                frozen elements; the base is p-coarsened down to p = 1 below it.
                                One degree, FP64, one right-hand side, no h_levels, CMG start-up,
                                crossover, graph, nodal nu or learned correction.  0: none */
+  int32_t null_space;       /* 1: the operator is semidefinite (kappa = 0 and no Dirichlet face: periodic
+                               or pure Neumann), with the constants as its null space; the root SCG
+                               projects its residual and every preconditioned residual onto the
+                               range of A (the zero-mean vectors; remark on IPCG for semidefinite
+                               systems, Sec. 4.3.2).  The right-hand side must have zero mean in every
+                               right-hand side; the solution is fixed up to a constant.  0: off */
 } dgfas_options;
 
 void dgfas_default_options(dgfas_options* opt);

@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ('graph', ctypes.c_int32), ('order', ctypes.c_int32), ('start', ctypes.c_int32),
                 ('ns0', ctypes.c_int32), ('nsc', ctypes.c_int32), ('weighting', ctypes.c_int32),
                 ('delta', ctypes.c_double), ('projection', ctypes.c_int32), ('h_levels', ctypes.c_int32),
-                ('h_only', ctypes.c_int32), ('local_steps', ctypes.c_int32)]
+                ('h_only', ctypes.c_int32), ('local_steps', ctypes.c_int32), ('null_space', ctypes.c_int32)]
 
 
 class DgfasError(RuntimeError):

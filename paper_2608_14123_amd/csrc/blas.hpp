@@ -30,6 +30,8 @@ void dot_partials(int64_t n, int nrhs, const T* a, const T* b, const T* c, doubl
 template <typename TI, typename TO>
 void convert(int64_t n, const TI* x, TO* y, int accumulate, hipStream_t st);
 void fill(int64_t n, double* y, double v, hipStream_t st);
+// v -= mean(v) per right-hand side (vectors [nrhs][n]); partial: [nrhs][1024] scratch
+void project_mean(int64_t n, int nrhs, double* v, double* partial, hipStream_t st);
 void mask_mul(int64_t n, double* y, const double* m, hipStream_t st);   // y *= m
 void fill(int64_t n, float* y, float v, hipStream_t st);
 

@@ -227,6 +227,44 @@ int reduction_blocks(int64_t n) {
   return (int)b;
 }
 
+// v -= mean(v), per right-hand side: block sums in a fixed order, then every thread adds the
+// (at most 1024) block sums of its right-hand side in order and subtracts the mean
+__global__ void __launch_bounds__(kRedThreads) sum_partial_kernel(int64_t n, const double* __restrict__ v,
+                                                                 double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads];
+  const double* x = v + (int64_t)blockIdx.y * n;
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+    s += x[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = kRedThreads / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * 1024 + blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) subtract_mean_kernel(int64_t n, int nb, double* __restrict__ v,
+                                                                   const double* __restrict__ partial) {
+  __shared__ double mean;
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int b = 0; b < nb; ++b) s += partial[(int64_t)blockIdx.y * 1024 + b];
+    mean = s / (double)n;
+  }
+  __syncthreads();
+  double* x = v + (int64_t)blockIdx.y * n;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+    x[i] -= mean;
+}
+
+void project_mean(int64_t n, int nrhs, double* v, double* partial, hipStream_t st) {
+  const int nb = reduction_blocks(n);
+  hipLaunchKernelGGL(sum_partial_kernel, dim3(nb, nrhs), dim3(kRedThreads), 0, st, n, v, partial);
+  hipLaunchKernelGGL(subtract_mean_kernel, dim3(nb, nrhs), dim3(kRedThreads), 0, st, n, nb, v, partial);
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
   sh[tid] = v;

@@ -216,6 +216,7 @@ struct Solver {
   std::vector<int8_t> h_bc;
   std::vector<Level> lv;   // lv[0] = root (level 1)
   std::vector<int64_t> rank;   // processing rank of every element (empty: natural order)
+  double* npart = nullptr;     // [nrhs][1024] block sums of the range projection (null_space)
   std::map<int, DegTab> tabs;
   double *Dall = nullptr, *Iall = nullptr;   // mixed-degree face tables for degrees 1..8
   int force_batch = -1;                      // autotuner: -1 options, 0 per degree, 1 one launch
@@ -572,8 +573,13 @@ struct Solver {
       for (int k = 0; k < nrhs; ++k) h[k * 8 + 6] = r_max[k];
       HIPC(hipMemcpyAsync(scal, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
     }
+    // semidefinite operator: the root SCG works in the range of A (remark on IPCG, Sec. 4.3.2),
+    // projecting its residual and every preconditioned residual (so no fused z^T r there)
+    const bool proj = sizeof(T) == 8 && opt.null_space && &L == &lv[0];
+    if constexpr (sizeof(T) == 8)
+      if (proj) project_mean(L.ndof, nrhs, r, npart, st);
     int it = 0, ran = 0;
-    const bool fused = L.zpart && !msel;
+    const bool fused = L.zpart && !msel && !proj;
     const bool with_net = learned && &L == &lv.back() && sizeof(T) == 8;
     for (int i = 1; i <= n; ++i) {
       if (fused) {
@@ -593,12 +599,16 @@ struct Solver {
         pupdate<T>(L.ndof, nrhs, z, pv, i > 1 ? x : nullptr, scal, i > 1 ? 0 : 1, st);
       } else if (i > 1) {
         schwarz_t(L, r, z, 0);
+        if constexpr (sizeof(T) == 8)
+          if (proj) project_mean(L.ndof, nrhs, z, npart, st);
         dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
         dot_partials<T>(L.ndof, nrhs, z, r, r0, partial2(), nb, st);
         finish(nb, nrhs, partial, partial2(), kOpBeta, scal, nullptr, st);
         pupdate<T>(L.ndof, nrhs, z, pv, x, scal, 0, st);
       } else {
         schwarz_t(L, r, z, 0);
+        if constexpr (sizeof(T) == 8)
+          if (proj) project_mean(L.ndof, nrhs, z, npart, st);
         dot_partials<T>(L.ndof, nrhs, z, r, nullptr, partial, nb, st);
         finish(nb, nrhs, partial, nullptr, kOpGamma, scal, nullptr, st);
         pupdate<T>(L.ndof, nrhs, z, pv, nullptr, scal, 1, st);
@@ -689,6 +699,7 @@ struct Solver {
     Level& L = lv[0];
     if (fixed_root()) return scg<double>(L, u, g, opt.root_max_iter, {}, breakdown);
     residual(L, u, g, L.r);
+    if (opt.null_space) project_mean(L.ndof, nrhs, L.r, npart, st);
     std::vector<double> rmax = dots_sync(L, L.r, L.r);
     bool any = false;
     for (double& v : rmax) {
@@ -1557,6 +1568,9 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
   if (o->nsc > 0 && o->nsc < o->ns2) throw Error(DGFAS_EINVAL, "nsc must be >= ns2 (or <= 0 for none)");
   if (o->h_levels < 0 || o->h_levels > 8) throw Error(DGFAS_EINVAL, "h_levels must be 0..8");
   if (o->local_steps < 0 || o->local_steps > 8) throw Error(DGFAS_EINVAL, "local_steps must be 0..8");
+  if (o->null_space != 0 && o->null_space != 1) throw Error(DGFAS_EINVAL, "null_space must be 0 or 1");
+  if (o->null_space && (o->kappa != 0.0 || o->local_steps > 0))
+    throw Error(DGFAS_EINVAL, "null_space needs kappa = 0 and no local refinement");
   if (o->local_steps > 0) {
     if (!m->refine_count || !m->refine_list) throw Error(DGFAS_EINVAL, "local refinement needs refine_count and refine_list");
     for (int e = 1; e < m->n_elem; ++e)
@@ -1775,6 +1789,7 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   std::unique_ptr<Solver> s(new Solver());
   HIPC(hipGetDevice(&s->dev));
   resolve_scratch(s->dev);
+  if (o->null_space) s->npart = s->own(dalloc<double>((size_t)1024 * std::max(1, o->n_rhs)));
   s->opt = *o;
   s->st = (hipStream_t)stream;
   s->E = m->n_elem;

@@ -157,3 +157,14 @@ def test_bad_nodal_nu_is_refused(lib, case):
     with pytest.raises(lib.DgfasError) as ei:
         lib.Solver(deg, X, nbr, bc, lib.default_options(), nu=nu)
     assert ei.value.code == (lib.DGFAS_EUNSUPPORTED if case == 'mixed_degrees' else lib.DGFAS_EINVAL)
+
+
+@pytest.mark.parametrize('bad', [dict(null_space=2), dict(null_space=1, kappa=0.5)])
+def test_bad_null_space_option_is_refused(lib, bad):
+    from paper_2608_14123_amd import workloads as W
+    ne, p = 2, 2
+    nbr, bc = W.box_topology(ne, ne, ne, periodic=(True,) * 3)
+    X = W.element_coords(W.box_vertices(ne, ne, ne), lib.gll(p)[0])
+    with pytest.raises(lib.DgfasError) as ei:
+        lib.Solver(np.full(ne ** 3, p, np.int32), X, nbr, bc, lib.default_options(**bad))
+    assert ei.value.code == lib.DGFAS_EINVAL
