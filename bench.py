@@ -134,8 +134,9 @@ def cpu_baseline(ne, p, n10_c2, reps=5):
 
 def front_bench(args, torch, B):
     """The hp front workload (27^3 unit cubes, degrees 2..8 from the front distance, 3,217,284
-    DOF, alpha = 50): per-degree launches, one-launch batches, and autotuned launches with the
-    cycle legs replayed from HIP graphs.  Prints one JSON line."""
+    DOF, alpha = 50): per-degree launches, one-launch batches (a workgroup per tile, or a
+    persistent grid striding through the tiles), and autotuned launches with the cycle legs
+    replayed from HIP graphs.  Prints one JSON line."""
     from paper_2608_14123_amd import workloads as W
     ne = 27
     degs, X, nbr, bc, f_host, uD_host = W.front_workload(ne, lambda p: B.gll(p)[0])
@@ -146,6 +147,7 @@ def front_bench(args, torch, B):
     f = torch.from_numpy(f_host).cuda()
     uD = torch.from_numpy(uD_host).cuda()
     modes = [('per_degree', dict(batch=B.BATCH_PER_DEGREE)), ('one_launch', dict(batch=B.BATCH_ONE_LAUNCH)),
+             ('persistent', dict(batch=B.BATCH_PERSISTENT)),
              ('tuned_graph', dict(batch=B.BATCH_TUNED, graph=1)),
              # a fixed 16-iteration root solve: every cycle is one captured graph
              ('tuned_whole_cycle_graph_fixed_root16', dict(batch=B.BATCH_TUNED, graph=1, root_max_iter=16))]

@@ -51,7 +51,7 @@ enum { DGFAS_INTERIOR = 0, DGFAS_DIRICHLET = 1, DGFAS_NEUMANN = 2,
        DGFAS_INTERIOR_NO_OVERLAP = 3 };
 enum { DGFAS_WAS = 0, DGFAS_SCG = 1 };
 enum { DGFAS_FP64 = 0, DGFAS_FP32 = 1, DGFAS_BF16 = 2, DGFAS_FP32_MFMA = 3 };
-enum { DGFAS_BATCH_PER_DEGREE = 0, DGFAS_BATCH_ONE_LAUNCH = 1, DGFAS_BATCH_TUNED = 2 };
+enum { DGFAS_BATCH_PER_DEGREE = 0, DGFAS_BATCH_ONE_LAUNCH = 1, DGFAS_BATCH_TUNED = 2, DGFAS_BATCH_PERSISTENT = 3 };
 enum { DGFAS_ORDER_NATURAL = 0, DGFAS_ORDER_MORTON = 1 };
 enum { DGFAS_START_NONE = 0, DGFAS_START_CMG = 1, DGFAS_START_FMG = 2 };
 enum { DGFAS_WEIGHT_QUINTIC = 0, DGFAS_WEIGHT_PLAIN = 1 };
@@ -125,8 +125,11 @@ typedef struct {
                                kept per right-hand side; the geometry is shared */
   int32_t batch;            /* mixed-degree levels: DGFAS_BATCH_PER_DEGREE (one launch per degree
                                bucket and stage), DGFAS_BATCH_ONE_LAUNCH (one launch per sweep
-                               stage over all buckets) or DGFAS_BATCH_TUNED (the choice per level
-                               and stage made by dgfas_autotune; per-degree until it has run).
+                               stage over all buckets, a workgroup per tile),
+                               DGFAS_BATCH_PERSISTENT (one launch per stage of two workgroups per
+                               compute unit that stride through the tile list) or
+                               DGFAS_BATCH_TUNED (the choice per level and stage made by
+                               dgfas_autotune; per-degree until it has run).
                                Levels with one degree always take one launch per stage */
   int32_t graph;            /* 1: dgfas_solve replays each V-cycle's smoothing and transfer legs
                                as two captured HIP graphs (the root solve between them runs
@@ -302,13 +305,14 @@ dgfas_status dgfas_solve(dgfas_solver s, double* u, const double* f, int32_t max
                          double* hist, int32_t* n_done);
 
 /* Autotuner of the mixed-degree launch shape: for every level with more than one degree and
- * each sweep stage (operator, subdomain solves, overlap add) it times the per-degree launches
- * against the one-launch batch with HIP events (median of `reps` runs on the solver's stream,
- * on scratch vectors) and keeps the faster one; it then sets opt.batch = DGFAS_BATCH_TUNED.
+ * each sweep stage (operator, subdomain solves, overlap add) it times the per-degree launches,
+ * the one-launch batch and the persistent one-launch batch with HIP events (median of `reps`
+ * runs on the solver's stream, on scratch vectors) and keeps the fastest; it then sets
+ * opt.batch = DGFAS_BATCH_TUNED.
  * cache_path (may be NULL): a JSON file of earlier choices keyed by device architecture,
  * level degree histogram, precision and n_rhs; entries found there are used without timing
- * and new ones are appended.  report (host, may be NULL): [n_levels][3][2] times in ms,
- * per-degree then one-launch, 0 where a level has one degree.  Synchronous. */
+ * and new ones are appended.  report (host, may be NULL): [n_levels][3][3] times in ms,
+ * per-degree, one-launch, persistent, 0 where a level has one degree.  Synchronous. */
 dgfas_status dgfas_autotune(dgfas_solver s, const char* cache_path, int32_t reps, double* report);
 
 /* Euclidean norm of a level-l vector per right-hand side, written to out (host, n_rhs doubles).

@@ -23,7 +23,7 @@ DGFAS_EINVAL, DGFAS_ENOMEM, DGFAS_EHIP, DGFAS_EUNSUPPORTED, DGFAS_EBREAKDOWN = -
 INTERIOR, DIRICHLET, NEUMANN = 0, 1, 2
 WAS, SCG = 0, 1
 FP64, FP32, BF16, FP32_MFMA = 0, 1, 2, 3
-BATCH_PER_DEGREE, BATCH_ONE_LAUNCH, BATCH_TUNED = 0, 1, 2
+BATCH_PER_DEGREE, BATCH_ONE_LAUNCH, BATCH_TUNED, BATCH_PERSISTENT = 0, 1, 2, 3
 ORDER_NATURAL, ORDER_MORTON = 0, 1
 START_NONE, START_CMG, START_FMG = 0, 1, 2
 WEIGHT_QUINTIC, WEIGHT_PLAIN = 0, 1
@@ -325,9 +325,9 @@ class Solver:
         return hist, code == DGFAS_OK
 
     def autotune(self, cache_path=None, reps=10):
-        """Time per-degree against one-launch batches per level and stage (see dgfas_autotune);
-        returns [n_levels][3][2] median times in ms."""
-        rep = np.zeros((self.n_levels, 3, 2))
+        """Time per-degree, one-launch and persistent batches per level and stage (see
+        dgfas_autotune); returns [n_levels][3][3] median times in ms."""
+        rep = np.zeros((self.n_levels, 3, 3))
         path = None if cache_path is None else str(cache_path).encode()
         _check(_lib.dgfas_autotune(self._h, path, reps, rep.ctypes.data_as(c_dp)))
         return rep

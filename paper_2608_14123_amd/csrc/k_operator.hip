@@ -302,16 +302,15 @@ constexpr size_t op_smem_upto() {
 }
 
 // all degrees up to NMAX - 1 in one launch; the workgroup is the widest tile's
-template <int NMAX, typename T>
+template <int NMAX, typename T, bool PERSIST>
 __global__ void __launch_bounds__(OpShape<NMAX>::THREADS)
 sipg_batched_kernel(OpArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
   __shared__ __align__(16) char smem[op_smem_upto<T, NMAX>()];
   // tiles dealt round-robin over the XCDs (the hardware order): the work list runs from the
   // largest degree to the smallest, and contiguous ranges per XCD would leave one XCD all
-  // the large tiles
-  const int t = blockIdx.x;
-  if (t >= ntiles) return;
-  {
+  // the large tiles.  The persistent form (fewer workgroups than tiles) strides through the
+  // list, with a barrier between tiles for the shared memory.
+  auto tile = [&](int t) {
     const int k = find_bucket(bd, nb, kStageOp, t);
     OpArgs<T> x = a;
     x.nel = bd[k].nel;
@@ -328,6 +327,14 @@ sipg_batched_kernel(OpArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, i
 #undef DGFAS_OPB
       default: break;
     }
+  };
+  if constexpr (PERSIST) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      if (t != (int)blockIdx.x) __syncthreads();
+      tile(t);
+    }
+  } else {
+    if ((int)blockIdx.x < ntiles) tile(blockIdx.x);
   }
 }
 
@@ -349,10 +356,14 @@ template <typename T>
 void sipg_apply_batched(int pmax, const OpArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l, hipStream_t st) {
   if (l.ntiles <= 0) return;
   const dim3 g(l.grid), b(stage_threads(kStageOp, pmax));
-  if (pmax <= 5) hipLaunchKernelGGL((sipg_batched_kernel<6, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
-  else if (pmax == 6) hipLaunchKernelGGL((sipg_batched_kernel<7, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
-  else if (pmax == 7) hipLaunchKernelGGL((sipg_batched_kernel<8, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
-  else hipLaunchKernelGGL((sipg_batched_kernel<9, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+#define DGFAS_OPL(NM)                                                                                     \
+  if (l.persistent) hipLaunchKernelGGL((sipg_batched_kernel<NM, T, true>), g, b, 0, st, a, bd, l.nb, l.ntiles); \
+  else hipLaunchKernelGGL((sipg_batched_kernel<NM, T, false>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+  if (pmax <= 5) { DGFAS_OPL(6) }
+  else if (pmax == 6) { DGFAS_OPL(7) }
+  else if (pmax == 7) { DGFAS_OPL(8) }
+  else { DGFAS_OPL(9) }
+#undef DGFAS_OPL
 }
 
 template void sipg_apply_batched<double>(int, const OpArgs<double>&, const BucketDesc<double>*, const BatchLaunch&,

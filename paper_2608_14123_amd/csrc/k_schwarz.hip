@@ -765,16 +765,15 @@ constexpr size_t sz_smem_upto() {
   }
 }
 
-template <int NMAX, typename T>
+template <int NMAX, typename T, bool PERSIST>
 __global__ void __launch_bounds__((SzShape<NMAX, 1>::THREADS))
 schwarz_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
   __shared__ __align__(16) char smem[sz_smem_upto<T, NMAX>()];
   // tiles dealt round-robin over the XCDs (the hardware order): the work list runs from the
   // largest degree to the smallest, and contiguous ranges per XCD would leave one XCD all
-  // the large tiles
-  const int t = blockIdx.x;
-  if (t >= ntiles) return;
-  {
+  // the large tiles.  The persistent form strides through the list, with a barrier between
+  // tiles for the shared memory.
+  auto tile = [&](int t) {
     const int k = find_bucket(bd, nb, kStageSolve, t);
     SchwarzArgs<T> x = a;
     x.nel = bd[k].nel;
@@ -795,19 +794,23 @@ schwarz_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, i
 #undef DGFAS_SZB
       default: break;
     }
+  };
+  if constexpr (PERSIST) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      if (t != (int)blockIdx.x) __syncthreads();
+      tile(t);
+    }
+  } else {
+    if ((int)blockIdx.x < ntiles) tile(blockIdx.x);
   }
 }
 
-template <int NMAX, typename T>
+template <int NMAX, typename T, bool PERSIST>
 __global__ void __launch_bounds__(AddShape<NMAX>::THREADS)
 overlap_add_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, int ntiles) {
   __shared__ AddSmem sm;
-  // tiles dealt round-robin over the XCDs (the hardware order): the work list runs from the
-  // largest degree to the smallest, and contiguous ranges per XCD would leave one XCD all
-  // the large tiles
-  const int t = blockIdx.x;
-  if (t >= ntiles) return;
-  {
+  // tiles dealt round-robin over the XCDs (the hardware order), strided in the persistent form
+  auto tile = [&](int t) {
     const int k = find_bucket(bd, nb, kStageAdd, t);
     SchwarzArgs<T> x = a;
     x.nel = bd[k].nel;
@@ -822,16 +825,27 @@ overlap_add_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ b
 #undef DGFAS_ADB
       default: break;
     }
+  };
+  if constexpr (PERSIST) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      if (t != (int)blockIdx.x) __syncthreads();
+      tile(t);
+    }
+  } else {
+    if ((int)blockIdx.x < ntiles) tile(blockIdx.x);
   }
 }
 
+#define DGFAS_BATCH_ONE(KERNEL, NM)                                                                     \
+  if (l.persistent) hipLaunchKernelGGL((KERNEL<NM, T, true>), g, b, 0, st, a, bd, l.nb, l.ntiles);     \
+  else hipLaunchKernelGGL((KERNEL<NM, T, false>), g, b, 0, st, a, bd, l.nb, l.ntiles);
 #define DGFAS_BATCH_LAUNCH(KERNEL, STAGE)                                                              \
   if (l.ntiles <= 0) return;                                                                           \
   const dim3 g(l.grid), b(stage_threads(STAGE, pmax));                                                 \
-  if (pmax <= 5) hipLaunchKernelGGL((KERNEL<6, T>), g, b, 0, st, a, bd, l.nb, l.ntiles); \
-  else if (pmax == 6) hipLaunchKernelGGL((KERNEL<7, T>), g, b, 0, st, a, bd, l.nb, l.ntiles); \
-  else if (pmax == 7) hipLaunchKernelGGL((KERNEL<8, T>), g, b, 0, st, a, bd, l.nb, l.ntiles); \
-  else hipLaunchKernelGGL((KERNEL<9, T>), g, b, 0, st, a, bd, l.nb, l.ntiles);
+  if (pmax <= 5) { DGFAS_BATCH_ONE(KERNEL, 6) }                                                        \
+  else if (pmax == 6) { DGFAS_BATCH_ONE(KERNEL, 7) }                                                   \
+  else if (pmax == 7) { DGFAS_BATCH_ONE(KERNEL, 8) }                                                   \
+  else { DGFAS_BATCH_ONE(KERNEL, 9) }
 
 template <typename T>
 void schwarz_solve_batched(int pmax, const SchwarzArgs<T>& a, const BucketDesc<T>* bd, const BatchLaunch& l,
@@ -844,6 +858,7 @@ void schwarz_overlap_add_batched(int pmax, const SchwarzArgs<T>& a, const Bucket
   DGFAS_BATCH_LAUNCH(overlap_add_batched_kernel, kStageAdd)
 }
 #undef DGFAS_BATCH_LAUNCH
+#undef DGFAS_BATCH_ONE
 
 template void schwarz_solve_batched<double>(int, const SchwarzArgs<double>&, const BucketDesc<double>*,
                                             const BatchLaunch&, hipStream_t);

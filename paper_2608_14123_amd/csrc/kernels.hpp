@@ -52,6 +52,7 @@ struct BatchLaunch {
   int nb = 0;           // buckets
   int ntiles = 0;       // tiles of the stage
   int grid = 0;         // workgroups (a multiple of 8)
+  bool persistent = false;   // fewer workgroups than tiles: each strides through the list
 };
 enum { kStageOp = 0, kStageSolve = 1, kStageAdd = 2 };
 // tiles per bucket of each stage (elements per tile times right-hand sides)

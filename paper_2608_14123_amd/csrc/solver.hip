@@ -161,7 +161,8 @@ struct Level {
   BucketDesc<double>* bd64 = nullptr;
   BucketDesc<float>* bd32 = nullptr;
   int tiles[3] = {0, 0, 0};             // work-list length per stage
-  int one_launch[3] = {0, 0, 0};        // tuned choice per stage
+  int one_launch[3] = {0, 0, 0};        // tuned choice per stage: 0 per degree, 1 one launch,
+                                        // 2 one persistent launch
   std::string hist;                     // degree histogram "p:count,..." (autotuner key)
   bool all_m1 = true;                   // every degree bucket has overlap 1 (batched Schwarz tiles)
   int nm = 0;                           // elements with a face to another degree
@@ -219,7 +220,9 @@ struct Solver {
   double* npart = nullptr;     // [nrhs][1024] block sums of the range projection (null_space)
   std::map<int, DegTab> tabs;
   double *Dall = nullptr, *Iall = nullptr;   // mixed-degree face tables for degrees 1..8
-  int force_batch = -1;                      // autotuner: -1 options, 0 per degree, 1 one launch
+  int force_batch = -1;                      // autotuner: -1 options, 0 per degree, 1 one launch,
+                                             // 2 one persistent launch
+  int persist_grid = 512;                    // workgroups of a persistent launch (2 per CU)
   // captured V-cycle legs (smoothing and transfers above the root, down and up)
   hipStream_t cap = nullptr;
   hipGraphExec_t gdown = nullptr, gup = nullptr;
@@ -311,10 +314,20 @@ struct Solver {
     if (L.uniform || L.bk.size() < 2) return false;
     if (stage != kStageOp && !L.all_m1) return false;   // batched Schwarz tiles take m = 1
     if (stage == kStageSolve && matrix_cores()) return false;   // matrix-core tiles per degree
-    if (force_batch >= 0) return force_batch == 1;
-    if (opt.batch == DGFAS_BATCH_ONE_LAUNCH) return true;
-    if (opt.batch == DGFAS_BATCH_TUNED) return L.one_launch[stage] != 0;
-    return false;
+    return batch_mode(L, stage) != 0;
+  }
+  int batch_mode(const Level& L, int stage) const {
+    if (force_batch >= 0) return force_batch;
+    if (opt.batch == DGFAS_BATCH_ONE_LAUNCH) return 1;
+    if (opt.batch == DGFAS_BATCH_PERSISTENT) return 2;
+    if (opt.batch == DGFAS_BATCH_TUNED) return L.one_launch[stage];
+    return 0;
+  }
+  // workgroups of a one-launch batch: one per tile, or a persistent grid that strides through
+  // the tiles (a multiple of 8, so that the round-robin XCD order of the tiles is kept)
+  int batch_grid(const Level& L, int stage, int ntiles) const {
+    if (batch_mode(L, stage) == 2 && ntiles > persist_grid) return persist_grid;
+    return xcd_grid(ntiles);
   }
   template <typename T>
   const BucketDesc<T>* bdesc(const Level& L) const {
@@ -338,7 +351,7 @@ struct Solver {
     if (use_batch(L, kStageOp)) {
       OpArgs<T> a = op_args<T>(L, L.bk[0], mode, u, g, out);
       BatchLaunch bl;
-      bl.nb = (int)L.bk.size(); bl.ntiles = L.tiles[kStageOp]; bl.grid = xcd_grid(bl.ntiles);
+      bl.nb = (int)L.bk.size(); bl.ntiles = L.tiles[kStageOp]; bl.grid = batch_grid(L, kStageOp, bl.ntiles); bl.persistent = bl.grid < bl.ntiles;
       sipg_apply_batched<T>(L.p, a, bdesc<T>(L), bl, st);
     } else {
       for (const Bucket& b : L.bk) {
@@ -402,7 +415,7 @@ struct Solver {
     if (use_batch(L, stage)) {
       SchwarzArgs<T> a = sz_args<T>(L, L.bk[0], r, z, mode);
       BatchLaunch bl;
-      bl.nb = (int)L.bk.size(); bl.ntiles = L.tiles[stage]; bl.grid = xcd_grid(bl.ntiles);
+      bl.nb = (int)L.bk.size(); bl.ntiles = L.tiles[stage]; bl.grid = batch_grid(L, stage, bl.ntiles); bl.persistent = bl.grid < bl.ntiles;
       if (stage == kStageSolve) schwarz_solve_batched<T>(L.p, a, bdesc<T>(L), bl, st);
       else schwarz_overlap_add_batched<T>(L.p, a, bdesc<T>(L), bl, st);
       return;
@@ -1460,7 +1473,8 @@ void Solver::autotune(const char* path, int reps, double* report) {
     for (size_t li = 0; li < lv.size(); ++li) {
       Level& L = lv[li];
       for (int sg = 0; sg < 3; ++sg)
-        if (report) report[(li * 3 + sg) * 2] = report[(li * 3 + sg) * 2 + 1] = 0.0;
+        if (report)
+          for (int v = 0; v < 3; ++v) report[(li * 3 + sg) * 3 + v] = 0.0;
       if (L.uniform || L.bk.size() < 2) continue;
       const size_t nv = (size_t)L.ndof * nrhs;
       if (x) { hipStreamSynchronize(st); hipFree(x); hipFree(y); hipFree(w); x = y = w = nullptr; }
@@ -1479,8 +1493,8 @@ void Solver::autotune(const char* path, int reps, double* report) {
           L.one_launch[sg] = it->second;
           continue;
         }
-        double med[2];
-        for (int v = 0; v < 2; ++v) {
+        double med[3];
+        for (int v = 0; v < 3; ++v) {
           force_batch = v;
           auto run = [&]() {
             if (sg == kStageOp) op<double>(L, 0, x, y, w);
@@ -1502,12 +1516,13 @@ void Solver::autotune(const char* path, int reps, double* report) {
           HIPC(hipGetLastError());
         }
         force_batch = -1;
-        L.one_launch[sg] = med[1] < med[0] ? 1 : 0;
-        cache[key] = L.one_launch[sg];
-        if (report) {
-          report[(li * 3 + sg) * 2] = med[0];
-          report[(li * 3 + sg) * 2 + 1] = med[1];
-        }
+        int best = 0;
+        for (int v = 1; v < 3; ++v)
+          if (med[v] < med[best]) best = v;
+        L.one_launch[sg] = best;
+        cache[key] = best;
+        if (report)
+          for (int v = 0; v < 3; ++v) report[(li * 3 + sg) * 3 + v] = med[v];
       }
     }
   } catch (...) {
@@ -1612,7 +1627,7 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
       o->precision != DGFAS_FP32_MFMA)
     throw Error(DGFAS_EINVAL, "unknown precision");
   if (o->n_rhs < 1 || o->n_rhs > 64) throw Error(DGFAS_EINVAL, "n_rhs must be 1..64");
-  if (o->batch < DGFAS_BATCH_PER_DEGREE || o->batch > DGFAS_BATCH_TUNED) throw Error(DGFAS_EINVAL, "unknown batch mode");
+  if (o->batch < DGFAS_BATCH_PER_DEGREE || o->batch > DGFAS_BATCH_PERSISTENT) throw Error(DGFAS_EINVAL, "unknown batch mode");
   if (o->graph != 0 && o->graph != 1) throw Error(DGFAS_EINVAL, "graph must be 0 or 1");
   if (o->order != DGFAS_ORDER_NATURAL && o->order != DGFAS_ORDER_MORTON) throw Error(DGFAS_EINVAL, "unknown order");
   if ((int64_t)m->n_elem * o->n_rhs > (int64_t)1 << 30) throw Error(DGFAS_EUNSUPPORTED, "n_elem * n_rhs too large");
@@ -1788,6 +1803,11 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   validate(m, o);
   std::unique_ptr<Solver> s(new Solver());
   HIPC(hipGetDevice(&s->dev));
+  {
+    int cus = 0;
+    HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->dev));
+    s->persist_grid = 8 * std::max(1, (2 * cus + 7) / 8);
+  }
   resolve_scratch(s->dev);
   if (o->null_space) s->npart = s->own(dalloc<double>((size_t)1024 * std::max(1, o->n_rhs)));
   s->opt = *o;

@@ -228,18 +228,19 @@ def test_front_workload_converges(binding, front27):
 
 @pytest.mark.parametrize('case', CASES, ids=repr)
 def test_one_launch_batches_match_per_degree_launches(binding, case):
-    """The one-launch batch of every sweep stage computes every element as its degree's own
-    launch does: bitwise equal results on every level, FP64 and FP32."""
+    """The one-launch batch (and its persistent form) of every sweep stage computes every
+    element as its degree's own launch does: bitwise equal results on every level."""
     print('one-launch batches', case, flush=True)
     lv = case.oracle_levels()
     per = case.library(binding)
     one = case.library(binding, batch=binding.BATCH_ONE_LAUNCH)
+    pst = case.library(binding, batch=binding.BATCH_PERSISTENT)
     rng = np.random.default_rng(15)
     for l in range(1, per.n_levels + 1):
         n = lv[l - 1].mesh.n_dof()
         u, g = dev(rng.uniform(-1, 1, n)), dev(rng.uniform(-1, 1, n))
         outs = []
-        for lib in (per, one):
+        for lib in (per, one, pst):
             a = torch.empty(n, dtype=torch.float64, device='cuda')
             r = torch.empty_like(a)
             z = torch.empty_like(a)
@@ -247,11 +248,37 @@ def test_one_launch_batches_match_per_degree_launches(binding, case):
             lib.residual(l, u, g, r)
             lib.schwarz(l, g, z)
             outs.append([host(a), host(r), host(z)])
-        for x, y in zip(*outs):
-            assert np.array_equal(x, y), (l, np.abs(x - y).max())
+        for other in outs[1:]:
+            for x, y in zip(outs[0], other):
+                assert np.array_equal(x, y), (l, np.abs(x - y).max())
         assert rel(outs[1][2], lv[l - 1].B(host(g))) <= 1e-11
     per.close()
     one.close()
+    pst.close()
+
+
+def test_persistent_batches_at_front_size(binding, front27):
+    """On the 27^3 front the stages have far more tiles than the persistent grid, so its
+    workgroups stride through the tile list: operator, residual and Schwarz results on the
+    finest level are bitwise those of per-degree launches."""
+    print('front 27^3 persistent', flush=True)
+    case, _ = front27
+    n = int(case.off[-1])
+    rng = np.random.default_rng(18)
+    u, g = dev(rng.uniform(-1, 1, n)), dev(rng.uniform(-1, 1, n))
+    outs = []
+    for batch in (binding.BATCH_PER_DEGREE, binding.BATCH_PERSISTENT):
+        lib = case.library(binding, smoother=binding.SCG, ns1=3, ns2=2, root_rtol=0.1, batch=batch)
+        L = lib.n_levels
+        a = torch.empty(n, dtype=torch.float64, device='cuda')
+        r, z = torch.empty_like(a), torch.empty_like(a)
+        lib.apply(L, u, a)
+        lib.residual(L, u, g, r)
+        lib.schwarz(L, g, z)
+        outs.append([host(a), host(r), host(z)])
+        lib.close()
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y), np.abs(x - y).max()
 
 
 @pytest.mark.parametrize('batch,precision', [(0, 'fp64'), (1, 'fp64'), (1, 'fp32')])
