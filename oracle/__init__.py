@@ -20,6 +20,9 @@ path.  Every module cites the passage it follows:
 * ``schwarz``   surrogate cuboid, 1D face-condition variants, generalized
                 eigenproblem, fast-diagonalisation solve, weighting, WAS
                 (Sec. 4.3.1, eq. schwarz:tpo, eq. schwarz:correction, Alg. 5).
+* ``unstructured`` Schwarz subdomains on unstructured meshes: walks across
+                oriented faces (Sec. 5.1), zero fill and merging at irregular
+                edges and vertices (Sec. 4.3.1, design principles 4-6).
 * ``transfer``  embedded interpolation I, restriction R = I^T, projection P
                 (Sec. 3.2).
 * ``solvers``   SCG (Alg. 6), FAS V-cycle (Alg. 2), CS V-cycle (Alg. 1).

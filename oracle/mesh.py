@@ -65,23 +65,40 @@ def _tangential(D, F, phi):
     return d_last, d_first   # normal xi_3: t1 = xi_1 (last), t2 = xi_2 (first)
 
 
+def orient_index(n, o):
+    """Neighbour face-node indices (ap[a, b], bp[a, b]) of our face node (a, b) under the
+    relative orientation o (Sec. 5.1 keeps one per face): bit 0 exchanges the two face axes,
+    bits 1 and 2 then reverse the first and the second."""
+    A, B = np.meshgrid(np.arange(n), np.arange(n), indexing='ij')
+    x, y = (B, A) if o & 1 else (A, B)
+    return (n - 1 - x if o & 2 else x), (n - 1 - y if o & 4 else y)
+
+
 class Mesh:
-    """Single-level conforming hex mesh of uniform degree p with aligned faces.
+    """Single-level conforming hex mesh of uniform degree p.
 
     X: (E, 3, n, n, n) nodal coordinates; nbr: (E, 6) neighbour ids (-1 = boundary);
     bc: (E, 6) boundary codes on boundary faces (1 Dirichlet, 2 Neumann).
+    nbr_face, nbr_orient: (E, 6) the neighbour's face and the relative orientation code of
+    `orient_index` (Sec. 5.1: neighbour, related face, relative orientation); None means aligned
+    neighbours (face phi ^ 1, code 0).
     nu: the diffusivity (eq. helmholtz:pde), a positive scalar, one value per element or one
     value per node (E, n, n, n).  nu_n holds it per node, nu_e the element averages
     int_e nu dx / int_e dx taken with the GLL quadrature (the averaged coefficient of the
     Schwarz surrogate, Sec. 4.3.1).
     """
 
-    def __init__(self, p, X, nbr, bc, nu=1.0, kappa=0.0, mu_star=2.0):
+    def __init__(self, p, X, nbr, bc, nu=1.0, kappa=0.0, mu_star=2.0, nbr_face=None, nbr_orient=None):
         self.p, self.n = p, p + 1
         self.X = np.asarray(X, dtype=np.float64)
         self.E = self.X.shape[0]
         self.nbr = np.asarray(nbr, dtype=np.int64)
         self.bc = np.asarray(bc, dtype=np.int64)
+        aligned_face = np.where(self.nbr >= 0, OPPOSITE[None, :], -1)
+        self.nbr_face = aligned_face if nbr_face is None else np.where(self.nbr >= 0, np.asarray(nbr_face, dtype=np.int64), -1)
+        self.nbr_orient = (np.zeros_like(self.nbr) if nbr_orient is None
+                           else np.where(self.nbr >= 0, np.asarray(nbr_orient, dtype=np.int64), 0))
+        self.oriented = bool(np.any(self.nbr_face != aligned_face) or np.any(self.nbr_orient != 0))
         n = self.n
         nu = np.asarray(nu, dtype=np.float64)
         if nu.ndim == 1:
@@ -147,9 +164,26 @@ class Mesh:
             nb = self.nbr[:, phi]
             interior = nb >= 0
             mu[:, phi] = self.mu_star * own[:, phi]
-            nbv = own[nb[interior], OPPOSITE[phi]]
+            nbv = own[nb[interior], self.nbr_face[interior, phi]]
             mu[interior, phi] = self.mu_star * 0.5 * (own[interior, phi] + nbv)
         self.mu = mu
+
+    def neighbour_face(self, V, phi, sel):
+        """The neighbours' face layers of V[E, ..., k, j, i] across face phi of the elements
+        `sel` (a boolean mask of interior faces), each in the own face's node order."""
+        idx = np.nonzero(sel)[0]
+        en = self.nbr[idx, phi]
+        nf = self.nbr_face[idx, phi]
+        no = self.nbr_orient[idx, phi]
+        out = np.empty((len(idx),) + V.shape[1:-3] + (self.n, self.n))
+        for f in range(6):
+            for o in range(8):
+                hit = (nf == f) & (no == o)
+                if not np.any(hit):
+                    continue
+                ap, bp = orient_index(self.n, o)
+                out[hit] = face_view(V[en[hit]], f)[..., ap, bp]
+        return out
 
     # -- helpers --------------------------------------------------------------
     def grad(self, u):

@@ -18,7 +18,7 @@ element's test functions its own value.
 """
 import numpy as np
 
-from .mesh import d_ref, dT_ref, face_view, OPPOSITE
+from .mesh import d_ref, dT_ref, face_view
 
 
 def _face_dn(mesh, gradf, phi):
@@ -61,14 +61,13 @@ def apply(mesh, u):
         nu_o = face_view(mesh.nu_n, phi)
         inter = nb >= 0
         if np.any(inter):
-            en = nb[inter]
-            u_nb = face_view(u[en], OPPOSITE[phi])
-            g_nb = face_view(grad[en], OPPOSITE[phi])
+            u_nb = mesh.neighbour_face(u, phi, inter)
+            g_nb = mesh.neighbour_face(grad, phi, inter)
             dn_nb = np.einsum('eaxy,eaxy->exy', mesh.face_n[phi][inter], g_nb)   # own normal
             jmp = uf[inter] - u_nb
             mu = mesh.mu[inter, phi][:, None, None]
             wsi = ws[inter]
-            nu_i, nu_n = nu_o[inter], face_view(mesh.nu_n[en], OPPOSITE[phi])
+            nu_i, nu_n = nu_o[inter], mesh.neighbour_face(mesh.nu_n, phi, inter)
             row[inter] = mu * np.maximum(nu_i, nu_n) * wsi * jmp - 0.5 * wsi * (nu_i * dn_own[inter] + nu_n * dn_nb)
             sigma[inter] = -0.5 * nu_i * wsi * jmp
         dir_ = (nb < 0) & (mesh.bc[:, phi] == 1)

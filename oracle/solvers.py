@@ -33,13 +33,18 @@ import numpy as np
 from . import operator as op
 from .mesh import Mesh
 from .schwarz import Schwarz
+from .unstructured import TopoSchwarz
 from . import transfer as tr
 
 
 class Level:
-    def __init__(self, mesh, m, weighting='quintic'):
+    """One p-level.  A mesh that carries its neighbours' faces and orientations (an
+    unstructured mesh, Sec. 5.1) takes the topology-walking Schwarz method of
+    oracle.unstructured; on a regular mesh both give the same subdomains."""
+
+    def __init__(self, mesh, m, weighting='quintic', topology=False):
         self.mesh = mesh
-        self.schwarz = Schwarz(mesh, m, weighting)
+        self.schwarz = TopoSchwarz(mesh, m, weighting) if topology else Schwarz(mesh, m, weighting)
         self.p = mesh.p
 
     def A(self, u):
@@ -49,11 +54,13 @@ class Level:
         return self.schwarz.apply(r)
 
 
-def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0, weighting='quintic', delta=None):
+def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0, weighting='quintic', delta=None,
+                 nbr_face=None, nbr_orient=None):
     """Level list (root first) for global p-coarsening of a uniform-degree mesh.  With `delta`
     the overlap of every level follows from its degree (Sec. 4.3.1 item 3), else it is m.
     A nodal nu (E, n, n, n) at the fine degree is, like the geometry, evaluated at the nodes of
-    each coarser level (reading: every level rediscretises the same coefficient field)."""
+    each coarser level (reading: every level rediscretises the same coefficient field).
+    nbr_face / nbr_orient describe an unstructured mesh (every level keeps the topology)."""
     from .schwarz import overlap_layers
     chain = tr.degree_chain(p)
     levels = [None] * len(chain)
@@ -67,7 +74,8 @@ def build_levels(p, X, nbr, bc, m=1, nu=1.0, kappa=0.0, mu_star=2.0, weighting='
             if nodal:
                 nul = tr.coarse_coords(pl, chain[li + 1], nul[:, None])[:, 0]
         ml = min(overlap_layers(pl, delta), pl) if delta is not None else m
-        levels[li] = Level(Mesh(pl, Xl, nbr, bc, nu=nul, kappa=kappa, mu_star=mu_star), ml, weighting)
+        mesh = Mesh(pl, Xl, nbr, bc, nu=nul, kappa=kappa, mu_star=mu_star, nbr_face=nbr_face, nbr_orient=nbr_orient)
+        levels[li] = Level(mesh, ml, weighting, topology=nbr_face is not None)
     return levels
 
 

@@ -263,3 +263,190 @@ def front_workload(ne, xi_of, center=(0.0, 0.0, 0.0), r0=0.7, alpha=50.0):
     uD = np.concatenate([front_solution(x, alpha=alpha, r0=r0, center=center).ravel() for x in X])
     return degrees, X, nbr, bc, f, uD
 
+
+
+# --- unstructured topology: face orientation and the extruded diamond mesh ----------------
+#
+# Face-node layout (first, second) of face phi: phi 0/1 -> (k, j), 2/3 -> (k, i), 4/5 -> (j, i).
+# Orientation code o of a face seen from element e toward its neighbour's face nf: bit 0 = T,
+# bit 1 = F1, bit 2 = F2.  The node (a, b) of e's face is the neighbour's face node (a', b') with
+# (x, y) = (b, a) if T else (a, b), a' = n-1-x if F1 else x, b' = n-1-y if F2 else y.
+# Aligned neighbours (the structured grids above) have nf = phi ^ 1 and o = 0.
+
+def _rotations():
+    """The 24 proper rotations of the reference cube as signed permutation matrices."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            R = np.zeros((3, 3), dtype=np.int64)
+            for r in range(3):
+                R[r, perm[r]] = signs[r]
+            if round(np.linalg.det(R)) == 1:
+                out.append(R)
+    return out
+
+
+ROTATIONS = _rotations()
+
+
+def rotate_local_axes(X, rot):
+    """Renumber every element's nodes by a proper rotation of its reference cube.
+
+    X (E, 3, n, n, n) [e, coord, k, j, i]; rot (E,) indices into ROTATIONS.  The new node
+    q' = (i', j', k') takes the old node q = R (q' - c) + c, c = (n - 1)/2, so the element, its
+    geometry and the sign of its Jacobian are unchanged, only its local axes turn."""
+    X = np.asarray(X)
+    E, n = X.shape[0], X.shape[2]
+    g = np.arange(n)
+    K, J, I = np.meshgrid(g, g, g, indexing='ij')
+    qp = np.stack([I, J, K], axis=-1).reshape(-1, 3)          # (n^3, 3) in (i, j, k)
+    out = np.empty_like(X)
+    for r, R in enumerate(ROTATIONS):
+        sel = np.nonzero(np.asarray(rot) == r)[0]
+        if len(sel) == 0:
+            continue
+        q = (qp * 2 - (n - 1)) @ R.T                            # 2 R (q' - c)
+        q = (q + (n - 1)) // 2
+        src = (q[:, 2] * n + q[:, 1]) * n + q[:, 0]
+        flat = X[sel].reshape(len(sel), 3, n ** 3)
+        out[sel] = flat[:, :, src].reshape(len(sel), 3, n, n, n)
+    return out
+
+
+def face_array(V, phi):
+    """Face-phi node layer of V[..., k, j, i] in the layout (first, second) above."""
+    s = 0 if phi % 2 == 0 else -1
+    if phi < 2:
+        return V[..., :, :, s]
+    if phi < 4:
+        return V[..., :, s, :]
+    return V[..., s, :, :]
+
+
+def orient_index(n, o):
+    """Index arrays (ap, bp) with neighbour face node (ap[a, b], bp[a, b]) for our node (a, b)."""
+    A, B = np.meshgrid(np.arange(n), np.arange(n), indexing='ij')
+    x, y = (B, A) if o & 1 else (A, B)
+    ap = n - 1 - x if o & 2 else x
+    bp = n - 1 - y if o & 4 else y
+    return ap, bp
+
+
+def face_connectivity(X, period=None, bc_code=DIRICHLET, tol=1e-9):
+    """Neighbour table from the element coordinates alone, by matching face nodes.
+
+    X (E, 3, n, n, n); period: None, or the box side length(s) of a periodic domain (faces
+    then match modulo the period).  Returns nbr (E, 6) int32 (-1 boundary), nbr_face (E, 6)
+    int8, nbr_orient (E, 6) int8 and bc (E, 6) int8."""
+    X = np.asarray(X, dtype=np.float64)
+    E, n = X.shape[0], X.shape[2]
+    per = None if period is None else np.broadcast_to(np.asarray(period, dtype=np.float64), (3,))
+    scale = max(1.0, float(np.abs(X).max()))
+    q = tol * scale * 1e3
+
+    def wrap(c):
+        return c if per is None else c - per[:, None] * np.floor(c / per[:, None] + 0.5 * q / per[:, None])
+
+    def key(F):
+        # the face centroid (faces of a valid mesh do not share one); with a period, wrapped
+        c = np.round(wrap(F.reshape(3, -1).mean(axis=1)[:, None]) / q).astype(np.int64)[:, 0]
+        if per is not None:
+            c = c % np.round(per / q).astype(np.int64)
+        return tuple(c)
+
+    def same(Fa, Fb):
+        d = Fa - Fb
+        if per is not None:
+            d = d - per[:, None, None] * np.round(d / per[:, None, None])
+        return np.max(np.abs(d)) <= tol * scale * 1e2
+
+    faces = [[face_array(X[e], phi) for phi in range(6)] for e in range(E)]
+    table = {}
+    for e in range(E):
+        for phi in range(6):
+            table.setdefault(key(faces[e][phi]), []).append((e, phi))
+    nbr = np.full((E, 6), -1, dtype=np.int32)
+    nbf = np.full((E, 6), -1, dtype=np.int8)
+    nbo = np.zeros((E, 6), dtype=np.int8)
+    for group in table.values():
+        if len(group) == 1:
+            continue
+        if len(group) != 2:
+            raise ValueError('a face is shared by %d element faces' % len(group))
+        for (e, phi), (en, nf) in (group, group[::-1]):
+            Fa, Fb = faces[e][phi], faces[en][nf]
+            hit = [o for o in range(8) if same(Fa, Fb[:, orient_index(n, o)[0], orient_index(n, o)[1]])]
+            if len(hit) != 1:
+                raise ValueError('element %d face %d: %d orientations match' % (e, phi, len(hit)))
+            nbr[e, phi], nbf[e, phi], nbo[e, phi] = en, nf, hit[0]
+    bc = np.where(nbr < 0, bc_code, 0).astype(np.int8)
+    return nbr, nbf, nbo, bc
+
+
+def diamond_quads(nc, rho=0.3, angle=0.0, shift_seed=None):
+    """2D diamond cells: the unit cell is split into a central quadrilateral (a square of
+    half-diagonal rho, turned by `angle` from the axes: the "diamond") and four trapezoids, one
+    per side, whose corner angles at the cell corners are 45 degrees (for angle 0); the cells are
+    repeated nc x nc over [0, nc]^2.  Returns vertices (Nv, 2) and quads (Q, 4)
+    counter-clockwise; with shift_seed every quad starts at a random corner (a rotation of its
+    local axes).  Cell corners are shared by 8 quads, the diamond's corners by 3."""
+    corner = {}
+    verts = []
+
+    def cvert(x, y):
+        k = (x, y)
+        if k not in corner:
+            corner[k] = len(verts)
+            verts.append((float(x), float(y)))
+        return corner[k]
+
+    quads = []
+    for cy in range(nc):
+        for cx in range(nc):
+            c00, c10, c11, c01 = cvert(cx, cy), cvert(cx + 1, cy), cvert(cx + 1, cy + 1), cvert(cx, cy + 1)
+            ins = []
+            for kk in range(4):
+                th = 1.25 * np.pi + kk * 0.5 * np.pi + angle
+                ins.append(len(verts))
+                verts.append((cx + 0.5 + rho * np.cos(th), cy + 0.5 + rho * np.sin(th)))
+            i0, i1, i2, i3 = ins
+            quads += [[i0, i1, i2, i3], [c00, c10, i1, i0], [c10, c11, i2, i1], [c11, c01, i3, i2],
+                      [c01, c00, i0, i3]]
+    quads = np.array(quads, dtype=np.int64)
+    if shift_seed is not None:
+        s = np.random.default_rng(shift_seed).integers(0, 4, size=len(quads))
+        quads = np.stack([np.roll(qd, -int(k)) for qd, k in zip(quads, s)])
+    return np.array(verts), quads
+
+
+def diamond_coords(nc, layers, xi, length=1.0, height=1.0, shift_seed=None, rot_seed=None):
+    """Coordinates (E, 3, n, n, n) of the extruded diamond mesh at tensor points xi.
+
+    nc x nc diamond cells (5 quads each) over [0, length]^2, extruded into `layers` layers over
+    [0, height]; element e = layer * Q + quad.  Each quad is bilinear in (xi_1, xi_2) through its
+    corners (-,-), (+,-), (+,+), (-,+); xi_3 runs along x_3.  rot_seed turns every element's
+    local axes by a random proper rotation (ROTATIONS)."""
+    V, quads = diamond_quads(nc, shift_seed=shift_seed)
+    V = V * (length / nc)
+    xi = np.asarray(xi, dtype=np.float64)
+    n = len(xi)
+    lo, hi = 0.5 * (1 - xi), 0.5 * (1 + xi)
+    Q = len(quads)
+    c = V[quads]                                              # (Q, 4, 2)
+    # [q, j, i, 2]: bilinear in (xi_1 = i, xi_2 = j)
+    P = (c[:, 0, None, None, :] * (lo[None, None, :, None] * lo[None, :, None, None])
+         + c[:, 1, None, None, :] * (hi[None, None, :, None] * lo[None, :, None, None])
+         + c[:, 2, None, None, :] * (hi[None, None, :, None] * hi[None, :, None, None])
+         + c[:, 3, None, None, :] * (lo[None, None, :, None] * hi[None, :, None, None]))
+    dz = height / layers
+    X = np.empty((layers * Q, 3, n, n, n))
+    for l in range(layers):
+        z = l * dz + dz * hi
+        X[l * Q:(l + 1) * Q, 0] = P[:, None, :, :, 0]
+        X[l * Q:(l + 1) * Q, 1] = P[:, None, :, :, 1]
+        X[l * Q:(l + 1) * Q, 2] = z[None, :, None, None]
+    if rot_seed is not None:
+        rot = np.random.default_rng(rot_seed).integers(0, len(ROTATIONS), size=len(X))
+        X = rotate_local_axes(X, rot)
+    return X
