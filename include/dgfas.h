@@ -96,6 +96,22 @@ typedef struct {
                                irregularly refined parent (b = 1: the upper half of the parent's
                                reference interval along that axis); a child's geometry is its
                                parent's map at the child's nodes */
+  const int8_t* face_nbr_face;  /* unstructured meshes (Sec. 5.1 keeps, per face, the neighbour, its related
+                               face and the relative orientation): [n_elem][6] the face (0..5) of the
+                               neighbour that meets each interior face, or NULL: aligned neighbours
+                               (face phi ^ 1, orientation 0; the structured grids).  With it the
+                               Schwarz subdomains of Sec. 4.3.1 are found by walking across oriented
+                               faces: edge and vertex neighbours without a counterpart are zero-filled,
+                               the nodes of surplus ones on the shared edge or vertex are averaged into
+                               one slot, and the corrections are normalised by the weight sum per node.
+                               One degree; no h_levels, local_steps, matrix-core precisions or learned
+                               correction */
+  const int8_t* face_orient;    /* [n_elem][6] relative orientation code 0..7 of each interior face, or
+                               NULL (all 0).  Face nodes are laid out (first, second) = (xi_3, xi_2) on
+                               faces 0/1, (xi_3, xi_1) on 2/3, (xi_2, xi_1) on 4/5; the own face node
+                               (a, b) is the neighbour's face node (a', b') with (x, y) = (b, a) if bit 0
+                               is set, else (a, b), then a' = n-1-x if bit 1, else x, and b' = n-1-y if
+                               bit 2, else y.  Both sides must list each other with inverse codes */
 } dgfas_mesh_desc;
 
 /* Solver options.  Defaults come from dgfas_default_options. */
@@ -204,6 +220,11 @@ dgfas_status dgfas_level_info(dgfas_solver s, int32_t level, int32_t* degree, in
 /* Schwarz overlap m (node layers) of a level's largest degree, as set by overlap or delta; the
  * subdomain tile of that degree has ns = degree + 1 + 2m nodes per direction. */
 dgfas_status dgfas_level_overlap(dgfas_solver s, int32_t level, int32_t* m);
+/* Subdomain blocks of an unstructured level (mesh.face_nbr_face given; Sec. 4.3.1 design
+ * principles 4-6): counts[5] = the element blocks, face blocks, edge and vertex blocks mapped
+ * one-to-one, zero-filled ones and merged ones, summed over the level's subdomains (host array,
+ * written; all zero on a structured level). */
+dgfas_status dgfas_level_blocks(dgfas_solver s, int32_t level, int64_t* counts);
 
 /* Workspace: the per-call scratch of the configured cycle (the work vectors of every level,
  * the overlap inboxes, reduction partials and SCG scalars; no state is kept in it between

@@ -35,7 +35,8 @@ c_dp = ctypes.POINTER(ctypes.c_double)
 class MeshDesc(ctypes.Structure):
     _fields_ = [('n_elem', ctypes.c_int32), ('degree', ctypes.c_void_p), ('coords', ctypes.c_void_p),
                 ('face_nbr', ctypes.c_void_p), ('face_bc', ctypes.c_void_p), ('box', ctypes.c_int32 * 3),
-                ('nu_nodal', ctypes.c_void_p), ('refine_count', ctypes.c_void_p), ('refine_list', ctypes.c_void_p)]
+                ('nu_nodal', ctypes.c_void_p), ('refine_count', ctypes.c_void_p), ('refine_list', ctypes.c_void_p),
+                ('face_nbr_face', ctypes.c_void_p), ('face_orient', ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -66,6 +67,7 @@ _sig = {
     'dgfas_levels': (_I, [_V, ctypes.POINTER(_I)]),
     'dgfas_level_info': (_I, [_V, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64)]),
     'dgfas_level_overlap': (_I, [_V, _I, ctypes.POINTER(_I)]),
+    'dgfas_level_blocks': (_I, [_V, _I, ctypes.POINTER(ctypes.c_int64)]),
     'dgfas_workspace_size': (_I, [_V, ctypes.POINTER(ctypes.c_size_t)]),
     'dgfas_set_workspace': (_I, [_V, _V, ctypes.c_size_t]),
     'dgfas_rhs': (_I, [_V, _V, _V, _V, _V]),
@@ -154,9 +156,11 @@ class Solver:
     """One level hierarchy on the current device (see dgfas_create)."""
 
     def __init__(self, degree, coords, face_nbr, face_bc, options=None, stream=None, box=None, nu=None,
-                 refine=None):
+                 refine=None, nbr_face=None, nbr_orient=None):
         """refine: with options.local_steps > 0, one list of element ids per refinement step
-        (ids of the level being refined; see dgfas_mesh_desc.refine_list)."""
+        (ids of the level being refined; see dgfas_mesh_desc.refine_list).  nbr_face, nbr_orient:
+        (n_elem, 6) the neighbour's face and the relative orientation code of an unstructured mesh
+        (dgfas_mesh_desc.face_nbr_face / face_orient)."""
         degree = np.ascontiguousarray(degree, dtype=np.int32)
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         face_nbr = np.ascontiguousarray(face_nbr, dtype=np.int32)
@@ -175,10 +179,20 @@ class Solver:
             rc = np.ascontiguousarray([len(r) for r in refine], dtype=np.int32)
             rl = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.int32) for r in refine])
                                       if len(refine) else np.zeros(0), dtype=np.int32)
-        self._keep = (degree, coords, face_nbr, face_bc, nu, rc, rl)
+        nf = no = None
+        if nbr_face is not None:
+            nf = np.ascontiguousarray(nbr_face, dtype=np.int8)
+            if nf.shape != (E, 6):
+                raise ValueError('nbr_face must be (n_elem, 6)')
+        if nbr_orient is not None:
+            no = np.ascontiguousarray(nbr_orient, dtype=np.int8)
+            if no.shape != (E, 6):
+                raise ValueError('nbr_orient must be (n_elem, 6)')
+        self._keep = (degree, coords, face_nbr, face_bc, nu, rc, rl, nf, no)
         desc = MeshDesc(E, degree.ctypes.data, coords.ctypes.data, face_nbr.ctypes.data, face_bc.ctypes.data,
                         (ctypes.c_int32 * 3)(*(box or (0, 0, 0))), None if nu is None else nu.ctypes.data,
-                        None if rc is None else rc.ctypes.data, None if rl is None or rl.size == 0 else rl.ctypes.data)
+                        None if rc is None else rc.ctypes.data, None if rl is None or rl.size == 0 else rl.ctypes.data,
+                        None if nf is None else nf.ctypes.data, None if no is None else no.ctypes.data)
         self.options = options if options is not None else default_options()
         h = _V()
         st = None if stream is None else _V(stream)
@@ -232,6 +246,13 @@ class Solver:
         m = _I()
         _check(_lib.dgfas_level_overlap(self._h, level, ctypes.byref(m)))
         return m.value
+
+    def level_blocks(self, level):
+        """Subdomain block counts of an unstructured level: (element, face, mapped, zero-filled,
+        merged), summed over its subdomains (zeros on a structured level)."""
+        c = (ctypes.c_int64 * 5)()
+        _check(_lib.dgfas_level_blocks(self._h, level, c))
+        return np.array(list(c), dtype=np.int64)
 
     def rhs(self, f, b, uD=None, qN=None):
         n = self._n(self.n_levels)

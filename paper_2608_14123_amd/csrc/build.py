@@ -9,7 +9,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, 'libdgfas.so')
 BUILD = os.path.join(ROOT, '_build')
-SOURCES = ['tables.cpp', 'k_operator.hip', 'k_mortar.hip', 'k_schwarz.hip', 'k_schwarz_mfma.hip', 'k_blas.hip', 'k_mlp.hip', 'solver.hip', 'mlp.hip']
+SOURCES = ['tables.cpp', 'k_operator.hip', 'k_mortar.hip', 'k_schwarz.hip', 'k_schwarz_mfma.hip', 'k_blas.hip', 'k_mlp.hip', 'k_topo.hip', 'topology.cpp', 'solver.hip', 'mlp.hip']
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 FLAGS = ['-O3', '-std=c++17', '-fPIC', '--offload-arch=gfx950', '-Wall', '-Wno-unused-result',
          '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',

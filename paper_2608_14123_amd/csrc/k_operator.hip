@@ -10,6 +10,10 @@
 // its normal node line (L2-resident) and its metric at the shared face.  The
 // three face axes are processed one after another so that no node is written
 // by two tasks at once: the result is deterministic without atomics.
+// On unstructured meshes (ORIENT) the neighbour may meet a face with any of its faces and any
+// relative orientation (Sec. 5.1): its node line is then read at the orientation-mapped face
+// node, and its tangential derivatives are the own face grid's, exchanged and negated as the
+// orientation requires.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -42,7 +46,19 @@ struct OpSmem {
 // One tile: EPB elements of one right-hand side (logical block lbr).  Every thread of the
 // workgroup passes every barrier; threads beyond EPB n^3 only take part in them, so the
 // tile also runs inside wider batched workgroups.
-template <int N, typename T>
+// the neighbour's face node of own face node f under orientation code o (bit 0: exchange the
+// face axes, bits 1 and 2: reverse the first and the second)
+template <int N>
+__device__ __forceinline__ int orient_face_node(int f, int o) {
+  const int a = f / N, b = f - (f / N) * N;
+  const int x = (o & 1) ? b : a, y = (o & 1) ? a : b;
+  return ((o & 2) ? N - 1 - x : x) * N + ((o & 4) ? N - 1 - y : y);
+}
+
+// first face axis of face phi (layout: phi 0/1 -> (xi_3, xi_2), 2/3 -> (xi_3, xi_1), 4/5 -> (xi_2, xi_1))
+__device__ __forceinline__ int face_axis_first(int phi) { return phi < 4 ? 2 : 1; }
+
+template <int N, typename T, bool ORIENT = false>
 __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpSmem<N, T>& sm) {
   using S = OpShape<N>;
   const int nrhs = a.nrhs, nel = a.nel, mode = a.mode;
@@ -89,12 +105,14 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   int en_t[TPT];
   T pen_t[TPT];
   int8_t bc_t[TPT];
+  int fo_t[TPT];   // ORIENT: the neighbour's face | orientation << 3
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     const int t = node + k * N3;
     en_t[k] = -1;
     pen_t[k] = 0;
     bc_t[k] = 0;
+    fo_t[k] = 0;
     if (active && t < 6 * N2) {
       const int phi = t / N2;
       int en = nbr[(int64_t)e * 6 + phi];
@@ -102,6 +120,7 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
       en_t[k] = en;
       pen_t[k] = pen[fbase + t];
       bc_t[k] = bc[(int64_t)e * 6 + phi];
+      if constexpr (ORIENT) fo_t[k] = a.nfo[(int64_t)e * 6 + phi];
     }
   }
   T uval = 0, gval = 0;
@@ -131,14 +150,16 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     const int phi = t / N2, f = t - phi * N2, ax = phi >> 1;
     const int en = en_t[k];
     if (en >= 0) {
-      const int phio = phi ^ 1;
+      const int phio = ORIENT ? (fo_t[k] & 7) : (phi ^ 1);
+      const int fo = ORIENT ? orient_face_node<N>(f, fo_t[k] >> 3) : f;
+      const int axo = ORIENT ? (phio >> 1) : ax;
       const int endo = (phio & 1) ? N - 1 : 0;
       const int64_t nbase = a.off ? a.off[en] : (int64_t)en * N3;
-      const T* line = u + nbase + face_node<N>(phio, f, 0);
-      const int st = axis_stride<N>(ax);
-      const int64_t gi = nbase + face_node<N>(phio, f, endo);
+      const T* line = u + nbase + face_node<N>(phio, fo, 0);
+      const int st = axis_stride<N>(axo);
+      const int64_t gi = nbase + face_node<N>(phio, fo, endo);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) gn[k][c] = G[sym_index(ax, c) * ndof + gi];
+      for (int c = 0; c < 3; ++c) gn[k][c] = G[sym_index(axo, c) * ndof + gi];
 #pragma unroll
       for (int m = 0; m < N; ++m) lnv[k][m] = line[m * st];
     }
@@ -172,7 +193,8 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     const int phi = t / N2, f = t - phi * N2;
     T tr = 0;
     if (en_t[k] >= 0) {
-      const int endo = ((phi ^ 1) & 1) ? N - 1 : 0;
+      const int phio = ORIENT ? (fo_t[k] & 7) : (phi ^ 1);
+      const int endo = (phio & 1) ? N - 1 : 0;
       T dn = 0;
 #pragma unroll
       for (int m = 0; m < N; ++m) {
@@ -208,11 +230,26 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
         dfirst += sDT[m * N + fa] * sTr[le][phi][m * P + fb];
       }
       T du0, du1, du2;
-      if (ax == 0) { du0 = dn_nb[kk]; du1 = dlast; du2 = dfirst; }
-      else if (ax == 1) { du0 = dlast; du1 = dn_nb[kk]; du2 = dfirst; }
-      else { du0 = dlast; du1 = dfirst; du2 = dn_nb[kk]; }
-      const T fl = gn[kk][0] * du0 + gn[kk][1] * du1 + gn[kk][2] * du2;
-      const T qn = -sgn * inv_wend * fl;             // neighbour's outward flux
+      T qn;
+      if constexpr (ORIENT) {
+        // the neighbour's reference derivatives: along its normal from its node line, along its
+        // face axes from the own face grid through the orientation
+        const int phio = fo_t[kk] & 7, o = fo_t[kk] >> 3;
+        const T dA = ((o & 2) ? T(-1) : T(1)) * ((o & 1) ? dlast : dfirst);
+        const T dB = ((o & 4) ? T(-1) : T(1)) * ((o & 1) ? dfirst : dlast);
+        const int an = phio >> 1, af = face_axis_first(phio);   // the third axis takes dB
+        du0 = an == 0 ? dn_nb[kk] : (af == 0 ? dA : dB);
+        du1 = an == 1 ? dn_nb[kk] : (af == 1 ? dA : dB);
+        du2 = an == 2 ? dn_nb[kk] : (af == 2 ? dA : dB);
+        const T fl = gn[kk][0] * du0 + gn[kk][1] * du1 + gn[kk][2] * du2;
+        qn = ((phio & 1) ? T(1) : T(-1)) * inv_wend * fl;   // neighbour's outward flux
+      } else {
+        if (ax == 0) { du0 = dn_nb[kk]; du1 = dlast; du2 = dfirst; }
+        else if (ax == 1) { du0 = dlast; du1 = dn_nb[kk]; du2 = dfirst; }
+        else { du0 = dlast; du1 = dfirst; du2 = dn_nb[kk]; }
+        const T fl = gn[kk][0] * du0 + gn[kk][1] * du1 + gn[kk][2] * du2;
+        qn = -sgn * inv_wend * fl;                   // neighbour's outward flux
+      }
       const T jmp = uo - sTr[le][phi][lf];
       row = pf * jmp - T(0.5) * (qo - qn);
       sigma = T(-0.5) * jmp;
@@ -273,21 +310,22 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   }
 }
 
-template <int N, typename T>
+template <int N, typename T, bool ORIENT>
 __global__ void __launch_bounds__(OpShape<N>::THREADS)
 sipg_apply_kernel(OpArgs<T> a) {
   using S = OpShape<N>;
   __shared__ OpSmem<N, T> sm;
   const int lbr = xcd_block(((a.nel + S::EPB - 1) / S::EPB) * a.nrhs);
   if (lbr < 0) return;
-  sipg_tile<N, T>(a, lbr, sm);
+  sipg_tile<N, T, ORIENT>(a, lbr, sm);
 }
 
 template <int N, typename T>
 void launch_sipg(const OpArgs<T>& a, hipStream_t st) {
   using S = OpShape<N>;
   const int nb = ((a.nel + S::EPB - 1) / S::EPB) * a.nrhs;
-  hipLaunchKernelGGL((sipg_apply_kernel<N, T>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
+  if (a.nfo) hipLaunchKernelGGL((sipg_apply_kernel<N, T, true>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
+  else hipLaunchKernelGGL((sipg_apply_kernel<N, T, false>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
 }
 
 // largest tile workspace of the degrees with n <= N
@@ -557,7 +595,7 @@ __device__ __forceinline__ int face_node_n(int n, int phi, int f, int t) {
 // muf[e][phi] = mu_F nu (Dirichlet: 2 mu nu) for the face integration on mixed-degree faces.
 __global__ void penalty_kernel(int E, int p, const int* __restrict__ deg, const int64_t* __restrict__ offF,
                                double mu_star, double nu, const double* __restrict__ nun,
-                               const int* __restrict__ nbr,
+                               const int* __restrict__ nbr, const int8_t* __restrict__ nfo,
                                const int8_t* __restrict__ bc, const double* __restrict__ vol,
                                const double* __restrict__ area, const double* __restrict__ ws,
                                double* __restrict__ pen, double* __restrict__ muf) {
@@ -568,10 +606,13 @@ __global__ void penalty_kernel(int E, int p, const int* __restrict__ deg, const 
   const int N2 = (pe + 1) * (pe + 1);
   const double own = pe * (pe + 1) / (2.0 * (vol[e] / area[t]));
   const int en = nbr[t];
+  // the neighbour's face and the relative orientation (unstructured meshes), else aligned
+  const int phio = nfo && en >= 0 ? (nfo[t] & 7) : (phi ^ 1);
+  const int ori = nfo && en >= 0 ? (nfo[t] >> 3) : 0;
   double fac = 0.0;
   if (en >= 0) {
     const int pn = deg ? deg[en] : p;
-    const double oth = pn * (pn + 1) / (2.0 * (vol[en] / area[(int64_t)en * 6 + (phi ^ 1)]));
+    const double oth = pn * (pn + 1) / (2.0 * (vol[en] / area[(int64_t)en * 6 + phio]));
     fac = mu_star * 0.5 * (own + oth);
   } else if (bc[t] == 1) {
     fac = 2.0 * mu_star * own;
@@ -583,20 +624,25 @@ __global__ void penalty_kernel(int E, int p, const int* __restrict__ deg, const 
     return;
   }
   const int n = pe + 1, N3 = N2 * n;
-  const int end = (phi & 1) ? n - 1 : 0, endo = end ? 0 : n - 1;
+  const int end = (phi & 1) ? n - 1 : 0, endo = (phio & 1) ? n - 1 : 0;
   for (int f = 0; f < N2; ++f) {
     double nf = nun[(int64_t)e * N3 + face_node_n(n, phi, f, end)];
-    if (en >= 0) nf = fmax(nf, nun[(int64_t)en * N3 + face_node_n(n, phi ^ 1, f, endo)]);
+    if (en >= 0) {
+      const int a = f / n, b = f % n;
+      const int x = (ori & 1) ? b : a, y = (ori & 1) ? a : b;
+      const int fo = ((ori & 2) ? n - 1 - x : x) * n + ((ori & 4) ? n - 1 - y : y);
+      nf = fmax(nf, nun[(int64_t)en * N3 + face_node_n(n, phio, fo, endo)]);
+    }
     pen[fb + f] = fac * nf * ws[fb + f];
   }
 }
 
 void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const double* nun,
-             const int* nbr, const int8_t* bc, const double* vol, const double* area, const double* ws, double* pen,
-             double* muf, hipStream_t st) {
+             const int* nbr, const int8_t* nfo, const int8_t* bc, const double* vol, const double* area,
+             const double* ws, double* pen, double* muf, hipStream_t st) {
   const int64_t n = (int64_t)E * 6;
   hipLaunchKernelGGL(penalty_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, E, p, deg, offF, mu_star,
-                     nu, nun, nbr, bc, vol, area, ws, pen, muf);
+                     nu, nun, nbr, nfo, bc, vol, area, ws, pen, muf);
 }
 
 }  // namespace dgfas

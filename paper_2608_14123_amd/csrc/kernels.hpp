@@ -29,6 +29,8 @@ struct OpArgs {
   T kappa = 0;
   T inv_wend = 0;             // 1 / w_0 = p (p + 1) / 2
   double* dotp = nullptr;     // mode 1 only: per tile u^T (A u) partial sums, [nrhs][tiles]
+  const int8_t* nfo = nullptr;   // [E][6] unstructured meshes: the neighbour's face | orientation
+                                 // code << 3 per interior face (null: aligned neighbours)
 };
 
 template <typename T>
@@ -94,7 +96,7 @@ void rhs(int p, const RhsArgs& r, const double* D, double inv_wend, hipStream_t 
 
 // nun: nodal diffusivity (uniform degree, offsets e (p+1)^3) or null for the scalar nu
 void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, double nu, const double* nun,
-             const int* nbr,
+             const int* nbr, const int8_t* nfo,
              const int8_t* bc, const double* vol, const double* area, const double* ws, double* pen, double* muf,
              hipStream_t st);
 
@@ -126,6 +128,37 @@ struct MortarArgs {
 };
 template <typename T>
 void sipg_mortar(const MortarArgs<T>& a, hipStream_t st);
+
+// Schwarz method on unstructured meshes (Sec. 4.3.1 with oriented faces and irregular edges and
+// vertices): the subdomain tiles are gathered through per-slot tables built on the host, and the
+// corrections are summed per node from the stored tiles.
+template <typename T>
+struct TopoArgs {
+  int nel = 0;                    // subdomains (the elements of the level)
+  int nrhs = 1;                   // vectors are [nrhs][ndof], tiles [nrhs][nel][nt]
+  int nt = 0;                     // slots per tile, ns^3
+  int64_t ndof = 0;
+  const T* r = nullptr;
+  T* z = nullptr;
+  int mode = 0;                   // 0: z = B r, 1: z += B r
+  const int* gather = nullptr;    // [nel][nt] node of each slot, -1 zero, -2 - j merged slot j
+  const int* mptr = nullptr;      // [merged slots + 1] into midx
+  const int* midx = nullptr;      // the nodes averaged into each merged slot
+  const int8_t* var = nullptr;    // [nel][3] 1D variant per direction
+  const T* S = nullptr;           // [variants][ns][ns] eigenvectors S[c][q], zero-padded
+  const T* ST = nullptr;          // their transposes
+  const T* lam = nullptr;         // [variants][ns] eigenvalues
+  const T* gco = nullptr;         // [nel][4] surrogate coefficients g0..g3
+  T* Zt = nullptr;                // [nrhs][nel][nt] subdomain solutions
+  const int64_t* sptr = nullptr;  // [ndof + 1] per node into sslot / scoef
+  const int* sslot = nullptr;     // subdomain * nt + slot of every contribution to the node
+  const T* scoef = nullptr;       // its weight: merge share x tensor weight x 1 / weight sum
+};
+
+template <typename T>
+void topo_schwarz_solve(int ns, const TopoArgs<T>& a, hipStream_t st);
+template <typename T>
+void topo_schwarz_scatter(const TopoArgs<T>& a, hipStream_t st);
 
 template <typename T>
 struct SchwarzArgs {

@@ -21,6 +21,7 @@
 #include "kernels.hpp"
 #include "tables.hpp"
 #include "mlp.hpp"
+#include "topology.hpp"
 
 namespace dgfas {
 namespace {
@@ -190,6 +191,19 @@ struct Level {
   double* cinv = nullptr;        // [ndof] 1 / weight sum per node where the tensor weights of the
   float* cinv32 = nullptr;       // subdomains reaching it do not add up to one; null on uniform levels
   double* J9 = nullptr;          // [E][9] linear map Jacobian / det^(1/3) (network input)
+  // unstructured mesh (the neighbours' faces and orientations of Sec. 5.1): the operator reads
+  // its neighbours through nfo, the Schwarz method runs from the slot tables of topology.cpp
+  bool topo = false;
+  int8_t* nfo = nullptr;         // [E][6] the neighbour's face | orientation << 3
+  std::vector<int8_t> h_nface, h_norient;
+  int tnt = 0;                   // slots per tile
+  int *tg = nullptr, *tmptr = nullptr, *tmidx = nullptr, *tsslot = nullptr;
+  int64_t* tsptr = nullptr;
+  double* tscoef = nullptr;
+  float* tscoef32 = nullptr;
+  double* Zt = nullptr;          // [nrhs][E][tnt] subdomain solutions (workspace)
+  float* Zt32 = nullptr;
+  int64_t tblocks[5] = {0, 0, 0, 0, 0};
   std::vector<int> h_nb27;       // host copy of the 26-neighbourhood
   // vectors
   double *u = nullptr, *g = nullptr, *ubar = nullptr, *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr,
@@ -434,8 +448,29 @@ struct Solver {
   }
   template <typename T>
   void schwarz_t2(Level& L, const T* r, T* z, int mode) {
+    if (L.topo) {
+      topo_apply<T>(L, r, z, mode);
+      return;
+    }
     schwarz_stage<T>(L, kStageSolve, r, z, mode);
     schwarz_stage<T>(L, kStageAdd, r, z, mode);
+  }
+  // unstructured levels: table-driven subdomain solves, then the per-node sums
+  template <typename T>
+  void topo_apply(Level& L, const T* r, T* z, int mode) {
+    const DegTab& t = *L.bk[0].t;
+    TopoArgs<T> a;
+    a.nel = L.E; a.nrhs = nrhs; a.nt = L.tnt; a.ndof = L.ndof;
+    a.r = r; a.z = z; a.mode = mode;
+    a.gather = L.tg; a.mptr = L.tmptr; a.midx = L.tmidx; a.var = L.var;
+    a.sptr = L.tsptr; a.sslot = L.tsslot;
+    if constexpr (sizeof(T) == 8) {
+      a.S = t.S; a.ST = t.ST; a.lam = t.lam; a.gco = L.gco; a.Zt = L.Zt; a.scoef = L.tscoef;
+    } else {
+      a.S = t.S32; a.ST = t.ST32; a.lam = t.lam32; a.gco = L.gco32; a.Zt = L.Zt32; a.scoef = L.tscoef32;
+    }
+    topo_schwarz_solve<T>(L.ns, a, st);
+    topo_schwarz_scatter<T>(a, st);
   }
 
   // kind 0: out = P in (projection), 1: out (+)= R in (restriction), 2: out += I (in - in2)
@@ -997,6 +1032,7 @@ OpArgs<T> Solver::op_args(Level& L, const Bucket& b, int mode, const T* u, const
   a.mode = mode;
   a.nbr = L.nbr;
   a.bc = L.bc;
+  a.nfo = L.nfo;
   a.kappa = (T)opt.kappa;
   a.inv_wend = (T)b.t->inv_wend;
   if constexpr (sizeof(T) == 8) {
@@ -1243,8 +1279,8 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     geometry(b.p, g, b.t->D, b.t->w1, b.t->x1, s.opt.nu, st);
     HIPC(hipGetLastError());
   }
-  penalty(E, L.p, L.deg, L.offF, s.opt.mu_star, s.opt.nu, L.nun, L.nbr, L.bc, L.vol, L.area, L.ws, L.pen, L.muf,
-          st);
+  penalty(E, L.p, L.deg, L.offF, s.opt.mu_star, s.opt.nu, L.nun, L.nbr, L.nfo, L.bc, L.vol, L.area, L.ws, L.pen,
+          L.muf, st);
   HIPC(hipGetLastError());
   int hbad = 0;
   HIPC(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1323,6 +1359,28 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   L.var = s.own(upload(var, st));
   L.nb27 = s.own(upload(nb27, st));
   L.h_nb27 = nb27;
+  // unstructured level: the subdomain slot tables (every slot's node, zero or merged nodes) and
+  // the per-node contribution lists with the normalised weights
+  if (L.topo) {
+    const DegTab& t = deg_tab(s, L.p);
+    TopoMesh tm;
+    tm.E = E; tm.n = L.n; tm.nbr = L.h_nbr.data(); tm.nface = L.h_nface.data(); tm.norient = L.h_norient.data();
+    TopoTables T;
+    try {
+      T = topo_tables(tm, t.ns, var.data(), t.h_map.data(), t.h_W.data(), s.opt.weighting == DGFAS_WEIGHT_QUINTIC);
+    } catch (const std::runtime_error& x) {
+      throw Error(DGFAS_EINVAL, std::string("unstructured mesh: ") + x.what());
+    }
+    L.tnt = T.nt;
+    for (int k = 0; k < 5; ++k) L.tblocks[k] = T.blocks[k];
+    L.tg = s.own(upload(T.gather, st));
+    L.tmptr = s.own(upload(T.mptr, st));
+    if (!T.midx.empty()) L.tmidx = s.own(upload(T.midx, st));
+    L.tsptr = s.own(upload(T.sptr, st));
+    L.tsslot = s.own(upload(T.sslot, st));
+    L.tscoef = s.own(upload(T.scoef, st));
+    if (s.opt.precision != DGFAS_FP64) L.tscoef32 = s.own(upload(to_float(T.scoef), st));
+  }
   // Weight sum C = sum_s R_s^T W_s R_s 1 at every node.  Near a degree jump the subdomains that
   // reach a node can disagree about who covers it (neighbours of another degree are zero filled),
   // so the corrections are normalised by C there (C > 0: the own subdomain always covers a node)
@@ -1371,13 +1429,20 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
   // another degree) are never written and must read as zero.
   const size_t nin = (size_t)L.nin * s.nrhs;
   const bool fp32 = s.opt.precision != DGFAS_FP64;
-  s.reserve(L.O, nin, true);
-  if (fp32) s.reserve(L.O32, nin, true);
+  if (L.topo) {
+    // the stored subdomain solutions replace the overlap inbox; SCG takes its dot products
+    // from separate reductions (no fused partial sums)
+    s.reserve(L.Zt, (size_t)E * L.tnt * s.nrhs);
+    if (fp32) s.reserve(L.Zt32, (size_t)E * L.tnt * s.nrhs);
+  } else {
+    s.reserve(L.O, nin, true);
+    if (fp32) s.reserve(L.O32, nin, true);
+  }
   if (L.uniform) {
     const int nsweep = L.lr ? L.nact : E;   // elements the sweep kernels take
     L.nlb = stage_tiles(kStageOp, L.p, nsweep, 1);
     s.reserve(L.kpart, (size_t)L.nlb * s.nrhs);
-    if (L.m > 0) {
+    if (L.m > 0 && !L.topo) {
       L.nla = stage_tiles(kStageAdd, L.p, nsweep, 1);
       s.reserve(L.zpart, (size_t)2 * L.nla * s.nrhs);
     }
@@ -1545,12 +1610,25 @@ void validate(const dgfas_mesh_desc* m, const dgfas_options* o) {
     for (int f = 0; f < 6; ++f) {
       const int en = m->face_nbr[e * 6 + f];
       if (en >= m->n_elem) throw Error(DGFAS_EINVAL, "face neighbour out of range");
-      if (en >= 0 && m->face_nbr[en * 6 + (f ^ 1)] != e)
-        throw Error(DGFAS_EUNSUPPORTED, "face neighbours must be aligned and mutual");
+      if (en >= 0 && !m->face_nbr_face && m->face_nbr[en * 6 + (f ^ 1)] != e)
+        throw Error(DGFAS_EUNSUPPORTED, "face neighbours must be aligned and mutual (or give face_nbr_face)");
       if (en < 0 && m->face_bc[e * 6 + f] != DGFAS_DIRICHLET && m->face_bc[e * 6 + f] != DGFAS_NEUMANN)
         throw Error(DGFAS_EINVAL, "boundary face without a Dirichlet/Neumann code");
     }
   if (!(o->nu > 0) || !(o->kappa >= 0) || !(o->mu_star > 0)) throw Error(DGFAS_EINVAL, "bad coefficients");
+  if (m->face_orient && !m->face_nbr_face) throw Error(DGFAS_EINVAL, "face_orient needs face_nbr_face");
+  if (m->face_nbr_face) {
+    for (int e = 1; e < m->n_elem; ++e)
+      if (m->degree[e] != m->degree[0]) throw Error(DGFAS_EUNSUPPORTED, "an unstructured mesh needs one degree");
+    if (o->h_levels > 0 || o->local_steps > 0 || o->precision == DGFAS_BF16 || o->precision == DGFAS_FP32_MFMA)
+      throw Error(DGFAS_EUNSUPPORTED, "unstructured meshes run without h_levels, local_steps and matrix-core "
+                                      "precisions");
+    TopoMesh tm;
+    tm.E = m->n_elem; tm.n = m->degree[0] + 1; tm.nbr = m->face_nbr; tm.nface = m->face_nbr_face;
+    tm.norient = m->face_orient;
+    const std::string bad = topo_check(tm);
+    if (!bad.empty()) throw Error(DGFAS_EINVAL, bad);
+  }
   if (m->nu_nodal) {
     const int p = m->degree[0];
     for (int e = 1; e < m->n_elem; ++e)
@@ -1916,6 +1994,17 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
       L.hM = s->own(upload(h_child_matrices(sp[li].deg[0]), s->st));
     }
     for (int d = 0; d < 3; ++d) L.box[d] = sp[li].box[d];
+    if (m->face_nbr_face) {
+      // p-levels keep the topology: every level has the mesh's faces and orientations
+      L.topo = true;
+      L.h_nface.assign(m->face_nbr_face, m->face_nbr_face + (size_t)E * 6);
+      L.h_norient.assign((size_t)E * 6, 0);
+      if (m->face_orient) L.h_norient.assign(m->face_orient, m->face_orient + (size_t)E * 6);
+      std::vector<int8_t> pk((size_t)E * 6, 0);
+      for (size_t q = 0; q < pk.size(); ++q)
+        if (L.h_nbr[q] >= 0) pk[q] = (int8_t)(L.h_nface[q] | (L.h_norient[q] << 3));
+      L.nfo = s->own(upload(pk, s->st));
+    }
     L.nbr = s->own(upload(L.h_nbr, s->st));
     L.bc = s->own(upload(L.h_bc, s->st));
     L.hdown = sp[li].hdown;
@@ -2175,6 +2264,14 @@ dgfas_status dgfas_level_overlap(dgfas_solver s, int32_t level, int32_t* m) {
   API_END
 }
 
+dgfas_status dgfas_level_blocks(dgfas_solver s, int32_t level, int64_t* counts) {
+  API_BEGIN
+  need(counts, "counts");
+  const Level& L = S_(s)->level(level);
+  for (int k = 0; k < 5; ++k) counts[k] = L.tblocks[k];
+  API_END
+}
+
 namespace dgfas {
 namespace {
 void level_rhs(Solver* s, Level& T, const double* f, const double* uD, const double* qN, double* b) {
@@ -2283,6 +2380,8 @@ dgfas_status dgfas_schwarz_noalloc(dgfas_solver sv, int32_t level, const double*
   Solver* s = S_(sv);
   need(r, "r"); need(z, "z");
   Level& L = s->level(level);
+  if (L.topo)
+    throw Error(DGFAS_EUNSUPPORTED, "the allocation-free Schwarz application covers structured meshes only");
   const size_t need_d = (size_t)L.nin * s->nrhs;
   if (need_d > kNoAllocDoubles)
     throw Error(DGFAS_EINVAL, "level " + std::to_string(level) + " needs an overlap inbox of " +
@@ -2513,6 +2612,7 @@ dgfas_status dgfas_set_learned(dgfas_solver sv, dgfas_mlp m, int32_t enabled) {
   Level& T = s->lv.back();
   if (!enabled) { s->learned = false; return DGFAS_OK; }
   if (s->opt.local_steps > 0) throw Error(DGFAS_EUNSUPPORTED, "no learned correction with local refinement");
+  if (T.topo) throw Error(DGFAS_EUNSUPPORTED, "no learned correction on unstructured meshes");
   if (!m) throw Error(DGFAS_EINVAL, "null network");
   if (!T.uniform) throw Error(DGFAS_EUNSUPPORTED, "learned correction needs one degree on the finest level");
   Mlp* net = dgfas_mlp_impl(m);
@@ -2543,6 +2643,7 @@ dgfas_status dgfas_learned_pairs(dgfas_solver sv, const double* r, const int32_t
   if (s->nrhs != 1) throw Error(DGFAS_EUNSUPPORTED, "pairs need n_rhs = 1");
   Level& L = s->lv.back();
   if (!L.uniform) throw Error(DGFAS_EUNSUPPORTED, "pairs need one degree on the finest level");
+  if (L.topo) throw Error(DGFAS_EUNSUPPORTED, "pairs need a structured mesh");
   if (n < 1 || n > L.E) throw Error(DGFAS_EINVAL, "bad number of centres");
   // centres must be 4 apart in the 26-neighbourhood graph: their 3x3x3 patches then neither
   // overlap nor touch, so the masked operator is block diagonal over the subdomains

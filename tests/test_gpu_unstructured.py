@@ -1,0 +1,193 @@
+"""Unstructured meshes through the library (oriented faces, Sec. 5.1; Schwarz subdomains with
+zero fill and merging at irregular edges and vertices, Sec. 4.3.1): the operator and the
+Schwarz method element by element against the oracle, the block classification, and V-cycle
+histories on the extruded diamond mesh (Sec. 6.2.4) and on meshes with randomly turned local
+axes."""
+import numpy as np
+import pytest
+
+from oracle import operator as oop, solvers as osv
+from oracle.gll import gll as ogll
+from oracle.mesh import Mesh
+from oracle.unstructured import TopoSchwarz
+from paper_2608_14123_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip('torch')
+
+
+@pytest.fixture(scope='module')
+def binding():
+    if not torch.cuda.is_available():
+        pytest.fail('GPU tests need a GPU')
+    from paper_2608_14123_amd import binding as b
+    return b
+
+
+def diamond(p, xi, nc=2, layers=2, periodic=False):
+    X = W.diamond_coords(nc, layers, xi, shift_seed=1, rot_seed=2)
+    nbr, nf, no, bc = W.face_connectivity(X, period=1.0 if periodic else None)
+    return X, nbr, nf, no, bc
+
+
+def rotated(p, xi, ne=3, seed=5):
+    nbr, bc = W.box_topology(ne, ne, ne)
+    X = W.element_coords(W.box_vertices(ne, ne, ne), xi, lambda Y: W.sine_bump_map(Y, 0.03))
+    X = W.rotate_local_axes(X, np.random.default_rng(seed).integers(0, len(W.ROTATIONS), size=len(X)))
+    nbr, nf, no, bc = W.face_connectivity(X)
+    return X, nbr, nf, no, bc
+
+
+CASES = {
+    'diamond_p3_2x2x2': lambda p, xi: diamond(p, xi),
+    'diamond_periodic_p2_2x2x3': lambda p, xi: diamond(p, xi, layers=3, periodic=True),
+    'rotated_bump_p3_3^3': lambda p, xi: rotated(p, xi),
+}
+DEG = {'diamond_p3_2x2x2': 3, 'diamond_periodic_p2_2x2x3': 2, 'rotated_bump_p3_3^3': 3}
+
+
+def both(binding, name, mu_star=5.0, kappa=1.0, **opt):
+    p = DEG[name]
+    Xo, nbr, nf, no, bc = CASES[name](p, ogll(p)[0])
+    mesh = Mesh(p, Xo, nbr, bc, kappa=kappa, mu_star=mu_star, nbr_face=nf, nbr_orient=no)
+    Xl = CASES[name](p, binding.gll(p)[0])[0]
+    o = binding.default_options(kappa=kappa, mu_star=mu_star, **opt)
+    lib = binding.Solver(np.full(len(Xl), p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+    return mesh, lib
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_operator_matches_oracle(binding, name):
+    print('unstructured operator', name, flush=True)
+    mesh, lib = both(binding, name)
+    u = np.random.default_rng(3).standard_normal(mesh.n_dof())
+    ref = oop.apply(mesh, u).ravel()
+    out = torch.empty(mesh.n_dof(), dtype=torch.float64, device='cuda')
+    lib.apply(lib.n_levels, torch.from_numpy(u).cuda(), out)
+    err = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-12, err
+    lib.close()
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_schwarz_matches_oracle(binding, name):
+    print('unstructured schwarz', name, flush=True)
+    mesh, lib = both(binding, name)
+    sz = TopoSchwarz(mesh, 1)
+    r = np.random.default_rng(4).standard_normal(mesh.n_dof())
+    ref = sz.apply(r).ravel()
+    z = torch.empty(mesh.n_dof(), dtype=torch.float64, device='cuda')
+    lib.schwarz(lib.n_levels, torch.from_numpy(r).cuda(), z)
+    err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-12, err
+    # the block classification of the library's walker is the oracle's
+    kinds = ('own', 'face', 'map', 'zero', 'merge')
+    want = np.array([sum(list(sd['kinds'].values()).count(k) for sd in sz.sub) for k in kinds])
+    assert np.array_equal(lib.level_blocks(lib.n_levels), want), (lib.level_blocks(lib.n_levels), want)
+    lib.close()
+
+
+def test_rotated_mesh_equals_structured_path(binding):
+    """Turning every element's local axes changes neither the operator nor the Schwarz method:
+    the unstructured path on the turned mesh equals the structured kernels on the original."""
+    p, ne = 3, 3
+    xi = binding.gll(p)[0]
+    nbr0, bc0 = W.box_topology(ne, ne, ne)
+    X0 = W.element_coords(W.box_vertices(ne, ne, ne), xi, lambda Y: W.sine_bump_map(Y, 0.03))
+    rot = np.random.default_rng(5).integers(0, len(W.ROTATIONS), size=len(X0))
+    X1 = W.rotate_local_axes(X0, rot)
+    nbr, nf, no, bc = W.face_connectivity(X1)
+    E, n = len(X0), p + 1
+    # node permutation from the coordinates: node k of turned element e is node P[e, k] of the original
+    a = X0.reshape(E, 3, -1).transpose(0, 2, 1)
+    b = X1.reshape(E, 3, -1).transpose(0, 2, 1)
+    P = np.argmin(((b[:, :, None, :] - a[:, None, :, :]) ** 2).sum(-1), axis=2)
+    base = (np.arange(E) * n ** 3)[:, None]
+    perm = (base + P).ravel()
+    o = binding.default_options(kappa=1.0, mu_star=5.0)
+    s0 = binding.Solver(np.full(E, p, np.int32), X0, nbr0, bc0, o)
+    s1 = binding.Solver(np.full(E, p, np.int32), X1, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+    r = torch.from_numpy(np.random.default_rng(8).standard_normal(E * n ** 3)).cuda()
+    rp = r[torch.from_numpy(perm).cuda()].contiguous()
+    for fn_name in ('apply', 'schwarz'):
+        z0 = torch.empty_like(r)
+        z1 = torch.empty_like(r)
+        getattr(s0, fn_name)(s0.n_levels, r, z0)
+        getattr(s1, fn_name)(s1.n_levels, rp, z1)
+        ref = z0.cpu().numpy()[perm]
+        err = np.abs(z1.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err < 1e-12, (fn_name, err)
+    s0.close()
+    s1.close()
+
+
+# on the diamond mesh WAS diverges (as reported in Sec. 6.2.4) and SCG needs more smoothing
+@pytest.mark.parametrize('name,smoother,ns', [('diamond_p3_2x2x2', 'scg', (8, 4)),
+                                              ('rotated_bump_p3_3^3', 'was', (2, 2)),
+                                              ('diamond_periodic_p2_2x2x3', 'scg', (8, 4))])
+def test_history_matches_oracle(binding, name, smoother, ns):
+    print('unstructured history', name, smoother, flush=True)
+    p = DEG[name]
+    periodic = 'periodic' in name
+    kappa = 0.0 if periodic else 1.0
+    Xo, nbr, nf, no, bc = CASES[name](p, ogll(p)[0])
+    levels = osv.build_levels(p, Xo, nbr, bc, kappa=kappa, mu_star=5.0, nbr_face=nf, nbr_orient=no)
+    n = p + 1
+    b = np.random.default_rng(6).uniform(-1, 1, (len(Xo), n, n, n))
+    if periodic:
+        b -= b.mean()
+    opts = osv.Options(smoother, *ns, null_space=periodic)
+    uo, ho = osv.solve(levels, np.zeros_like(b), b, opts, max_cycles=25, rtol=1e-10)
+    Xl = CASES[name](p, binding.gll(p)[0])[0]
+    o = binding.default_options(kappa=kappa, mu_star=5.0, null_space=int(periodic), ns1=ns[0], ns2=ns[1],
+                                smoother=binding.SCG if smoother == 'scg' else binding.WAS)
+    lib = binding.Solver(np.full(len(Xl), p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+    u = torch.zeros(b.size, dtype=torch.float64, device='cuda')
+    hist, ok = lib.solve(u, torch.from_numpy(b.ravel()).cuda(), max_cycles=25, rtol=1e-10)
+    hist = list(hist)
+    assert ok and len(hist) == len(ho), (hist, ho)
+    for a, c in zip(hist, ho):
+        assert abs(a - c) <= 1e-6 * c + 1e-14, (hist, ho)
+    ug, ref = u.cpu().numpy(), uo.ravel()
+    if periodic:
+        ug, ref = ug - ug.mean(), ref - ref.mean()
+    assert np.abs(ug - ref).max() < 1e-9 * np.abs(ref).max()
+    lib.close()
+
+
+def test_fp32_smoother_reaches_the_fp64_solution(binding):
+    name = 'diamond_p3_2x2x2'
+    p = DEG[name]
+    Xl, nbr, nf, no, bc = CASES[name](p, binding.gll(p)[0])
+    n = p + 1
+    b = torch.from_numpy(np.random.default_rng(6).uniform(-1, 1, len(Xl) * n ** 3)).cuda()
+    sols = []
+    for prec in (binding.FP64, binding.FP32):
+        o = binding.default_options(kappa=1.0, mu_star=5.0, smoother=binding.SCG, ns1=8, ns2=4, precision=prec)
+        lib = binding.Solver(np.full(len(Xl), p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+        u = torch.zeros_like(b)
+        hist, ok = lib.solve(u, b, max_cycles=30, rtol=1e-10)
+        assert ok, list(hist)
+        sols.append(u.cpu().numpy())
+        lib.close()
+    assert np.abs(sols[0] - sols[1]).max() < 1e-8 * np.abs(sols[0]).max()
+
+
+def test_refusals(binding):
+    p = 2
+    Xl, nbr, nf, no, bc = diamond(p, binding.gll(p)[0])
+    E = len(Xl)
+    o = binding.default_options(mu_star=5.0)
+    bad = no.copy()
+    i = np.argwhere(nbr >= 0)[0]
+    bad[i[0], i[1]] = (bad[i[0], i[1]] + 1) % 8          # no longer the inverse of the other side's code
+    with pytest.raises(binding.DgfasError):
+        binding.Solver(np.full(E, p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=bad)
+    with pytest.raises(binding.DgfasError):
+        binding.Solver(np.full(E, p, np.int32), Xl, nbr, bc, binding.default_options(mu_star=5.0, h_levels=1),
+                       box=(1, 1, E), nbr_face=nf, nbr_orient=no)
+    lib = binding.Solver(np.full(E, p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+    r = torch.zeros(E * (p + 1) ** 3, dtype=torch.float64, device='cuda')
+    with pytest.raises(binding.DgfasError):
+        lib.schwarz_noalloc(lib.n_levels, r, torch.empty_like(r))
+    lib.close()
