@@ -26,7 +26,7 @@ BF16_PEAK_TFLOPS = 2500.0     # dense BF16 matrix-core peak
 # HBM bytes of one residual launch of the operator kernel at 32^3, p = 7 from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a 1 GiB copy (profiles/c2_curved_p7_hbm_traffic_pmc.md);
 # valid only for the kernel source it was measured on.
-OPERATOR_TRAFFIC = {'sha256_prefix': '766af14cbdda7b53', 'bytes': 1.675e9, 'ne': 32, 'p': 7}
+OPERATOR_TRAFFIC = {'sha256_prefix': '7a30df6350d27f6a', 'bytes': 1.671e9, 'ne': 32, 'p': 7}
 
 
 def parse():
@@ -40,11 +40,13 @@ def parse():
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle cpu_baseline leg')
     ap.add_argument('--no-t10', action='store_true', help='skip the time-to-tolerance solves')
     ap.add_argument('--calib-copy', action='store_true', help='also run a plain copy kernel (PMC calibration)')
-    ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched', 'mlp', 'local'],
+    ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched', 'mlp', 'local',
+                                                              'diamond'],
                     help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8); '
                          'stretched: 48^3, p = 8, aspect 1:100, 16 right-hand sides; mlp: the learned '
                          'correction network at its p = 8 size; local: local refinement, 16^3 p = 7 with two '
-                         'nested zones')
+                         'nested zones; diamond: the periodic cube of extruded diamond cells (irregular edges '
+                         'and vertices) at p = 4 and 8')
     ap.add_argument('--cycles', type=int, default=40, help='stretched workload: largest V-cycle count of a solve')
     return ap.parse_args()
 
@@ -328,6 +330,108 @@ def local_bench(args, torch, B):
     print(json.dumps(out))
 
 
+def diamond_bench(args, torch, B):
+    """The irregular mesh of Sec. 6.2.4: the periodic cube [0, 2 pi)^3 of the Cartesian study
+    (kappa = 0, semidefinite, null-space projection in the root SCG) built from nc x nc diamond
+    cells (a central quadrilateral and four trapezoids; cell corners shared by 8 elements, the
+    diamond's corners by 3) extruded into layers, every element's local axes turned at random.
+    About 32^3 elements' worth of DOF at p = 4 (nc = 16, 24 layers) and 16^3 at p = 8 (nc = 8,
+    12 layers), as the Cartesian study sizes its meshes.  Per mode: set-up, V-cycle time, n10 and
+    t10 from u = 0 on random zero-mean data; per degree the unstructured operator and Schwarz
+    application (medians of per-call HIP-event timings) and the WAS sweep they make."""
+    from paper_2608_14123_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    sizes = {4: (16, 24), 8: (8, 12)}
+    modes, kernels, struct = {}, {}, {}
+    for p, (nc, layers) in sizes.items():
+        t0 = time.perf_counter()
+        X = W.diamond_coords(nc, layers, B.gll(p)[0], length=2 * np.pi, height=2 * np.pi, shift_seed=1, rot_seed=2)
+        nbr, nf, no, bc = W.face_connectivity(X, period=2 * np.pi)
+        mesh_s = time.perf_counter() - t0
+        E, n3 = len(X), (p + 1) ** 3
+        ndof = E * n3
+        b = W.uniform_nodal(ndof, 11)
+        b -= b.mean()
+        bd = torch.from_numpy(b).cuda()
+        for name, kw in (('scg84', dict(smoother=B.SCG, ns1=8, ns2=4)),
+                         ('scg84_fmg', dict(smoother=B.SCG, ns1=8, ns2=4, start=B.START_FMG)),
+                         ('was22', dict(smoother=B.WAS, ns1=2, ns2=2))):
+            t0 = time.perf_counter()
+            lib = B.Solver(np.full(E, p, np.int32), X, nbr, bc,
+                           B.default_options(kappa=0.0, null_space=1, mu_star=5.0, root_rtol=0.1, **kw),
+                           stream=stream.cuda_stream, nbr_face=nf, nbr_orient=no)
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            L = lib.n_levels
+            if p not in struct:
+                struct[p] = {'cells': nc, 'layers': layers, 'elements': E, 'dof': ndof, 'mesh_build_s': round(mesh_s, 2),
+                             'blocks_finest': dict(zip(('own', 'face', 'mapped', 'zero_filled', 'merged'),
+                                                       lib.level_blocks(L).tolist()))}
+            u = torch.zeros_like(bd)
+            cycles = 40
+            if name != 'was22':
+                lib.solve(u, bd, max_cycles=args.warmup, rtol=0.0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lib.solve(u.zero_(), bd, max_cycles=args.steps, rtol=0.0)
+                torch.cuda.synchronize()
+                ms_cycle = (time.perf_counter() - t0) * 1e3 / args.steps
+            else:
+                ms_cycle, cycles = None, 4
+            t0 = time.perf_counter()
+            try:
+                hist, ok = lib.solve(u.zero_(), bd, max_cycles=cycles, rtol=1e-10)
+            except B.DgfasError as ex:          # a diverging cycle is recorded, not fatal
+                hist, ok = [float('nan')], False
+                print(name, 'solve failed:', ex, file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            t10 = time.perf_counter() - t0
+            modes['p%d_%s' % (p, name)] = {'setup_s': round(setup_s, 3), 'ms_per_cycle': None if ms_cycle is None else
+                                           round(ms_cycle, 3), 'n10': len(hist) - 1 if ok else None,
+                                           't10_s': round(t10, 4) if ok else None, 'converged': bool(ok),
+                                           'hist': ['%.3e' % h for h in hist]}
+            print(p, name, modes['p%d_%s' % (p, name)], file=sys.stderr, flush=True)
+            if name == 'scg84':
+                # the finest level's operator and Schwarz application, medians of per-call timings
+                g = torch.from_numpy(W.uniform_nodal(ndof, 3)).cuda()
+                r, z = torch.zeros_like(g), torch.zeros_like(g)
+                ts = {'operator': [], 'schwarz': []}
+                for _ in range(2):
+                    lib.residual(L, u, g, r)
+                    lib.schwarz(L, r, z)
+                for _ in range(args.reps):
+                    for key, fn in (('operator', lambda: lib.residual(L, u, g, r)), ('schwarz', lambda: lib.schwarz(L, r, z))):
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        fn()
+                        e1.record(stream)
+                        e1.synchronize()
+                        ts[key].append(e0.elapsed_time(e1))
+                op_ms, sz_ms = float(np.median(ts['operator'])), float(np.median(ts['schwarz']))
+                kernels[p] = {'operator_ms': round(op_ms, 4), 'operator_gdofs': round(ndof / op_ms / 1e6, 2),
+                              'operator_frac_48B': round(48.0 * ndof / (op_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              'schwarz_ms': round(sz_ms, 4), 'schwarz_gdofs': round(ndof / sz_ms / 1e6, 2),
+                              'was_sweep_gdofs': round(ndof / (op_ms + sz_ms) / 1e6, 2)}
+                print(p, kernels[p], file=sys.stderr, flush=True)
+            lib.close()
+    k4 = kernels[4]
+    out = {
+        'metric': 'GDOF/s per Schwarz sweep; time-to-1e-10 residual, plain FP64 vs mixed/learned',
+        'value': k4['was_sweep_gdofs'], 'unit': 'GDOF/s', 'n_gpus': 1, 'steps': args.steps, 'warmup': args.warmup,
+        'ms_per_step': modes['p4_scg84']['ms_per_cycle'], 'higher_is_better': True, 'scaling': 'weak',
+        'vs_baseline': None, 'dtype': 'f64', 'data': 'synthetic',
+        'config': {'workload': 'diamond_periodic_2pi^3', 'sizes': {'p%d' % k: v for k, v in struct.items()},
+                   'value': 'p = 4 WAS sweep (unstructured residual + Schwarz application), DOF / median time',
+                   'rhs': 'uniform random, zero mean', 'kappa': 0.0, 'mu_star': 5.0, 'root': 'SCG to 1e-1'},
+        'roofline': {'kernel': 'sipg_apply_kernel<5,double,orient> (residual, p = 4)', 'bound': 'hbm',
+                     'achieved': round(k4['operator_frac_48B'] * HBM_PEAK_GBS, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+                     'frac': k4['operator_frac_48B'], 'traffic': None},
+        'kernels': {'p%d' % k: v for k, v in kernels.items()},
+        'modes': modes,
+    }
+    print(json.dumps(out))
+
+
 def mlp_bench(args, torch, B):
     """The learned correction's network at the size of the p = 8, m = 1 subdomain tile: 1340 -> 256
     -> 256 -> 1331, batch 4096 (BF16 weights, FP32 accumulation on the matrix cores).  Times the
@@ -475,6 +579,8 @@ def main():
         return
     if args.workload == 'local':
         return local_bench(args, torch, B)
+    if args.workload == 'diamond':
+        return diamond_bench(args, torch, B)
     if args.workload == 'mlp':
         mlp_bench(args, torch, B)
         return

@@ -344,42 +344,46 @@ def face_connectivity(X, period=None, bc_code=DIRICHLET, tol=1e-9):
     per = None if period is None else np.broadcast_to(np.asarray(period, dtype=np.float64), (3,))
     scale = max(1.0, float(np.abs(X).max()))
     q = tol * scale * 1e3
-
-    def wrap(c):
-        return c if per is None else c - per[:, None] * np.floor(c / per[:, None] + 0.5 * q / per[:, None])
-
-    def key(F):
-        # the face centroid (faces of a valid mesh do not share one); with a period, wrapped
-        c = np.round(wrap(F.reshape(3, -1).mean(axis=1)[:, None]) / q).astype(np.int64)[:, 0]
-        if per is not None:
-            c = c % np.round(per / q).astype(np.int64)
-        return tuple(c)
-
-    def same(Fa, Fb):
-        d = Fa - Fb
-        if per is not None:
-            d = d - per[:, None, None] * np.round(d / per[:, None, None])
-        return np.max(np.abs(d)) <= tol * scale * 1e2
-
-    faces = [[face_array(X[e], phi) for phi in range(6)] for e in range(E)]
-    table = {}
-    for e in range(E):
-        for phi in range(6):
-            table.setdefault(key(faces[e][phi]), []).append((e, phi))
-    nbr = np.full((E, 6), -1, dtype=np.int32)
-    nbf = np.full((E, 6), -1, dtype=np.int8)
-    nbo = np.zeros((E, 6), dtype=np.int8)
-    for group in table.values():
-        if len(group) == 1:
-            continue
-        if len(group) != 2:
-            raise ValueError('a face is shared by %d element faces' % len(group))
-        for (e, phi), (en, nf) in (group, group[::-1]):
-            Fa, Fb = faces[e][phi], faces[en][nf]
-            hit = [o for o in range(8) if same(Fa, Fb[:, orient_index(n, o)[0], orient_index(n, o)[1]])]
-            if len(hit) != 1:
-                raise ValueError('element %d face %d: %d orientations match' % (e, phi, len(hit)))
-            nbr[e, phi], nbf[e, phi], nbo[e, phi] = en, nf, hit[0]
+    F = np.stack([face_array(X, phi) for phi in range(6)], axis=1)        # (E, 6, 3, n, n)
+    # pair the faces by their centroids (faces of a valid mesh do not share one), wrapped
+    c = F.reshape(E, 6, 3, -1).mean(axis=3)
+    if per is not None:
+        c = c - per * np.floor(c / per + 0.5 * q / per)
+    key = np.round(c / q).astype(np.int64)
+    if per is not None:
+        key = key % np.round(per / q).astype(np.int64)
+    flat = key.reshape(-1, 3)
+    _, inv, cnt = np.unique(flat, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    if np.any(cnt > 2):
+        raise ValueError('a face is shared by %d element faces' % cnt.max())
+    order = np.argsort(inv, kind='stable')
+    grp = inv[order]
+    first = np.nonzero((grp[1:] == grp[:-1]))[0]
+    a, b = order[first], order[first + 1]                                  # paired (e * 6 + phi)
+    nbr = np.full(E * 6, -1, dtype=np.int32)
+    nbf = np.full(E * 6, -1, dtype=np.int8)
+    nbo = np.zeros(E * 6, dtype=np.int8)
+    Ff = F.reshape(E * 6, 3, n, n)
+    for x, y in ((a, b), (b, a)):
+        Fa, Fb = Ff[x], Ff[y]
+        code = np.full(len(x), -1)
+        hits = np.zeros(len(x), dtype=int)
+        for o in range(8):
+            ap, bp = orient_index(n, o)
+            d = Fa - Fb[:, :, ap, bp]
+            if per is not None:
+                d = d - per[None, :, None, None] * np.round(d / per[None, :, None, None])
+            ok = np.abs(d).reshape(len(x), -1).max(axis=1) <= tol * scale * 1e2
+            code = np.where(ok, o, code)
+            hits += ok
+        if np.any(hits != 1):
+            k = int(np.nonzero(hits != 1)[0][0])
+            raise ValueError('element %d face %d: %d orientations match' % (x[k] // 6, x[k] % 6, hits[k]))
+        nbr[x] = y // 6
+        nbf[x] = y % 6
+        nbo[x] = code
+    nbr, nbf, nbo = nbr.reshape(E, 6), nbf.reshape(E, 6), nbo.reshape(E, 6)
     bc = np.where(nbr < 0, bc_code, 0).astype(np.int8)
     return nbr, nbf, nbo, bc
 
