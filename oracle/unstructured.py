@@ -168,11 +168,15 @@ class TopoSchwarz:
     """Weighted overlapping Schwarz method on an unstructured mesh (oriented faces, irregular
     edges and vertices), with the interface of oracle.schwarz.Schwarz."""
 
-    def __init__(self, mesh, m, weighting='quintic'):
+    def __init__(self, mesh, m, weighting='quintic', subset=None):
+        """subset: build only these elements' subdomains (sampled checks on large meshes; the
+        weight sums, and so z, are then exact at the nodes that only these subdomains reach,
+        e.g. the nodes of an element when every element sharing a vertex with it is in the
+        subset)."""
         self.mesh, self.m, self.weighting = mesh, m, weighting
         self.g = surrogate_coefficients(mesh)
         self.variants = {}
-        self.sub = [self._subdomain(e) for e in range(mesh.E)]
+        self.sub = [self._subdomain(int(e)) for e in (range(mesh.E) if subset is None else subset)]
         if weighting == 'quintic':
             C = np.zeros(mesh.n_dof())
             for sd in self.sub:
@@ -320,5 +324,6 @@ class TopoSchwarz:
             du = (sd['W'] * self.local_solve(sd, self.gather(sd, r))).ravel()
             np.add.at(z, sd['gidx'], sd['coef'] * du[sd['slot']])
         if self.C is not None:
-            z = z / self.C
+            cov = self.C > 0                     # every node, unless only a subset is built
+            z = np.where(cov, z / np.where(cov, self.C, 1.0), 0.0)
         return z.reshape(self.mesh.E, self.mesh.n, self.mesh.n, self.mesh.n)

@@ -155,6 +155,71 @@ def test_history_matches_oracle(binding, name, smoother, ns):
     lib.close()
 
 
+def test_fmg_history_matches_oracle(binding):
+    name = 'diamond_p3_2x2x2'
+    p = DEG[name]
+    Xo, nbr, nf, no, bc = CASES[name](p, ogll(p)[0])
+    levels = osv.build_levels(p, Xo, nbr, bc, kappa=1.0, mu_star=5.0, nbr_face=nf, nbr_orient=no)
+    n = p + 1
+    b = np.random.default_rng(6).uniform(-1, 1, (len(Xo), n, n, n))
+    uo, ho = osv.solve(levels, np.zeros_like(b), b, osv.Options('scg', 8, 4, start='fmg'), max_cycles=20, rtol=1e-10)
+    Xl = CASES[name](p, binding.gll(p)[0])[0]
+    o = binding.default_options(kappa=1.0, mu_star=5.0, ns1=8, ns2=4, smoother=binding.SCG, start=binding.START_FMG)
+    lib = binding.Solver(np.full(len(Xl), p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+    u = torch.zeros(b.size, dtype=torch.float64, device='cuda')
+    hist, ok = lib.solve(u, torch.from_numpy(b.ravel()).cuda(), max_cycles=20, rtol=1e-10)
+    hist = list(hist)
+    assert ok and len(hist) == len(ho), (hist, ho)
+    for a, c in zip(hist, ho):
+        assert abs(a - c) <= 1e-6 * c + 1e-14, (hist, ho)
+    assert np.abs(u.cpu().numpy() - uo.ravel()).max() < 1e-9 * np.abs(uo).max()
+    lib.close()
+
+
+def test_graph_batch_and_workspace_agree_with_the_plain_solve(binding):
+    """The whole cycle as one graph (fixed-iteration root) replays the eager cycle bitwise; in a
+    batch of 3 right-hand sides each follows its own single solve (to rounding); a caller-owned
+    workspace changes nothing."""
+    name = 'rotated_bump_p3_3^3'
+    p = DEG[name]
+    Xl, nbr, nf, no, bc = CASES[name](p, binding.gll(p)[0])
+    E, n3 = len(Xl), (p + 1) ** 3
+    rng = np.random.default_rng(9)
+    bs = [torch.from_numpy(rng.uniform(-1, 1, E * n3)).cuda() for _ in range(3)]
+    kw = dict(kappa=1.0, mu_star=5.0, smoother=binding.SCG, ns1=3, ns2=2, root_rtol=0.0, root_max_iter=12)
+
+    def run(b, **extra):
+        o = binding.default_options(**kw, **extra)
+        lib = binding.Solver(np.full(E, p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+        u = torch.zeros_like(b)
+        hist, ok = lib.solve(u, b, max_cycles=8, rtol=0.0)
+        lib.close()
+        return u.cpu().numpy(), list(hist)
+
+    u0, h0 = run(bs[0])
+    ug, hg = run(bs[0], graph=1)
+    assert np.array_equal(u0, ug) and h0 == hg
+    # a batch of three right-hand sides
+    o = binding.default_options(n_rhs=3, **kw)
+    lib = binding.Solver(np.full(E, p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+    u = torch.zeros(3 * E * n3, dtype=torch.float64, device='cuda')
+    lib.solve(u, torch.cat(bs), max_cycles=8, rtol=0.0)
+    for k in range(3):
+        uk, _ = run(bs[k]) if k else (u0, h0)
+        got = u[k * E * n3:(k + 1) * E * n3].cpu().numpy()
+        assert np.abs(got - uk).max() <= 1e-12 * np.abs(uk).max(), k
+    lib.close()
+    # a caller-owned workspace
+    o = binding.default_options(**kw)
+    lib = binding.Solver(np.full(E, p, np.int32), Xl, nbr, bc, o, nbr_face=nf, nbr_orient=no)
+    ws = torch.empty(lib.workspace_size(), dtype=torch.uint8, device='cuda')
+    lib.set_workspace(ws)
+    u = torch.zeros_like(bs[0])
+    lib.solve(u, bs[0], max_cycles=8, rtol=0.0)
+    assert np.array_equal(u.cpu().numpy(), u0)
+    lib.close()
+
+
 def test_fp32_smoother_reaches_the_fp64_solution(binding):
     name = 'diamond_p3_2x2x2'
     p = DEG[name]
