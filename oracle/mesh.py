@@ -173,16 +173,14 @@ class Mesh:
         `sel` (a boolean mask of interior faces), each in the own face's node order."""
         idx = np.nonzero(sel)[0]
         en = self.nbr[idx, phi]
-        nf = self.nbr_face[idx, phi]
-        no = self.nbr_orient[idx, phi]
+        if not self.oriented:
+            return face_view(V[en], OPPOSITE[phi])
+        code = self.nbr_face[idx, phi] * 8 + self.nbr_orient[idx, phi]
         out = np.empty((len(idx),) + V.shape[1:-3] + (self.n, self.n))
-        for f in range(6):
-            for o in range(8):
-                hit = (nf == f) & (no == o)
-                if not np.any(hit):
-                    continue
-                ap, bp = orient_index(self.n, o)
-                out[hit] = face_view(V[en[hit]], f)[..., ap, bp]
+        for c in np.unique(code):
+            hit = code == c
+            ap, bp = orient_index(self.n, int(c) % 8)
+            out[hit] = face_view(V[en[hit]], int(c) // 8)[..., ap, bp]
         return out
 
     # -- helpers --------------------------------------------------------------
