@@ -65,21 +65,24 @@ def perturb_vertices(V, fraction, seed):
 def element_coords(V, xi, map_fn=None):
     """Coordinates (E, 3, n, n, n) at tensor points xi (1D, ascending) of every element.
 
-    Trilinear interpolation of the vertex grid, then the optional pointwise map.
+    Trilinear interpolation of the vertex grid (one direction at a time), then the optional
+    pointwise map.
     """
     xi = np.asarray(xi, dtype=np.float64)
     nz, ny, nx = (s - 1 for s in V.shape[:3])
     lo, hi = 0.5 * (1.0 - xi), 0.5 * (1.0 + xi)
-    shape_fn = (lo, hi)
     E, n = nx * ny * nz, len(xi)
-    X = np.zeros((nz, ny, nx, n, n, n, 3))
-    for dz in (0, 1):
-        for dy in (0, 1):
-            for dx in (0, 1):
-                wgt = shape_fn[dz][:, None, None] * shape_fn[dy][None, :, None] * shape_fn[dx][None, None, :]
-                corner = V[dz:dz + nz, dy:dy + ny, dx:dx + nx]          # (nz, ny, nx, 3)
-                X += wgt[None, None, None, :, :, :, None] * corner[:, :, :, None, None, None, :]
-    X = X.reshape(E, n, n, n, 3)
+    V = np.asarray(V, dtype=np.float64)
+    # along x: (nz+1, ny+1, nx, n_i, 3)
+    A = lo[None, None, None, :, None] * V[:, :, :-1, None, :] + hi[None, None, None, :, None] * V[:, :, 1:, None, :]
+    # along y: (nz+1, ny, n_j, nx, n_i, 3)
+    Bv = (lo[None, None, :, None, None, None] * A[:, :-1, None] + hi[None, None, :, None, None, None] * A[:, 1:, None])
+    del A
+    # along z: (nz, n_k, ny, n_j, nx, n_i, 3)
+    C = (lo[None, :, None, None, None, None, None] * Bv[:-1, None] + hi[None, :, None, None, None, None, None] * Bv[1:, None])
+    del Bv
+    X = C.transpose(0, 2, 4, 1, 3, 5, 6).reshape(E, n, n, n, 3)    # (ez, ey, ex, k, j, i, coord)
+    del C
     if map_fn is not None:
         X = map_fn(X)
     return np.ascontiguousarray(np.moveaxis(X, -1, 1))
