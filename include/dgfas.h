@@ -142,8 +142,8 @@ typedef struct {
   int32_t batch;            /* mixed-degree levels: DGFAS_BATCH_PER_DEGREE (one launch per degree
                                bucket and stage), DGFAS_BATCH_ONE_LAUNCH (one launch per sweep
                                stage over all buckets, a workgroup per tile),
-                               DGFAS_BATCH_PERSISTENT (one launch per stage of two workgroups per
-                               compute unit that stride through the tile list) or
+                               DGFAS_BATCH_PERSISTENT (one launch per stage whose workgroups, about
+                               24 waves per compute unit, stride through the tile list) or
                                DGFAS_BATCH_TUNED (the choice per level and stage made by
                                dgfas_autotune; per-degree until it has run).
                                Levels with one degree always take one launch per stage */

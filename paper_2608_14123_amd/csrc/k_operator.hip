@@ -58,8 +58,9 @@ __device__ __forceinline__ int orient_face_node(int f, int o) {
 // first face axis of face phi (layout: phi 0/1 -> (xi_3, xi_2), 2/3 -> (xi_3, xi_1), 4/5 -> (xi_2, xi_1))
 __device__ __forceinline__ int face_axis_first(int phi) { return phi < 4 ? 2 : 1; }
 
+// tid_in: the thread index when the caller passes it (the persistent batches), else threadIdx.x
 template <int N, typename T, bool ORIENT = false>
-__device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpSmem<N, T>& sm) {
+__device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpSmem<N, T>& sm, int tid_in = -1) {
   using S = OpShape<N>;
   const int nrhs = a.nrhs, nel = a.nel, mode = a.mode;
   const T* __restrict__ u = a.u;
@@ -82,7 +83,7 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   u += voff;
   out += voff;
   if (g) g += voff;
-  const int tid = threadIdx.x;
+  const int tid = tid_in >= 0 ? tid_in : (int)threadIdx.x;
   const int le = tid / N3;
   const int node = tid - le * N3;
   const int li = lb * EPB + le;
@@ -347,8 +348,15 @@ sipg_batched_kernel(OpArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, i
   // tiles dealt round-robin over the XCDs (the hardware order): the work list runs from the
   // largest degree to the smallest, and contiguous ranges per XCD would leave one XCD all
   // the large tiles.  The persistent form (fewer workgroups than tiles) strides through the
-  // list, with a barrier between tiles for the shared memory.
+  // list, with a barrier between tiles for the shared memory.  It takes the thread index
+  // through an opaque register copy in every tile, so that no degree branch's index arithmetic
+  // is hoisted above the loop and kept live across it (that cost 48 VGPRs and scratch).
   auto tile = [&](int t) {
+    int tid = -1;
+    if constexpr (PERSIST) {
+      tid = threadIdx.x;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(tid));
+    }
     const int k = find_bucket(bd, nb, kStageOp, t);
     OpArgs<T> x = a;
     x.nel = bd[k].nel;
@@ -359,7 +367,7 @@ sipg_batched_kernel(OpArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, i
     switch (bd[k].p) {
 #define DGFAS_OPB(P)                                                                        \
   case P:                                                                                   \
-    if constexpr (P + 1 <= NMAX) sipg_tile<P + 1, T>(x, lbr, *reinterpret_cast<OpSmem<P + 1, T>*>(smem)); \
+    if constexpr (P + 1 <= NMAX) sipg_tile<P + 1, T>(x, lbr, *reinterpret_cast<OpSmem<P + 1, T>*>(smem), tid); \
     break;
       DGFAS_OPB(1) DGFAS_OPB(2) DGFAS_OPB(3) DGFAS_OPB(4) DGFAS_OPB(5) DGFAS_OPB(6) DGFAS_OPB(7) DGFAS_OPB(8)
 #undef DGFAS_OPB

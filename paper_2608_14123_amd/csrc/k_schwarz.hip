@@ -54,7 +54,7 @@ struct SzSmem {
 // One subdomain solve (logical block lbr = element in the list, right-hand side fastest).
 // Threads at or beyond THR (wider batched workgroups) only pass the barriers.
 template <int N, int M, typename T>
-__device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, SzSmem<N, M, T>& sm) {
+__device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, SzSmem<N, M, T>& sm, int tid_in = -1) {
   using Sh = SzShape<N, M>;
   constexpr int NS = Sh::NS, LS = Sh::LS, THR = Sh::THREADS;
   constexpr Regions<N, M> R{};
@@ -64,7 +64,7 @@ __device__ __forceinline__ void schwarz_tile(SchwarzArgs<T> a, const int lbr, Sz
   a.r += (int64_t)rhs * a.ndof;
   a.z += (int64_t)rhs * a.ndof;
   a.O += (int64_t)rhs * a.nin;
-  const int tid = threadIdx.x;
+  const int tid = tid_in >= 0 ? tid_in : (int)threadIdx.x;   // tid_in: from a persistent batch
 
   T(&tA)[Sh::TILE] = sm.tA;
   T(&sW)[3][NS] = sm.sW;
@@ -291,7 +291,7 @@ struct PtSmem {
 
 template <int N, int M, typename T>
 __device__ __forceinline__ void schwarz_point_tile(SchwarzArgs<T> a, const int lbr, PtSmem<N, M, T>& sm,
-                                                   const int nthr) {
+                                                   const int nthr, int tid_in = -1) {
   constexpr int NS = N + 2 * M, NT = NS * NS * NS, MAXP = (NT + 63) / 64;
   constexpr Regions<N, M> R{};
   const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
@@ -300,7 +300,7 @@ __device__ __forceinline__ void schwarz_point_tile(SchwarzArgs<T> a, const int l
   a.r += (int64_t)rhs * a.ndof;
   a.z += (int64_t)rhs * a.ndof;
   a.O += (int64_t)rhs * a.nin;
-  const int tid = threadIdx.x;
+  const int tid = tid_in >= 0 ? tid_in : (int)threadIdx.x;
   const int vv[3] = {__builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 0]),
                      __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 1]),
                      __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 2])};
@@ -435,14 +435,14 @@ struct AddSmem {
 // inbox, in a fixed order.  Inbox regions of absent neighbours stay zero.  With dotz set,
 // also the tile's sums of z dr and z (dr - dr0) over every node (deterministic order).
 template <int N, int M, typename T>
-__device__ __forceinline__ void overlap_add_tile(SchwarzArgs<T> a, const int lbr, AddSmem& sm) {
+__device__ __forceinline__ void overlap_add_tile(SchwarzArgs<T> a, const int lbr, AddSmem& sm, int tid_in = -1) {
   using Sh = AddShape<N>;
   constexpr int N3 = Sh::N3, EPB = Sh::EPB;
   constexpr Regions<N, M> R{};
   const int lb = lbr / a.nrhs, rhs = lbr - lb * a.nrhs;
   a.z += (int64_t)rhs * a.ndof;
   a.O += (int64_t)rhs * a.nin;
-  const int tid = threadIdx.x;
+  const int tid = tid_in >= 0 ? tid_in : (int)threadIdx.x;
   int(&sOff)[27] = sm.sOff;
   if (tid < 27) sOff[tid] = R.off[tid];
   const int le = tid / N3, node = tid - le * N3;
@@ -774,6 +774,11 @@ schwarz_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, i
   // the large tiles.  The persistent form strides through the list, with a barrier between
   // tiles for the shared memory.
   auto tile = [&](int t) {
+    int tid = -1;   // persistent form: an opaque copy per tile (see sipg_batched_kernel)
+    if constexpr (PERSIST) {
+      tid = threadIdx.x;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(tid));
+    }
     const int k = find_bucket(bd, nb, kStageSolve, t);
     SchwarzArgs<T> x = a;
     x.nel = bd[k].nel;
@@ -787,8 +792,8 @@ schwarz_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ bd, i
     switch (bd[k].p) {
 #define DGFAS_SZB(P)                                                                                  \
   case P:                                                                                             \
-    if constexpr (P + 1 <= 3) schwarz_point_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<PtSmem<P + 1, 1, T>*>(smem), blockDim.x); \
-    else if constexpr (P + 1 <= NMAX) schwarz_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<SzSmem<P + 1, 1, T>*>(smem)); \
+    if constexpr (P + 1 <= 3) schwarz_point_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<PtSmem<P + 1, 1, T>*>(smem), blockDim.x, tid); \
+    else if constexpr (P + 1 <= NMAX) schwarz_tile<P + 1, 1, T>(x, lbr, *reinterpret_cast<SzSmem<P + 1, 1, T>*>(smem), tid); \
     break;
       DGFAS_SZB(1) DGFAS_SZB(2) DGFAS_SZB(3) DGFAS_SZB(4) DGFAS_SZB(5) DGFAS_SZB(6) DGFAS_SZB(7) DGFAS_SZB(8)
 #undef DGFAS_SZB
@@ -811,6 +816,11 @@ overlap_add_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ b
   __shared__ AddSmem sm;
   // tiles dealt round-robin over the XCDs (the hardware order), strided in the persistent form
   auto tile = [&](int t) {
+    int tid = -1;   // persistent form: an opaque copy per tile (see sipg_batched_kernel)
+    if constexpr (PERSIST) {
+      tid = threadIdx.x;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(tid));
+    }
     const int k = find_bucket(bd, nb, kStageAdd, t);
     SchwarzArgs<T> x = a;
     x.nel = bd[k].nel;
@@ -819,7 +829,7 @@ overlap_add_batched_kernel(SchwarzArgs<T> a, const BucketDesc<T>* __restrict__ b
     switch (bd[k].p) {
 #define DGFAS_ADB(P)                                                          \
   case P:                                                                     \
-    if constexpr (P + 1 <= NMAX) overlap_add_tile<P + 1, 1, T>(x, lbr, sm);  \
+    if constexpr (P + 1 <= NMAX) overlap_add_tile<P + 1, 1, T>(x, lbr, sm, tid);  \
     break;
       DGFAS_ADB(1) DGFAS_ADB(2) DGFAS_ADB(3) DGFAS_ADB(4) DGFAS_ADB(5) DGFAS_ADB(6) DGFAS_ADB(7) DGFAS_ADB(8)
 #undef DGFAS_ADB

@@ -236,7 +236,7 @@ struct Solver {
   double *Dall = nullptr, *Iall = nullptr;   // mixed-degree face tables for degrees 1..8
   int force_batch = -1;                      // autotuner: -1 options, 0 per degree, 1 one launch,
                                              // 2 one persistent launch
-  int persist_grid = 512;                    // workgroups of a persistent launch (2 per CU)
+  int cus = 256;                             // compute units of the device
   // captured V-cycle legs (smoothing and transfers above the root, down and up)
   hipStream_t cap = nullptr;
   hipGraphExec_t gdown = nullptr, gup = nullptr;
@@ -339,8 +339,19 @@ struct Solver {
   }
   // workgroups of a one-launch batch: one per tile, or a persistent grid that strides through
   // the tiles (a multiple of 8, so that the round-robin XCD order of the tiles is kept)
+  // A persistent launch keeps about 24 waves per CU: the workgroups per CU follow the stage's
+  // workgroup width at the level's largest degree (2 for the 768-thread operator tile at p = 8,
+  // 12 for the 2-wave subdomain solve, 6 for the 4-wave overlap add).
+  int persistent_grid(int stage, int pmax) const {
+    const int waves = std::max(1, stage_threads(stage, pmax) / 64);
+    const int per_cu = std::max(1, 24 / waves);
+    return 8 * std::max(1, (cus * per_cu + 7) / 8);
+  }
   int batch_grid(const Level& L, int stage, int ntiles) const {
-    if (batch_mode(L, stage) == 2 && ntiles > persist_grid) return persist_grid;
+    if (batch_mode(L, stage) == 2) {
+      const int g = persistent_grid(stage, L.p);
+      if (ntiles > g) return g;
+    }
     return xcd_grid(ntiles);
   }
   template <typename T>
@@ -1884,7 +1895,7 @@ Solver* create(const dgfas_mesh_desc* m, const dgfas_options* o, void* stream) {
   {
     int cus = 0;
     HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->dev));
-    s->persist_grid = 8 * std::max(1, (2 * cus + 7) / 8);
+    s->cus = std::max(1, cus);
   }
   resolve_scratch(s->dev);
   if (o->null_space) s->npart = s->own(dalloc<double>((size_t)1024 * std::max(1, o->n_rhs)));
