@@ -7,11 +7,12 @@
 // transposed interpolation.  The lifting term uses the restricted jump times the own
 // nu n.grad xi_c, written into the transposed volume contractions as in sipg_apply.
 //
-// Two launches: one workgroup per (face between degrees, right-hand side) computes the
-// face's row and lifting terms on both sides' face grids into two result slots, then one workgroup
-// per (element, right-hand side) adds its faces' terms in face order, every output node
-// written by one thread, so the result is deterministic.  Degrees are runtime values; the
-// face's D and interpolation tables are staged in LDS.
+// One workgroup per (face between degrees, right-hand side) computes the face's row and
+// lifting terms on both sides' face grids into two result slots.  The operator kernels of the
+// level, launched afterwards, add them to their own face terms (row at the face node, lifting
+// into the contravariant fluxes before the transposed contractions), every output node written
+// by one thread, so the result is deterministic.  Degrees are runtime values; the face's D and
+// interpolation tables are staged in LDS.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -19,7 +20,7 @@ namespace dgfas {
 
 namespace {
 
-constexpr int kMaxN = 9, kMaxN2 = 81, kMortarThreads = 256;
+constexpr int kMaxN = 9, kMaxN2 = 81;
 // face kernel: one thread per face node of both sides in its first phases (n^2 + nn^2 <= 162)
 constexpr int kFaceThreads = 192;
 
@@ -53,7 +54,7 @@ __device__ T face_flux(int n, int phi, int f, const T* D, const T* tr, const T* 
 
 // Face results per (right-hand side, face side): the row term and the three lifting rows on
 // that side's face grid; a face task writes slot 2k (its own side) and 2k + 1 (the other)
-constexpr int kFaceRes = 4 * kMaxN2;
+constexpr int kFaceRes = kMortarFaceRes;
 
 // One workgroup per (face between degrees, right-hand side): phases 0 to D of the face once,
 // then the restriction to both sides' grids.  Seen from the other side the jump and flux
@@ -231,70 +232,15 @@ __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T>
   }
 }
 
-// One workgroup per (element with faces between degrees, right-hand side): the faces'
-// results in face order, row at the face and lifting through D^T along every axis, added to
-// (mode 1) or subtracted from (mode 0) the element's output.
-template <typename T>
-__global__ void __launch_bounds__(kMortarThreads) mortar_gather_kernel(MortarArgs<T> a) {
-  const int lbr = xcd_block(a.nel * a.nrhs);
-  if (lbr < 0) return;
-  const int li = lbr / a.nrhs, rhs = lbr - li * a.nrhs;
-  const int e = a.elist[li];
-  const int tid = threadIdx.x;
-  T* __restrict__ out = a.out + (int64_t)rhs * a.ndof;
-  const T* __restrict__ fres = reinterpret_cast<const T*>(a.fres) + (int64_t)rhs * 2 * a.nface * kFaceRes;
-  const int po = a.deg[e], n = po + 1, n2 = n * n, n3 = n2 * n;
-  const int64_t base = a.off[e];
-
-  __shared__ T sDo[kMaxN2];
-  __shared__ T row[6][kMaxN2], lift[6][3][kMaxN2];
-  __shared__ int ftk[6];
-  if (tid < 6) ftk[tid] = a.fmap[(int64_t)li * 6 + tid];
-  if (tid < n2) sDo[tid] = (T)a.Dall[(po - 1) * kMaxN2 + tid];
-  __syncthreads();
-  for (int phi = 0; phi < 6; ++phi) {
-    const int k = ftk[phi];
-    if (k < 0) continue;                      // uniform over the workgroup
-    const T* r = fres + (int64_t)k * kFaceRes;
-    for (int t = tid; t < n2; t += kMortarThreads) {
-      row[phi][t] = r[t];
-      for (int c = 0; c < 3; ++c) lift[phi][c][t] = r[(1 + c) * kMaxN2 + t];
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < n3; t += kMortarThreads) {
-    const int idx[3] = {t % n, (t / n) % n, t / n2};
-    T acc = 0;
-    for (int phi = 0; phi < 6; ++phi) {
-      if (ftk[phi] < 0) continue;
-      const int ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0;
-      const int tb = ax == 0 ? 1 : 0;   // axis of the fast face index b
-      const int ta = ax == 2 ? 1 : 2;   // axis of the slow face index a
-      const int l = idx[ax], fa = idx[ta], fb = idx[tb], ff = fa * n + fb;
-      T v = sDo[endo * n + l] * lift[phi][ax][ff];
-      if (l == endo) {
-        v += row[phi][ff];
-        for (int m = 0; m < n; ++m) {
-          v += sDo[m * n + fb] * lift[phi][tb][fa * n + m];
-          v += sDo[m * n + fa] * lift[phi][ta][m * n + fb];
-        }
-      }
-      acc += v;
-    }
-    out[base + t] = a.mode == 0 ? out[base + t] - acc : out[base + t] + acc;
-  }
-}
-
 }  // namespace
 
 template <typename T>
-void sipg_mortar(const MortarArgs<T>& a, hipStream_t st) {
-  if (a.nel <= 0 || a.nface <= 0) return;
+void sipg_mortar_faces(const MortarArgs<T>& a, hipStream_t st) {
+  if (a.nface <= 0) return;
   hipLaunchKernelGGL((mortar_face_kernel<T>), dim3(xcd_grid(a.nface * a.nrhs)), dim3(kFaceThreads), 0, st, a);
-  hipLaunchKernelGGL((mortar_gather_kernel<T>), dim3(xcd_grid(a.nel * a.nrhs)), dim3(kMortarThreads), 0, st, a);
 }
 
-template void sipg_mortar<double>(const MortarArgs<double>&, hipStream_t);
-template void sipg_mortar<float>(const MortarArgs<float>&, hipStream_t);
+template void sipg_mortar_faces<double>(const MortarArgs<double>&, hipStream_t);
+template void sipg_mortar_faces<float>(const MortarArgs<float>&, hipStream_t);
 
 }  // namespace dgfas

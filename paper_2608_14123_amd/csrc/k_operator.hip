@@ -59,7 +59,8 @@ __device__ __forceinline__ int orient_face_node(int f, int o) {
 __device__ __forceinline__ int face_axis_first(int phi) { return phi < 4 ? 2 : 1; }
 
 // tid_in: the thread index when the caller passes it (the persistent batches), else threadIdx.x
-template <int N, typename T, bool ORIENT = false>
+// MORTAR: the level has faces between degrees (OpArgs::fmapE), whose terms the tile adds.
+template <int N, typename T, bool ORIENT = false, bool MORTAR = false>
 __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpSmem<N, T>& sm, int tid_in = -1) {
   using S = OpShape<N>;
   const int nrhs = a.nrhs, nel = a.nel, mode = a.mode;
@@ -279,6 +280,18 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
       sF[le][0][lnode] += sg * gl[sym_index(ax, 0)];
       sF[le][1][lnode] += sg * gl[sym_index(ax, 1)];
       sF[le][2][lnode] += sg * gl[sym_index(ax, 2)];
+      if constexpr (MORTAR) {
+        // a face to another degree: its row and lifting terms from the mortar face kernel
+        const int kf = a.fmapE[(int64_t)e * 6 + phi];
+        if (kf >= 0) {
+          const T* __restrict__ r = a.fres + (int64_t)(lbr - lb * nrhs) * a.fres_stride + (int64_t)kf * kMortarFaceRes;
+          const int ff = ax == 0 ? k * N + j : (ax == 1 ? k * N + i : j * N + i);
+          rowsum += r[ff];
+          sF[le][0][lnode] += r[81 + ff];
+          sF[le][1][lnode] += r[162 + ff];
+          sF[le][2][lnode] += r[243 + ff];
+        }
+      }
     }
   }
   __syncthreads();
@@ -311,22 +324,23 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   }
 }
 
-template <int N, typename T, bool ORIENT>
+template <int N, typename T, bool ORIENT, bool MORTAR>
 __global__ void __launch_bounds__(OpShape<N>::THREADS)
 sipg_apply_kernel(OpArgs<T> a) {
   using S = OpShape<N>;
   __shared__ OpSmem<N, T> sm;
   const int lbr = xcd_block(((a.nel + S::EPB - 1) / S::EPB) * a.nrhs);
   if (lbr < 0) return;
-  sipg_tile<N, T, ORIENT>(a, lbr, sm);
+  sipg_tile<N, T, ORIENT, MORTAR>(a, lbr, sm);
 }
 
 template <int N, typename T>
 void launch_sipg(const OpArgs<T>& a, hipStream_t st) {
   using S = OpShape<N>;
   const int nb = ((a.nel + S::EPB - 1) / S::EPB) * a.nrhs;
-  if (a.nfo) hipLaunchKernelGGL((sipg_apply_kernel<N, T, true>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
-  else hipLaunchKernelGGL((sipg_apply_kernel<N, T, false>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
+  if (a.nfo) hipLaunchKernelGGL((sipg_apply_kernel<N, T, true, false>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
+  else if (a.fmapE) hipLaunchKernelGGL((sipg_apply_kernel<N, T, false, true>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
+  else hipLaunchKernelGGL((sipg_apply_kernel<N, T, false, false>), dim3(xcd_grid(nb)), dim3(S::THREADS), 0, st, a);
 }
 
 // largest tile workspace of the degrees with n <= N
@@ -367,7 +381,7 @@ sipg_batched_kernel(OpArgs<T> a, const BucketDesc<T>* __restrict__ bd, int nb, i
     switch (bd[k].p) {
 #define DGFAS_OPB(P)                                                                        \
   case P:                                                                                   \
-    if constexpr (P + 1 <= NMAX) sipg_tile<P + 1, T>(x, lbr, *reinterpret_cast<OpSmem<P + 1, T>*>(smem), tid); \
+    if constexpr (P + 1 <= NMAX) sipg_tile<P + 1, T, false, true>(x, lbr, *reinterpret_cast<OpSmem<P + 1, T>*>(smem), tid); \
     break;
       DGFAS_OPB(1) DGFAS_OPB(2) DGFAS_OPB(3) DGFAS_OPB(4) DGFAS_OPB(5) DGFAS_OPB(6) DGFAS_OPB(7) DGFAS_OPB(8)
 #undef DGFAS_OPB

@@ -5,6 +5,10 @@
 
 namespace dgfas {
 
+// face results of the faces between degrees, per side: the row term and the three lifting rows
+// on that side's face grid (first, second layout), 81 values each
+constexpr int kMortarFaceRes = 4 * 81;
+
 template <typename T>
 struct OpArgs {
   int E = 0;
@@ -31,6 +35,10 @@ struct OpArgs {
   double* dotp = nullptr;     // mode 1 only: per tile u^T (A u) partial sums, [nrhs][tiles]
   const int8_t* nfo = nullptr;   // [E][6] unstructured meshes: the neighbour's face | orientation
                                  // code << 3 per interior face (null: aligned neighbours)
+  // mixed levels: the faces between degrees, computed beforehand by the mortar face kernel
+  const int* fmapE = nullptr;    // [E][6] result slot of face phi, or -1 (null: no such faces)
+  const T* fres = nullptr;       // [nrhs][2 nface][kMortarFaceRes] row and lifting terms per side
+  int64_t fres_stride = 0;       // values per right-hand side
 };
 
 template <typename T>
@@ -123,11 +131,12 @@ struct MortarArgs {
   const double* Iall = nullptr;     // interpolation degree q -> r at ((q-1) * 8 + (r-1)) * 81
   int nface = 0;                    // faces between degrees (one task per face, both sides)
   const int* ftask = nullptr;       // [nface] e * 6 + phi of the face's lower-id side
-  const int* fmap = nullptr;        // [nel][6] result slot of face phi of the list's element, or -1
-  void* fres = nullptr;             // [nrhs][2 nface][4][81] T: row and lifting terms per face side
+  void* fres = nullptr;             // [nrhs][2 nface][kMortarFaceRes] T: row and lifting terms per side
 };
+// The face terms of every face between degrees, into fres; the operator kernels of the level
+// then add them (OpArgs::fmapE / fres), so this runs before them.
 template <typename T>
-void sipg_mortar(const MortarArgs<T>& a, hipStream_t st);
+void sipg_mortar_faces(const MortarArgs<T>& a, hipStream_t st);
 
 // Schwarz method on unstructured meshes (Sec. 4.3.1 with oriented faces and irregular edges and
 // vertices): the subdomain tiles are gathered through per-slot tables built on the host, and the

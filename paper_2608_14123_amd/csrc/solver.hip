@@ -174,7 +174,7 @@ struct Level {
   int* mlist = nullptr;
   int nmf = 0;                          // faces to another degree (one task per face)
   int* mftask = nullptr;                // [nmf] e * 6 + phi of the lower-id side
-  int* mfmap = nullptr;                 // [nm][6] result slot of (list element, phi), or -1
+  int* mfmapE = nullptr;                // [E][6] result slot of face phi, or -1
   double* mfres = nullptr;              // [nrhs][2 nmf][4][81] face results per side
   double* muf = nullptr;                // [E][6] mu_F nu
   // geometry
@@ -369,10 +369,20 @@ struct Solver {
   template <typename T>
   OpArgs<T> op_args(Level& L, const Bucket& b, int mode, const T* u, const T* g, T* out);
 
-  // out = A u (mode 1) or g - A u (mode 0): one launch per degree bucket, then the faces
-  // between degrees
+  // out = A u (mode 1) or g - A u (mode 0): the faces between degrees first, then one launch
+  // per degree bucket (or one batched launch), which adds their terms
   template <typename T>
   void op(Level& L, int mode, const T* u, const T* g, T* out) {
+    if (L.nm) {
+      MortarArgs<T> m;
+      m.nel = L.nm; m.elist = L.mlist; m.nrhs = nrhs; m.ndof = L.ndof; m.u = u; m.out = out; m.mode = mode;
+      m.deg = L.deg; m.off = L.off; m.offF = L.offF; m.nbr = L.nbr; m.ws = L.ws; m.muf = L.muf;
+      m.Dall = Dall; m.Iall = Iall;
+      m.nface = L.nmf; m.ftask = L.mftask; m.fres = L.mfres;
+      if constexpr (sizeof(T) == 8) m.G = L.G;
+      else m.G = L.G32;
+      sipg_mortar_faces<T>(m, st);
+    }
     if (use_batch(L, kStageOp)) {
       OpArgs<T> a = op_args<T>(L, L.bk[0], mode, u, g, out);
       BatchLaunch bl;
@@ -383,16 +393,6 @@ struct Solver {
         OpArgs<T> a = op_args<T>(L, b, mode, u, g, out);
         sipg_apply<T>(b.p, a, st);
       }
-    }
-    if (L.nm) {
-      MortarArgs<T> m;
-      m.nel = L.nm; m.elist = L.mlist; m.nrhs = nrhs; m.ndof = L.ndof; m.u = u; m.out = out; m.mode = mode;
-      m.deg = L.deg; m.off = L.off; m.offF = L.offF; m.nbr = L.nbr; m.ws = L.ws; m.muf = L.muf;
-      m.Dall = Dall; m.Iall = Iall;
-      m.nface = L.nmf; m.ftask = L.mftask; m.fmap = L.mfmap; m.fres = L.mfres;
-      if constexpr (sizeof(T) == 8) m.G = L.G;
-      else m.G = L.G32;
-      sipg_mortar<T>(m, st);
     }
   }
   void apply(Level& L, const double* u, double* Au) { op<double>(L, 1, u, nullptr, Au); }
@@ -1044,6 +1044,11 @@ OpArgs<T> Solver::op_args(Level& L, const Bucket& b, int mode, const T* u, const
   a.nbr = L.nbr;
   a.bc = L.bc;
   a.nfo = L.nfo;
+  if (L.nm) {
+    a.fmapE = L.mfmapE;
+    a.fres = reinterpret_cast<const T*>(L.mfres);
+    a.fres_stride = (int64_t)2 * L.nmf * kMortarFaceRes;
+  }
   a.kappa = (T)opt.kappa;
   a.inv_wend = (T)b.t->inv_wend;
   if constexpr (sizeof(T) == 8) {
@@ -1249,24 +1254,23 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
       L.mlist = s.own(upload(ml, st));
       // one task per face, listed from its lower-id side; slot 2k is that side's result,
       // 2k + 1 the other side's
-      std::vector<int> ft, fm((size_t)L.nm * 6, -1), lidx(E, -1);
-      for (int li = 0; li < L.nm; ++li) lidx[ml[li]] = li;
+      std::vector<int> ft, fm((size_t)E * 6, -1);
       for (int li = 0; li < L.nm; ++li) {
         const int e = ml[li];
         for (int f = 0; f < 6; ++f) {
           const int en = L.h_nbr[e * 6 + f];
           if (en >= 0 && deg[en] != deg[e] && e < en) {
             const int k = (int)ft.size();
-            fm[(size_t)li * 6 + f] = 2 * k;
-            fm[(size_t)lidx[en] * 6 + (f ^ 1)] = 2 * k + 1;
+            fm[(size_t)e * 6 + f] = 2 * k;
+            fm[(size_t)en * 6 + (f ^ 1)] = 2 * k + 1;
             ft.push_back(e * 6 + f);
           }
         }
       }
       L.nmf = (int)ft.size();
       L.mftask = s.own(upload(ft, st));
-      L.mfmap = s.own(upload(fm, st));
-      s.reserve(L.mfres, (size_t)s.nrhs * 2 * L.nmf * 4 * 81);
+      L.mfmapE = s.own(upload(fm, st));
+      s.reserve(L.mfres, (size_t)s.nrhs * 2 * L.nmf * kMortarFaceRes);
     }
   }
   // geometry per bucket
