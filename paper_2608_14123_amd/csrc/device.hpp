@@ -42,9 +42,11 @@ __device__ __forceinline__ constexpr int axis_stride(int ax) {
   return ax == 0 ? 1 : (ax == 1 ? N : N * N);
 }
 
-// index of symmetric metric component (b, c) in G[6] = {00, 01, 02, 11, 12, 22}
+// index of symmetric metric component (b, c) in G[6] = {00, 01, 02, 11, 12, 22}; written
+// without recursion, which the compiler turns into a per-lane loop for run-time axes
 __device__ __forceinline__ constexpr int sym_index(int b, int c) {
-  return (b > c) ? sym_index(c, b) : (b == 0 ? c : (b == 1 ? 2 + c : 5));
+  const int lo = b < c ? b : c, hi = b < c ? c : b;
+  return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
 }
 
 // offsets of the 26 overlap regions (region index (d3+1)*9 + (d2+1)*3 + (d1+1); 13 unused)

@@ -103,44 +103,51 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
 
   const int64_t base = a.off ? a.off[e] : (int64_t)e * N3;
   const int64_t fbase = a.offF ? a.offF[e] : (int64_t)e * 6 * N2;
-  // prologue: every independent load first (neighbour ids, penalties, boundary codes, u, metric, g)
+  // prologue: every load that needs only the element goes out in one batch (the D table, u,
+  // the face tasks' neighbour ids, penalties and boundary codes, the metric, g) and nothing
+  // uses them before the batch is issued, so that the tile waits for memory once before the
+  // neighbour loads that need the neighbour ids
+  T dv = 0;
+  if (tid < N2) dv = Dg[tid];
   int en_t[TPT];
   T pen_t[TPT];
   int8_t bc_t[TPT];
   int fo_t[TPT];   // ORIENT: the neighbour's face | orientation << 3
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
-    const int t = node + k * N3;
     en_t[k] = -1;
     pen_t[k] = 0;
     bc_t[k] = 0;
     fo_t[k] = 0;
-    if (active && t < 6 * N2) {
-      const int phi = t / N2;
-      int en = nbr[(int64_t)e * 6 + phi];
-      if (en >= 0 && a.deg && a.deg[en] != N - 1) en = -2;   // other degree: mortar kernel
-      en_t[k] = en;
-      pen_t[k] = pen[fbase + t];
-      bc_t[k] = bc[(int64_t)e * 6 + phi];
-      if constexpr (ORIENT) fo_t[k] = a.nfo[(int64_t)e * 6 + phi];
-    }
   }
   T uval = 0, gval = 0;
   T gl[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
     uval = u[base + node];
 #pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int t = node + k * N3;
+      if (t < 6 * N2) {
+        const int phi = t / N2;
+        en_t[k] = nbr[(int64_t)e * 6 + phi];
+        pen_t[k] = pen[fbase + t];
+        bc_t[k] = bc[(int64_t)e * 6 + phi];
+        if constexpr (ORIENT) fo_t[k] = a.nfo[(int64_t)e * 6 + phi];
+      }
+    }
+#pragma unroll
     for (int c = 0; c < 6; ++c) gl[c] = G[c * ndof + base + node];
     if (mode == 0) gval = g[base + node];
   }
   if (tid < N2) {
-    const T dv = Dg[tid];
     sD[tid] = dv;
     sDT[(tid % N) * N + tid / N] = dv;
   }
   if (active) su[le][lnode] = uval;
   // phase 0: the neighbour data of every face node (normal node line and metric row) is
-  // loaded into registers here and used after the volume phase, which hides its latency
+  // loaded into registers here and used after the volume phase, which hides its latency.  On
+  // levels of several degrees the neighbour's degree and offset go out together; a neighbour
+  // of another degree is left to the mortar face kernel (en = -2).
   T lnv[TPT][N], gn[TPT][3];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
@@ -150,13 +157,16 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
     gn[k][0] = gn[k][1] = gn[k][2] = 0;
     if (!active || t >= 6 * N2) continue;
     const int phi = t / N2, f = t - phi * N2, ax = phi >> 1;
-    const int en = en_t[k];
+    int en = en_t[k];
+    if (en < 0) continue;
+    const int64_t nbase = a.off ? a.off[en] : (int64_t)en * N3;
+    if (a.deg && a.deg[en] != N - 1) en = -2;
+    en_t[k] = en;
     if (en >= 0) {
       const int phio = ORIENT ? (fo_t[k] & 7) : (phi ^ 1);
       const int fo = ORIENT ? orient_face_node<N>(f, fo_t[k] >> 3) : f;
       const int axo = ORIENT ? (phio >> 1) : ax;
       const int endo = (phio & 1) ? N - 1 : 0;
-      const int64_t nbase = a.off ? a.off[en] : (int64_t)en * N3;
       const T* line = u + nbase + face_node<N>(phio, fo, 0);
       const int st = axis_stride<N>(axo);
       const int64_t gi = nbase + face_node<N>(phio, fo, endo);
@@ -201,7 +211,7 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
 #pragma unroll
       for (int m = 0; m < N; ++m) {
         const T v = lnv[k][m];
-        dn += Dg[endo * N + m] * v;
+        dn += sD[endo * N + m] * v;
         if (m == endo) tr = v;
       }
       dn_nb[k] = dn;
