@@ -48,27 +48,32 @@ __global__ void __launch_bounds__(TopoShape<NS>::THREADS) topo_solve_kernel(Topo
   const int lbr = blockIdx.x;
   const int e = lbr / a.nrhs, rhs = lbr - e * a.nrhs;   // right-hand side fastest
   const T* __restrict__ r = a.r + (int64_t)rhs * a.ndof;
-  const int v0 = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 0]);
-  const int v1 = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 1]);
-  const int v2 = __builtin_amdgcn_readfirstlane(a.var[(int64_t)e * 3 + 2]);
+  // the 1D variants are read here and made uniform after the gather, so that the gather does
+  // not wait for them
+  const int v0r = a.var[(int64_t)e * 3 + 0], v1r = a.var[(int64_t)e * 3 + 1], v2r = a.var[(int64_t)e * 3 + 2];
   const T g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
   const T g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
   const int tid = threadIdx.x;
   const bool act = tid < NS * NS;
   const int c1 = tid % NS, c2 = tid / NS;   // the thread's xi_3 column (s1, s2)
 
-  // gather r_s = R_s r: every load of the column first, then the LDS stores
+  // gather r_s = R_s r: the column's slot entries go out in one batch, then the values of
+  // every slot at once (a zero or merged slot reads node 0 and discards it), so that the
+  // column waits for memory twice; the rare merged slots (means over several nodes) follow
   if (act) {
     const int* __restrict__ gt = a.gather + (int64_t)e * NT + c2 * NS + c1;
+    int gi[NS];
+#pragma unroll
+    for (int s3 = 0; s3 < NS; ++s3) gi[s3] = gt[s3 * NS * NS];
     T vals[NS];
 #pragma unroll
+    for (int s3 = 0; s3 < NS; ++s3) vals[s3] = r[gi[s3] >= 0 ? gi[s3] : 0];
+#pragma unroll
     for (int s3 = 0; s3 < NS; ++s3) {
-      const int gi = gt[s3 * NS * NS];
+      if (gi[s3] >= 0) continue;
       T v = 0;
-      if (gi >= 0) {
-        v = r[gi];
-      } else if (gi < -1) {
-        const int j = -2 - gi, b = a.mptr[j], en = a.mptr[j + 1];
+      if (gi[s3] < -1) {
+        const int j = -2 - gi[s3], b = a.mptr[j], en = a.mptr[j + 1];
         const T share = T(1) / T(en - b);
         for (int k = b; k < en; ++k) v += share * r[a.midx[k]];
       }
@@ -79,6 +84,9 @@ __global__ void __launch_bounds__(TopoShape<NS>::THREADS) topo_solve_kernel(Topo
   }
   __syncthreads();
 
+  const int v0 = __builtin_amdgcn_readfirstlane(v0r);
+  const int v1 = __builtin_amdgcn_readfirstlane(v1r);
+  const int v2 = __builtin_amdgcn_readfirstlane(v2r);
   const T* __restrict__ S1 = a.S + v0 * NS * NS;
   const T* __restrict__ S2 = a.S + v1 * NS * NS;
   const T* __restrict__ S3 = a.S + v2 * NS * NS;
@@ -132,7 +140,23 @@ __global__ void __launch_bounds__(256) topo_scatter_kernel(TopoArgs<T> a) {
   const T* __restrict__ Z = a.Zt + rhs * a.nel * (int64_t)a.nt;
   T acc = 0;
   const int64_t b = a.sptr[g], en = a.sptr[g + 1];
-  for (int64_t k = b; k < en; ++k) acc += a.scoef[k] * Z[a.sslot[k]];
+  // four contributions per step: their slot entries in one batch, then their values, summed
+  // in list order (entries past the end repeat the last one and are not added)
+  for (int64_t k0 = b; k0 < en; k0 += 4) {
+    int sl[4];
+    T cf[4], zv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t k = k0 + j < en ? k0 + j : en - 1;
+      sl[j] = a.sslot[k];
+      cf[j] = a.scoef[k];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) zv[j] = Z[sl[j]];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (k0 + j < en) acc += cf[j] * zv[j];
+  }
   if (a.mode == 0) a.z[t] = acc;
   else a.z[t] += acc;
 }
