@@ -26,7 +26,7 @@ BF16_PEAK_TFLOPS = 2500.0     # dense BF16 matrix-core peak
 # HBM bytes of one residual launch of the operator kernel at 32^3, p = 7 from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a 1 GiB copy (profiles/c2_curved_p7_hbm_traffic_pmc.md);
 # valid only for the kernel source it was measured on.
-OPERATOR_TRAFFIC = {'sha256_prefix': '736cc9a3ff9bea7c', 'bytes': 1.671e9, 'ne': 32, 'p': 7}
+OPERATOR_TRAFFIC = {'sha256_prefix': '61deb11c012bf61b', 'bytes': 1.670e9, 'ne': 32, 'p': 7}
 
 
 def parse():

@@ -145,9 +145,9 @@ __device__ __forceinline__ void sipg_tile(const OpArgs<T>& a, const int lbr, OpS
   }
   if (active) su[le][lnode] = uval;
   // phase 0: the neighbour data of every face node (normal node line and metric row) is
-  // loaded into registers here and used after the volume phase, which hides its latency.  On
-  // levels of several degrees the neighbour's degree and offset go out together; a neighbour
-  // of another degree is left to the mortar face kernel (en = -2).
+  // loaded into registers here, as soon as the neighbour ids have arrived, and used from the
+  // neighbour trace on.  On levels of several degrees the neighbour's degree and offset go
+  // out together; a neighbour of another degree is left to the mortar face kernel (en = -2).
   T lnv[TPT][N], gn[TPT][3];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {

@@ -48,8 +48,7 @@ __global__ void __launch_bounds__(TopoShape<NS>::THREADS) topo_solve_kernel(Topo
   const int lbr = blockIdx.x;
   const int e = lbr / a.nrhs, rhs = lbr - e * a.nrhs;   // right-hand side fastest
   const T* __restrict__ r = a.r + (int64_t)rhs * a.ndof;
-  // the 1D variants are read here and made uniform after the gather, so that the gather does
-  // not wait for them
+  // the 1D variants, made uniform where the contractions need them
   const int v0r = a.var[(int64_t)e * 3 + 0], v1r = a.var[(int64_t)e * 3 + 1], v2r = a.var[(int64_t)e * 3 + 2];
   const T g0 = a.gco[(int64_t)e * 4 + 0], g1 = a.gco[(int64_t)e * 4 + 1];
   const T g2 = a.gco[(int64_t)e * 4 + 2], g3 = a.gco[(int64_t)e * 4 + 3];
