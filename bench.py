@@ -40,6 +40,9 @@ def parse():
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle cpu_baseline leg')
     ap.add_argument('--no-t10', action='store_true', help='skip the time-to-tolerance solves')
     ap.add_argument('--calib-copy', action='store_true', help='also run a plain copy kernel (PMC calibration)')
+    ap.add_argument('--order', default='natural', choices=['natural', 'morton'],
+                    help='curved workload: element order of the sweep kernels (the h-coarsening solves keep '
+                         'the natural order, the only one the library takes with h-levels)')
     ap.add_argument('--workload', default='curved', choices=['curved', 'front', 'stretched', 'mlp', 'local',
                                                               'diamond'],
                     help='curved: the 32^3 p = 7 headline workload; front: the hp front (27^3, degrees 2..8); '
@@ -595,9 +598,13 @@ def main():
     cyc = dict(smoother=B.SCG, ns1=3, ns2=2, mu_star=5.0, root_rtol=0.1)
     degs = np.full(E, p, np.int32)
 
+    order = B.ORDER_MORTON if args.order == 'morton' else B.ORDER_NATURAL
+
     def solver(**kw):
-        return B.Solver(degs, X, nbr, bc, B.default_options(**dict(cyc, **kw)), stream=stream.cuda_stream,
-                        box=(ne, ne, ne))
+        o = dict(cyc, **kw)
+        if 'h_levels' not in o:
+            o['order'] = order
+        return B.Solver(degs, X, nbr, bc, B.default_options(**o), stream=stream.cuda_stream, box=(ne, ne, ne))
 
     t_setup = time.perf_counter()
     lib = solver()
@@ -780,7 +787,7 @@ def main():
                    'value': 'FP64 WAS sweep (residual + Schwarz + update) on the finest level, median of %d'
                             % args.reps,
                    'step': 'one FAS-MG-SCG(3,2) V-cycle, p-levels %s, root SCG to 1e-1' % levels_str,
-                   'overlap': 1, 'mu_star': 5.0, 'rhs': 'U[-1,1] seed 2'},
+                   'overlap': 1, 'mu_star': 5.0, 'rhs': 'U[-1,1] seed 2', 'element_order': args.order},
         'roofline': dominant,
         'roofline_other': other,
         'was_sweep': lib_sweeps,
