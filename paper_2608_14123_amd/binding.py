@@ -16,6 +16,13 @@ LIB_PATH = os.path.join(_HERE, 'libdgfas.so')
 if not os.path.exists(LIB_PATH):
     raise ImportError("libdgfas.so not built: run __graft_entry__.build() (or "
                       "python paper_2608_14123_amd/csrc/build.py) first")
+# The library links the HIP runtime by its soname, and torch ships its own copy under the same
+# soname: whichever is loaded first serves both.  torch cannot initialise the GPU on a runtime
+# loaded before it, so it is imported first whenever it is installed.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 DGFAS_OK, DGFAS_ENOTCONV = 0, 1

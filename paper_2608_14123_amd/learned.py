@@ -128,3 +128,40 @@ def evaluate(torch, net, ne, mesh_seed, rhs_seed, p=8, opts=None, max_cycles=60,
     B.set_learned(lib, None, False)
     lib.close()
     return out
+
+
+def main(argv=None):
+    """The learned-correction experiment on seeded meshes of one family: pairs from plain
+    FAS-MG-SCG cycles on the training meshes (the initial residual of one right-hand side),
+    training, then plain vs learned on the held-out mesh.  Prints one JSON line per stage."""
+    import argparse, json
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument('--ne', type=int, default=48)
+    ap.add_argument('--family', default='stretched', choices=['stretched', 'curved'])
+    ap.add_argument('--train-seeds', default='40-47', help='mesh seeds of the training pairs, a-b')
+    ap.add_argument('--eval-seed', type=int, default=4, help='held-out mesh seed')
+    ap.add_argument('--ns1', type=int, default=12)
+    ap.add_argument('--ns2', type=int, default=4)
+    ap.add_argument('--epochs', type=int, default=8)
+    ap.add_argument('--max-cycles', type=int, default=40)
+    args = ap.parse_args(argv)
+    import torch
+    a, b = (int(x) for x in args.train_seeds.split('-'))
+    opts = dict(smoother=B.SCG, ns1=args.ns1, ns2=args.ns2, mu_star=5.0, root_rtol=1e-1)
+    log = lambda s: print(s, flush=True)
+    X, T, st = generate_pairs(torch, args.ne, list(range(a, b + 1)), [4100], [0], opts=opts, family=args.family,
+                              log=log)
+    print(json.dumps({'pairs': st}), flush=True)
+    net, tr = train(torch, X, T, epochs=args.epochs, batch=4096, log=log)
+    print(json.dumps({'training': tr}), flush=True)
+    del X, T
+    torch.cuda.empty_cache()
+    ev = evaluate(torch, net, args.ne, args.eval_seed, 4000, opts=opts, max_cycles=args.max_cycles,
+                  family=args.family)
+    for k, v in ev.items():
+        print(json.dumps({k: v}), flush=True)
+    net.close()
+
+
+if __name__ == '__main__':
+    main()
