@@ -65,13 +65,15 @@ __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T>
   const int lbr = xcd_block(a.nface * a.nrhs);
   if (lbr < 0) return;
   const int task = lbr / a.nrhs, rhs = lbr - task * a.nrhs;
-  const int ep = a.ftask[task], e = ep / 6, phi = ep - e * 6;
+  // the face's descriptor, built at set-up: one scalar load in place of a chain of dependent ones
+  const int64_t* __restrict__ fd = a.fdesc + (int64_t)task * 8;
+  const int ep = (int)fd[0], e = ep / 6, phi = ep - e * 6;
   const int tid = threadIdx.x;
   const T* __restrict__ u = a.u + (int64_t)rhs * a.ndof;
   T* __restrict__ res = reinterpret_cast<T*>(a.fres) + ((int64_t)rhs * 2 * a.nface + 2 * task) * kFaceRes;
   T* __restrict__ resn = res + kFaceRes;
-  const int po = a.deg[e], n = po + 1, n2 = n * n;
-  const int64_t base = a.off[e], fbase = a.offF[e];
+  const int po = (int)fd[2], n = po + 1, n2 = n * n;
+  const int64_t base = fd[4], fbase = fd[5];
   const T inv_wend_o = (T)(0.5 * po * (po + 1));
 
   __shared__ T sDo[kMaxN2], sDn[kMaxN2], sIo[kMaxN2], sIn[kMaxN2];
@@ -81,15 +83,15 @@ __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T>
   __shared__ T rF[kMaxN2], sF[kMaxN2];        // row term and lifting weight on the finer grid
   __shared__ T y1[4][kMaxN2];                 // half-restricted row and lifting weight, both sides
 
-  const int en = a.nbr[(int64_t)e * 6 + phi];
-  const int pn = a.deg[en];
+  const int en = (int)fd[1];
+  const int pn = (int)fd[3];
   const int nn = pn + 1, nn2 = nn * nn, nF = nn > n ? nn : n, nF2 = nF * nF;
   const int phin = phi ^ 1, ax = phi >> 1, endo = (phi & 1) ? n - 1 : 0, endn = (phin & 1) ? nn - 1 : 0;
   const int pF = nF - 1;
   const T sgn = (phi & 1) ? T(1) : T(-1);
   const T inv_wend_n = (T)(0.5 * pn * (pn + 1));
   const T mu = (T)a.muf[(int64_t)e * 6 + phi];
-  const int64_t nbase = a.off[en], nfbase = a.offF[en];
+  const int64_t nbase = fd[6], nfbase = fd[7];
 
   // 0: every global load of the face first (both sides' normal lines, metric rows, omega s)
   // and the face's tables into LDS; one face-node task per thread (n^2 + nn^2 <= 162)
@@ -113,11 +115,17 @@ __global__ void __launch_bounds__(kFaceThreads) mortar_face_kernel(MortarArgs<T>
     for (int c = 0; c < 3; ++c) g3[c] = a.G[sym_index(ax, c) * a.ndof + base + vi];
     wsv = (T)a.ws[fbase + phi * n2 + f];
   }
+  // the four tables: every load before the LDS stores
   for (int t = tid; t < kMaxN2; t += kFaceThreads) {
-    if (t < n2) sDo[t] = (T)a.Dall[(po - 1) * kMaxN2 + t];
-    if (t < nn2) sDn[t] = (T)a.Dall[(pn - 1) * kMaxN2 + t];
-    if (t < nF * n) sIo[t] = (T)a.Iall[((po - 1) * 8 + (pF - 1)) * kMaxN2 + t];     // nF x n
-    if (t < nF * nn) sIn[t] = (T)a.Iall[((pn - 1) * 8 + (pF - 1)) * kMaxN2 + t];    // nF x nn
+    double d_o = 0, d_n = 0, i_o = 0, i_n = 0;
+    if (t < n2) d_o = a.Dall[(po - 1) * kMaxN2 + t];
+    if (t < nn2) d_n = a.Dall[(pn - 1) * kMaxN2 + t];
+    if (t < nF * n) i_o = a.Iall[((po - 1) * 8 + (pF - 1)) * kMaxN2 + t];     // nF x n
+    if (t < nF * nn) i_n = a.Iall[((pn - 1) * 8 + (pF - 1)) * kMaxN2 + t];    // nF x nn
+    if (t < n2) sDo[t] = (T)d_o;
+    if (t < nn2) sDn[t] = (T)d_n;
+    if (t < nF * n) sIo[t] = (T)i_o;
+    if (t < nF * nn) sIn[t] = (T)i_n;
   }
   __syncthreads();
   // A: traces and normal-line derivatives of both sides

@@ -113,24 +113,18 @@ void penalty(int E, int p, const int* deg, const int64_t* offF, double mu_star, 
 // the output of sipg_apply, which leaves these faces out.
 template <typename T>
 struct MortarArgs {
-  int nel = 0;                      // elements with at least one such face
-  const int* elist = nullptr;       // [nel]
   int nrhs = 1;
   int64_t ndof = 0;
   const T* u = nullptr;
-  T* out = nullptr;
-  int mode = 0;
-  const int* deg = nullptr;         // [E]
-  const int64_t* off = nullptr;     // [E]
-  const int64_t* offF = nullptr;    // [E]
-  const int* nbr = nullptr;         // [E][6]
   const T* G = nullptr;             // [6][ndof]
   const double* ws = nullptr;       // face omega s, [offF]
   const double* muf = nullptr;      // [E][6] mu_F nu
   const double* Dall = nullptr;     // differentiation matrices of degrees 1..8, degree p at (p-1) * 81
   const double* Iall = nullptr;     // interpolation degree q -> r at ((q-1) * 8 + (r-1)) * 81
   int nface = 0;                    // faces between degrees (one task per face, both sides)
-  const int* ftask = nullptr;       // [nface] e * 6 + phi of the face's lower-id side
+  // [nface][8] per face: e * 6 + phi of its lower-id side e, the neighbour en, the degrees of e
+  // and en, then the first DOF and the first face-node slot of e and of en
+  const int64_t* fdesc = nullptr;
   void* fres = nullptr;             // [nrhs][2 nface][kMortarFaceRes] T: row and lifting terms per side
 };
 // The face terms of every face between degrees, into fres; the operator kernels of the level

@@ -171,9 +171,8 @@ struct Level {
   double* kpart = nullptr;              // [nrhs][nlb] fused p^T A p partial sums (uniform levels)
   int nla = 0;                          // overlap-add tiles per right-hand side (uniform levels)
   double* zpart = nullptr;              // [2][nrhs][nla] fused z^T r, z^T (r - r0) partial sums
-  int* mlist = nullptr;
   int nmf = 0;                          // faces to another degree (one task per face)
-  int* mftask = nullptr;                // [nmf] e * 6 + phi of the lower-id side
+  int64_t* mfdesc = nullptr;            // [nmf][8] face descriptors (MortarArgs::fdesc)
   int* mfmapE = nullptr;                // [E][6] result slot of face phi, or -1
   double* mfres = nullptr;              // [nrhs][2 nmf][4][81] face results per side
   double* muf = nullptr;                // [E][6] mu_F nu
@@ -375,10 +374,9 @@ struct Solver {
   void op(Level& L, int mode, const T* u, const T* g, T* out) {
     if (L.nm) {
       MortarArgs<T> m;
-      m.nel = L.nm; m.elist = L.mlist; m.nrhs = nrhs; m.ndof = L.ndof; m.u = u; m.out = out; m.mode = mode;
-      m.deg = L.deg; m.off = L.off; m.offF = L.offF; m.nbr = L.nbr; m.ws = L.ws; m.muf = L.muf;
+      m.nrhs = nrhs; m.ndof = L.ndof; m.u = u; m.ws = L.ws; m.muf = L.muf;
       m.Dall = Dall; m.Iall = Iall;
-      m.nface = L.nmf; m.ftask = L.mftask; m.fres = L.mfres;
+      m.nface = L.nmf; m.fdesc = L.mfdesc; m.fres = L.mfres;
       if constexpr (sizeof(T) == 8) m.G = L.G;
       else m.G = L.G32;
       sipg_mortar_faces<T>(m, st);
@@ -1251,24 +1249,25 @@ void build_level(Solver& s, Level& L, const std::vector<int>& deg, const double*
     }
     L.nm = (int)ml.size();
     if (L.nm) {
-      L.mlist = s.own(upload(ml, st));
       // one task per face, listed from its lower-id side; slot 2k is that side's result,
       // 2k + 1 the other side's
-      std::vector<int> ft, fm((size_t)E * 6, -1);
+      std::vector<int64_t> fd;
+      std::vector<int> fm((size_t)E * 6, -1);
       for (int li = 0; li < L.nm; ++li) {
         const int e = ml[li];
         for (int f = 0; f < 6; ++f) {
           const int en = L.h_nbr[e * 6 + f];
           if (en >= 0 && deg[en] != deg[e] && e < en) {
-            const int k = (int)ft.size();
+            const int k = (int)(fd.size() / 8);
             fm[(size_t)e * 6 + f] = 2 * k;
             fm[(size_t)en * 6 + (f ^ 1)] = 2 * k + 1;
-            ft.push_back(e * 6 + f);
+            const int64_t d[8] = {(int64_t)e * 6 + f, en, deg[e], deg[en], off[e], offF[e], off[en], offF[en]};
+            fd.insert(fd.end(), d, d + 8);
           }
         }
       }
-      L.nmf = (int)ft.size();
-      L.mftask = s.own(upload(ft, st));
+      L.nmf = (int)(fd.size() / 8);
+      L.mfdesc = s.own(upload(fd, st));
       L.mfmapE = s.own(upload(fm, st));
       s.reserve(L.mfres, (size_t)s.nrhs * 2 * L.nmf * kMortarFaceRes);
     }
